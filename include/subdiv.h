@@ -1,0 +1,171 @@
+/*
+ * subdiv.h - C ABI of the MI355X (gfx950) AlSub refinement library.
+ *
+ * One call refines a polygon control mesh L levels with Catmull-Clark, Loop
+ * or sqrt(3) subdivision, written as the sparse-matrix algebra of AlSub
+ * (Mlakar et al., "AlSub: Fully Parallel and Modular Subdivision", ACM TOG):
+ *
+ *   - the mesh is its mesh matrix M (Sec. 3.2): one column per face, row
+ *     indices = the face's vertices in counter-clockwise cyclic order;
+ *     a uniform face order drops the column pointer (reduced form, Sec. 4.1);
+ *   - a build step derives edge ids (the upper triangle of E = M M^T mapped
+ *     with Q_c + Q_c^{c-1}, eq:CC_E) and face adjacency (F = M M^T mapped with
+ *     Q_c, eq:F; G for Loop, App. B) and emits the refined mesh matrix
+ *     (Sec. 3.2 "Topology refinement", App. A, App. B);
+ *   - an eval step computes face, edge and vertex points (eq:spla_fp, the
+ *     edge-point rule, eq:vo and the vertex update; equ:sqrt2; eq:loop_smooth),
+ *     boundary repair (eq::CC_boundary) and creases (Sec. 3.3).
+ *
+ * All pointers in these structs are DEVICE pointers owned by the caller.
+ * The library never allocates device memory in these calls: every buffer is
+ * the caller's (outputs) or carved from the caller's workspace. All work is
+ * enqueued on the given HIP stream (`void *stream` is a hipStream_t, NULL =
+ * the null stream). Calls on different streams with different workspaces are
+ * independent; calls sharing a workspace must be serialised by the caller.
+ *
+ * Vertex order of a refined level (fixed by the paper's index rules):
+ *   Catmull-Clark  [vertex points | face points | edge points]  (|v|+r, |v|+|f|+e)
+ *   Loop           [vertex points | edge points]
+ *   sqrt(3)        [vertex points | face points]                (App. A, |v|+i)
+ * Edge ids enumerate the strict upper triangle of E in CSC order, i.e. the
+ * edges {lo < hi} sorted ascending by (hi, lo).
+ * Child faces: Catmull-Clark child j of face r is at col_ptr[r] + j and is
+ * (v_j, edge(v_j,v_j+1), face r, edge(v_j-1,v_j)); Loop children 4r+j (j<3)
+ * are (v_j, e(j,j+1), e(j-1,j)) and 4r+3 = (e01, e12, e20); sqrt(3) child
+ * 3r+j is (v_j, face across edge j, face r), or (v_j, v_j+1, face r) on a
+ * boundary edge.
+ */
+#ifndef SUBDIV_H
+#define SUBDIV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- schemes and status codes ---------------------------------------- */
+enum {
+  SUBDIV_CATMULL_CLARK = 0, /* Sec. 3 */
+  SUBDIV_LOOP = 1,          /* App. B, triangle meshes */
+  SUBDIV_SQRT3 = 2          /* App. A, triangle meshes */
+};
+
+enum {
+  SUBDIV_OK = 0,
+  SUBDIV_INVALID_ARG = -1,  /* null pointer, bad enum/level count, index out of range, size overflow */
+  SUBDIV_SCHEME_MESH = -2,  /* Loop / sqrt(3) given a face that is not a triangle */
+  SUBDIV_NONMANIFOLD = -3,  /* edge with > 2 faces, a directed edge twice, or a vertex whose faces form > 1 fan */
+  SUBDIV_DEGENERATE = -4,   /* face order < 3, repeated vertex in a face, or a vertex in no face */
+  SUBDIV_BAD_CREASE = -5,   /* crease end points not an edge, sharpness < 0 or NaN, or an edge tagged twice */
+  SUBDIV_WORKSPACE = -6,    /* workspace too small */
+  SUBDIV_HIP = -7,          /* a HIP runtime call failed; subdiv_last_error() has the HIP message */
+  SUBDIV_STATE = -8         /* plan / state does not match the call (different mesh or scheme) */
+};
+
+/* When an input has several faults, the code reported is the first of
+ * INVALID_ARG, SCHEME_MESH, DEGENERATE, NONMANIFOLD, BAD_CREASE that applies. */
+
+#define SUBDIV_MAX_LEVELS 10
+#define SUBDIV_MAX_VALENCE 1024 /* vertices of higher valence are rejected (INVALID_ARG) */
+
+/* flags for subdiv_plan */
+#define SUBDIV_FLAG_REBUILD_EACH_LEVEL 1u /* rebuild E/F from M at every level (generic M M^T path)
+                                             instead of carrying them over in closed form */
+#define SUBDIV_FLAG_KEEP_STATE 2u         /* keep every level's topology in the workspace for
+                                             subdiv_backward */
+
+/* ---- inputs ----------------------------------------------------------- */
+typedef struct subdiv_mesh {
+  int32_t num_vertices;           /* |v| >= 1 */
+  int32_t num_faces;              /* |f| >= 1 */
+  int32_t face_order;             /* 3 or 4 when face_offsets == NULL (reduced M), else ignored */
+  int32_t num_halfedges;          /* H = nnz(M); must equal face_offsets[|f|] when face_offsets != NULL,
+                                     ignored (= |f|*face_order) otherwise */
+  const int32_t *face_offsets;    /* [|f|+1] column pointer of M (starts at 0, non-decreasing), or NULL */
+  const int32_t *face_verts;      /* [H] row indices of M, CCW per face */
+  const float *positions;         /* [|v|*3] row-major x,y,z */
+  int32_t num_creases;            /* crease matrix C as a list (Sec. 3.3); Catmull-Clark only */
+  const int32_t *crease_verts;    /* [2*num_creases] end points of crease edges */
+  const float *crease_sharpness;  /* [num_creases] sharpness sigma >= 0 (0 = smooth edge) */
+} subdiv_mesh;
+
+/* ---- sizes ------------------------------------------------------------ */
+typedef struct subdiv_level_info {
+  int64_t num_vertices;
+  int64_t num_edges;
+  int64_t num_faces;
+  int64_t num_halfedges;     /* H = nnz(M) */
+  int64_t num_boundary_edges;
+  int32_t face_order;        /* uniform face order, 0 = mixed (column pointer present) */
+  int32_t max_creases;       /* upper bound on the crease edges of this level (0 = smooth) */
+} subdiv_level_info;
+
+typedef struct subdiv_plan_info {
+  int32_t scheme;
+  int32_t levels;
+  uint32_t flags;
+  int32_t max_valence;
+  float max_sharpness;
+  int32_t reserved0;
+  subdiv_level_info level[SUBDIV_MAX_LEVELS + 1]; /* level[0] = the cage */
+  size_t workspace_bytes;   /* device workspace subdiv_refine needs */
+  /* private to the library: identity of the cage and of the plan workspace */
+  const void *priv_mesh_verts;
+  const void *priv_ws;
+  uint64_t priv_stamp;
+} subdiv_plan_info;
+
+/* ---- outputs ---------------------------------------------------------- */
+/* One refined level, all device buffers owned by the caller. face_verts has
+ * level[k].num_halfedges entries (F*4 for Catmull-Clark, F*3 for Loop and
+ * sqrt(3)); positions has level[k].num_vertices*3 floats. Optional buffers
+ * may be NULL. */
+typedef struct subdiv_level_out {
+  int32_t *face_verts;       /* [H_k] reduced M of level k (uniform order) */
+  float *positions;          /* [V_k*3] */
+  int32_t *edge_verts;       /* optional [2*E_{k-1}]: (lo, hi) of the PARENT level's edges in id order */
+  double *crease_sharpness;  /* optional [E_k]: sharpness per edge id of level k (0 = smooth);
+                                written only while max_creases > 0 */
+} subdiv_level_out;
+
+/* Upper bound of the workspace bytes subdiv_plan and subdiv_refine need for
+ * a cage of V vertices, F faces, H = nnz(M) and C creases refined `levels`
+ * times (host-only, no device work). A workspace of this size can be passed
+ * to subdiv_plan and then, unchanged, to subdiv_refine, which then reuses the
+ * plan's level-0 adjacency instead of rebuilding it. */
+size_t subdiv_workspace_bound(int32_t V, int32_t F, int64_t H, int32_t C, int scheme, int levels, uint32_t flags);
+
+/* Symbolic pass (Sec. 4.2): validates the cage, builds its edge ids and
+ * adjacency on the device in `ws`, waits for the stream, and fills `plan`
+ * with the exact size of every level and the workspace subdiv_refine needs.
+ * Returns SUBDIV_OK or a status code; on error `plan` is zeroed. */
+int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags, void *ws, size_t ws_bytes,
+                subdiv_plan_info *plan, void *stream);
+
+/* Refines the cage plan->levels times (dynamic topology: build and eval
+ * alternate per level, Sec. 3.6). outs[k] for k = 1..levels receive level k;
+ * outs[levels].face_verts and .positions are required, the other levels are
+ * written only where the caller gives buffers (outs may hold NULLs there;
+ * outs[0] is ignored). `ws` needs plan->workspace_bytes bytes; when it is the
+ * workspace plan used, the level-0 adjacency is reused. The mesh must be the
+ * one planned (same face_verts pointer); positions may change, the crease
+ * tags and sharpness are read by subdiv_plan.
+ * Enqueues work only: no host synchronisation. */
+int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* HIP error text of the last SUBDIV_HIP status on this thread ("" if none). */
+const char *subdiv_last_error(void);
+
+/* Human-readable name of a status code. */
+const char *subdiv_strerror(int status);
+
+/* Library version, 1000*major + minor. */
+int subdiv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBDIV_H */

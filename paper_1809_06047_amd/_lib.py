@@ -1,0 +1,93 @@
+"""ctypes view of the C ABI in include/subdiv.h (argument marshalling only).
+
+Loading fails loudly when libsubdiv.so has not been built: there is no CPU
+fallback anywhere in the product path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsubdiv.so")
+
+CATMULL_CLARK, LOOP, SQRT3 = 0, 1, 2
+SCHEMES = {"cc": CATMULL_CLARK, "catmull-clark": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3}
+
+OK, INVALID_ARG, SCHEME_MESH, NONMANIFOLD, DEGENERATE, BAD_CREASE, WORKSPACE, HIP, STATE = 0, -1, -2, -3, -4, -5, \
+    -6, -7, -8
+MAX_LEVELS = 10
+MAX_VALENCE = 1024
+FLAG_REBUILD_EACH_LEVEL = 1
+FLAG_KEEP_STATE = 2
+
+c_i32, c_i64, c_u32, c_u64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, \
+    ctypes.c_void_p, ctypes.c_size_t
+
+
+class subdiv_mesh(ctypes.Structure):
+    _fields_ = [("num_vertices", c_i32), ("num_faces", c_i32), ("face_order", c_i32), ("num_halfedges", c_i32),
+                ("face_offsets", c_vp), ("face_verts", c_vp), ("positions", c_vp), ("num_creases", c_i32),
+                ("crease_verts", c_vp), ("crease_sharpness", c_vp)]
+
+
+class subdiv_level_info(ctypes.Structure):
+    _fields_ = [("num_vertices", c_i64), ("num_edges", c_i64), ("num_faces", c_i64), ("num_halfedges", c_i64),
+                ("num_boundary_edges", c_i64), ("face_order", c_i32), ("max_creases", c_i32)]
+
+
+class subdiv_plan_info(ctypes.Structure):
+    _fields_ = [("scheme", c_i32), ("levels", c_i32), ("flags", c_u32), ("max_valence", c_i32),
+                ("max_sharpness", ctypes.c_float), ("reserved0", c_i32),
+                ("level", subdiv_level_info * (MAX_LEVELS + 1)), ("workspace_bytes", c_sz),
+                ("priv_mesh_verts", c_vp), ("priv_ws", c_vp), ("priv_stamp", c_u64)]
+
+
+class subdiv_level_out(ctypes.Structure):
+    _fields_ = [("face_verts", c_vp), ("positions", c_vp), ("edge_verts", c_vp), ("crease_sharpness", c_vp)]
+
+
+# every function the header declares, with its signature
+SIGNATURES = {
+    "subdiv_workspace_bound": (c_sz, [c_i32, c_i32, c_i64, c_i32, ctypes.c_int, ctypes.c_int, c_u32]),
+    "subdiv_plan": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, c_u32, c_vp, c_sz,
+                                   ctypes.POINTER(subdiv_plan_info), c_vp]),
+    "subdiv_refine": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
+                                     ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_last_error": (ctypes.c_char_p, []),
+    "subdiv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "subdiv_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_06047_amd.build` "
+                              "(there is no fallback path)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class SubdivError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        lib = load()
+        msg = lib.subdiv_strerror(status).decode()
+        if status == HIP:
+            msg += ": " + lib.subdiv_last_error().decode()
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+def check(status: int, where: str):
+    if status != OK:
+        raise SubdivError(status, where)

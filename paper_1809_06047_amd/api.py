@@ -1,0 +1,167 @@
+"""Python surface over the C ABI: device uploads, workspace and output
+allocation with torch (device memory and streams only), plan + refine.
+
+Every step of the refinement runs in libsubdiv's HIP kernels; this module
+only allocates buffers and passes pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def current_stream_handle(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class DeviceMesh:
+    """A cage uploaded to the device; keeps its tensors alive."""
+
+    def __init__(self, mesh, device="cuda"):
+        dev = torch.device(device)
+        self.device = dev
+        self.name = getattr(mesh, "name", "")
+        self.verts = torch.from_numpy(np.ascontiguousarray(mesh.verts, np.int32)).to(dev)
+        self.offsets = None if mesh.offsets is None else torch.from_numpy(
+            np.ascontiguousarray(mesh.offsets, np.int32)).to(dev)
+        self.positions = torch.from_numpy(np.ascontiguousarray(mesh.positions, np.float32)).to(dev)
+        C = mesh.num_creases
+        self.crease_verts = torch.from_numpy(np.ascontiguousarray(mesh.crease_verts, np.int32)).to(dev) if C else None
+        self.crease_sharp = torch.from_numpy(np.ascontiguousarray(mesh.crease_sharp, np.float32)).to(dev) if C \
+            else None
+        self.V = int(mesh.num_vertices)
+        self.F = int(mesh.num_faces)
+        self.H = int(mesh.num_halfedges)
+        self.C = int(C)
+        self.order = 0 if mesh.offsets is not None else int(mesh.face_order)
+        self.struct = self._make_struct()
+
+    def _make_struct(self):
+        m = _lib.subdiv_mesh()
+        m.num_vertices = self.V
+        m.num_faces = self.F
+        m.face_order = self.order
+        m.num_halfedges = self.H
+        m.face_offsets = None if self.offsets is None else self.offsets.data_ptr()
+        m.face_verts = self.verts.data_ptr()
+        m.positions = self.positions.data_ptr()
+        m.num_creases = self.C
+        m.crease_verts = None if self.crease_verts is None else self.crease_verts.data_ptr()
+        m.crease_sharpness = None if self.crease_sharp is None else self.crease_sharp.data_ptr()
+        return m
+
+    def set_positions(self, P: torch.Tensor):
+        """Point the cage at other positions (same topology), e.g. for autograd."""
+        assert P.shape == (self.V, 3) and P.dtype == torch.float32 and P.is_contiguous()
+        self.positions = P
+        self.struct.positions = P.data_ptr()
+
+
+class Refiner:
+    """Plan + refine of one cage. `keep` selects the levels whose meshes are
+    kept as outputs (the final level always is)."""
+
+    def __init__(self, mesh, scheme, levels: int, flags: int = 0, keep: str = "final", edges: bool = False,
+                 creases: bool = False, device="cuda"):
+        load()
+        self.dmesh = mesh if isinstance(mesh, DeviceMesh) else DeviceMesh(mesh, device)
+        self.scheme = _lib.SCHEMES.get(scheme, scheme)
+        self.levels = int(levels)
+        self.flags = int(flags)
+        self.keep = keep
+        self.want_edges = edges
+        self.want_creases = creases
+        lib = load()
+        d = self.dmesh
+        self.ws_bytes = int(lib.subdiv_workspace_bound(d.V, d.F, d.H, d.C, self.scheme, self.levels, self.flags))
+        if self.ws_bytes == 0:
+            raise _lib.SubdivError(_lib.INVALID_ARG, "subdiv_workspace_bound")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d.device)
+        self.plan_info = _lib.subdiv_plan_info()
+        self.outs: List[Dict[str, torch.Tensor]] = []
+        self._outs_struct = None
+
+    def plan(self, stream=None):
+        lib = load()
+        s = current_stream_handle(self.dmesh.device) if stream is None else stream
+        st = lib.subdiv_plan(ctypes.byref(self.dmesh.struct), self.scheme, self.levels, self.flags,
+                             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.byref(self.plan_info),
+                             ctypes.c_void_p(s))
+        check(st, "subdiv_plan")
+        if self.plan_info.workspace_bytes > self.ws_bytes:
+            raise _lib.SubdivError(_lib.WORKSPACE, "workspace bound below the planned size")
+        self._alloc_outputs()
+        return self.plan_info
+
+    def level_info(self, k):
+        li = self.plan_info.level[k]
+        return dict(V=li.num_vertices, E=li.num_edges, F=li.num_faces, H=li.num_halfedges,
+                    B=li.num_boundary_edges, order=li.face_order, max_creases=li.max_creases)
+
+    def _alloc_outputs(self):
+        dev = self.dmesh.device
+        L = self.levels
+        arr = (_lib.subdiv_level_out * (L + 1))()
+        self.outs = [dict() for _ in range(L + 1)]
+        for k in range(1, L + 1):
+            if self.keep != "all" and k != L:
+                continue
+            li = self.plan_info.level[k]
+            o = self.outs[k]
+            o["face_verts"] = torch.empty(li.num_halfedges, dtype=torch.int32, device=dev)
+            o["positions"] = torch.empty((li.num_vertices, 3), dtype=torch.float32, device=dev)
+            if self.want_edges:
+                o["edge_verts"] = torch.empty((self.plan_info.level[k - 1].num_edges, 2), dtype=torch.int32,
+                                              device=dev)
+            if self.want_creases and li.max_creases > 0:
+                o["crease_sharpness"] = torch.zeros(li.num_edges, dtype=torch.float64, device=dev)
+            arr[k].face_verts = o["face_verts"].data_ptr()
+            arr[k].positions = o["positions"].data_ptr()
+            if "edge_verts" in o:
+                arr[k].edge_verts = o["edge_verts"].data_ptr()
+            if "crease_sharpness" in o:
+                arr[k].crease_sharpness = o["crease_sharpness"].data_ptr()
+        self._outs_struct = arr
+
+    def run(self, stream=None):
+        """Enqueue the refinement (no host synchronisation)."""
+        lib = load()
+        s = current_stream_handle(self.dmesh.device) if stream is None else stream
+        st = lib.subdiv_refine(ctypes.byref(self.dmesh.struct), ctypes.byref(self.plan_info), self._outs_struct,
+                               ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.c_void_p(s))
+        check(st, "subdiv_refine")
+        return self.outs
+
+    @property
+    def final(self):
+        return self.outs[self.levels]
+
+
+def refine(mesh, scheme, levels: int, flags: int = 0, keep: str = "final", edges: bool = False,
+           creases: bool = False, device="cuda"):
+    """Refine `mesh` (a meshgen.Mesh or DeviceMesh) `levels` times; returns
+    the list of per-level output dicts (index 0 empty) after synchronising."""
+    r = Refiner(mesh, scheme, levels, flags, keep, edges, creases, device)
+    r.plan()
+    outs = r.run()
+    torch.cuda.synchronize(r.dmesh.device)
+    return outs, r
+
+
+def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
+    """Status subdiv_plan reports for this cage (0 = accepted)."""
+    try:
+        Refiner(mesh, scheme, levels, device=device).plan()
+        return 0
+    except _lib.SubdivError as e:
+        return e.status

@@ -1,0 +1,458 @@
+// Generic build step on gfx950: from a mesh matrix M to its edge ids and
+// adjacency, i.e. the mapped products E = M M^T {Q_c + Q_c^{c-1}} (eq:CC_E)
+// and F = M M^T {Q_c}[gamma] (eq:F), computed without forming the product
+// (Sec. 4.2): every collision of M(i,k) with M^T(k,j) is a pair of cyclic
+// neighbours i, j inside face k, so the work is organised per vertex over
+// the faces it touches.
+//
+//   1. valence n = M 1 (eq:vo) by integer atomics, plus input validation
+//   2. exclusive scan of n -> row pointer of the row view of M
+//   3. incidence fill: the half-edges leaving each vertex (a transpose of M
+//      by atomic cursors; rows are sorted afterwards so nothing depends on
+//      atomic order)
+//   4. per vertex: twin half-edges (the F pattern), boundary starts, fan
+//      check, and the sorted set of lower neighbours (the column of the
+//      strict upper triangle of E owned by this vertex); its size is the
+//      symbolic count of Sec. 4.2
+//   5. exclusive scan of the counts -> column pointer of triu(E) = edge base
+//   6. per vertex: edge id = base[hi] + rank of lo (CSC enumeration of the
+//      upper triangle), edge -> half-edge map, boundary flags (E == 1)
+// plus the crease matrix C placed onto edge ids (Sec. 3.3) and the device
+// exclusive scan used by every step.
+#include "subdiv_internal.h"
+
+namespace subdiv {
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_i32(int32_t *p, int32_t value, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = value;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned g = grid_for(n);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(kBlock), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s) {
+  // callers only clear 4-byte aligned regions whose size is a multiple of 4
+  return launch_fill_i32(reinterpret_cast<int32_t *>(p), 0, nbytes / 4, s);
+}
+
+// ------------------------------------------------------------------- scan
+// Block-wide scans: 256 threads x 8 items. A wave-64 inclusive scan with
+// cross-lane shuffles, then the 4 wave totals through LDS.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across the block; *total = block sum.
+__device__ __forceinline__ int block_excl_scan(int x, int *total) {
+  __shared__ int wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int incl = wave_incl_scan(x);
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    const int s = wsum[w];
+    off += (w < wid) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - x;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t *in, long long n, int32_t *partials) {
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += in[base + i];
+  int tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of partials[0..nb) in place, partials[nb] = total
+__global__ void __launch_bounds__(kScanThreads) k_scan_partials(int32_t *partials, long long nb) {
+  int carry = 0;
+  for (long long t0 = 0; t0 < nb; t0 += kScanTile) {
+    const long long base = t0 + (long long)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = (base + i < nb) ? partials[base + i] : 0;
+      s += v[i];
+    }
+    int tot;
+    int off = block_excl_scan(s, &tot) + carry;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < nb) partials[base + i] = off;
+      off += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partials[nb] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t *in, int32_t *out, long long n,
+                                                            const int32_t *partials, long long nb,
+                                                            int32_t *total_dst) {
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int tot;
+  int off = block_excl_scan(s, &tot) + (partials ? partials[blockIdx.x] : 0);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = off;
+    off += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
+    const int total = partials ? partials[nb] : off;
+    out[n] = total;
+    if (total_dst) *total_dst = total;
+  }
+}
+
+long long scan_partials_ints(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan(const int32_t *in, int32_t *out, long long n, int32_t *partials, int32_t *total_dst,
+                       hipStream_t s) {
+  const long long nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const int32_t *)nullptr, 0ll,
+                       total_dst);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                     (const int32_t *)partials, nb, total_dst);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ build
+// 1. per face: validation, valence atomics, column of every non-zero
+template <int ORDER>
+__global__ void k_build_faces(Topo t, int scheme, int32_t *nval, int32_t *hface_out, DeviceInfo *info) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= t.F) return;
+  uint32_t fault = 0;
+  int b, e;
+  if constexpr (ORDER > 0) {
+    b = f * ORDER;
+    e = b + ORDER;
+  } else {
+    b = t.off[f];
+    e = t.off[f + 1];
+    if (f == 0 && b != 0) fault |= FAULT_INVALID_ARG;
+    if (f == t.F - 1 && e != t.H) fault |= FAULT_INVALID_ARG;
+    if (e < b || b < 0 || e > t.H) {
+      atomicOr(&info->faults, fault | FAULT_INVALID_ARG);
+      return;
+    }
+  }
+  const int c = e - b;
+  if (c < 3) fault |= FAULT_DEGENERATE;
+  if (scheme != SUBDIV_CATMULL_CLARK && c != 3) fault |= FAULT_SCHEME_MESH;
+  for (int h = b; h < e; ++h) {
+    const int v = t.fv[h];
+    if (hface_out) hface_out[h] = f;
+    if (v < 0 || v >= t.V) {
+      fault |= FAULT_INVALID_ARG;
+      continue;
+    }
+    atomicAdd(&nval[v], 1);
+    for (int g = b; g < h; ++g)
+      if (t.fv[g] == v) fault |= FAULT_DEGENERATE;
+  }
+  if (fault) atomicOr(&info->faults, fault);
+}
+
+// 3. row view of M: half-edges leaving each vertex
+__global__ void k_build_incidence(Topo t, const int32_t *rowptr, int32_t *cursor, int32_t *inc) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= t.H) return;
+  const int v = t.fv[h];
+  const int pos = atomicAdd(&cursor[v], 1);
+  inc[rowptr[v] + pos] = h;
+}
+
+// in-place insertion sort of a short int list (per-thread, global memory)
+__device__ void sort_small(int32_t *a, int n) {
+  for (int i = 1; i < n; ++i) {
+    const int x = a[i];
+    int j = i - 1;
+    while (j >= 0 && a[j] > x) {
+      a[j + 1] = a[j];
+      --j;
+    }
+    a[j + 1] = x;
+  }
+}
+
+// 4. per vertex: twins, boundary start, fan check, lower neighbours
+template <int ORDER>
+__global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int32_t *cand, int32_t *twin,
+                               int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= t.V) return;
+  const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
+  uint32_t fault = 0;
+  if (n == 0 || n > SUBDIV_MAX_VALENCE) {
+    atomicOr(&info->faults, n == 0 ? FAULT_DEGENERATE : FAULT_INVALID_ARG);
+    vhe[v] = -1;
+    cntlo[v] = 0;
+    return;
+  }
+  atomicMax(&info->max_valence, n);
+  int32_t *row = inc + r0;
+  sort_small(row, n);
+  int start = row[0], nbnd = 0;
+  for (int i = 0; i < n; ++i) {
+    const int h = row[i];
+    const int w = t.fv[he_next<ORDER>(t, h)];
+    int tw = -1, hits = 0;
+    for (int m = 0; m < n; ++m) {
+      const int hp = he_prev<ORDER>(t, row[m]);
+      if (t.fv[hp] == w) {
+        tw = hp;
+        ++hits;
+      }
+    }
+    if (hits > 1) fault |= FAULT_NONMANIFOLD;
+    for (int m = 0; m < i; ++m)
+      if (t.fv[he_next<ORDER>(t, row[m])] == w) fault |= FAULT_NONMANIFOLD;  // directed edge v->w twice
+    twin[h] = tw;
+    if (tw < 0) {
+      if (nbnd == 0) start = h;
+      ++nbnd;
+    }
+  }
+  if (nbnd > 1) fault |= FAULT_NONMANIFOLD;
+  vhe[v] = start;
+  // one fan: walk from the start around v through twin(prev(h))
+  int steps = 0, h = start;
+  while (true) {
+    ++steps;
+    if (steps > n) break;
+    const int u = t.fv[he_prev<ORDER>(t, h)];
+    int hn = -1;
+    for (int m = 0; m < n; ++m)
+      if (t.fv[he_next<ORDER>(t, row[m])] == u) hn = row[m];
+    if (hn < 0 || hn == start) break;
+    h = hn;
+  }
+  if (steps != n) fault |= FAULT_NONMANIFOLD;
+  // lower neighbours (one column of triu(E)), sorted and distinct
+  int32_t *c = cand + 2 * r0;
+  int k = 0;
+  for (int i = 0; i < n; ++i) {
+    const int w = t.fv[he_next<ORDER>(t, row[i])];
+    const int u = t.fv[he_prev<ORDER>(t, row[i])];
+    if (w < v) c[k++] = w;
+    if (u < v) c[k++] = u;
+  }
+  sort_small(c, k);
+  int d = 0;
+  for (int i = 0; i < k; ++i)
+    if (i == 0 || c[i] != c[i - 1]) c[d++] = c[i];
+  cntlo[v] = d;
+  if (fault) atomicOr(&info->faults, fault);
+}
+
+__device__ __forceinline__ int rank_of(const int32_t *c, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (c[m] < x) lo = m + 1;
+    else hi = m;
+  }
+  return lo;
+}
+
+// 6. edge ids (CSC order of triu(E)), edge -> half-edge, boundary flags
+template <int ORDER>
+__global__ void k_build_eid(Topo t, const int32_t *rowptr, const int32_t *inc, const int32_t *cand,
+                            const int32_t *cntlo, const int32_t *ebase, const int32_t *twin, int32_t *eid,
+                            int32_t *e2h, int32_t *bflag, DeviceInfo *info) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= t.V) return;
+  const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
+  const int32_t *c = cand + 2 * r0;
+  const int cnt = cntlo[v], base = ebase[v];
+  int nb = 0;
+  for (int i = 0; i < n; ++i) {
+    const int h = inc[r0 + i];
+    const int w = t.fv[he_next<ORDER>(t, h)];
+    if (w < v) {
+      const int e = base + rank_of(c, cnt, w);
+      eid[h] = e;
+      const int tw = twin[h];
+      e2h[e] = (tw >= 0 && tw < h) ? tw : h;
+      bflag[e] = tw < 0;
+      nb += tw < 0;
+    }
+    const int hp = he_prev<ORDER>(t, h);
+    const int u = t.fv[hp];
+    if (u < v) {
+      const int e = base + rank_of(c, cnt, u);
+      eid[hp] = e;
+      if (twin[hp] < 0) {  // boundary edge u->v with no half-edge v->u
+        e2h[e] = hp;
+        bflag[e] = 1;
+        ++nb;
+      }
+    }
+  }
+  if (nb) atomicAdd(&info->num_boundary, nb);
+}
+
+hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s) {
+  hipError_t err;
+  if ((err = launch_fill_i32(b.nval, 0, t.V + 1ll, s)) != hipSuccess) return err;
+  if ((err = launch_fill_i32(b.cursor, 0, t.V, s)) != hipSuccess) return err;
+  const unsigned gf = grid_for(t.F);
+  if (t.order == 4)
+    hipLaunchKernelGGL(k_build_faces<4>, dim3(gf), dim3(kBlock), 0, s, t, scheme, b.nval, (int32_t *)nullptr, info);
+  else if (t.order == 3)
+    hipLaunchKernelGGL(k_build_faces<3>, dim3(gf), dim3(kBlock), 0, s, t, scheme, b.nval, (int32_t *)nullptr, info);
+  else
+    hipLaunchKernelGGL(k_build_faces<0>, dim3(gf), dim3(kBlock), 0, s, t, scheme, b.nval,
+                       const_cast<int32_t *>(t.hface), info);
+  return hipGetLastError();
+}
+
+hipError_t build_adjacency(const Topo &t, int scheme, const BuildScratch &b, Adj &a, DeviceInfo *info,
+                           hipStream_t s) {
+  (void)scheme;
+  hipError_t err;
+  if ((err = launch_scan(b.nval, b.rowptr, t.V, b.partials, nullptr, s)) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_build_incidence, dim3(grid_for(t.H)), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr,
+                     b.cursor, b.inc);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  const unsigned gv = grid_for(t.V);
+  if (t.order == 4)
+    hipLaunchKernelGGL(k_build_vertex<4>, dim3(gv), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr, b.inc, b.cand,
+                       a.twin, a.vhe, b.cntlo, info);
+  else if (t.order == 3)
+    hipLaunchKernelGGL(k_build_vertex<3>, dim3(gv), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr, b.inc, b.cand,
+                       a.twin, a.vhe, b.cntlo, info);
+  else
+    hipLaunchKernelGGL(k_build_vertex<0>, dim3(gv), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr, b.inc, b.cand,
+                       a.twin, a.vhe, b.cntlo, info);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if ((err = launch_scan(b.cntlo, b.ebase, t.V, b.partials, &info->num_edges, s)) != hipSuccess) return err;
+#define SUBDIV_EID_ARGS                                                                                        \
+  t, (const int32_t *)b.rowptr, (const int32_t *)b.inc, (const int32_t *)b.cand, (const int32_t *)b.cntlo,     \
+      (const int32_t *)b.ebase, (const int32_t *)a.twin, a.eid, a.e2h, b.bflag, info
+  if (t.order == 4)
+    hipLaunchKernelGGL(k_build_eid<4>, dim3(gv), dim3(kBlock), 0, s, SUBDIV_EID_ARGS);
+  else if (t.order == 3)
+    hipLaunchKernelGGL(k_build_eid<3>, dim3(gv), dim3(kBlock), 0, s, SUBDIV_EID_ARGS);
+  else
+    hipLaunchKernelGGL(k_build_eid<0>, dim3(gv), dim3(kBlock), 0, s, SUBDIV_EID_ARGS);
+#undef SUBDIV_EID_ARGS
+  return hipGetLastError();
+}
+
+hipError_t build_bscan(const Topo &t, const BuildScratch &b, Adj &a, hipStream_t s) {
+  (void)t;
+  return launch_scan(b.bflag, a.bscan, a.E, b.partials, nullptr, s);
+}
+
+// crease matrix C (Sec. 3.3) placed on edge ids: sig[eid] = sigma
+template <int ORDER>
+__global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *inc, const int32_t *eid, int C,
+                                const int32_t *cv, const float *cs, double *sig, int32_t *sigcnt,
+                                DeviceInfo *info) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C) return;
+  const int a = cv[2 * i], b = cv[2 * i + 1];
+  const float s = cs[i];
+  if (a < 0 || a >= t.V || b < 0 || b >= t.V || a == b || !(s >= 0.0f) || isinf(s)) {
+    atomicOr(&info->faults, FAULT_BAD_CREASE);
+    return;
+  }
+  if (s == 0.0f) return;  // a smooth edge
+  const int hi = a > b ? a : b, lo = a > b ? b : a;
+  int e = -1;
+  for (int r = rowptr[hi]; r < rowptr[hi + 1]; ++r) {
+    const int h = inc[r];
+    if (t.fv[he_next<ORDER>(t, h)] == lo) e = eid[h];
+    const int hp = he_prev<ORDER>(t, h);
+    if (t.fv[hp] == lo) e = eid[hp];
+  }
+  if (e < 0 || atomicAdd(&sigcnt[e], 1) != 0) {
+    atomicOr(&info->faults, FAULT_BAD_CREASE);
+    return;
+  }
+  sig[e] = (double)s;
+  atomicMax(&info->max_sharp_bits, __float_as_uint(s));
+}
+
+hipError_t build_creases(const Topo &t, const BuildScratch &b, const Adj &a, int C, const int32_t *cv,
+                         const float *cs, DeviceInfo *info, hipStream_t s) {
+  if (C <= 0) return hipSuccess;
+#define SUBDIV_CR_ARGS                                                                                       \
+  t, (const int32_t *)b.rowptr, (const int32_t *)b.inc, (const int32_t *)a.eid, C, cv, cs, a.sig, b.sigcnt, info
+  if (t.order == 4)
+    hipLaunchKernelGGL(k_build_creases<4>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
+  else if (t.order == 3)
+    hipLaunchKernelGGL(k_build_creases<3>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
+  else
+    hipLaunchKernelGGL(k_build_creases<0>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
+#undef SUBDIV_CR_ARGS
+  return hipGetLastError();
+}
+
+// (lo, hi) of every edge in id order
+template <int ORDER>
+__global__ void k_edge_export(Topo t, const int32_t *e2h, int E, int32_t *out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int h = e2h[e];
+  const int a = t.fv[h], b = t.fv[he_next<ORDER>(t, h)];
+  out[2 * e] = a < b ? a : b;
+  out[2 * e + 1] = a < b ? b : a;
+}
+
+hipError_t launch_edge_export(const Topo &t, const Adj &a, int32_t *out, hipStream_t s) {
+  if (t.order == 4)
+    hipLaunchKernelGGL(k_edge_export<4>, dim3(grid_for(a.E)), dim3(kBlock), 0, s, t, (const int32_t *)a.e2h, a.E,
+                       out);
+  else if (t.order == 3)
+    hipLaunchKernelGGL(k_edge_export<3>, dim3(grid_for(a.E)), dim3(kBlock), 0, s, t, (const int32_t *)a.e2h, a.E,
+                       out);
+  else
+    hipLaunchKernelGGL(k_edge_export<0>, dim3(grid_for(a.E)), dim3(kBlock), 0, s, t, (const int32_t *)a.e2h, a.E,
+                       out);
+  return hipGetLastError();
+}
+
+}  // namespace subdiv

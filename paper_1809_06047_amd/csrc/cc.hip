@@ -1,0 +1,251 @@
+// One Catmull-Clark level on gfx950: eval (face, edge and vertex points,
+// boundary repair, creases) fused with the build of the next level.
+//
+// Rules (Sec. 3.1 / 3.2): face point f_r = mapped M^T P (eq:spla_fp); edge
+// point 1/4 (p_k + p_l + f_r + f_s) with f_r, f_s = F(k,l), F(l,k) (eq:F);
+// vertex update s1 + s2 + s3 = (1 - 2/n) p + 1/n^2 sum p_j + 1/n^2 sum f_j with
+// n = M 1 (eq:vo); boundary repair (eq::CC_boundary); creases overwrite the
+// smooth values (Sec. 3.3, fig. module_creases) and are inherited with the
+// Chaikin-type sharpness rule.
+//
+// Topology of level k+1 (Sec. 3.2 "Topology refinement"): child j of face r
+// is (v_j, |v|+|f|+e(v_j,v_j+1), |v|+r, |v|+|f|+e(v_j-1,v_j)) at index
+// col_ptr[r] + j, i.e. child index == parent half-edge index h.
+//
+// Next-level build in closed form. Every edge of level k+1 has an edge
+// point as its higher end, so its lower neighbours are, ascending:
+// lo(e), hi(e), then the face points of the (one or two) faces of e. The
+// upper triangle of E_{k+1} is therefore enumerated by
+//     base(e) = sum_{e' < e} (2 + faces(e')) = 4 e - (boundary edges before e)
+// plus a rank in {0,1,2,3}. Twins of the 4 child half-edges of h follow from
+// twin(h) and twin(prev(h)). This replaces the symbolic pass and the mapped
+// product at every level after the cage (whose adjacency comes from the
+// generic build) and produces the same canonical ids bit for bit.
+#include "subdiv_internal.h"
+
+namespace subdiv {
+
+__device__ __forceinline__ double chaikin(double si, double sj) {
+  // max(1/4 (si + 3 sj) - 1, 0) in this exact operation order, no contraction
+  const double t = __dadd_rn(__dmul_rn(0.25, __dadd_rn(si, __dmul_rn(3.0, sj))), -1.0);
+  return t > 0.0 ? t : 0.0;
+}
+
+__device__ __forceinline__ int edge_base(const CCStep &c, int e) {
+  return 4 * e - (c.has_bnd ? c.a.bscan[e] : 0);
+}
+
+// ---------------------------------------------------------------- faces
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_cc_face(CCStep c) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= c.t.F) return;
+  const int V = c.t.V, F = c.t.F;
+  const int VF = V + F;
+  if constexpr (ORDER == 4) {
+    const int4 q = reinterpret_cast<const int4 *>(c.t.fv)[r];
+    const int4 ed = reinterpret_cast<const int4 *>(c.a.eid)[r];
+    const int v[4] = {q.x, q.y, q.z, q.w};
+    const int e[4] = {ed.x, ed.y, ed.z, ed.w};
+    const f3 p0 = ld3(c.P, v[0]), p1 = ld3(c.P, v[1]), p2 = ld3(c.P, v[2]), p3 = ld3(c.P, v[3]);
+    st3(c.P1, V + r, mul3(0.25f, add3(add3(p0, p1), add3(p2, p3))));
+    int4 *out = reinterpret_cast<int4 *>(c.fv1) + 4ll * r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = make_int4(v[j], VF + e[j], V + r, VF + e[(j + 3) & 3]);
+    if (c.a1.twin) {
+      const int4 tq = reinterpret_cast<const int4 *>(c.a.twin)[r];
+      const int tw[4] = {tq.x, tq.y, tq.z, tq.w};
+      int base[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) base[j] = edge_base(c, e[j]);
+      int4 *tout = reinterpret_cast<int4 *>(c.a1.twin) + 4ll * r;
+      int4 *eout = reinterpret_cast<int4 *>(c.a1.eid) + 4ll * r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int jp = (j + 3) & 3;
+        const int t = tw[j], tp = tw[jp];
+        const int tn = t < 0 ? -1 : ((t & ~3) | ((t + 1) & 3));  // next(t)
+        tout[j] = make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * (4 * r + ((j + 1) & 3)) + 2, 4 * (4 * r + jp) + 1,
+                            tp < 0 ? -1 : 4 * tp);
+        const int s = t < 0 ? -1 : (t >> 2), sp = tp < 0 ? -1 : (tp >> 2);
+        eout[j] = make_int4(base[j] + (v[j] > v[(j + 1) & 3]), base[j] + 2 + (s >= 0 && s < r),
+                            base[jp] + 2 + (sp >= 0 && sp < r), base[jp] + (v[j] > v[jp]));
+      }
+      c.a1.vhe[V + r] = 4 * (4 * r) + 2;
+    }
+  } else {
+    // general polygons (a cage with a column pointer) and triangle cages
+    const int b = face_begin<ORDER>(c.t, r), en = face_end<ORDER>(c.t, r), n = en - b;
+    f3 acc{0.f, 0.f, 0.f};
+    for (int h = b; h < en; ++h) acc = add3(acc, ld3(c.P, c.t.fv[h]));
+    st3(c.P1, V + r, mul3(1.0f / (float)n, acc));
+    for (int h = b; h < en; ++h) {
+      const int hp = (h == b) ? en - 1 : h - 1;
+      const int hn = (h + 1 == en) ? b : h + 1;
+      reinterpret_cast<int4 *>(c.fv1)[h] = make_int4(c.t.fv[h], VF + c.a.eid[h], V + r, VF + c.a.eid[hp]);
+      if (c.a1.twin) {
+        const int t = c.a.twin[h], tp = c.a.twin[hp];
+        const int tn = t < 0 ? -1 : he_next<ORDER>(c.t, t);
+        reinterpret_cast<int4 *>(c.a1.twin)[h] =
+            make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * hn + 2, 4 * hp + 1, tp < 0 ? -1 : 4 * tp);
+        const int s = t < 0 ? -1 : he_face<ORDER>(c.t, t), sp = tp < 0 ? -1 : he_face<ORDER>(c.t, tp);
+        const int bj = edge_base(c, c.a.eid[h]), bp = edge_base(c, c.a.eid[hp]);
+        const int vj = c.t.fv[h], vn = c.t.fv[hn], vp = c.t.fv[hp];
+        reinterpret_cast<int4 *>(c.a1.eid)[h] = make_int4(bj + (vj > vn), bj + 2 + (s >= 0 && s < r),
+                                                          bp + 2 + (sp >= 0 && sp < r), bp + (vj > vp));
+      }
+    }
+    if (c.a1.twin) c.a1.vhe[V + r] = 4 * b + 2;
+  }
+}
+
+// ---------------------------------------------------------------- vertices
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_cc_vertex(CCStep c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c.t.V) return;
+  const int V = c.t.V;
+  const int h0 = c.a.vhe[v];
+  const f3 p = ld3(c.P, v);
+  const bool bnd = c.a.twin[h0] < 0;
+  f3 sp{0.f, 0.f, 0.f}, sf{0.f, 0.f, 0.f};
+  int n = 0, k = 0, cv0 = -1, cv1 = -1, ce0 = -1, ce1 = -1, ub = -1;
+  double ssum = 0.0;
+  int h = h0;
+  while (true) {
+    const int w = c.t.fv[he_next<ORDER>(c.t, h)];
+    sp = add3(sp, ld3(c.P, w));
+    sf = add3(sf, ld3(c.P1, V + he_face<ORDER>(c.t, h)));
+    ++n;
+    if (c.creases) {
+      const int e = c.a.eid[h];
+      const double s = c.a.sig[e];
+      if (s > 0.0) {
+        if (k == 0) { cv0 = w; ce0 = e; } else if (k == 1) { cv1 = w; ce1 = e; }
+        ++k;
+        ssum += s;
+      }
+    }
+    const int hp = he_prev<ORDER>(c.t, h);
+    const int t = c.a.twin[hp];
+    if (t < 0) {
+      ub = c.t.fv[hp];
+      if (c.creases) {
+        const int e = c.a.eid[hp];
+        const double s = c.a.sig[e];
+        if (s > 0.0) {
+          if (k == 0) { cv0 = ub; ce0 = e; } else if (k == 1) { cv1 = ub; ce1 = e; }
+          ++k;
+          ssum += s;
+        }
+      }
+      break;
+    }
+    if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
+    h = t;
+  }
+  f3 S;
+  if (bnd) {  // eq::CC_boundary: 3/4 p + 1/8 (p_prev + p_next)
+    const int w0 = c.t.fv[he_next<ORDER>(c.t, h0)];
+    S = fma3(0.75f, p, mul3(0.125f, add3(ld3(c.P, w0), ld3(c.P, ub))));
+  } else {
+    const float fn = (float)n;
+    const float inv2 = 1.0f / (fn * fn);
+    S = fma3(1.0f - 2.0f / fn, p, mul3(inv2, add3(sp, sf)));
+    if (c.creases && k >= 2) {
+      const f3 sharp = (k == 2) ? fma3(0.75f, p, mul3(0.125f, add3(ld3(c.P, cv0), ld3(c.P, cv1)))) : p;
+      const double s = ssum / (double)k;
+      if (s >= 1.0) S = sharp;
+      else {
+        const float fs = (float)s;
+        S = fma3(1.0f - fs, S, mul3(fs, sharp));
+      }
+    }
+  }
+  st3(c.P1, v, S);
+  if (c.creases) c.a.vcr[v] = make_int4(k, ce0, ce1, 0);
+  if (c.a1.twin) c.a1.vhe[v] = 4 * h0;
+}
+
+// ---------------------------------------------------------------- edges
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_cc_edge(CCStep c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c.a.E) return;
+  const int V = c.t.V, F = c.t.F;
+  const int h = c.a.e2h[e];
+  const int hn = he_next<ORDER>(c.t, h);
+  const int a = c.t.fv[h], b = c.t.fv[hn];
+  const int t = c.a.twin[h];
+  const int r = he_face<ORDER>(c.t, h);
+  const f3 pab = add3(ld3(c.P, a), ld3(c.P, b));
+  f3 ep;
+  const double sj = c.creases ? c.a.sig[e] : 0.0;
+  if (t < 0) {
+    ep = mul3(0.5f, pab);
+  } else {
+    const int s = he_face<ORDER>(c.t, t);
+    ep = mul3(0.25f, add3(pab, add3(ld3(c.P1, V + r), ld3(c.P1, V + s))));
+    if (sj >= 1.0) ep = mul3(0.5f, pab);
+    else if (sj > 0.0) {
+      const float fs = (float)sj;
+      ep = fma3(1.0f - fs, ep, mul3(fs * 0.5f, pab));
+    }
+  }
+  st3(c.P1, V + F + e, ep);
+  if (!c.a1.e2h && !c.a1.sig) return;
+  const int base = edge_base(c, e);
+  const int nchild = t < 0 ? 3 : 4;
+  if (c.a1.e2h) {
+    const int hx0 = 4 * h, hx1 = 4 * hn + 3;  // a->ep in child h, ep->b in child next(h)
+    c.a1.e2h[base + 0] = a < b ? hx0 : hx1;
+    c.a1.e2h[base + 1] = a < b ? hx1 : hx0;
+    if (t < 0) {
+      c.a1.e2h[base + 2] = 4 * h + 1;
+      c.a1.vhe[V + F + e] = hx1;  // boundary vertex: its boundary half-edge
+    } else {
+      const int s = he_face<ORDER>(c.t, t);
+      c.a1.e2h[base + (r < s ? 2 : 3)] = 4 * h + 1;
+      c.a1.e2h[base + (r < s ? 3 : 2)] = 4 * t + 1;
+      c.a1.vhe[V + F + e] = 4 * h + 1;
+    }
+    if (c.has_bnd) {
+      const int b2 = 2 * c.a.bscan[e];
+      for (int i = 0; i < nchild; ++i) c.a1.bscan[base + i] = b2 + (t < 0 ? (i < 2 ? i : 2) : 0);
+    }
+  }
+  if (c.a1.sig) {
+    double s_lo = 0.0, s_hi = 0.0;
+    if (sj > 0.0) {
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      const int4 cl = c.a.vcr[lo], ch = c.a.vcr[hi];
+      const double si = cl.x == 2 ? c.a.sig[cl.y == e ? cl.z : cl.y] : sj;
+      const double sk = ch.x == 2 ? c.a.sig[ch.y == e ? ch.z : ch.y] : sj;
+      s_lo = chaikin(si, sj);
+      s_hi = chaikin(sk, sj);
+    }
+    c.a1.sig[base + 0] = s_lo;
+    c.a1.sig[base + 1] = s_hi;
+    for (int i = 2; i < nchild; ++i) c.a1.sig[base + i] = 0.0;
+  }
+}
+
+hipError_t cc_step(const CCStep &c, hipStream_t s) {
+  const unsigned gf = grid_for(c.t.F), gv = grid_for(c.t.V), ge = grid_for(c.a.E);
+  if (c.t.order == 4) {
+    hipLaunchKernelGGL(k_cc_face<4>, dim3(gf), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_vertex<4>, dim3(gv), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_edge<4>, dim3(ge), dim3(kBlock), 0, s, c);
+  } else if (c.t.order == 3) {
+    hipLaunchKernelGGL(k_cc_face<3>, dim3(gf), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_vertex<3>, dim3(gv), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_edge<3>, dim3(ge), dim3(kBlock), 0, s, c);
+  } else {
+    hipLaunchKernelGGL(k_cc_face<0>, dim3(gf), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_vertex<0>, dim3(gv), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cc_edge<0>, dim3(ge), dim3(kBlock), 0, s, c);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace subdiv

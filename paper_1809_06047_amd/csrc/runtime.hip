@@ -1,0 +1,458 @@
+// Host runtime and C ABI of libsubdiv: size planning (closed-form counts per
+// level), workspace carving, the plan (symbolic pass on the cage) and the
+// per-level build/eval loop of the dynamic-topology mode (Sec. 3.6).
+#include <atomic>
+#include <cstring>
+#include <string>
+
+#include "subdiv_internal.h"
+
+using namespace subdiv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_fail(hipError_t e) {
+  g_last_error = hipGetErrorString(e);
+  return SUBDIV_HIP;
+}
+
+#define SUBDIV_TRY(expr)                         \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hip_fail(_e);   \
+  } while (0)
+
+int status_from_faults(uint32_t f) {
+  if (f & FAULT_INVALID_ARG) return SUBDIV_INVALID_ARG;
+  if (f & FAULT_SCHEME_MESH) return SUBDIV_SCHEME_MESH;
+  if (f & FAULT_DEGENERATE) return SUBDIV_DEGENERATE;
+  if (f & FAULT_NONMANIFOLD) return SUBDIV_NONMANIFOLD;
+  if (f & FAULT_BAD_CREASE) return SUBDIV_BAD_CREASE;
+  return SUBDIV_OK;
+}
+
+struct Sizes {
+  long long V, E, F, H, B;
+  int order;
+  int creases;  // level may carry creases
+};
+
+// Closed-form counts of the refined levels (index rules of Sec. 3.2, App. A, App. B).
+void level_sizes(int scheme, int levels, long long V0, long long F0, long long H0, long long E0, long long B0,
+                 int order0, float max_sharp, long long C0, Sizes *L) {
+  L[0] = Sizes{V0, E0, F0, H0, B0, order0, (scheme == SUBDIV_CATMULL_CLARK && C0 > 0 && max_sharp > 0.f) ? 1 : 0};
+  for (int k = 0; k < levels; ++k) {
+    const Sizes &a = L[k];
+    Sizes b{};
+    if (scheme == SUBDIV_CATMULL_CLARK) {
+      b = Sizes{a.V + a.F + a.E, 2 * a.E + a.H, a.H, 4 * a.H, 2 * a.B, 4, 0};
+    } else if (scheme == SUBDIV_LOOP) {
+      b = Sizes{a.V + a.E, 2 * a.E + 3 * a.F, 4 * a.F, 12 * a.F, 2 * a.B, 3, 0};
+    } else {
+      b = Sizes{a.V + a.F, a.E + 3 * a.F, 3 * a.F, 9 * a.F, a.B, 3, 0};
+    }
+    // child sharpness <= parent sharpness - 1 (Chaikin rule), so level k+1 can
+    // only hold creases while the cage's largest sharpness exceeds k+1
+    b.creases = (L[0].creases && (double)max_sharp > (double)(k + 1)) ? 1 : 0;
+    L[k + 1] = b;
+  }
+}
+
+bool sizes_fit_int32(const Sizes *L, int levels) {
+  const long long lim = 0x7fffffffLL - 16;
+  for (int k = 0; k <= levels; ++k) {
+    const Sizes &s = L[k];
+    if (s.V > lim || s.E > lim || s.F > lim || s.H > lim || 3 * s.V > lim * 2) return false;
+    if (s.V + s.F + s.E > lim) return false;
+  }
+  return true;
+}
+
+// ---- workspace layout --------------------------------------------------
+struct Carver {
+  size_t at = 0;
+  size_t take(size_t bytes) {
+    at = (at + 255) & ~size_t(255);
+    const size_t p = at;
+    at += bytes;
+    return p;
+  }
+};
+
+struct AdjOffsets {
+  size_t twin, eid, vhe, e2h, bscan, sig, vcr;
+};
+
+struct Layout {
+  size_t info, info2;
+  // level-0 region (depends on V0, F0, H0, C0 only)
+  size_t nval, rowptr, cursor, inc, cand, cntlo, ebase, bflag, sigcnt, partials0;
+  size_t hface0;
+  AdjOffsets adj0;
+  size_t level0_end;
+  // per-level regions
+  AdjOffsets slot[2];
+  size_t partials;  // scan partials of every level after the cage
+  size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
+  size_t mfv[2], mP[2];
+  size_t total;
+};
+
+AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool creases) {
+  AdjOffsets a{};
+  a.twin = c.take(4 * H);
+  a.eid = c.take(4 * H);
+  a.vhe = c.take(4 * V);
+  a.e2h = c.take(4 * (E > 0 ? E : 1));
+  a.bscan = c.take(4 * (E + 1));
+  a.sig = creases ? c.take(8 * (E > 0 ? E : 1)) : 0;
+  a.vcr = creases ? c.take(16 * V) : 0;
+  return a;
+}
+
+Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long long C0) {
+  Layout y{};
+  Carver c;
+  const long long V0 = L[0].V, H0 = L[0].H;
+  y.info = c.take(sizeof(DeviceInfo));
+  y.info2 = c.take(sizeof(DeviceInfo));
+  y.nval = c.take(4 * (V0 + 1));
+  y.rowptr = c.take(4 * (V0 + 1));
+  y.cursor = c.take(4 * V0);
+  y.inc = c.take(4 * H0);
+  y.cand = c.take(8 * H0);
+  y.cntlo = c.take(4 * (V0 + 1));
+  y.ebase = c.take(4 * (V0 + 1));
+  y.bflag = c.take(4 * (H0 + 1));
+  y.sigcnt = c.take(4 * H0);
+  y.partials0 = c.take(4 * (scan_partials_ints(V0 > H0 ? V0 : H0) + 8));
+  y.hface0 = c.take(4 * H0);
+  // level-0 adjacency: edge-indexed arrays sized by H0 >= E0
+  y.adj0 = carve_adj(c, V0, H0, H0, C0 > 0);
+  y.level0_end = c.at;
+  // everything below may depend on the level count and on E0
+  long long maxn = 1;
+  for (int k = 1; k <= levels; ++k) {
+    maxn = L[k].V > maxn ? L[k].V : maxn;
+    maxn = L[k].E > maxn ? L[k].E : maxn;
+  }
+  y.partials = c.take(4 * (scan_partials_ints(maxn) + 8));
+  if (levels >= 2) {
+    long long mV = 0, mE = 0, mH = 0, mF = 0;
+    bool cr = false;
+    for (int k = 1; k < levels; ++k) {
+      mV = L[k].V > mV ? L[k].V : mV;
+      mE = L[k].E > mE ? L[k].E : mE;
+      mH = L[k].H > mH ? L[k].H : mH;
+      mF = L[k].F > mF ? L[k].F : mF;
+      cr = cr || L[k].creases;
+    }
+    for (int s = 0; s < 2; ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr);
+    const bool rebuild = scheme != SUBDIV_CATMULL_CLARK || (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL);
+    if (rebuild) {
+      y.bnval = c.take(4 * (mV + 1));
+      y.browptr = c.take(4 * (mV + 1));
+      y.bcursor = c.take(4 * mV);
+      y.binc = c.take(4 * mH);
+      y.bcand = c.take(8 * mH);
+      y.bcntlo = c.take(4 * (mV + 1));
+      y.bebase = c.take(4 * (mV + 1));
+      y.bbflag = c.take(4 * (mH + 1));
+      y.bsigcnt = c.take(4 * mH);
+    }
+    for (int s = 0; s < 2; ++s) {
+      y.mfv[s] = c.take(4 * mH);
+      y.mP[s] = c.take(12 * mV);
+    }
+  }
+  y.total = c.at + 256;
+  return y;
+}
+
+template <class T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+Adj adj_at(void *ws, const AdjOffsets &o, long long E, bool creases) {
+  Adj a{};
+  a.twin = at<int32_t>(ws, o.twin);
+  a.eid = at<int32_t>(ws, o.eid);
+  a.vhe = at<int32_t>(ws, o.vhe);
+  a.e2h = at<int32_t>(ws, o.e2h);
+  a.bscan = at<int32_t>(ws, o.bscan);
+  a.sig = creases && o.sig ? at<double>(ws, o.sig) : nullptr;
+  a.vcr = creases && o.vcr ? at<int4>(ws, o.vcr) : nullptr;
+  a.E = (int32_t)E;
+  return a;
+}
+
+BuildScratch scratch0(void *ws, const Layout &y) {
+  BuildScratch b{};
+  b.nval = at<int32_t>(ws, y.nval);
+  b.rowptr = at<int32_t>(ws, y.rowptr);
+  b.cursor = at<int32_t>(ws, y.cursor);
+  b.inc = at<int32_t>(ws, y.inc);
+  b.cand = at<int32_t>(ws, y.cand);
+  b.cntlo = at<int32_t>(ws, y.cntlo);
+  b.ebase = at<int32_t>(ws, y.ebase);
+  b.bflag = at<int32_t>(ws, y.bflag);
+  b.sigcnt = at<int32_t>(ws, y.sigcnt);
+  b.partials = at<int32_t>(ws, y.partials0);
+  return b;
+}
+
+BuildScratch scratch_rebuild(void *ws, const Layout &y) {
+  BuildScratch b{};
+  b.nval = at<int32_t>(ws, y.bnval);
+  b.rowptr = at<int32_t>(ws, y.browptr);
+  b.cursor = at<int32_t>(ws, y.bcursor);
+  b.inc = at<int32_t>(ws, y.binc);
+  b.cand = at<int32_t>(ws, y.bcand);
+  b.cntlo = at<int32_t>(ws, y.bcntlo);
+  b.ebase = at<int32_t>(ws, y.bebase);
+  b.bflag = at<int32_t>(ws, y.bbflag);
+  b.sigcnt = at<int32_t>(ws, y.bsigcnt);
+  b.partials = at<int32_t>(ws, y.partials);
+  return b;
+}
+
+Topo cage_topo(const subdiv_mesh *m, long long H, void *ws, const Layout &y) {
+  Topo t{};
+  t.V = m->num_vertices;
+  t.F = m->num_faces;
+  t.H = (int32_t)H;
+  t.order = m->face_offsets ? 0 : m->face_order;
+  t.off = m->face_offsets;
+  t.hface = m->face_offsets ? at<int32_t>(ws, y.hface0) : nullptr;
+  t.fv = m->face_verts;
+  return t;
+}
+
+int check_mesh_args(const subdiv_mesh *m, int scheme, int levels) {
+  if (!m || !m->face_verts || !m->positions) return SUBDIV_INVALID_ARG;
+  if (scheme < 0 || scheme > 2 || levels < 1 || levels > SUBDIV_MAX_LEVELS) return SUBDIV_INVALID_ARG;
+  if (m->num_vertices < 1 || m->num_faces < 1) return SUBDIV_INVALID_ARG;
+  if (!m->face_offsets && m->face_order != 3 && m->face_order != 4) return SUBDIV_INVALID_ARG;
+  if (m->face_offsets && m->num_halfedges < 3) return SUBDIV_INVALID_ARG;
+  if (m->num_creases < 0 || (m->num_creases > 0 && (!m->crease_verts || !m->crease_sharpness)))
+    return SUBDIV_INVALID_ARG;
+  if (m->num_creases > 0 && scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;
+  return SUBDIV_OK;
+}
+
+long long cage_H(const subdiv_mesh *m) {
+  return m->face_offsets ? (long long)m->num_halfedges : (long long)m->num_faces * m->face_order;
+}
+
+// Level-0 build: validation pass (phase A) then the adjacency (phase B).
+hipError_t build_level0_faces(const subdiv_mesh *m, int scheme, const Topo &t, void *ws, const Layout &y,
+                              hipStream_t s) {
+  DeviceInfo *info = at<DeviceInfo>(ws, y.info);
+  hipError_t err;
+  if ((err = launch_fill_i32(reinterpret_cast<int32_t *>(info), 0, sizeof(DeviceInfo) / 4, s)) != hipSuccess)
+    return err;
+  BuildScratch b = scratch0(ws, y);
+  Adj a = adj_at(ws, y.adj0, t.H, m->num_creases > 0);
+  // clear edge-indexed crease state (E <= H)
+  if (a.sig) {
+    if ((err = launch_fill_i32(reinterpret_cast<int32_t *>(a.sig), 0, 2ll * t.H, s)) != hipSuccess) return err;
+    if ((err = launch_fill_i32(b.sigcnt, 0, t.H, s)) != hipSuccess) return err;
+  }
+  return build_faces(t, scheme, b, info, s);
+}
+
+}  // namespace
+
+// ---- the C ABI ---------------------------------------------------------
+extern "C" {
+
+int subdiv_version(void) { return 1000; }
+
+const char *subdiv_last_error(void) { return g_last_error.c_str(); }
+
+const char *subdiv_strerror(int st) {
+  switch (st) {
+    case SUBDIV_OK: return "ok";
+    case SUBDIV_INVALID_ARG: return "invalid argument";
+    case SUBDIV_SCHEME_MESH: return "scheme needs a triangle mesh";
+    case SUBDIV_NONMANIFOLD: return "non-manifold or inconsistently oriented mesh";
+    case SUBDIV_DEGENERATE: return "degenerate face or isolated vertex";
+    case SUBDIV_BAD_CREASE: return "bad crease";
+    case SUBDIV_WORKSPACE: return "workspace too small";
+    case SUBDIV_HIP: return "HIP runtime error";
+    case SUBDIV_STATE: return "plan does not match the call";
+    default: return "unknown status";
+  }
+}
+
+size_t subdiv_workspace_bound(int32_t V, int32_t F, int64_t H, int32_t C, int scheme, int levels, uint32_t flags) {
+  if (V < 1 || F < 1 || H < 3 || levels < 1 || levels > SUBDIV_MAX_LEVELS || scheme < 0 || scheme > 2) return 0;
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  // E0 <= H0 and B0 <= H0 bound every later level from above
+  level_sizes(scheme, levels, V, F, H, H, H, 0, C > 0 ? 1e30f : 0.f, C, L);
+  if (!sizes_fit_int32(L, levels)) return 0;
+  return make_layout(scheme, levels, flags, L, C).total;
+}
+
+int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags, void *ws, size_t ws_bytes,
+                subdiv_plan_info *plan, void *stream) {
+  if (!plan) return SUBDIV_INVALID_ARG;
+  std::memset(plan, 0, sizeof(*plan));
+  int st = check_mesh_args(mesh, scheme, levels);
+  if (st != SUBDIV_OK) return st;
+  if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;  // KEEP_STATE: not in this version
+  if (!ws) return SUBDIV_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long H0 = cage_H(mesh);
+  Sizes L0[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, 0, mesh->num_vertices, mesh->num_faces, H0, H0, H0, 0, 0.f, mesh->num_creases, L0);
+  const Layout y0 = make_layout(scheme, 0, flags, L0, mesh->num_creases);
+  if (ws_bytes < y0.level0_end) return SUBDIV_WORKSPACE;
+  SUBDIV_TRY(init_weight_tables());
+  Topo t = cage_topo(mesh, H0, ws, y0);
+  DeviceInfo *dinfo = at<DeviceInfo>(ws, y0.info);
+  DeviceInfo hinfo{};
+  // phase A: validate faces and indices, valence
+  SUBDIV_TRY(build_level0_faces(mesh, scheme, t, ws, y0, s));
+  SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipStreamSynchronize(s));
+  if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
+  // phase B: adjacency, edge ids, creases
+  BuildScratch b = scratch0(ws, y0);
+  Adj a0 = adj_at(ws, y0.adj0, H0, mesh->num_creases > 0);
+  SUBDIV_TRY(build_adjacency(t, scheme, b, a0, dinfo, s));
+  SUBDIV_TRY(build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+  SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipStreamSynchronize(s));
+  if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
+  float max_sharp;
+  std::memcpy(&max_sharp, &hinfo.max_sharp_bits, 4);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, levels, mesh->num_vertices, mesh->num_faces, H0, hinfo.num_edges, hinfo.num_boundary,
+              t.order, max_sharp, mesh->num_creases, L);
+  if (!sizes_fit_int32(L, levels)) return SUBDIV_INVALID_ARG;
+  const Layout y = make_layout(scheme, levels, flags, L, mesh->num_creases);
+  plan->scheme = scheme;
+  plan->levels = levels;
+  plan->flags = flags;
+  plan->max_valence = hinfo.max_valence;
+  plan->max_sharpness = max_sharp;
+  for (int k = 0; k <= levels; ++k) {
+    subdiv_level_info &li = plan->level[k];
+    li.num_vertices = L[k].V;
+    li.num_edges = L[k].E;
+    li.num_faces = L[k].F;
+    li.num_halfedges = L[k].H;
+    li.num_boundary_edges = L[k].B;
+    li.face_order = L[k].order;
+    long long cmax = 0;
+    if (L[k].creases) {
+      cmax = (long long)mesh->num_creases << (k < 30 ? k : 30);
+      if (cmax > L[k].E) cmax = L[k].E;
+    }
+    li.max_creases = (int32_t)cmax;
+  }
+  plan->workspace_bytes = y.total;
+  plan->priv_mesh_verts = mesh->face_verts;
+  plan->priv_ws = ws;
+  static std::atomic<uint64_t> stamp{1};
+  plan->priv_stamp = stamp++;
+  return SUBDIV_OK;
+}
+
+int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
+                  size_t ws_bytes, void *stream) {
+  if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts) return SUBDIV_STATE;
+  const int scheme = plan->scheme, levels = plan->levels;
+  if (!outs[levels].face_verts || !outs[levels].positions) return SUBDIV_INVALID_ARG;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(scheme, levels, plan->flags, L, mesh->num_creases);
+  const bool rebuild = scheme != SUBDIV_CATMULL_CLARK || (plan->flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL);
+  Topo t = cage_topo(mesh, H0, ws, y);
+  DeviceInfo *dinfo = at<DeviceInfo>(ws, y.info);
+  const bool cr0 = mesh->num_creases > 0;
+  Adj a = adj_at(ws, y.adj0, L[0].E, cr0 && L[0].creases);
+  if (ws != plan->priv_ws) {  // the plan's level-0 adjacency is not in this workspace: build it again
+    SUBDIV_TRY(build_level0_faces(mesh, scheme, t, ws, y, s));
+    BuildScratch b = scratch0(ws, y);
+    Adj full = adj_at(ws, y.adj0, H0, cr0);
+    SUBDIV_TRY(build_adjacency(t, scheme, b, full, dinfo, s));
+    SUBDIV_TRY(build_creases(t, b, full, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+  }
+  if (L[0].B > 0) {
+    BuildScratch b = scratch0(ws, y);
+    SUBDIV_TRY(build_bscan(t, b, a, s));
+  }
+  const float *P = mesh->positions;
+  DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
+  for (int k = 0; k < levels; ++k) {
+    const bool final = (k == levels - 1);
+    int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
+    float *P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
+    if (final) {
+      fv1 = outs[k + 1].face_verts;
+      P1 = outs[k + 1].positions;
+    }
+    if (k >= 1 && rebuild) {
+      // generic mapped M M^T build of level k (the paper's per-level build)
+      BuildScratch b = scratch_rebuild(ws, y);
+      Adj slot = adj_at(ws, y.slot[k & 1], L[k].E, L[k].creases);
+      SUBDIV_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(dinfo2), 0, sizeof(DeviceInfo) / 4, s));
+      SUBDIV_TRY(build_faces(t, scheme, b, dinfo2, s));
+      SUBDIV_TRY(build_adjacency(t, scheme, b, slot, dinfo2, s));
+      if (L[k].B > 0) SUBDIV_TRY(build_bscan(t, b, slot, s));
+      a = slot;
+    }
+    if (outs[k + 1].edge_verts) SUBDIV_TRY(launch_edge_export(t, a, outs[k + 1].edge_verts, s));
+    if (scheme == SUBDIV_CATMULL_CLARK) {
+      CCStep c{};
+      c.t = t;
+      c.a = a;
+      c.P = P;
+      c.fv1 = fv1;
+      c.P1 = P1;
+      c.has_bnd = L[k].B > 0;
+      c.creases = L[k].creases && a.sig != nullptr;
+      c.creases1 = L[k + 1].creases != 0;
+      Adj a1{};
+      if (!final) {
+        a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
+        if (rebuild) {  // only the inherited sharpness is carried over
+          a1.twin = a1.eid = a1.vhe = a1.e2h = a1.bscan = nullptr;
+        }
+        if (!c.creases1) a1.sig = nullptr;
+      } else if (c.creases1 && outs[k + 1].crease_sharpness) {
+        a1.sig = outs[k + 1].crease_sharpness;
+      }
+      a1.vcr = nullptr;
+      c.a1 = a1;
+      if (!c.creases) c.a1.sig = nullptr;
+      SUBDIV_TRY(cc_step(c, s));
+      if (!final && c.a1.sig && outs[k + 1].crease_sharpness)
+        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.a1.sig, 8 * L[k + 1].E, hipMemcpyDeviceToDevice,
+                                  s));
+      a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
+    } else {
+      TriStep c{t, a, P, fv1, P1};
+      SUBDIV_TRY(scheme == SUBDIV_LOOP ? loop_step(c, s) : sqrt3_step(c, s));
+    }
+    // level k+1 becomes the input of the next step
+    t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, L[k + 1].order, nullptr, nullptr, fv1};
+    P = P1;
+  }
+  return SUBDIV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libsubdiv (gfx950). Not part of the public C ABI (include/subdiv.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/subdiv.h"
+
+namespace subdiv {
+
+// ---- fault flags written by the device validators (atomicOr) -------------
+enum : uint32_t {
+  FAULT_INVALID_ARG = 1u,
+  FAULT_SCHEME_MESH = 2u,
+  FAULT_DEGENERATE = 4u,
+  FAULT_NONMANIFOLD = 8u,
+  FAULT_BAD_CREASE = 16u,
+};
+
+// Small block of device-side results the plan reads back.
+struct DeviceInfo {
+  uint32_t faults;
+  int32_t num_edges;          // E of the analysed level (scan total)
+  int32_t num_boundary;       // boundary edges
+  uint32_t max_sharp_bits;    // float bits of the largest crease sharpness (>= 0 so ordered as uint)
+  int32_t max_valence;
+  int32_t pad[11];
+};
+
+// ---- one level's mesh matrix -------------------------------------------
+// Half-edge h is the h-th non-zero of M in CSC order: face f = column, slot j
+// = cyclic position, the half-edge runs from fv[h] to fv[next(h)].
+struct Topo {
+  int32_t V;
+  int32_t F;
+  int32_t H;
+  int32_t order;             // 3 or 4 uniform, 0 = general (off/hface used)
+  const int32_t *off;        // [F+1] column pointer (general only)
+  const int32_t *hface;      // [H] column of each non-zero (general only)
+  const int32_t *fv;         // [H] row indices
+};
+
+template <int ORDER>
+__device__ __forceinline__ int he_face(const Topo &t, int h) {
+  if constexpr (ORDER > 0) return h / ORDER;
+  else return t.hface[h];
+}
+template <int ORDER>
+__device__ __forceinline__ int he_next(const Topo &t, int h) {
+  if constexpr (ORDER > 0) return (h % ORDER == ORDER - 1) ? h - (ORDER - 1) : h + 1;
+  else {
+    const int f = t.hface[h];
+    return h + 1 == t.off[f + 1] ? t.off[f] : h + 1;
+  }
+}
+template <int ORDER>
+__device__ __forceinline__ int he_prev(const Topo &t, int h) {
+  if constexpr (ORDER > 0) return (h % ORDER == 0) ? h + (ORDER - 1) : h - 1;
+  else {
+    const int f = t.hface[h];
+    return h == t.off[f] ? t.off[f + 1] - 1 : h - 1;
+  }
+}
+template <int ORDER>
+__device__ __forceinline__ int face_begin(const Topo &t, int f) {
+  if constexpr (ORDER > 0) return f * ORDER;
+  else return t.off[f];
+}
+template <int ORDER>
+__device__ __forceinline__ int face_end(const Topo &t, int f) {
+  if constexpr (ORDER > 0) return (f + 1) * ORDER;
+  else return t.off[f + 1];
+}
+
+// ---- adjacency of one level (the build step's products) ---------------
+//   twin[h]  : half-edge opposite to h (F(j,i) of eq:F as a half-edge), -1 on the boundary
+//   eid[h]   : id of h's edge (upper triangle of E, ascending (hi, lo))
+//   vhe[v]   : one half-edge leaving v; the boundary one if v is on the boundary
+//   e2h[e]   : one half-edge of edge e (the lower index of its two)
+//   bscan[e] : boundary edges with id < e (only when the level has a boundary)
+//   sig[e]   : crease sharpness of edge e (only on levels that may have creases)
+//   vcr[v]   : crease valency k and the ids of the first two incident creases
+struct Adj {
+  int32_t *twin;
+  int32_t *eid;
+  int32_t *vhe;
+  int32_t *e2h;
+  int32_t *bscan;
+  double *sig;
+  int4 *vcr;
+  int32_t E;
+};
+
+// ---- small vector helpers ---------------------------------------------
+struct f3 {
+  float x, y, z;
+};
+__device__ __forceinline__ f3 ld3(const float *P, int i) { return *reinterpret_cast<const f3 *>(P + 3ll * i); }
+__device__ __forceinline__ void st3(float *P, int i, f3 v) { *reinterpret_cast<f3 *>(P + 3ll * i) = v; }
+__device__ __forceinline__ f3 add3(f3 a, f3 b) { return f3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 mul3(float s, f3 a) { return f3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ f3 fma3(float s, f3 a, f3 b) { return f3{s * a.x + b.x, s * a.y + b.y, s * a.z + b.z}; }
+
+constexpr int kBlock = 256;
+inline unsigned grid_for(long long n, int block = kBlock) {
+  long long g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- launchers (each returns hipGetLastError() of its launches) --------
+hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s);
+// exclusive scan of n ints into out[0..n] (out[n] = total); partials needs scan_partials_ints(n) ints;
+// when total_dst != nullptr the total is also stored there.
+long long scan_partials_ints(long long n);
+hipError_t launch_scan(const int32_t *in, int32_t *out, long long n, int32_t *partials, int32_t *total_dst,
+                       hipStream_t s);
+
+// Generic build (the symbolic pass + mapped M M^T of Sec. 4.2) on any level.
+struct BuildScratch {
+  int32_t *nval;     // [V+1]
+  int32_t *rowptr;   // [V+1]
+  int32_t *cursor;   // [V]
+  int32_t *inc;      // [H]  half-edges leaving each vertex (row view of M)
+  int32_t *cand;     // [2H] per-vertex candidate neighbour lists
+  int32_t *cntlo;    // [V+1]
+  int32_t *ebase;    // [V+1]
+  int32_t *bflag;    // [H+1] boundary flag per edge id (E <= H)
+  int32_t *sigcnt;   // [H]  crease tags per edge id
+  int32_t *partials; // scan partials
+};
+// phase A: validation of faces / indices, valence counts, column of every
+// non-zero (written to t.hface for a general cage)
+hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s);
+// phase B: row view of M, twins, edge ids, edge -> half-edge map, boundary flags
+hipError_t build_adjacency(const Topo &t, int scheme, const BuildScratch &b, Adj &a, DeviceInfo *info,
+                           hipStream_t s);
+hipError_t build_creases(const Topo &t, const BuildScratch &b, const Adj &a, int num_creases,
+                         const int32_t *crease_verts, const float *crease_sharp, DeviceInfo *info, hipStream_t s);
+// boundary prefix of a built level (needs the DeviceInfo's E on device: passed as E)
+hipError_t build_bscan(const Topo &t, const BuildScratch &b, Adj &a, hipStream_t s);
+hipError_t launch_edge_export(const Topo &t, const Adj &a, int32_t *edge_out, hipStream_t s);
+
+// Catmull-Clark level step.
+struct CCStep {
+  Topo t;
+  Adj a;            // adjacency of level k (input)
+  const float *P;   // [V*3]
+  int32_t *fv1;     // [4H] refined M
+  float *P1;        // [(V+F+E)*3]
+  Adj a1;           // adjacency of level k+1 (output; twin == nullptr => final level, not emitted)
+  bool has_bnd;     // level k has boundary edges (bscan valid)
+  bool creases;     // level k may have creases (a.sig, a.vcr valid)
+  bool creases1;    // level k+1 may have creases (a1.sig to be written)
+};
+hipError_t cc_step(const CCStep &c, hipStream_t s);
+
+// Loop / sqrt(3) level steps (adjacency from a build of the same level).
+struct TriStep {
+  Topo t;
+  Adj a;
+  const float *P;
+  int32_t *fv1;
+  float *P1;
+};
+hipError_t loop_step(const TriStep &c, hipStream_t s);
+hipError_t sqrt3_step(const TriStep &c, hipStream_t s);
+hipError_t init_weight_tables();
+
+}  // namespace subdiv

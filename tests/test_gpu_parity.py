@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Topology (face tables, edge enumeration, crease sharpness) must be bit-exact;
+positions within 1e-5 normwise relative error at every level.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_06047_amd import _lib, api
+from paper_1809_06047_amd import meshgen as G
+from tests.parity_util import POS_TOL, crease_table, level_edges, normwise_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(mesh, scheme, levels, flags=0):
+    outs, r = api.refine(mesh, scheme, levels, flags=flags, keep="all", edges=True, creases=True)
+    return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs], r
+
+
+def _compare(mesh, scheme, levels, oracle_mod, flags=0, label=""):
+    print(f"[parity] {label} {mesh.name} scheme={scheme} levels={levels} flags={flags}", flush=True)
+    ref = oracle_mod.refine(mesh, scheme, levels)
+    got, r = _gpu(mesh, scheme, levels, flags)
+    order = 4 if scheme == "cc" else 3
+    errs = []
+    for k in range(1, levels + 1):
+        g, o = got[k], ref[k]
+        info = r.level_info(k)
+        assert (info["V"], info["F"], info["H"]) == (o.num_vertices, o.num_faces, o.verts.size), k
+        np.testing.assert_array_equal(g["face_verts"], o.verts, err_msg=f"{label} topology level {k}")
+        np.testing.assert_array_equal(g["edge_verts"], ref[k - 1].edges, err_msg=f"{label} edges of level {k-1}")
+        e = normwise_err(g["positions"], o.positions)
+        errs.append(e)
+        assert e <= POS_TOL, f"{label} level {k}: positions err {e:.3e}"
+        if "crease_sharpness" in g:
+            sig = crease_table(o, level_edges(o.verts, order))
+            np.testing.assert_array_equal(g["crease_sharpness"], sig, err_msg=f"{label} creases level {k}")
+    print(f"[parity] {label} errors per level: " + " ".join(f"{x:.2e}" for x in errs), flush=True)
+    return got
+
+
+def test_cc_torus_levels_1_to_4(oracle_mod):
+    _compare(G.torus_cage(), "cc", 4, oracle_mod, label="torus")
+
+
+def test_cc_mixed_cage_with_creases(oracle_mod):
+    m = G.cc_cage(seed=11, level=3)
+    assert m.num_creases > 0
+    _compare(m, "cc", 4, oracle_mod, label="mixed+creases")
+
+
+def test_cc_rebuild_each_level_matches_carried_adjacency(oracle_mod):
+    """The paper's per-level mapped M M^T build and the closed-form carry-over
+    give identical ids, hence bitwise-identical outputs."""
+    m = G.cc_cage(seed=12, level=2)
+    a, _ = _gpu(m, "cc", 3)
+    b, _ = _gpu(m, "cc", 3, flags=_lib.FLAG_REBUILD_EACH_LEVEL)
+    for k in range(1, 4):
+        for key in a[k]:
+            np.testing.assert_array_equal(a[k][key], b[k][key], err_msg=f"level {k} {key}")
+
+
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
+def test_triangle_schemes_with_holes(oracle_mod, scheme):
+    m = G.tri_cage(seed=13, level=3, hole_frac=0.02)
+    _compare(m, scheme, 3, oracle_mod, label="holes")
+
+
+@pytest.mark.parametrize("scheme", ["cc", "loop", "sqrt3"])
+def test_open_grid_patches(oracle_mod, scheme):
+    rng = np.random.default_rng(4)
+    m = G.grid_patch(7, 5, tri=(scheme != "cc"), z_fn=lambda x, y: rng.normal(0, 0.2, x.shape))
+    _compare(m, scheme, 3, oracle_mod, label="grid")
+    if scheme == "cc":
+        t = G.grid_patch(6, 4, tri=True, z_fn=lambda x, y: rng.normal(0, 0.2, x.shape))
+        _compare(t, "cc", 3, oracle_mod, label="tri-grid-cc")
+
+
+def _prism(n, h=1.0):
+    """Closed n-gon prism: two n-gons and n quads (general polygon cage)."""
+    a = 2 * np.pi * np.arange(n) / n
+    P = np.concatenate([np.stack([np.cos(a), np.sin(a), np.zeros(n)], 1),
+                        np.stack([np.cos(a), np.sin(a), np.full(n, h)], 1)]).astype(np.float32)
+    faces = [list(range(n - 1, -1, -1)), list(range(n, 2 * n))]
+    for i in range(n):
+        j = (i + 1) % n
+        faces.append([i, j, n + j, n + i])
+    off = np.cumsum([0] + [len(f) for f in faces]).astype(np.int32)
+    return G.Mesh(positions=P, verts=np.array(sum(faces, []), np.int32), offsets=off, name=f"prism{n}")
+
+
+@pytest.mark.parametrize("n", [3, 5, 6, 9])
+def test_general_polygon_cages(oracle_mod, n):
+    _compare(_prism(n), "cc", 3, oracle_mod, label=f"prism{n}")
+
+
+def test_single_faces(oracle_mod):
+    quad = G.Mesh(positions=np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0.5], [0, 1, 0]], np.float32),
+                  verts=np.arange(4, dtype=np.int32), face_order=4, name="quad")
+    tri = G.Mesh(positions=np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0.5]], np.float32),
+                 verts=np.arange(3, dtype=np.int32), face_order=3, name="tri")
+    _compare(quad, "cc", 3, oracle_mod, label="one-quad")
+    for s in ("cc", "loop", "sqrt3"):
+        _compare(tri, s, 3, oracle_mod, label="one-tri")
+
+
+def test_deterministic_repeat():
+    m = G.cc_cage(seed=14, level=3)
+    a, _ = _gpu(m, "cc", 4)
+    b, _ = _gpu(m, "cc", 4)
+    for k in range(1, 5):
+        for key in a[k]:
+            np.testing.assert_array_equal(a[k][key], b[k][key])
+
+
+def _tri(P, F):
+    return G.Mesh(positions=np.asarray(P, np.float32), verts=np.array(F, np.int32).reshape(-1), face_order=3)
+
+
+def test_status_codes_match_oracle(oracle_mod):
+    P = np.zeros((6, 3))
+    c = G.cube()
+    e = G.mesh_edges(None, c.verts, 4)[:1].astype(np.int32)
+    cases = [
+        (G.cube(), "loop"),
+        (_tri(P, [[0, 1, 1]]), "cc"),
+        (G.Mesh(positions=np.zeros((4, 3), np.float32), verts=np.array([0, 1, 2, 3, 2], np.int32),
+                offsets=np.array([0, 2, 5], np.int32)), "cc"),
+        (_tri(P, [[0, 1, 7]]), "cc"),
+        (_tri(P, [[0, 1, 2]]), "cc"),
+        (_tri(P[:5], [[0, 1, 2], [1, 0, 3], [0, 1, 4]]), "cc"),
+        (_tri(P[:4], [[0, 1, 2], [0, 1, 3]]), "cc"),
+        (_tri(P[:5], [[0, 1, 2], [0, 3, 4]]), "cc"),
+        (G.Mesh(positions=c.positions, verts=c.verts, face_order=4, crease_verts=np.array([[0, 7]], np.int32),
+                crease_sharp=np.array([1.0], np.float32)), "cc"),
+        (G.Mesh(positions=c.positions, verts=c.verts, face_order=4, crease_verts=e,
+                crease_sharp=np.array([-1.0], np.float32)), "cc"),
+        (G.Mesh(positions=c.positions, verts=c.verts, face_order=4, crease_verts=np.concatenate([e, e[:, ::-1]]),
+                crease_sharp=np.array([1.0, 2.0], np.float32)), "cc"),
+        (G.cube(), "cc"),
+    ]
+    for i, (m, s) in enumerate(cases):
+        want = oracle_mod.status_of(m, s)
+        got = api.plan_status(m, s)
+        assert got == want, f"case {i}: gpu {got} oracle {want}"
+        if i < len(cases) - 1:
+            assert got != 0
