@@ -207,7 +207,11 @@ __global__ void __launch_bounds__(kBlock) k_cc_edge(CCStep c) {
       const int s = he_face<ORDER>(c.t, t);
       c.a1.e2h[base + (r < s ? 2 : 3)] = 4 * h + 1;
       c.a1.e2h[base + (r < s ? 3 : 2)] = 4 * t + 1;
-      c.a1.vhe[V + F + e] = 4 * h + 1;
+      // an interior vertex starts its ring at its lowest outgoing half-edge,
+      // as the generic build does, so both builds sum rings in one order
+      const int tn = he_next<ORDER>(c.t, t);
+      const int m0 = min(4 * h + 1, 4 * hn + 3), m1 = min(4 * t + 1, 4 * tn + 3);
+      c.a1.vhe[V + F + e] = min(m0, m1);
     }
     if (c.has_bnd) {
       const int b2 = 2 * c.a.bscan[e];
