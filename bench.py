@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark: Catmull-Clark refined faces/s at level 6 on the 10k-vertex
+mixed triangle/quad cage (icosphere level 5, 30% of adjacent triangle pairs
+merged into quads, 3% of edges creased with sharpness U[0,4), jitter
+N(0, 0.01)), one MI355X.
+
+One step = subdiv_plan (cage validation + adjacency, the symbolic pass, with
+its host read-back) + subdiv_refine levels 0 -> 6 (build and eval at every
+level, dynamic topology: nothing is precomputed across steps). The cage is
+resident in HBM before the timed region; outputs are written to preallocated
+device buffers.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel (timed live with HIP events on the library's stream) and the FP64
+oracle timed on one host core over a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CC refined faces/s at level 6 (10k cage); batched p99 ms vs per-mesh launch"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic (compulsory) bytes per processed element of each Catmull-Clark
+# kernel at a level whose next-level adjacency is not emitted (the last one),
+# 3 x fp32 positions and int32 indices:
+#   cc_face   per parent face : read M_k row 16 + write 4 children 64 + write face point 12 = 92 B
+#   cc_vertex per vertex      : read p 12 + write vertex point 12                        = 24 B
+#   cc_edge   per edge        : write edge point 12                                      = 12 B
+# Summed per quad (V ~ F, E ~ 2F): 92 + 24 + 24 = 140 B per parent face = 35 B per refined face.
+BYTES_PER_UNIT = {"cc_face": ("F", 92), "cc_vertex": ("V", 24), "cc_edge": ("E", 12)}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--cpu-levels", type=int, default=5, help="levels of the oracle sample (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy kernel of known size: under rocprofv3 --pmc its FETCH_SIZE /
+    WRITE_SIZE per dispatch give the factor between counter units and bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "dispatches": 5}))
+
+
+def cpu_baseline(mesh, levels):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    lv = oracle.refine(mesh, "cc", levels)
+    dt = time.perf_counter() - t0
+    faces = lv[-1].num_faces
+    return {"value": faces / dt, "unit": "refined faces/s", "cores": 1, "kind": "oracle",
+            "sample": f"same cage refined to level {levels} ({faces} faces) by the serial FP64 oracle, "
+                      f"{dt:.1f} s on one host core"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the refinement of one cage "
+              "is a single-GPU workload; see the design notes for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    import torch
+    from paper_1809_06047_amd import _lib, api
+    from paper_1809_06047_amd import meshgen as G
+
+    mesh = G.cc_cage(seed=args.seed)
+    r = api.Refiner(mesh, "cc", args.levels)
+    r.plan()
+    torch.cuda.synchronize()
+    L = args.levels
+    info = [r.level_info(k) for k in range(L + 1)]
+    faces_out = info[L]["F"]
+
+    for _ in range(args.warmup):
+        r.plan()
+        r.run()
+    torch.cuda.synchronize()
+
+    _lib.timing_enable(True)
+    _lib.timing_read()  # drop anything recorded before the timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.plan()
+        r.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = _lib.timing_read()
+    _lib.timing_enable(False)
+
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = faces_out / (ms_per_step / 1000.0)
+
+    # dominant kernel: largest total device time among the level kernels
+    cand = {k: v for k, v in stages.items() if k[0] in BYTES_PER_UNIT}
+    (dname, dlevel), (launches, total_ms) = max(cand.items(), key=lambda kv: kv[1][1])
+    unit_key, per_unit = BYTES_PER_UNIT[dname]
+    units = info[dlevel][unit_key]
+    avg_ms = total_ms / launches
+    achieved = per_unit * units / (avg_ms / 1000.0) / 1e9
+    device_ms = sum(v[1] for v in stages.values()) / args.steps
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "refined faces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Catmull-Clark levels 0->{L} of a mixed tri/quad cage: icosphere level 5 "
+                        f"(V={info[0]['V']}, F={info[0]['F']}, H={info[0]['H']}), 30% of triangle pairs merged, "
+                        f"{mesh.num_creases} creases sharpness U[0,4), seed {args.seed}",
+            "faces_out": faces_out,
+            "vertices_out": info[L]["V"],
+            "step": "subdiv_plan + subdiv_refine (dynamic topology)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dname} (level {dlevel} -> {dlevel + 1})",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_ms": round(avg_ms, 5),
+            "algorithmic_bytes_per_launch": per_unit * units,
+        },
+        "device_ms_per_step": round(device_ms, 4),
+        "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(stages.items())},
+    }
+    if args.cpu_levels > 0:
+        out["cpu_baseline"] = cpu_baseline(mesh, args.cpu_levels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

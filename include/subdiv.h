@@ -156,6 +156,26 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* ---- optional stage timing ---------------------------------------------
+ * When enabled (process-wide switch, default off), subdiv_plan and
+ * subdiv_refine record a HIP event pair on their stream around every kernel
+ * (or kernel group) they launch. subdiv_timing_read waits for the recorded
+ * events, writes up to max_out entries aggregated by (stage, level) and
+ * clears the records; it returns the number of entries written, or a
+ * negative status. Stage names: "build" (cage adjacency), "rebuild" (per-level
+ * generic build), "bscan", "cc_face", "cc_vertex", "cc_edge", "loop_edge",
+ * "loop_vertex", "loop_face", "sqrt3_face", "sqrt3_vertex", "edge_export";
+ * level = the level the kernel reads. */
+typedef struct subdiv_stage_time {
+  char name[24];
+  int32_t level;
+  int32_t launches;
+  double total_ms;
+} subdiv_stage_time;
+
+void subdiv_timing_enable(int on);
+int subdiv_timing_read(subdiv_stage_time *out, int max_out);
+
 /* HIP error text of the last SUBDIV_HIP status on this thread ("" if none). */
 const char *subdiv_last_error(void);
 

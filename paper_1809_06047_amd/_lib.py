@@ -47,6 +47,10 @@ class subdiv_level_out(ctypes.Structure):
     _fields_ = [("face_verts", c_vp), ("positions", c_vp), ("edge_verts", c_vp), ("crease_sharpness", c_vp)]
 
 
+class subdiv_stage_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("level", c_i32), ("launches", c_i32), ("total_ms", ctypes.c_double)]
+
+
 # every function the header declares, with its signature
 SIGNATURES = {
     "subdiv_workspace_bound": (c_sz, [c_i32, c_i32, c_i64, c_i32, ctypes.c_int, ctypes.c_int, c_u32]),
@@ -54,6 +58,8 @@ SIGNATURES = {
                                    ctypes.POINTER(subdiv_plan_info), c_vp]),
     "subdiv_refine": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                      ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_timing_enable": (None, [ctypes.c_int]),
+    "subdiv_timing_read": (ctypes.c_int, [ctypes.POINTER(subdiv_stage_time), ctypes.c_int]),
     "subdiv_last_error": (ctypes.c_char_p, []),
     "subdiv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "subdiv_version": (ctypes.c_int, []),
@@ -86,6 +92,19 @@ class SubdivError(RuntimeError):
             msg += ": " + lib.subdiv_last_error().decode()
         super().__init__(f"{where}: status {status} ({msg})")
         self.status = status
+
+
+def timing_enable(on: bool = True):
+    load().subdiv_timing_enable(1 if on else 0)
+
+
+def timing_read(max_out: int = 512):
+    """{(stage, level): (launches, total_ms)} recorded since the last read."""
+    buf = (subdiv_stage_time * max_out)()
+    n = load().subdiv_timing_read(buf, max_out)
+    if n < 0:
+        raise SubdivError(n, "subdiv_timing_read")
+    return {(buf[i].name.decode(), buf[i].level): (buf[i].launches, buf[i].total_ms) for i in range(n)}
 
 
 def check(status: int, where: str):

@@ -234,21 +234,20 @@ __global__ void __launch_bounds__(kBlock) k_cc_edge(CCStep c) {
   }
 }
 
-hipError_t cc_step(const CCStep &c, hipStream_t s) {
-  const unsigned gf = grid_for(c.t.F), gv = grid_for(c.t.V), ge = grid_for(c.a.E);
-  if (c.t.order == 4) {
-    hipLaunchKernelGGL(k_cc_face<4>, dim3(gf), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_vertex<4>, dim3(gv), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_edge<4>, dim3(ge), dim3(kBlock), 0, s, c);
-  } else if (c.t.order == 3) {
-    hipLaunchKernelGGL(k_cc_face<3>, dim3(gf), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_vertex<3>, dim3(gv), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_edge<3>, dim3(ge), dim3(kBlock), 0, s, c);
-  } else {
-    hipLaunchKernelGGL(k_cc_face<0>, dim3(gf), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_vertex<0>, dim3(gv), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cc_edge<0>, dim3(ge), dim3(kBlock), 0, s, c);
-  }
+template <int ORDER>
+static void cc_launch_t(int which, const CCStep &c, hipStream_t s) {
+  if (which == CC_FACE)
+    hipLaunchKernelGGL(k_cc_face<ORDER>, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+  else if (which == CC_VERTEX)
+    hipLaunchKernelGGL(k_cc_vertex<ORDER>, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_cc_edge<ORDER>, dim3(grid_for(c.a.E)), dim3(kBlock), 0, s, c);
+}
+
+hipError_t cc_launch(int which, const CCStep &c, hipStream_t s) {
+  if (c.t.order == 4) cc_launch_t<4>(which, c, s);
+  else if (c.t.order == 3) cc_launch_t<3>(which, c, s);
+  else cc_launch_t<0>(which, c, s);
   return hipGetLastError();
 }
 

@@ -3,7 +3,9 @@
 // per-level build/eval loop of the dynamic-topology mode (Sec. 3.6).
 #include <atomic>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "subdiv_internal.h"
 
@@ -22,6 +24,61 @@ int hip_fail(hipError_t e) {
   do {                                           \
     hipError_t _e = (expr);                      \
     if (_e != hipSuccess) return hip_fail(_e);   \
+  } while (0)
+
+// ---- optional stage timing (HIP events on the call's stream) ------------
+struct TimingRec {
+  const char *name;
+  int level;
+  hipEvent_t a, b;
+};
+std::mutex g_tmu;
+std::atomic<bool> g_timing{false};
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t timing_begin(hipStream_t s) {
+  if (!g_timing.load(std::memory_order_relaxed)) return nullptr;
+  std::lock_guard<std::mutex> lock(g_tmu);
+  hipEvent_t e = nullptr;
+  if (!g_pool.empty()) {
+    e = g_pool.back();
+    g_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) {
+    g_pool.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void timing_end(hipEvent_t a, const char *name, int level, hipStream_t s) {
+  if (!a) return;
+  std::lock_guard<std::mutex> lock(g_tmu);
+  hipEvent_t b = nullptr;
+  if (!g_pool.empty()) {
+    b = g_pool.back();
+    g_pool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    g_pool.push_back(a);
+    return;
+  }
+  if (hipEventRecord(b, s) != hipSuccess) {
+    g_pool.push_back(a);
+    g_pool.push_back(b);
+    return;
+  }
+  g_recs.push_back(TimingRec{name, level, a, b});
+}
+
+#define SUBDIV_TIMED(name, level, expr)          \
+  do {                                           \
+    hipEvent_t _ta = timing_begin(s);            \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hip_fail(_e);   \
+    timing_end(_ta, name, level, s);             \
   } while (0)
 
 int status_from_faults(uint32_t f) {
@@ -271,6 +328,38 @@ extern "C" {
 
 int subdiv_version(void) { return 1000; }
 
+void subdiv_timing_enable(int on) { g_timing.store(on != 0); }
+
+int subdiv_timing_read(subdiv_stage_time *out, int max_out) {
+  if (!out || max_out < 0) return SUBDIV_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tmu);
+  int n = 0;
+  hipError_t first = hipSuccess;
+  for (const TimingRec &r : g_recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && first == hipSuccess) first = e;
+    int i = 0;
+    for (; i < n; ++i)
+      if (out[i].level == r.level && std::strncmp(out[i].name, r.name, sizeof(out[i].name)) == 0) break;
+    if (i == n) {
+      if (n == max_out) continue;
+      std::memset(&out[n], 0, sizeof(out[n]));
+      std::strncpy(out[n].name, r.name, sizeof(out[n].name) - 1);
+      out[n].level = r.level;
+      ++n;
+    }
+    out[i].launches += 1;
+    out[i].total_ms += ms;
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  if (first != hipSuccess) return hip_fail(first);
+  return n;
+}
+
 const char *subdiv_last_error(void) { return g_last_error.c_str(); }
 
 const char *subdiv_strerror(int st) {
@@ -316,15 +405,16 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   DeviceInfo *dinfo = at<DeviceInfo>(ws, y0.info);
   DeviceInfo hinfo{};
   // phase A: validate faces and indices, valence
-  SUBDIV_TRY(build_level0_faces(mesh, scheme, t, ws, y0, s));
+  SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y0, s));
   SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
   if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
   // phase B: adjacency, edge ids, creases
   BuildScratch b = scratch0(ws, y0);
   Adj a0 = adj_at(ws, y0.adj0, H0, mesh->num_creases > 0);
-  SUBDIV_TRY(build_adjacency(t, scheme, b, a0, dinfo, s));
-  SUBDIV_TRY(build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+  SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, a0, dinfo, s));
+  SUBDIV_TIMED("build", 0,
+               build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
   SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
   if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
@@ -385,15 +475,16 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   const bool cr0 = mesh->num_creases > 0;
   Adj a = adj_at(ws, y.adj0, L[0].E, cr0 && L[0].creases);
   if (ws != plan->priv_ws) {  // the plan's level-0 adjacency is not in this workspace: build it again
-    SUBDIV_TRY(build_level0_faces(mesh, scheme, t, ws, y, s));
+    SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y, s));
     BuildScratch b = scratch0(ws, y);
     Adj full = adj_at(ws, y.adj0, H0, cr0);
-    SUBDIV_TRY(build_adjacency(t, scheme, b, full, dinfo, s));
-    SUBDIV_TRY(build_creases(t, b, full, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+    SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, full, dinfo, s));
+    SUBDIV_TIMED("build", 0,
+                 build_creases(t, b, full, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
   }
   if (L[0].B > 0) {
     BuildScratch b = scratch0(ws, y);
-    SUBDIV_TRY(build_bscan(t, b, a, s));
+    SUBDIV_TIMED("bscan", 0, build_bscan(t, b, a, s));
   }
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
@@ -410,12 +501,12 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       BuildScratch b = scratch_rebuild(ws, y);
       Adj slot = adj_at(ws, y.slot[k & 1], L[k].E, L[k].creases);
       SUBDIV_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(dinfo2), 0, sizeof(DeviceInfo) / 4, s));
-      SUBDIV_TRY(build_faces(t, scheme, b, dinfo2, s));
-      SUBDIV_TRY(build_adjacency(t, scheme, b, slot, dinfo2, s));
-      if (L[k].B > 0) SUBDIV_TRY(build_bscan(t, b, slot, s));
+      SUBDIV_TIMED("rebuild", k, build_faces(t, scheme, b, dinfo2, s));
+      SUBDIV_TIMED("rebuild", k, build_adjacency(t, scheme, b, slot, dinfo2, s));
+      if (L[k].B > 0) SUBDIV_TIMED("bscan", k, build_bscan(t, b, slot, s));
       a = slot;
     }
-    if (outs[k + 1].edge_verts) SUBDIV_TRY(launch_edge_export(t, a, outs[k + 1].edge_verts, s));
+    if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, a, outs[k + 1].edge_verts, s));
     if (scheme == SUBDIV_CATMULL_CLARK) {
       CCStep c{};
       c.t = t;
@@ -439,14 +530,23 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       a1.vcr = nullptr;
       c.a1 = a1;
       if (!c.creases) c.a1.sig = nullptr;
-      SUBDIV_TRY(cc_step(c, s));
+      SUBDIV_TIMED("cc_face", k, cc_launch(CC_FACE, c, s));
+      SUBDIV_TIMED("cc_vertex", k, cc_launch(CC_VERTEX, c, s));
+      SUBDIV_TIMED("cc_edge", k, cc_launch(CC_EDGE, c, s));
       if (!final && c.a1.sig && outs[k + 1].crease_sharpness)
         SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.a1.sig, 8 * L[k + 1].E, hipMemcpyDeviceToDevice,
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else {
       TriStep c{t, a, P, fv1, P1};
-      SUBDIV_TRY(scheme == SUBDIV_LOOP ? loop_step(c, s) : sqrt3_step(c, s));
+      if (scheme == SUBDIV_LOOP) {
+        SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
+        SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
+        SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
+      } else {
+        SUBDIV_TIMED("sqrt3_face", k, tri_launch(SQRT3_FACE, c, s));
+        SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, c, s));
+      }
     }
     // level k+1 becomes the input of the next step
     t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, L[k + 1].order, nullptr, nullptr, fv1};

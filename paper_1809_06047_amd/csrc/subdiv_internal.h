@@ -102,6 +102,19 @@ __device__ __forceinline__ f3 mul3(float s, f3 a) { return f3{s * a.x, s * a.y, 
 __device__ __forceinline__ f3 fma3(float s, f3 a, f3 b) { return f3{s * a.x + b.x, s * a.y + b.y, s * a.z + b.z}; }
 
 constexpr int kBlock = 256;
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD
+// b % 8), each with its own L2. Remap so that XCD x processes one contiguous
+// 1/8 of the index range: neighbouring faces / vertices / edges (which the
+// hierarchical index order of refined levels keeps spatially close) then
+// share one L2. A bijection on [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+__device__ __forceinline__ int xcd_index() { return xcd_block() * blockDim.x + threadIdx.x; }
 inline unsigned grid_for(long long n, int block = kBlock) {
   long long g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -153,7 +166,9 @@ struct CCStep {
   bool creases;     // level k may have creases (a.sig, a.vcr valid)
   bool creases1;    // level k+1 may have creases (a1.sig to be written)
 };
-hipError_t cc_step(const CCStep &c, hipStream_t s);
+enum { CC_FACE = 0, CC_VERTEX = 1, CC_EDGE = 2 };
+// one of the three kernels of a Catmull-Clark level (launch in this order)
+hipError_t cc_launch(int which, const CCStep &c, hipStream_t s);
 
 // Loop / sqrt(3) level steps (adjacency from a build of the same level).
 struct TriStep {
@@ -163,8 +178,8 @@ struct TriStep {
   int32_t *fv1;
   float *P1;
 };
-hipError_t loop_step(const TriStep &c, hipStream_t s);
-hipError_t sqrt3_step(const TriStep &c, hipStream_t s);
+enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4 };
+hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
 hipError_t init_weight_tables();
 
 }  // namespace subdiv

@@ -118,13 +118,6 @@ __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
   o[2] = make_int4(e1, e0, e1, e2);
 }
 
-hipError_t loop_step(const TriStep &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_loop_edge, dim3(grid_for(c.a.E)), dim3(kBlock), 0, s, c);
-  hipLaunchKernelGGL(k_loop_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
-  hipLaunchKernelGGL(k_loop_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ sqrt(3)
 __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,9 +156,24 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
   st3(c.P1, v, S);
 }
 
-hipError_t sqrt3_step(const TriStep &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_sqrt3_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
-  hipLaunchKernelGGL(k_sqrt3_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+hipError_t tri_launch(int which, const TriStep &c, hipStream_t s) {
+  switch (which) {
+    case LOOP_EDGE:
+      hipLaunchKernelGGL(k_loop_edge, dim3(grid_for(c.a.E)), dim3(kBlock), 0, s, c);
+      break;
+    case LOOP_VERTEX:
+      hipLaunchKernelGGL(k_loop_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+      break;
+    case LOOP_FACE:
+      hipLaunchKernelGGL(k_loop_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      break;
+    case SQRT3_FACE:
+      hipLaunchKernelGGL(k_sqrt3_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      break;
+    default:
+      hipLaunchKernelGGL(k_sqrt3_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+      break;
+  }
   return hipGetLastError();
 }
 
