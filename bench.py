@@ -26,14 +26,18 @@ sys.path.insert(0, ROOT)
 METRIC = "CC refined faces/s at level 6 (10k cage); batched p99 ms vs per-mesh launch"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic (compulsory) bytes per processed element of each Catmull-Clark
-# kernel at a level whose next-level adjacency is not emitted (the last one),
-# 3 x fp32 positions and int32 indices:
-#   cc_face   per parent face : read M_k row 16 + write 4 children 64 + write face point 12 = 92 B
-#   cc_vertex per vertex      : read p 12 + write vertex point 12                        = 24 B
-#   cc_edge   per edge        : write edge point 12                                      = 12 B
-# Summed per quad (V ~ F, E ~ 2F): 92 + 24 + 24 = 140 B per parent face = 35 B per refined face.
-BYTES_PER_UNIT = {"cc_face": ("F", 92), "cc_vertex": ("V", 24), "cc_edge": ("E", 12)}
+# Algorithmic (compulsory) bytes of the kernels of the last Catmull-Clark step
+# (level k -> k+1, refined from the parent level m = k-1, no adjacency
+# emitted), 3 x fp32 positions and int32 indices. The step's compulsory
+# traffic -- read M_k and P_k once, write M_{k+1} and P_{k+1} once -- is split
+# over the kernel that owns each part:
+#   cc_group      per parent face   : read M_k rows 4x16 + write M_{k+1} 16x16 + write 4 face points 48
+#                                     + read and write the face-point vertex 12 + 12         = 392 B
+#   cc_old_vertex per parent vertex : read p 12 + write its vertex point 12                  = 24 B
+#   cc_edge_group per parent edge   : write 4 edge points 48 + read and write the edge-point
+#                                     vertex 12 + 12                                         = 72 B
+# Per parent quad (V ~ F, E ~ 2F): 392 + 24 + 144 = 560 B = 35 B per refined face.
+BYTES_PER_UNIT = {"cc_group": ("F", 392), "cc_old_vertex": ("V", 24), "cc_edge_group": ("E", 72)}
 
 
 def parse():
@@ -119,7 +123,7 @@ def main():
     cand = {k: v for k, v in stages.items() if k[0] in BYTES_PER_UNIT}
     (dname, dlevel), (launches, total_ms) = max(cand.items(), key=lambda kv: kv[1][1])
     unit_key, per_unit = BYTES_PER_UNIT[dname]
-    units = info[dlevel][unit_key]
+    units = info[dlevel - 1][unit_key]  # one thread per element of the parent level
     avg_ms = total_ms / launches
     achieved = per_unit * units / (avg_ms / 1000.0) / 1e9
     device_ms = sum(v[1] for v in stages.values()) / args.steps

@@ -163,9 +163,11 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
  * events, writes up to max_out entries aggregated by (stage, level) and
  * clears the records; it returns the number of entries written, or a
  * negative status. Stage names: "build" (cage adjacency), "rebuild" (per-level
- * generic build), "bscan", "cc_face", "cc_vertex", "cc_edge", "loop_edge",
- * "loop_vertex", "loop_face", "sqrt3_face", "sqrt3_vertex", "edge_export";
- * level = the level the kernel reads. */
+ * generic build), "bscan", "cc_face", "cc_vertex", "cc_edge" (a level refined
+ * from its own adjacency), "cc_group", "cc_old_vertex", "cc_edge_group" (a
+ * Catmull-Clark level refined from its parent level's adjacency, one thread
+ * per parent face / vertex / edge), "loop_edge", "loop_vertex", "loop_face",
+ * "sqrt3_face", "sqrt3_vertex", "edge_export"; level = the level refined. */
 typedef struct subdiv_stage_time {
   char name[24];
   int32_t level;

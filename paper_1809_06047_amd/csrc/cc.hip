@@ -49,9 +49,11 @@ __global__ void __launch_bounds__(kBlock) k_cc_face(CCStep c) {
     const int e[4] = {ed.x, ed.y, ed.z, ed.w};
     const f3 p0 = ld3(c.P, v[0]), p1 = ld3(c.P, v[1]), p2 = ld3(c.P, v[2]), p3 = ld3(c.P, v[3]);
     st3(c.P1, V + r, mul3(0.25f, add3(add3(p0, p1), add3(p2, p3))));
-    int4 *out = reinterpret_cast<int4 *>(c.fv1) + 4ll * r;
+    if (c.fv1) {
+      int4 *out = reinterpret_cast<int4 *>(c.fv1) + 4ll * r;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) out[j] = make_int4(v[j], VF + e[j], V + r, VF + e[(j + 3) & 3]);
+      for (int j = 0; j < 4; ++j) out[j] = make_int4(v[j], VF + e[j], V + r, VF + e[(j + 3) & 3]);
+    }
     if (c.a1.twin) {
       const int4 tq = reinterpret_cast<const int4 *>(c.a.twin)[r];
       const int tw[4] = {tq.x, tq.y, tq.z, tq.w};
@@ -82,7 +84,8 @@ __global__ void __launch_bounds__(kBlock) k_cc_face(CCStep c) {
     for (int h = b; h < en; ++h) {
       const int hp = (h == b) ? en - 1 : h - 1;
       const int hn = (h + 1 == en) ? b : h + 1;
-      reinterpret_cast<int4 *>(c.fv1)[h] = make_int4(c.t.fv[h], VF + c.a.eid[h], V + r, VF + c.a.eid[hp]);
+      if (c.fv1)
+        reinterpret_cast<int4 *>(c.fv1)[h] = make_int4(c.t.fv[h], VF + c.a.eid[h], V + r, VF + c.a.eid[hp]);
       if (c.a1.twin) {
         const int t = c.a.twin[h], tp = c.a.twin[hp];
         const int tn = t < 0 ? -1 : he_next<ORDER>(c.t, t);

@@ -1,0 +1,514 @@
+// Catmull-Clark levels k >= 1 on gfx950, computed from the adjacency of the
+// parent level m = k-1 (the level k was refined from).
+//
+// Level k is itself the Catmull-Clark refinement of level m, so everything
+// the build step of level k would produce (its mesh matrix M_k, the mapped
+// products E_k, F_k) is a closed-form function of M_m and of E_m, F_m
+// (Sec. 3.2 "Topology refinement"):
+//   * face q of level k is child j of parent face p (q = col_ptr_m[p] + j =
+//     parent half-edge h) with corners (v_j, EP(e_j), FP(p), EP(e_{j-1})),
+//     EP(e) = |v_m| + |f_m| + e, FP(p) = |v_m| + p;
+//   * every level-k edge has an edge point EP(e) as its higher end, so the
+//     upper triangle of E_k enumerates the children of parent edge e at
+//     base(e) + rank, base(e) = 4 e - (boundary edges before e), rank over
+//     the ascending lower neighbours lo(e), hi(e), FP(min face), FP(max face);
+//   * F_k (twin half-edges) follows from F_m.
+// The kernels therefore iterate over the parent level's faces, edges and
+// vertices, whose arrays are 4x smaller than level k's, and read every
+// level-k quantity in the order it is laid out:
+//   k_lag_group  (per parent face p) : face points of p's children (eq:spla_fp),
+//                                      the vertex point of FP(p), child topology
+//                                      of level k+1, level-k rows of M, E, F
+//   k_lag_vertex (per parent vertex) : vertex points of the level-m vertices
+//                                      (ring walk on level m), crease valency
+//   k_lag_edge   (per parent edge e) : the 3-4 edge points of e's children, the
+//                                      vertex point of EP(e), crease inheritance
+//                                      (Chaikin rule), edge -> half-edge map
+// The rules are those of Sec. 3.1 / 3.3 (see cc.hip). Sums over a symmetric
+// pair are written as balanced trees of commutative additions, so results do
+// not depend on which half-edge of an edge is its owner.
+#include "subdiv_internal.h"
+
+namespace subdiv {
+
+__device__ __forceinline__ double chaikin_lag(double si, double sj) {
+  const double t = __dadd_rn(__dmul_rn(0.25, __dadd_rn(si, __dmul_rn(3.0, sj))), -1.0);
+  return t > 0.0 ? t : 0.0;
+}
+
+__device__ __forceinline__ int lag_base(const LagStep &c, int e) { return 4 * e - (c.bnd ? c.am.bscan[e] : 0); }
+
+template <int OM>
+__device__ __forceinline__ int face_of(const LagStep &c, int h) {
+  return he_face<OM>(c.tm, h);
+}
+
+// ------------------------------------------------------------- group kernel
+template <int OM>
+__global__ void __launch_bounds__(kBlock) k_lag_group(LagStep c) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= c.tm.F) return;
+  const Topo &tm = c.tm;
+  const int Vm = tm.V, VFm = tm.V + tm.F;
+  const int Vk = c.Vk, VFk = c.Vk + c.Fk;
+  const int b = face_begin<OM>(tm, p), en = face_end<OM>(tm, p), n = en - b;
+  const int FP = Vm + p;
+  const f3 pFP = ld3(c.Pk, FP);
+  f3 sum_ep{0.f, 0.f, 0.f}, sum_f{0.f, 0.f, 0.f};
+  const bool emit = c.ak.twin != nullptr;
+  // previous corner (slot n-1) for child 0
+  int hp = en - 1;
+  int vprev = tm.fv[hp], eprev = c.am.eid[hp], tprev = c.am.twin[hp];
+  f3 pEPprev = ld3(c.Pk, VFm + eprev);
+  for (int h = b; h < en; ++h) {
+    const int hn = (h + 1 == en) ? b : h + 1;
+    const int v = tm.fv[h], e = c.am.eid[h], t = c.am.twin[h];
+    const int vnext = tm.fv[hn];
+    const f3 pv = ld3(c.Pk, v), pEP = ld3(c.Pk, VFm + e);
+    // face point of level-k face q = h: corners (v, EP(e), FP, EP(eprev))
+    const f3 f = mul3(0.25f, add3(add3(pv, pEP), add3(pFP, pEPprev)));
+    st3(c.P1, Vk + h, f);
+    sum_ep = add3(sum_ep, pEP);
+    sum_f = add3(sum_f, f);
+    // level-k edge ids of the 4 half-edges of q (upper triangle of E_k)
+    const int bj = lag_base(c, e), bp = lag_base(c, eprev);
+    const int s = t < 0 ? -1 : face_of<OM>(c, t), sp = tprev < 0 ? -1 : face_of<OM>(c, tprev);
+    const int k0 = bj + (v > vnext);
+    const int k1 = bj + 2 + (s >= 0 && s < p);
+    const int k2 = bp + 2 + (sp >= 0 && sp < p);
+    const int k3 = bp + (v > vprev);
+    const int c0 = v, c1 = VFm + e, c2 = FP, c3 = VFm + eprev;
+    if (c.fvk) reinterpret_cast<int4 *>(c.fvk)[h] = make_int4(c0, c1, c2, c3);
+    if (emit) {
+      const int tn = t < 0 ? -1 : he_next<OM>(tm, t);
+      reinterpret_cast<int4 *>(c.ak.twin)[h] =
+          make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * hn + 2, 4 * hp + 1, tprev < 0 ? -1 : 4 * tprev);
+      reinterpret_cast<int4 *>(c.ak.eid)[h] = make_int4(k0, k1, k2, k3);
+    }
+    if (c.fv1) {
+      // children of q at level k+1: (corner_i, EP_k(k_i), FP_k(q), EP_k(k_{i-1}))
+      int4 *o = reinterpret_cast<int4 *>(c.fv1) + 4ll * h;
+      const int fq = Vk + h;
+      o[0] = make_int4(c0, VFk + k0, fq, VFk + k3);
+      o[1] = make_int4(c1, VFk + k1, fq, VFk + k0);
+      o[2] = make_int4(c2, VFk + k2, fq, VFk + k1);
+      o[3] = make_int4(c3, VFk + k3, fq, VFk + k2);
+    }
+    hp = h;
+    vprev = v;
+    eprev = e;
+    tprev = t;
+    pEPprev = pEP;
+  }
+  // vertex point of FP(p): interior, valence n, neighbours EP(e_j), faces = children
+  const float fn = (float)n;
+  st3(c.P1, FP, fma3(1.0f - 2.0f / fn, pFP, mul3(1.0f / (fn * fn), add3(sum_ep, sum_f))));
+  if (emit) c.ak.vhe[FP] = 4 * b + 2;
+}
+
+// ------------------------------------------------------------ vertex kernel
+template <int OM>
+__global__ void __launch_bounds__(kBlock) k_lag_vertex(LagStep c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c.tm.V) return;
+  const Topo &tm = c.tm;
+  const int VFm = tm.V + tm.F, Vk = c.Vk;
+  const int h0 = c.am.vhe[v];
+  const f3 p = ld3(c.Pk, v);
+  const bool creases = c.sigk != nullptr;
+  f3 sum_ep{0.f, 0.f, 0.f}, sum_f{0.f, 0.f, 0.f};
+  int n = 0, k = 0, cv0 = -1, cv1 = -1, ce0 = -1, ce1 = -1, ep_last = -1;
+  double ssum = 0.0;
+  int h = h0;
+  while (true) {
+    const int e = c.am.eid[h];
+    const int EP = VFm + e;
+    sum_ep = add3(sum_ep, ld3(c.Pk, EP));
+    sum_f = add3(sum_f, ld3(c.P1, Vk + h));  // face point of level-k face h (v at slot 0)
+    ++n;
+    if (creases) {
+      const int w = tm.fv[he_next<OM>(tm, h)];
+      const int eps = lag_base(c, e) + (v > w);  // level-k edge (v, EP)
+      const double s = c.sigk[eps];
+      if (s > 0.0) {
+        if (k == 0) { cv0 = EP; ce0 = eps; } else if (k == 1) { cv1 = EP; ce1 = eps; }
+        ++k;
+        ssum += s;
+      }
+    }
+    const int hpv = he_prev<OM>(tm, h);
+    const int t = c.am.twin[hpv];
+    if (t < 0) {  // boundary: the incoming boundary half-edge u -> v ends the fan
+      const int e2 = c.am.eid[hpv];
+      ep_last = VFm + e2;
+      if (creases) {
+        const int u = tm.fv[hpv];
+        const int eps = lag_base(c, e2) + (v > u);
+        const double s = c.sigk[eps];
+        if (s > 0.0) {
+          if (k == 0) { cv0 = ep_last; ce0 = eps; } else if (k == 1) { cv1 = ep_last; ce1 = eps; }
+          ++k;
+          ssum += s;
+        }
+      }
+      break;
+    }
+    if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
+    h = t;
+  }
+  f3 S;
+  if (ep_last >= 0) {  // boundary vertex: 3/4 p + 1/8 (two boundary neighbours at level k)
+    const int ep_first = VFm + c.am.eid[h0];
+    S = fma3(0.75f, p, mul3(0.125f, add3(ld3(c.Pk, ep_first), ld3(c.Pk, ep_last))));
+  } else {
+    const float fn = (float)n;
+    S = fma3(1.0f - 2.0f / fn, p, mul3(1.0f / (fn * fn), add3(sum_ep, sum_f)));
+    if (creases && k >= 2) {
+      const f3 sharp = (k == 2) ? fma3(0.75f, p, mul3(0.125f, add3(ld3(c.Pk, cv0), ld3(c.Pk, cv1)))) : p;
+      const double s = ssum / (double)k;
+      if (s >= 1.0) S = sharp;
+      else {
+        const float fs = (float)s;
+        S = fma3(1.0f - fs, S, mul3(fs, sharp));
+      }
+    }
+  }
+  st3(c.P1, v, S);
+  if (creases && c.vcrk) c.vcrk[v] = make_int4(k, ce0, ce1, 0);
+  if (c.ak.vhe) c.ak.vhe[v] = 4 * h0;
+}
+
+// -------------------------------------------------------------- edge kernel
+template <int OM>
+__global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c.am.E) return;
+  const Topo &tm = c.tm;
+  const int Vm = tm.V, VFm = tm.V + tm.F;
+  const int Vk = c.Vk, VFk = c.Vk + c.Fk;
+  const int h = c.am.e2h[e];
+  const int t = c.am.twin[h];
+  const int hn = he_next<OM>(tm, h);
+  const int a = tm.fv[h], bv = tm.fv[hn];
+  const int pf = face_of<OM>(c, h);
+  const int EP = VFm + e;
+  const int base = lag_base(c, e);
+  const f3 pa = ld3(c.Pk, a), pb = ld3(c.Pk, bv), pEP = ld3(c.Pk, EP), pFPp = ld3(c.Pk, Vm + pf);
+  const f3 fh = ld3(c.P1, Vk + h), fhn = ld3(c.P1, Vk + hn);
+  const bool creases = c.sigk != nullptr;
+  const int ra = a < bv ? 0 : 1;  // rank of (a, EP) among e's children
+  const double sa = creases ? c.sigk[base + ra] : 0.0, sb = creases ? c.sigk[base + 1 - ra] : 0.0;
+  f3 ea, eb, S;
+  int s = -1, tn = -1;
+  if (t < 0) {
+    ea = mul3(0.5f, add3(pa, pEP));
+    eb = mul3(0.5f, add3(pb, pEP));
+    // boundary edge point vertex: 3/4 p + 1/8 (a + b)
+    S = fma3(0.75f, pEP, mul3(0.125f, add3(pa, pb)));
+    st3(c.P1, VFk + base + 2, mul3(0.25f, add3(add3(pFPp, pEP), add3(fh, fhn))));
+  } else {
+    s = face_of<OM>(c, t);
+    tn = he_next<OM>(tm, t);
+    const f3 pFPs = ld3(c.Pk, Vm + s);
+    const f3 ft = ld3(c.P1, Vk + t), ftn = ld3(c.P1, Vk + tn);
+    ea = mul3(0.25f, add3(add3(pa, pEP), add3(fh, ftn)));
+    eb = mul3(0.25f, add3(add3(pb, pEP), add3(fhn, ft)));
+    const f3 ep_p = mul3(0.25f, add3(add3(pFPp, pEP), add3(fh, fhn)));
+    const f3 ep_s = mul3(0.25f, add3(add3(pFPs, pEP), add3(ft, ftn)));
+    st3(c.P1, VFk + base + (pf < s ? 2 : 3), ep_p);
+    st3(c.P1, VFk + base + (pf < s ? 3 : 2), ep_s);
+    // interior edge point vertex: valence 4, neighbours a, b, FP(p), FP(s)
+    const f3 nb = add3(add3(pa, pb), add3(pFPp, pFPs));
+    const f3 fs = add3(add3(fh, fhn), add3(ft, ftn));
+    S = fma3(0.5f, pEP, mul3(1.0f / 16.0f, add3(nb, fs)));
+    if (creases) {
+      const int kk = (sa > 0.0) + (sb > 0.0);
+      if (kk == 2) {
+        const f3 sharp = fma3(0.75f, pEP, mul3(0.125f, add3(pa, pb)));
+        const double sv = (sa + sb) * 0.5;
+        if (sv >= 1.0) S = sharp;
+        else {
+          const float fsv = (float)sv;
+          S = fma3(1.0f - fsv, S, mul3(fsv, sharp));
+        }
+      }
+    }
+    // crease edges among the halves (boundary halves stay midpoints)
+    if (sa >= 1.0) ea = mul3(0.5f, add3(pa, pEP));
+    else if (sa > 0.0) {
+      const float w = (float)sa;
+      ea = fma3(1.0f - w, ea, mul3(w * 0.5f, add3(pa, pEP)));
+    }
+    if (sb >= 1.0) eb = mul3(0.5f, add3(pb, pEP));
+    else if (sb > 0.0) {
+      const float w = (float)sb;
+      eb = fma3(1.0f - w, eb, mul3(w * 0.5f, add3(pb, pEP)));
+    }
+  }
+  st3(c.P1, VFk + base + ra, ea);
+  st3(c.P1, VFk + base + 1 - ra, eb);
+  st3(c.P1, EP, S);
+  const int nchild = t < 0 ? 3 : 4;
+  if (c.edges_k) {  // (lo, hi) of level-k edges, in id order
+    int2 *o = reinterpret_cast<int2 *>(c.edges_k);
+    o[base + ra] = make_int2(a, EP);
+    o[base + 1 - ra] = make_int2(bv, EP);
+    if (t < 0) o[base + 2] = make_int2(Vm + pf, EP);
+    else {
+      o[base + 2] = make_int2(Vm + (pf < s ? pf : s), EP);
+      o[base + 3] = make_int2(Vm + (pf < s ? s : pf), EP);
+    }
+  }
+  if (c.ak.e2h) {
+    const int hx0 = 4 * h, hx1 = 4 * hn + 3;
+    c.ak.e2h[base + ra] = hx0;
+    c.ak.e2h[base + 1 - ra] = hx1;
+    if (t < 0) {
+      c.ak.e2h[base + 2] = 4 * h + 1;
+      c.ak.vhe[EP] = hx1;
+    } else {
+      c.ak.e2h[base + (pf < s ? 2 : 3)] = 4 * h + 1;
+      c.ak.e2h[base + (pf < s ? 3 : 2)] = 4 * t + 1;
+      const int m0 = min(4 * h + 1, 4 * hn + 3), m1 = min(4 * t + 1, 4 * tn + 3);
+      c.ak.vhe[EP] = min(m0, m1);
+    }
+    if (c.bnd) {
+      const int b2 = 2 * c.am.bscan[e];
+      for (int i = 0; i < nchild; ++i) c.ak.bscan[base + i] = b2 + (t < 0 ? (i < 2 ? i : 2) : 0);
+    }
+  }
+  if (c.sig1) {
+    // children of the level-k edges of e, at level k+1: base_k(eps) + rank
+    const int b2 = c.bnd ? 2 * c.am.bscan[e] : 0;
+    for (int r = 0; r < nchild; ++r) {
+      const int eps = base + r;
+      const int bs = c.bnd ? b2 + (t < 0 ? (r < 2 ? r : 2) : 0) : 0;
+      const int base1 = 4 * eps - bs;
+      const int nc1 = (t < 0 && r < 2) ? 3 : 4;  // a boundary half has one face
+      double c0 = 0.0, c1 = 0.0;
+      if (r < 2) {
+        const double sj = (r == ra) ? sa : sb;
+        if (sj > 0.0) {
+          const int x = (r == ra) ? a : bv;  // the old end of the half (its lower end)
+          const int4 cx = c.vcrk[x];
+          const double si = cx.x == 2 ? c.sigk[cx.y == eps ? cx.z : cx.y] : sj;
+          const double so = (r == ra) ? sb : sa;  // the other half at EP
+          const double sk = (so > 0.0) ? so : sj;
+          c0 = chaikin_lag(si, sj);
+          c1 = chaikin_lag(sk, sj);
+        }
+      }
+      c.sig1[base1 + 0] = c0;
+      c.sig1[base1 + 1] = c1;
+      for (int i = 2; i < nc1; ++i) c.sig1[base1 + i] = 0.0;
+    }
+  }
+}
+
+template <int OM>
+static void lag_launch_t(int which, const LagStep &c, hipStream_t s) {
+  if (which == LAG_GROUP)
+    hipLaunchKernelGGL(k_lag_group<OM>, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
+  else if (which == LAG_VERTEX)
+    hipLaunchKernelGGL(k_lag_vertex<OM>, dim3(grid_for(c.tm.V)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_lag_edge<OM>, dim3(grid_for(c.am.E)), dim3(kBlock), 0, s, c);
+}
+
+hipError_t lag_launch(int which, const LagStep &c, hipStream_t s) {
+  if (c.tm.order == 4) lag_launch_t<4>(which, c, s);
+  else if (c.tm.order == 3) lag_launch_t<3>(which, c, s);
+  else lag_launch_t<0>(which, c, s);
+  return hipGetLastError();
+}
+
+
+// ===========================================================================
+// Crease-free levels whose grandparent level g = m-1 is also all quads: the
+// level-m vertices fall into three classes by the corner they occupy in a
+// level-m face p = child j of grandparent quad pg (corners v_j, EP_g(e_j),
+// FP_g(pg), EP_g(e_{j-1})):
+//   corner 2: FP_g(pg), valence 4, its ring is corner 2 of the four siblings
+//             4pg..4pg+3 (four adjacent lanes: a quad reduction);
+//   corner 1: EP_g(e_j), valence 4, half of its ring is corner 1 of p and
+//             corner 3 of the next sibling (lane (j+1)&3); the other half lies
+//             in the quad on the far side of e_j;
+//   corner 0: a vertex of level g, whose ring is walked on level g.
+// Each corner's ring term (edge point of the level-k edge leaving it plus the
+// face point of its level-k corner face) is formed once, by the thread that
+// owns the face, in face order.
+// ===========================================================================
+
+__device__ __forceinline__ f3 shfl3(f3 v, int src, int width) {
+  return f3{__shfl(v.x, src, width), __shfl(v.y, src, width), __shfl(v.z, src, width)};
+}
+__device__ __forceinline__ f3 shfl_xor3(f3 v, int mask, int width) {
+  return f3{__shfl_xor(v.x, mask, width), __shfl_xor(v.y, mask, width), __shfl_xor(v.z, mask, width)};
+}
+
+__global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
+  const LagStep &L = c.s;
+  const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = pid < L.tm.F;  // F_m is a multiple of 4: quads of lanes are complete
+  const int p = valid ? pid : L.tm.F - 1;
+  const int j = p & 3, pg = p >> 2;
+  const int Vm = L.tm.V, VFm = L.tm.V + L.tm.F;
+  const int Vk = L.Vk, VFk = L.Vk + L.Fk;
+  const int4 q = reinterpret_cast<const int4 *>(L.tm.fv)[p];
+  const int4 ed = reinterpret_cast<const int4 *>(L.am.eid)[p];
+  const int4 tq = reinterpret_cast<const int4 *>(L.am.twin)[p];
+  const int cv[4] = {q.x, q.y, q.z, q.w};
+  const int e[4] = {ed.x, ed.y, ed.z, ed.w};
+  const int tw[4] = {tq.x, tq.y, tq.z, tq.w};
+  const int FP = Vm + p;
+  const f3 pFP = ld3(L.Pk, FP);
+  f3 pc[4], pe[4], f[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    pc[i] = ld3(L.Pk, cv[i]);
+    pe[i] = ld3(L.Pk, VFm + e[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f[i] = mul3(0.25f, add3(add3(pc[i], pe[i]), add3(pFP, pe[(i + 3) & 3])));
+  int base[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) base[i] = lag_base(L, e[i]);
+  int kk[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int ip = (i + 3) & 3;
+    const int s = tw[i] < 0 ? -1 : (tw[i] >> 2), sp = tw[ip] < 0 ? -1 : (tw[ip] >> 2);
+    kk[i][0] = base[i] + (cv[i] > cv[(i + 1) & 3]);
+    kk[i][1] = base[i] + 2 + (s >= 0 && s < p);
+    kk[i][2] = base[ip] + 2 + (sp >= 0 && sp < p);
+    kk[i][3] = base[ip] + (cv[i] > cv[ip]);
+  }
+  if (valid) {
+    // face points of the four level-k children of p and the vertex point of FP_m(p)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st3(L.P1, Vk + 4 * p + i, f[i]);
+    const f3 sum = add3(add3(add3(pe[0], pe[1]), add3(pe[2], pe[3])), add3(add3(f[0], f[1]), add3(f[2], f[3])));
+    st3(L.P1, FP, fma3(0.5f, pFP, mul3(1.0f / 16.0f, sum)));
+    if (L.fvk) {
+      int4 *o = reinterpret_cast<int4 *>(L.fvk) + 4ll * p;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = make_int4(cv[i], VFm + e[i], FP, VFm + e[(i + 3) & 3]);
+    }
+    if (L.ak.twin) {
+      int4 *to = reinterpret_cast<int4 *>(L.ak.twin) + 4ll * p;
+      int4 *eo = reinterpret_cast<int4 *>(L.ak.eid) + 4ll * p;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ip = (i + 3) & 3;
+        const int t = tw[i], tp = tw[ip];
+        const int tn = t < 0 ? -1 : ((t & ~3) | ((t + 1) & 3));
+        to[i] = make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * (4 * p + ((i + 1) & 3)) + 2, 4 * (4 * p + ip) + 1,
+                          tp < 0 ? -1 : 4 * tp);
+        eo[i] = make_int4(kk[i][0], kk[i][1], kk[i][2], kk[i][3]);
+      }
+      L.ak.vhe[FP] = 4 * (4 * p) + 2;
+    }
+    if (L.fv1) {
+      int4 *o = reinterpret_cast<int4 *>(L.fv1) + 16ll * p;
+      const int cc[4][4] = {{cv[0], VFm + e[0], FP, VFm + e[3]},
+                            {cv[1], VFm + e[1], FP, VFm + e[0]},
+                            {cv[2], VFm + e[2], FP, VFm + e[1]},
+                            {cv[3], VFm + e[3], FP, VFm + e[2]}};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int fq = Vk + 4 * p + i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          o[4 * i + r] = make_int4(cc[i][r], VFk + kk[i][r], fq, VFk + kk[i][(r + 3) & 3]);
+      }
+    }
+  }
+  // ring terms of the level-m corners: edge point of the outgoing level-k edge + face point
+  f3 term[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) term[i] = add3(pe[i], f[i]);
+  // corner 2: FP_g(pg), quad reduction over the siblings (symmetric tree)
+  f3 r2 = add3(term[2], shfl_xor3(term[2], 1, 4));
+  r2 = add3(r2, shfl_xor3(r2, 2, 4));
+  // corner 1: EP_g(e_j) gets corner 3 of the next sibling
+  const f3 t3n = shfl3(term[3], (j + 1) & 3, 4);
+  const f3 pe3n = shfl3(pe[3], (j + 1) & 3, 4);
+  if (!valid) return;
+  if (j == 0) {
+    st3(L.P1, cv[2], fma3(0.5f, pc[2], mul3(1.0f / 16.0f, r2)));
+    if (L.ak.vhe) L.ak.vhe[cv[2]] = 4 * (4 * (4 * pg) + 2);
+  }
+  const f3 half = add3(term[1], t3n);
+  if (tw[0] < 0) {
+    // EP_g(e_j) on the boundary: 3/4 p + 1/8 (the two boundary neighbours at level k)
+    st3(L.P1, cv[1], fma3(0.75f, pc[1], mul3(0.125f, add3(pe[0], pe3n))));
+  } else {
+    const int sg = tw[0] >> 4;  // grandparent quad across e_j
+    const int eg = cv[1] - c.VFg;
+    reinterpret_cast<f3 *>(c.hs)[2 * eg + (pg < sg ? 0 : 1)] = half;
+  }
+  // corner 0: a level-g vertex; its term is gathered by k_lag2_older
+  reinterpret_cast<f3 *>(c.term0)[p] = term[0];
+}
+
+// interior edge points of level g (EP_g vertices): two half rings
+__global__ void __launch_bounds__(kBlock) k_lag2_combine(Lag2Step c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c.Eg) return;
+  const int EPg = c.VFg + e;
+  if (c.s.ak.vhe) c.s.ak.vhe[EPg] = 4 * c.s.am.vhe[EPg];
+  if (c.s.bnd && c.twin_g[c.e2h_g[e]] < 0) return;  // boundary: written by k_lag2_group
+  const f3 *hs = reinterpret_cast<const f3 *>(c.hs);
+  st3(c.s.P1, EPg, fma3(0.5f, ld3(c.s.Pk, EPg), mul3(1.0f / 16.0f, add3(hs[2 * e], hs[2 * e + 1]))));
+}
+
+// level-g vertices: walk the ring on level g, summing the corner terms
+__global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c.Vg) return;
+  const LagStep &L = c.s;
+  const int VFm = L.tm.V + L.tm.F;
+  const int h0 = c.vhe_g[v];
+  const f3 *term0 = reinterpret_cast<const f3 *>(c.term0);
+  f3 sum{0.f, 0.f, 0.f};
+  int n = 0, h = h0, hlast = h0;
+  bool bnd = false;
+  while (true) {
+    sum = add3(sum, term0[h]);
+    ++n;
+    hlast = h;
+    const int hp = (h & 3) == 0 ? h + 3 : h - 1;
+    const int t = c.twin_g[hp];
+    if (t < 0) {
+      bnd = true;
+      break;
+    }
+    if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
+    h = t;
+  }
+  const f3 p = ld3(L.Pk, v);
+  f3 S;
+  if (bnd) {
+    // boundary neighbours at level k: edge points of the level-m half-edges
+    // v -> EP_g (corner 0 of child h0) and EP_g -> v (corner 3 of child hlast)
+    const f3 b1 = ld3(L.Pk, VFm + L.am.eid[4 * h0]), b2 = ld3(L.Pk, VFm + L.am.eid[4 * hlast + 3]);
+    S = fma3(0.75f, p, mul3(0.125f, add3(b1, b2)));
+  } else {
+    const float fn = (float)n;
+    S = fma3(1.0f - 2.0f / fn, p, mul3(1.0f / (fn * fn), sum));
+  }
+  st3(L.P1, v, S);
+  if (L.ak.vhe) L.ak.vhe[v] = 16 * h0;
+}
+
+hipError_t lag2_launch(int which, const Lag2Step &c, hipStream_t s) {
+  if (which == LAG2_GROUP)
+    hipLaunchKernelGGL(k_lag2_group, dim3(grid_for(c.s.tm.F)), dim3(kBlock), 0, s, c);
+  else if (which == LAG2_COMBINE)
+    hipLaunchKernelGGL(k_lag2_combine, dim3(grid_for(c.Eg)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_lag2_older, dim3(grid_for(c.Vg)), dim3(kBlock), 0, s, c);
+  return hipGetLastError();
+}
+
+}  // namespace subdiv

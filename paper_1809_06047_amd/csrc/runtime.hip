@@ -139,7 +139,7 @@ struct Carver {
 };
 
 struct AdjOffsets {
-  size_t twin, eid, vhe, e2h, bscan, sig, vcr;
+  size_t fv, twin, eid, vhe, e2h, bscan, sig, vcr;
 };
 
 struct Layout {
@@ -150,15 +150,17 @@ struct Layout {
   AdjOffsets adj0;
   size_t level0_end;
   // per-level regions
-  AdjOffsets slot[2];
-  size_t partials;  // scan partials of every level after the cage
+  AdjOffsets slot[3];  // adjacency of levels k-2, k-1, k rotate through these (index level % 3)
+  size_t hs, term0;    // half rings / corner-0 terms of the crease-free fast path
+  size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
   size_t total;
 };
 
-AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool creases) {
+AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool creases, bool with_fv) {
   AdjOffsets a{};
+  a.fv = with_fv ? c.take(4 * H) : 0;
   a.twin = c.take(4 * H);
   a.eid = c.take(4 * H);
   a.vhe = c.take(4 * V);
@@ -187,7 +189,7 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   y.partials0 = c.take(4 * (scan_partials_ints(V0 > H0 ? V0 : H0) + 8));
   y.hface0 = c.take(4 * H0);
   // level-0 adjacency: edge-indexed arrays sized by H0 >= E0
-  y.adj0 = carve_adj(c, V0, H0, H0, C0 > 0);
+  y.adj0 = carve_adj(c, V0, H0, H0, C0 > 0, false);
   y.level0_end = c.at;
   // everything below may depend on the level count and on E0
   long long maxn = 1;
@@ -206,8 +208,12 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       mF = L[k].F > mF ? L[k].F : mF;
       cr = cr || L[k].creases;
     }
-    for (int s = 0; s < 2; ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr);
     const bool rebuild = scheme != SUBDIV_CATMULL_CLARK || (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL);
+    for (int s = 0; s < (rebuild ? 2 : 3); ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
+    if (!rebuild && levels >= 4) {
+      y.hs = c.take(24 * mE);
+      y.term0 = c.take(12 * mF);
+    }
     if (rebuild) {
       y.bnval = c.take(4 * (mV + 1));
       y.browptr = c.take(4 * (mV + 1));
@@ -235,6 +241,7 @@ T *at(void *ws, size_t off) {
 
 Adj adj_at(void *ws, const AdjOffsets &o, long long E, bool creases) {
   Adj a{};
+  a.fv = o.fv ? at<int32_t>(ws, o.fv) : nullptr;
   a.twin = at<int32_t>(ws, o.twin);
   a.eid = at<int32_t>(ws, o.eid);
   a.vhe = at<int32_t>(ws, o.vhe);
@@ -488,6 +495,91 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   }
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
+  if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
+    // ---- Catmull-Clark, adjacency carried over in closed form ------------
+    // step 0 on the cage adjacency; steps k >= 1 from the parent level's
+    // adjacency (level k's own adjacency is written only when step k+1 needs it)
+    const bool final0 = (levels == 1);
+    CCStep c{};
+    c.t = t;
+    c.a = a;
+    c.P = P;
+    c.fv1 = final0 ? outs[1].face_verts : nullptr;
+    c.P1 = outs[1].positions ? outs[1].positions : at<float>(ws, y.mP[1]);
+    c.has_bnd = L[0].B > 0;
+    c.creases = L[0].creases && a.sig != nullptr;
+    c.creases1 = c.creases && L[1].creases;
+    if (c.creases1)
+      c.a1.sig = final0 ? outs[1].crease_sharpness : adj_at(ws, y.slot[1 % 3], L[1].E, true).sig;
+    if (outs[1].edge_verts) SUBDIV_TIMED("edge_export", 0, launch_edge_export(t, a, outs[1].edge_verts, s));
+    SUBDIV_TIMED("cc_face", 0, cc_launch(CC_FACE, c, s));
+    SUBDIV_TIMED("cc_vertex", 0, cc_launch(CC_VERTEX, c, s));
+    SUBDIV_TIMED("cc_edge", 0, cc_launch(CC_EDGE, c, s));
+    if (!final0 && c.a1.sig && outs[1].crease_sharpness)
+      SUBDIV_TRY(hipMemcpyAsync(outs[1].crease_sharpness, c.a1.sig, 8 * L[1].E, hipMemcpyDeviceToDevice, s));
+    Topo tm = t;
+    Adj am = a;
+    Adj ag{};  // grandparent adjacency (levels >= 1 only)
+    const double *sig_cur = c.creases1 ? c.a1.sig : nullptr;
+    P = c.P1;
+    for (int k = 1; k < levels; ++k) {
+      const bool final = (k == levels - 1);
+      const Adj slotk = adj_at(ws, y.slot[k % 3], L[k].E, L[k].creases);
+      LagStep g{};
+      g.tm = tm;
+      g.am = am;
+      g.bnd = L[0].B > 0;
+      g.Vk = (int32_t)L[k].V;
+      g.Fk = (int32_t)L[k].F;
+      g.Ek = (int32_t)L[k].E;
+      g.Pk = P;
+      g.sigk = L[k].creases ? sig_cur : nullptr;
+      g.vcrk = g.sigk ? slotk.vcr : nullptr;
+      g.P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
+      g.fv1 = final ? outs[levels].face_verts : nullptr;
+      g.fvk = outs[k].face_verts ? outs[k].face_verts : (final ? nullptr : slotk.fv);
+      if (!final) {  // step k+1 refines level k from this adjacency
+        g.ak = slotk;
+        g.ak.fv = nullptr;
+        g.ak.sig = nullptr;
+        g.ak.vcr = nullptr;
+        if (!g.bnd) g.ak.bscan = nullptr;
+      }
+      if (g.sigk && L[k + 1].creases)
+        g.sig1 = final ? outs[levels].crease_sharpness : adj_at(ws, y.slot[(k + 1) % 3], L[k + 1].E, true).sig;
+      g.edges_k = outs[k + 1].edge_verts;
+      if (k >= 3 && !g.sigk) {
+        // crease-free, quad parent and grandparent: rings from corner classes
+        Lag2Step g2{};
+        g2.s = g;
+        g2.Vg = (int32_t)L[k - 2].V;
+        g2.Fg = (int32_t)L[k - 2].F;
+        g2.Eg = (int32_t)L[k - 2].E;
+        g2.VFg = g2.Vg + g2.Fg;
+        g2.vhe_g = ag.vhe;
+        g2.twin_g = ag.twin;
+        g2.e2h_g = ag.e2h;
+        g2.hs = at<float>(ws, y.hs);
+        g2.term0 = at<float>(ws, y.term0);
+        SUBDIV_TIMED("cc_group", k, lag2_launch(LAG2_GROUP, g2, s));
+        SUBDIV_TIMED("cc_ep_vertex", k, lag2_launch(LAG2_COMBINE, g2, s));
+        SUBDIV_TIMED("cc_old_vertex", k, lag2_launch(LAG2_OLDER, g2, s));
+      } else {
+        SUBDIV_TIMED("cc_group", k, lag_launch(LAG_GROUP, g, s));
+        SUBDIV_TIMED("cc_old_vertex", k, lag_launch(LAG_VERTEX, g, s));
+      }
+      SUBDIV_TIMED("cc_edge_group", k, lag_launch(LAG_EDGE, g, s));
+      if (!final && g.sig1 && outs[k + 1].crease_sharpness)
+        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, g.sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
+      tm = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, g.fvk};
+      ag = am;
+      am = slotk;
+      sig_cur = g.sig1;
+      P = g.P1;
+    }
+    return SUBDIV_OK;
+  }
+  // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -517,17 +609,12 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       c.has_bnd = L[k].B > 0;
       c.creases = L[k].creases && a.sig != nullptr;
       c.creases1 = L[k + 1].creases != 0;
-      Adj a1{};
+      Adj a1{};  // only the inherited sharpness is carried over: the next level is rebuilt
       if (!final) {
-        a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
-        if (rebuild) {  // only the inherited sharpness is carried over
-          a1.twin = a1.eid = a1.vhe = a1.e2h = a1.bscan = nullptr;
-        }
-        if (!c.creases1) a1.sig = nullptr;
+        if (c.creases1) a1.sig = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, true).sig;
       } else if (c.creases1 && outs[k + 1].crease_sharpness) {
         a1.sig = outs[k + 1].crease_sharpness;
       }
-      a1.vcr = nullptr;
       c.a1 = a1;
       if (!c.creases) c.a1.sig = nullptr;
       SUBDIV_TIMED("cc_face", k, cc_launch(CC_FACE, c, s));

@@ -81,6 +81,7 @@ __device__ __forceinline__ int face_end(const Topo &t, int f) {
 //   sig[e]   : crease sharpness of edge e (only on levels that may have creases)
 //   vcr[v]   : crease valency k and the ids of the first two incident creases
 struct Adj {
+  int32_t *fv;      // mesh matrix of the level (levels >= 1 only; the cage's is the caller's)
   int32_t *twin;
   int32_t *eid;
   int32_t *vhe;
@@ -169,6 +170,40 @@ struct CCStep {
 enum { CC_FACE = 0, CC_VERTEX = 1, CC_EDGE = 2 };
 // one of the three kernels of a Catmull-Clark level (launch in this order)
 hipError_t cc_launch(int which, const CCStep &c, hipStream_t s);
+
+// Catmull-Clark level k >= 1 from the adjacency of its parent level m = k-1.
+enum { LAG_GROUP = 0, LAG_VERTEX = 1, LAG_EDGE = 2 };
+struct LagStep {
+  Topo tm;              // parent level m
+  Adj am;               // its adjacency (twin, eid, vhe, e2h, bscan; E = E_m)
+  bool bnd;             // the mesh has boundary edges (bscan valid)
+  int32_t Vk, Fk, Ek;   // sizes of level k
+  const float *Pk;      // [Vk*3]
+  const double *sigk;   // [Ek] crease sharpness of level k, or nullptr
+  int4 *vcrk;           // [Vm] crease valency / first two creases of level-m vertices at level k
+  float *P1;            // [(Vk+Fk+Ek)*3] positions of level k+1
+  int32_t *fv1;         // [16*Hm] mesh matrix of level k+1, or nullptr
+  int32_t *fvk;         // [4*Hm] mesh matrix of level k, or nullptr
+  double *sig1;         // [E_{k+1}] sharpness of level k+1, or nullptr
+  int32_t *edges_k;     // [2*Ek] (lo, hi) of level-k edges, or nullptr
+  Adj ak;               // level-k adjacency to emit (twin/eid/vhe/e2h/bscan), nullptrs = none
+};
+hipError_t lag_launch(int which, const LagStep &c, hipStream_t s);
+
+// Crease-free Catmull-Clark level k >= 3: the parent m = k-1 and grandparent
+// g = k-2 are quad levels, so each level-m vertex's ring is known from the
+// corner it occupies in its level-m faces (see cc_lag.hip).
+enum { LAG2_GROUP = 0, LAG2_COMBINE = 1, LAG2_OLDER = 2 };
+struct Lag2Step {
+  LagStep s;                 // the parent-level view (no creases)
+  int32_t Vg, Fg, Eg, VFg;   // grandparent sizes, VFg = Vg + Fg
+  const int32_t *vhe_g;      // grandparent adjacency
+  const int32_t *twin_g;
+  const int32_t *e2h_g;
+  float *hs;                 // [2*Eg*3] half rings of the grandparent's edge points
+  float *term0;              // [Fm*3] ring term of corner 0 of every level-m face
+};
+hipError_t lag2_launch(int which, const Lag2Step &c, hipStream_t s);
 
 // Loop / sqrt(3) level steps (adjacency from a build of the same level).
 struct TriStep {
