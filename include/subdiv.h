@@ -156,6 +156,19 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* Adjoint of the refinement (reverse mode; Catmull-Clark). Refinement is
+ * linear in the vertex data, P_L = R P_0 with R = R_{L-1} ... R_0 fixed by
+ * the topology and creases (Sec. 3.6, eq:singleSpMV), so
+ * grad_in = R^T grad_out, computed level by level as transposed gathers over
+ * the adjacency each level kept. Requires a plan made with
+ * SUBDIV_FLAG_KEEP_STATE and a completed subdiv_refine with the same plan,
+ * mesh and workspace (the workspace holds every level's topology; it must not
+ * be reused in between). grad_out: [V_L*3] device, grad_in: [V_0*3] device,
+ * both caller-owned; grad_in is overwritten. Enqueues work only.
+ * Returns SUBDIV_STATE when the plan was not made for the adjoint. */
+int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
+                    void *ws, size_t ws_bytes, void *stream);
+
 /* ---- optional stage timing ---------------------------------------------
  * When enabled (process-wide switch, default off), subdiv_plan and
  * subdiv_refine record a HIP event pair on their stream around every kernel

@@ -58,6 +58,8 @@ SIGNATURES = {
                                    ctypes.POINTER(subdiv_plan_info), c_vp]),
     "subdiv_refine": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                      ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_backward": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, c_vp,
+                                       c_vp, c_sz, c_vp]),
     "subdiv_timing_enable": (None, [ctypes.c_int]),
     "subdiv_timing_read": (ctypes.c_int, [ctypes.POINTER(subdiv_stage_time), ctypes.c_int]),
     "subdiv_last_error": (ctypes.c_char_p, []),

@@ -146,6 +146,49 @@ class Refiner:
     def final(self):
         return self.outs[self.levels]
 
+    def backward(self, grad_out: torch.Tensor, grad_in: Optional[torch.Tensor] = None, stream=None):
+        """grad_in = R^T grad_out for the last run (needs flags with
+        FLAG_KEEP_STATE). Enqueues work only."""
+        lib = load()
+        d = self.dmesh
+        g = grad_out.contiguous()
+        assert g.dtype == torch.float32 and g.shape == (self.plan_info.level[self.levels].num_vertices, 3)
+        if grad_in is None:
+            grad_in = torch.empty((d.V, 3), dtype=torch.float32, device=d.device)
+        s = current_stream_handle(d.device) if stream is None else stream
+        st = lib.subdiv_backward(ctypes.byref(d.struct), ctypes.byref(self.plan_info), ctypes.c_void_p(g.data_ptr()),
+                                 ctypes.c_void_p(grad_in.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                 self.ws_bytes, ctypes.c_void_p(s))
+        check(st, "subdiv_backward")
+        return grad_in
+
+
+class SubdivFunction(torch.autograd.Function):
+    """P_L = refine(P_0) with the hand-written adjoint as its backward.
+    `refiner` must be planned with FLAG_KEEP_STATE; the topology (and
+    creases) are the refiner's, the positions the differentiable input."""
+
+    @staticmethod
+    def forward(ctx, P0: torch.Tensor, refiner: "Refiner"):
+        P0c = P0.detach().contiguous()
+        refiner.dmesh.set_positions(P0c)
+        outs = refiner.run()
+        ctx.refiner = refiner
+        ctx.keep = P0c
+        return outs[refiner.levels]["positions"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.refiner.backward(grad_out.float())
+        return g, None
+
+
+def differentiable_refiner(mesh, levels: int, device="cuda") -> "Refiner":
+    """A planned Catmull-Clark refiner whose runs can be differentiated."""
+    r = Refiner(mesh, "cc", levels, flags=_lib.FLAG_KEEP_STATE, device=device)
+    r.plan()
+    return r
+
 
 def refine(mesh, scheme, levels: int, flags: int = 0, keep: str = "final", edges: bool = False,
            creases: bool = False, device="cuda"):

@@ -155,6 +155,9 @@ struct Layout {
   size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
+  // SUBDIV_FLAG_KEEP_STATE: adjacency of every level 1..L-1 and the backward scratch
+  AdjOffsets keep[SUBDIV_MAX_LEVELS + 1];
+  size_t bg[2], bgf, bcoef;
   size_t total;
 };
 
@@ -229,6 +232,18 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       y.mfv[s] = c.take(4 * mH);
       y.mP[s] = c.take(12 * mV);
     }
+  }
+  if (flags & SUBDIV_FLAG_KEEP_STATE) {
+    long long gV = L[0].V, gF = L[0].F;
+    for (int k = 1; k < levels; ++k) {
+      y.keep[k] = carve_adj(c, L[k].V, L[k].E, L[k].H, L[k].creases != 0, true);
+      gF = L[k].F > gF ? L[k].F : gF;
+    }
+    for (int k = 1; k <= levels; ++k) gV = L[k].V > gV ? L[k].V : gV;
+    y.bg[0] = c.take(12 * gV);
+    y.bg[1] = c.take(12 * gV);
+    y.bgf = c.take(12 * gF);
+    y.bcoef = c.take(16 * gV);
   }
   y.total = c.at + 256;
   return y;
@@ -399,7 +414,11 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   std::memset(plan, 0, sizeof(*plan));
   int st = check_mesh_args(mesh, scheme, levels);
   if (st != SUBDIV_OK) return st;
-  if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;  // KEEP_STATE: not in this version
+  if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL | SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_INVALID_ARG;
+  // the adjoint covers Catmull-Clark with the carried-over adjacency
+  if ((flags & SUBDIV_FLAG_KEEP_STATE) &&
+      (scheme != SUBDIV_CATMULL_CLARK || (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL)))
+    return SUBDIV_INVALID_ARG;
   if (!ws) return SUBDIV_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
@@ -495,6 +514,43 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   }
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
+  if (plan->flags & SUBDIV_FLAG_KEEP_STATE) {
+    // ---- Catmull-Clark keeping every level's adjacency for subdiv_backward:
+    // each level's kernels emit the next level's adjacency in closed form
+    for (int k = 0; k < levels; ++k) {
+      const bool final = (k == levels - 1);
+      const Adj ak = (k == 0) ? a : adj_at(ws, y.keep[k], L[k].E, L[k].creases);
+      CCStep c{};
+      c.t = t;
+      c.a = ak;
+      c.P = P;
+      c.P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
+      c.has_bnd = L[0].B > 0;
+      c.creases = L[k].creases && ak.sig != nullptr;
+      c.creases1 = c.creases && L[k + 1].creases;
+      if (!final) {
+        c.a1 = adj_at(ws, y.keep[k + 1], L[k + 1].E, L[k + 1].creases);
+        c.fv1 = c.a1.fv;
+        c.a1.fv = nullptr;
+        c.a1.vcr = nullptr;
+        if (!c.creases1) c.a1.sig = nullptr;
+      } else {
+        c.fv1 = outs[levels].face_verts;
+        if (c.creases1) c.a1.sig = outs[levels].crease_sharpness;
+      }
+      if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, ak, outs[k + 1].edge_verts, s));
+      SUBDIV_TIMED("cc_face", k, cc_launch(CC_FACE, c, s));
+      SUBDIV_TIMED("cc_vertex", k, cc_launch(CC_VERTEX, c, s));
+      SUBDIV_TIMED("cc_edge", k, cc_launch(CC_EDGE, c, s));
+      if (!final && outs[k + 1].face_verts)
+        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].face_verts, c.fv1, 4 * L[k + 1].H, hipMemcpyDeviceToDevice, s));
+      if (!final && c.a1.sig && outs[k + 1].crease_sharpness)
+        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.a1.sig, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
+      t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, 4, nullptr, nullptr, c.fv1};
+      P = c.P1;
+    }
+    return SUBDIV_OK;
+  }
   if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
     // ---- Catmull-Clark, adjacency carried over in closed form ------------
     // step 0 on the cage adjacency; steps k >= 1 from the parent level's
@@ -638,6 +694,44 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     // level k+1 becomes the input of the next step
     t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, L[k + 1].order, nullptr, nullptr, fv1};
     P = P1;
+  }
+  return SUBDIV_OK;
+}
+
+int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
+                    void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !grad_out || !grad_in || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_STATE;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int levels = plan->levels;
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(plan->scheme, levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
+  const float *g1 = grad_out;
+  for (int k = levels - 1; k >= 0; --k) {
+    BwdStep b{};
+    if (k == 0) {
+      b.t = cage_topo(mesh, H0, ws, y);
+      b.a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
+    } else {
+      b.a = adj_at(ws, y.keep[k], L[k].E, L[k].creases);
+      b.t = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, b.a.fv};
+    }
+    b.g1 = g1;
+    b.g0 = (k == 0) ? grad_in : at<float>(ws, y.bg[k & 1]);
+    b.gf = at<float>(ws, y.bgf);
+    b.coef = at<float>(ws, y.bcoef);
+    SUBDIV_TIMED("bw_coef", k, bw_launch(BW_COEF, b, s));
+    SUBDIV_TIMED("bw_face", k, bw_launch(BW_FACE, b, s));
+    SUBDIV_TIMED("bw_vertex", k, bw_launch(BW_VERTEX, b, s));
+    g1 = b.g0;
   }
   return SUBDIV_OK;
 }

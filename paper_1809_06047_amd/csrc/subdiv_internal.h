@@ -205,6 +205,18 @@ struct Lag2Step {
 };
 hipError_t lag2_launch(int which, const Lag2Step &c, hipStream_t s);
 
+// Adjoint of one Catmull-Clark level: g0 = R_k^T g1 (launch in this order).
+enum { BW_COEF = 0, BW_FACE = 1, BW_VERTEX = 2 };
+struct BwdStep {
+  Topo t;            // level k
+  Adj a;             // its adjacency (twin, eid, vhe; sig when the level may carry creases)
+  const float *g1;   // [V_{k+1}*3] gradient w.r.t. the positions of level k+1
+  float *g0;         // [V_k*3] gradient w.r.t. the positions of level k
+  float *gf;         // [F_k*3] scratch: face-point adjoints divided by the face order
+  float *coef;       // [V_k*4] scratch: vertex-rule coefficients (a, b, d, flags)
+};
+hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s);
+
 // Loop / sqrt(3) level steps (adjacency from a build of the same level).
 struct TriStep {
   Topo t;
