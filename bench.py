@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-levels", type=int, default=5, help="levels of the oracle sample (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving trace (Poisson arrivals; 0 = skip the serving leg)")
+    ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2",
+                    help="arrival rates as multiples of the per-mesh-launch saturation rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -163,9 +167,30 @@ def main():
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(stages.items())},
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(args)
     if args.cpu_levels > 0:
         out["cpu_baseline"] = cpu_baseline(mesh, args.cpu_levels)
     print(json.dumps(out), flush=True)
+
+
+def serving(args):
+    """Continuous-batching server against one plan + refine per request on the
+    same Poisson trace (cages of 100..50k faces, Catmull-Clark or Loop, levels
+    1..4), at multiples of the per-mesh-launch saturation rate."""
+    from paper_1809_06047_amd import serve as S
+    res = S.sweep(n_requests=args.serve_requests, factors=tuple(float(x) for x in args.serve_factors.split(",")),
+                  log=lambda m: print(m, file=sys.stderr, flush=True))
+
+    def side(d, keys):
+        return {k: (round(d[k], 3) if isinstance(d[k], float) else d[k]) for k in keys}
+    pts = []
+    for p in res["points"]:
+        pts.append({"factor": p["factor"], "qps": round(p["qps"], 1),
+                    "batched": side(p["batched"], ("p50_ms", "p99_ms", "faces_per_s", "mean_batch", "max_queue")),
+                    "per_mesh": side(p["per_mesh"], ("p50_ms", "p99_ms", "faces_per_s"))})
+    return {"requests": res["requests"], "per_mesh_saturation_qps": round(res["per_mesh_saturation_qps"], 1),
+            "budget_gib": res["budget_gib"], "slots": res["slots"], "max_batch": res["max_batch"], "points": pts}
 
 
 if __name__ == "__main__":

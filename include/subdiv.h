@@ -169,6 +169,46 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- batches of uneven meshes (one scheme and level count per batch) ---
+ * The meshes are packed into one disjoint union cage and refined together:
+ * every stage runs as one launch over all meshes of the batch. Each mesh's
+ * final level is then written to its own buffers in its own numbering and is
+ * bit-identical to refining that mesh alone with the same plan flags (the
+ * union's index rules keep every mesh's elements in their relative order).
+ * A fault in any mesh fails the whole batch with that mesh's status code.
+ * Loop and sqrt(3) batches need triangle meshes; creases: Catmull-Clark only. */
+typedef struct subdiv_batch_plan {
+  int32_t num_meshes;
+  int32_t scheme;
+  int32_t levels;
+  uint32_t flags;
+  subdiv_plan_info union_plan; /* plan of the packed union cage */
+  size_t workspace_bytes;      /* the workspace size the batch was planned in */
+  const void *priv_ws;         /* private: the planned workspace */
+  uint64_t priv_stamp;
+} subdiv_batch_plan;
+
+#define SUBDIV_MAX_BATCH 65536
+
+/* Upper bound of the workspace a batch needs (host-only). `meshes` are read
+ * for their sizes only (host structs with device pointers). */
+size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags);
+
+/* Packs the n meshes into the union cage inside `ws`, plans it (validation,
+ * adjacency, one host wait), and fills plans[i] with the sizes of every level
+ * of mesh i (size reports only: they cannot be passed to subdiv_refine). */
+int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags, void *ws,
+                      size_t ws_bytes, subdiv_batch_plan *bplan, subdiv_plan_info *plans, void *stream);
+
+/* Refines a planned batch: outs[i] receives the final level of mesh i
+ * (face_verts [H_L], positions [V_L*3], sized from plans[i]; edge_verts and
+ * crease_sharpness are not written). The meshes must be the planned ones
+ * (positions may change); `ws` must be the planned workspace. Enqueues work
+ * only (the pointer tables go to the device through library-owned pinned
+ * host memory). */
+int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_plan *bplan, subdiv_level_out *outs,
+                        void *ws, size_t ws_bytes, void *stream);
+
 /* ---- optional stage timing ---------------------------------------------
  * When enabled (process-wide switch, default off), subdiv_plan and
  * subdiv_refine record a HIP event pair on their stream around every kernel

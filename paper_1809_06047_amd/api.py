@@ -46,6 +46,23 @@ class DeviceMesh:
         self.order = 0 if mesh.offsets is not None else int(mesh.face_order)
         self.struct = self._make_struct()
 
+    @classmethod
+    def from_tensors(cls, verts, offsets, positions, crease_verts, crease_sharp, face_order: int, name: str = ""):
+        """A cage whose arrays already live on the device (e.g. views into one
+        packed upload); offsets None means uniform `face_order`."""
+        self = cls.__new__(cls)
+        self.device = verts.device
+        self.name = name
+        self.verts, self.offsets, self.positions = verts, offsets, positions
+        self.crease_verts, self.crease_sharp = crease_verts, crease_sharp
+        self.V = int(positions.shape[0])
+        self.F = int(offsets.shape[0] - 1) if offsets is not None else int(verts.shape[0]) // int(face_order)
+        self.H = int(verts.shape[0])
+        self.C = 0 if crease_verts is None else int(crease_verts.shape[0])
+        self.order = 0 if offsets is not None else int(face_order)
+        self.struct = self._make_struct()
+        return self
+
     def _make_struct(self):
         m = _lib.subdiv_mesh()
         m.num_vertices = self.V
@@ -208,3 +225,77 @@ def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
         return 0
     except _lib.SubdivError as e:
         return e.status
+
+
+class BatchRefiner:
+    """Plan + refine of a batch of uneven meshes (one scheme and level count):
+    one launch per stage for the whole batch, each mesh's final level in its
+    own tensors. Meshes are meshgen.Mesh or DeviceMesh."""
+
+    def __init__(self, meshes, scheme, levels: int, flags: int = 0, device="cuda", ws: Optional[torch.Tensor] = None):
+        lib = load()
+        self.dmeshes = [m if isinstance(m, DeviceMesh) else DeviceMesh(m, device) for m in meshes]
+        self.n = len(self.dmeshes)
+        self.scheme = _lib.SCHEMES.get(scheme, scheme)
+        self.levels = int(levels)
+        self.flags = int(flags)
+        self.device = self.dmeshes[0].device
+        self.structs = (_lib.subdiv_mesh * self.n)(*[d.struct for d in self.dmeshes])
+        self.ws_bytes = int(lib.subdiv_batch_workspace_bound(self.structs, self.n, self.scheme, self.levels, self.flags))
+        if self.ws_bytes == 0:
+            raise _lib.SubdivError(_lib.INVALID_ARG, "subdiv_batch_workspace_bound")
+        if ws is not None and ws.numel() >= self.ws_bytes:
+            self.ws = ws
+        else:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.bplan = _lib.subdiv_batch_plan()
+        self.plans = (_lib.subdiv_plan_info * self.n)()
+        self.outs: List[Dict[str, torch.Tensor]] = []
+
+    @staticmethod
+    def footprint(meshes, scheme, levels: int, flags: int = 0) -> int:
+        """Device bytes a batch needs: workspace bound (host-only)."""
+        lib = load()
+        structs = (_lib.subdiv_mesh * len(meshes))()
+        for i, m in enumerate(meshes):
+            s = structs[i]
+            s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
+            s.face_order = 0 if m.offsets is not None else m.face_order
+            s.face_offsets = 8 if m.offsets is not None else None  # sizes only: never dereferenced
+            s.face_verts = s.positions = 8
+            s.num_creases = m.num_creases
+            if m.num_creases:
+                s.crease_verts = s.crease_sharpness = 8
+        return int(lib.subdiv_batch_workspace_bound(structs, len(meshes), _lib.SCHEMES.get(scheme, scheme), levels,
+                                                    flags))
+
+    def plan(self, stream=None):
+        lib = load()
+        s = current_stream_handle(self.device) if stream is None else stream
+        st = lib.subdiv_plan_batch(self.structs, self.n, self.scheme, self.levels, self.flags,
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.byref(self.bplan),
+                                   self.plans, ctypes.c_void_p(s))
+        check(st, "subdiv_plan_batch")
+        L = self.levels
+        arr = (_lib.subdiv_level_out * self.n)()
+        self.outs = []
+        for i in range(self.n):
+            li = self.plans[i].level[L]
+            fv = torch.empty(li.num_halfedges, dtype=torch.int32, device=self.device)
+            P = torch.empty((li.num_vertices, 3), dtype=torch.float32, device=self.device)
+            arr[i].face_verts = fv.data_ptr()
+            arr[i].positions = P.data_ptr()
+            self.outs.append({"face_verts": fv, "positions": P})
+        self._outs_struct = arr
+        return self.plans
+
+    def output_faces(self) -> int:
+        return sum(int(self.plans[i].level[self.levels].num_faces) for i in range(self.n))
+
+    def run(self, stream=None):
+        lib = load()
+        s = current_stream_handle(self.device) if stream is None else stream
+        st = lib.subdiv_refine_batch(self.structs, self.n, ctypes.byref(self.bplan), self._outs_struct,
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.c_void_p(s))
+        check(st, "subdiv_refine_batch")
+        return self.outs

@@ -1,0 +1,182 @@
+// Batched refinement of uneven meshes on gfx950: the meshes of a batch are
+// packed into one disjoint union cage (vertex, face, half-edge and crease
+// offsets), the union is refined by the ordinary per-level kernels -- one
+// launch per stage for the whole batch -- and every mesh's final level is
+// then gathered into its own buffers in its own local numbering.
+//
+// Why this gives every mesh exactly its solo result: the refinement of a
+// disjoint union is the union of the refinements, and the union's index
+// rules keep each mesh's elements in their relative order. A refined level
+// lists [vertex points | face points | edge points] (Catmull-Clark; Loop
+// has no face block, sqrt(3) no edge block); inside each block the meshes
+// appear one after the other, each in its own order, because faces stay
+// grouped by mesh (children of face r sit at col_ptr[r] + j) and edges stay
+// grouped by mesh (every edge of a refined Catmull-Clark or Loop level has
+// an edge point as its higher end, and the upper triangle of E is
+// enumerated by that end). Ranks within a mesh are unchanged, so the
+// arithmetic on every element is the same as when the mesh is refined alone.
+#include "subdiv_internal.h"
+
+namespace subdiv {
+
+__device__ __forceinline__ int seg_of(const int32_t *pre, int n, int x) {
+  // largest i in [0, n) with pre[i] <= x
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---- pack the cages into the union (topology and creases) ---------------
+__global__ void k_concat_topology(const BatchMesh *m, int n, BatchUnion u) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int total_h = m[n - 1].hofs + m[n - 1].H;
+  const int total_f = m[n - 1].fofs + m[n - 1].F;
+  const int total_c = m[n - 1].cofs + m[n - 1].C;
+  if (gid < total_h) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (m[mid].hofs <= gid) lo = mid;
+      else hi = mid;
+    }
+    const BatchMesh &b = m[lo];
+    u.fv[gid] = b.fv[gid - b.hofs] + b.vofs;
+  }
+  if (u.off && gid <= total_f) {
+    if (gid == total_f) {
+      u.off[gid] = total_h;
+    } else {
+      int lo = 0, hi = n;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m[mid].fofs <= gid) lo = mid;
+        else hi = mid;
+      }
+      const BatchMesh &b = m[lo];
+      const int f = (int)gid - b.fofs;
+      u.off[gid] = b.hofs + (b.off ? b.off[f] : f * b.order);
+    }
+  }
+  if (gid < total_c) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (m[mid].cofs <= gid) lo = mid;
+      else hi = mid;
+    }
+    const BatchMesh &b = m[lo];
+    const int c = (int)gid - b.cofs;
+    u.cv[2 * gid] = b.cv[2 * c] + b.vofs;
+    u.cv[2 * gid + 1] = b.cv[2 * c + 1] + b.vofs;
+    u.cs[gid] = b.cs[c];
+  }
+}
+
+__global__ void k_concat_positions(const BatchMesh *m, int n, float *P) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total_v = m[n - 1].vofs + m[n - 1].V;
+  if (gid >= total_v) return;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m[mid].vofs <= gid) lo = mid;
+    else hi = mid;
+  }
+  const BatchMesh &b = m[lo];
+  st3(P, gid, ld3(b.P, gid - b.vofs));
+}
+
+// ---- per-mesh edge and boundary counts of the union cage --------------
+// ebase = exclusive scan of lower-neighbour counts (edge base per vertex);
+// the edges of mesh i are ebase[vofs_i] .. ebase[vofs_{i+1}]
+__global__ void k_batch_edge_ranges(const BatchMesh *m, int n, const int32_t *ebase, int32_t *epre) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int v = (i == n) ? m[n - 1].vofs + m[n - 1].V : m[i].vofs;
+  epre[i] = ebase[v];
+}
+
+__global__ void k_batch_boundary_counts(const int32_t *epre, int n, const int32_t *bflag, int32_t *bcount) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= epre[n]) return;
+  if (bflag[e]) atomicAdd(&bcount[seg_of(epre, n + 1, e)], 1);
+}
+
+// ---- gather the union's final level into each mesh's buffers ----------
+// local index of a vertex of the union's level L (see the file header)
+__device__ int local_vertex(const BatchTables &t, int u, int *mesh) {
+  const int n1 = t.n + 1;
+  for (int k = t.L - 1; k >= 0; --k) {
+    const int32_t *vp = t.vpre + k * n1, *fp = t.fpre + k * n1, *ep = t.epre + k * n1;
+    const int UV = vp[t.n], UF = t.has_f ? fp[t.n] : 0;
+    if (u < UV) continue;  // a vertex point keeps the index of its level-k vertex
+    if (u < UV + UF) {
+      const int f = u - UV;
+      const int i = seg_of(fp, n1, f);
+      *mesh = i;
+      return (vp[i + 1] - vp[i]) + (f - fp[i]);
+    }
+    const int e = u - UV - UF;
+    const int i = seg_of(ep, n1, e);
+    *mesh = i;
+    return (vp[i + 1] - vp[i]) + (t.has_f ? fp[i + 1] - fp[i] : 0) + (e - ep[i]);
+  }
+  const int i = seg_of(t.vpre, n1, u);
+  *mesh = i;
+  return u - t.vpre[i];
+}
+
+__global__ void k_extract_faces(BatchTables t, const int32_t *fvL, const BatchOut *out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1 = t.n + 1;
+  const int32_t *fpL = t.fpre + t.L * n1;
+  if (f >= fpL[t.n]) return;
+  const int i = seg_of(fpL, n1, f);
+  const int lf = f - fpL[i];
+  int32_t *dst = out[i].fv + (long long)t.order * lf;
+  for (int j = 0; j < t.order; ++j) {
+    int mesh;
+    dst[j] = local_vertex(t, fvL[(long long)t.order * f + j], &mesh);
+  }
+}
+
+__global__ void k_extract_positions(BatchTables t, const float *PL, const BatchOut *out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= t.vpre[t.L * (t.n + 1) + t.n]) return;
+  int i;
+  const int x = local_vertex(t, u, &i);
+  st3(out[i].P, x, ld3(PL, u));
+}
+
+hipError_t batch_concat_topology(const BatchMesh *m, int n, const BatchUnion &u, long long items, hipStream_t s) {
+  hipLaunchKernelGGL(k_concat_topology, dim3(grid_for(items)), dim3(kBlock), 0, s, m, n, u);
+  return hipGetLastError();
+}
+
+hipError_t batch_concat_positions(const BatchMesh *m, int n, float *P, long long V, hipStream_t s) {
+  hipLaunchKernelGGL(k_concat_positions, dim3(grid_for(V)), dim3(kBlock), 0, s, m, n, P);
+  return hipGetLastError();
+}
+
+hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, long long E,
+                       int32_t *epre, int32_t *bcount, hipStream_t s) {
+  hipError_t err = launch_fill_i32(bcount, 0, n, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_batch_edge_ranges, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, m, n, ebase, epre);
+  hipLaunchKernelGGL(k_batch_boundary_counts, dim3(grid_for(E)), dim3(kBlock), 0, s, (const int32_t *)epre, n, bflag,
+                     bcount);
+  return hipGetLastError();
+}
+
+hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out, long long F,
+                         long long V, hipStream_t s) {
+  hipLaunchKernelGGL(k_extract_faces, dim3(grid_for(F)), dim3(kBlock), 0, s, t, fvL, out);
+  hipLaunchKernelGGL(k_extract_positions, dim3(grid_for(V)), dim3(kBlock), 0, s, t, PL, out);
+  return hipGetLastError();
+}
+
+}  // namespace subdiv

@@ -48,7 +48,9 @@ __global__ void __launch_bounds__(kBlock) k_cc_face(CCStep c) {
     const int v[4] = {q.x, q.y, q.z, q.w};
     const int e[4] = {ed.x, ed.y, ed.z, ed.w};
     const f3 p0 = ld3(c.P, v[0]), p1 = ld3(c.P, v[1]), p2 = ld3(c.P, v[2]), p3 = ld3(c.P, v[3]);
-    st3(c.P1, V + r, mul3(0.25f, add3(add3(p0, p1), add3(p2, p3))));
+    // summed in slot order, as the general-polygon path does, so a quad cage
+    // gives the same bits whether or not it comes with a column pointer
+    st3(c.P1, V + r, mul3(0.25f, add3(add3(add3(p0, p1), p2), p3)));
     if (c.fv1) {
       int4 *out = reinterpret_cast<int4 *>(c.fv1) + 4ll * r;
 #pragma unroll

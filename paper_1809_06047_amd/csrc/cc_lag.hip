@@ -324,10 +324,10 @@ hipError_t lag_launch(int which, const LagStep &c, hipStream_t s) {
 
 
 // ===========================================================================
-// Crease-free levels whose grandparent level g = m-1 is also all quads: the
-// level-m vertices fall into three classes by the corner they occupy in a
-// level-m face p = child j of grandparent quad pg (corners v_j, EP_g(e_j),
-// FP_g(pg), EP_g(e_{j-1})):
+// Levels whose grandparent level g = m-1 is also all quads: the level-m
+// vertices fall into three classes by the corner they occupy in a level-m
+// face p = child j of grandparent quad pg (corners v_j, EP_g(e_j), FP_g(pg),
+// EP_g(e_{j-1})):
 //   corner 2: FP_g(pg), valence 4, its ring is corner 2 of the four siblings
 //             4pg..4pg+3 (four adjacent lanes: a quad reduction);
 //   corner 1: EP_g(e_j), valence 4, half of its ring is corner 1 of p and
@@ -337,6 +337,13 @@ hipError_t lag_launch(int which, const LagStep &c, hipStream_t s) {
 // Each corner's ring term (edge point of the level-k edge leaving it plus the
 // face point of its level-k corner face) is formed once, by the thread that
 // owns the face, in face order.
+// Creases: a level-k edge can only be sharp if its parent level-m edge is a
+// half of a sharp grandparent edge, so FP_g vertices are never on a crease,
+// an EP_g(e) vertex has at most the two children of the halves of e (level-m
+// ids base_g(e) + 0/1, their children at EP_g at base_m(.) + 1), and a level-g
+// vertex v meets the children base_m(eid_m(4h)) + 0 of the level-m edges
+// (v, EP_g) met on its ring walk. The crease rules are those of the general
+// vertex kernel above, which these kernels replace on such levels.
 // ===========================================================================
 
 __device__ __forceinline__ f3 shfl3(f3 v, int src, int width) {
@@ -451,15 +458,38 @@ __global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
   reinterpret_cast<f3 *>(c.term0)[p] = term[0];
 }
 
-// interior edge points of level g (EP_g vertices): two half rings
+// edge points of level g (EP_g vertices): two half rings, crease valency
 __global__ void __launch_bounds__(kBlock) k_lag2_combine(Lag2Step c) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= c.Eg) return;
+  const LagStep &L = c.s;
+  const int VFm = L.tm.V + L.tm.F;
   const int EPg = c.VFg + e;
-  if (c.s.ak.vhe) c.s.ak.vhe[EPg] = 4 * c.s.am.vhe[EPg];
-  if (c.s.bnd && c.twin_g[c.e2h_g[e]] < 0) return;  // boundary: written by k_lag2_group
+  if (L.ak.vhe) L.ak.vhe[EPg] = 4 * L.am.vhe[EPg];
+  const int bg = 4 * e - (L.bnd ? c.bscan_g[e] : 0);  // level-m halves of e: bg (lo end), bg + 1 (hi end)
+  int kc = 0;
+  double s0 = 0.0, s1 = 0.0;
+  if (L.sigk) {
+    const int x0 = lag_base(L, bg) + 1, x1 = lag_base(L, bg + 1) + 1;  // their level-k children at EP_g
+    s0 = L.sigk[x0];
+    s1 = L.sigk[x1];
+    kc = (s0 > 0.0) + (s1 > 0.0);
+    if (L.vcrk) L.vcrk[EPg] = make_int4(kc, s0 > 0.0 ? x0 : x1, kc == 2 ? x1 : -1, 0);
+  }
+  if (L.bnd && c.twin_g[c.e2h_g[e]] < 0) return;  // boundary: written by k_lag2_group
   const f3 *hs = reinterpret_cast<const f3 *>(c.hs);
-  st3(c.s.P1, EPg, fma3(0.5f, ld3(c.s.Pk, EPg), mul3(1.0f / 16.0f, add3(hs[2 * e], hs[2 * e + 1]))));
+  const f3 p = ld3(L.Pk, EPg);
+  f3 S = fma3(0.5f, p, mul3(1.0f / 16.0f, add3(hs[2 * e], hs[2 * e + 1])));
+  if (kc == 2) {
+    const f3 sharp = fma3(0.75f, p, mul3(0.125f, add3(ld3(L.Pk, VFm + bg), ld3(L.Pk, VFm + bg + 1))));
+    const double sv = (s0 + s1) * 0.5;
+    if (sv >= 1.0) S = sharp;
+    else {
+      const float fs = (float)sv;
+      S = fma3(1.0f - fs, S, mul3(fs, sharp));
+    }
+  }
+  st3(L.P1, EPg, S);
 }
 
 // level-g vertices: walk the ring on level g, summing the corner terms
@@ -470,13 +500,27 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
   const int VFm = L.tm.V + L.tm.F;
   const int h0 = c.vhe_g[v];
   const f3 *term0 = reinterpret_cast<const f3 *>(c.term0);
+  const bool creases = L.sigk != nullptr;
   f3 sum{0.f, 0.f, 0.f};
   int n = 0, h = h0, hlast = h0;
+  int kc = 0, cv0 = -1, cv1 = -1, ce0 = -1, ce1 = -1;
+  double ssum = 0.0;
   bool bnd = false;
+  // one incident level-m edge em = (v, EP_g): its level-k child at v has v as lower end
+  auto crease = [&](int em) {
+    const int x = lag_base(L, em);
+    const double s = L.sigk[x];
+    if (s > 0.0) {
+      if (kc == 0) { cv0 = VFm + em; ce0 = x; } else if (kc == 1) { cv1 = VFm + em; ce1 = x; }
+      ++kc;
+      ssum += s;
+    }
+  };
   while (true) {
     sum = add3(sum, term0[h]);
     ++n;
     hlast = h;
+    if (creases) crease(L.am.eid[4 * h]);
     const int hp = (h & 3) == 0 ? h + 3 : h - 1;
     const int t = c.twin_g[hp];
     if (t < 0) {
@@ -486,6 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
     if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
     h = t;
   }
+  if (creases && bnd) crease(L.am.eid[4 * hlast + 3]);  // the incoming boundary edge
   const f3 p = ld3(L.Pk, v);
   f3 S;
   if (bnd) {
@@ -496,8 +541,18 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
   } else {
     const float fn = (float)n;
     S = fma3(1.0f - 2.0f / fn, p, mul3(1.0f / (fn * fn), sum));
+    if (kc >= 2) {
+      const f3 sharp = (kc == 2) ? fma3(0.75f, p, mul3(0.125f, add3(ld3(L.Pk, cv0), ld3(L.Pk, cv1)))) : p;
+      const double s = ssum / (double)kc;
+      if (s >= 1.0) S = sharp;
+      else {
+        const float fs = (float)s;
+        S = fma3(1.0f - fs, S, mul3(fs, sharp));
+      }
+    }
   }
   st3(L.P1, v, S);
+  if (creases && L.vcrk) L.vcrk[v] = make_int4(kc, ce0, ce1, 0);
   if (L.ak.vhe) L.ak.vhe[v] = 16 * h0;
 }
 

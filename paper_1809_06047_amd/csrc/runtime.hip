@@ -151,7 +151,7 @@ struct Layout {
   size_t level0_end;
   // per-level regions
   AdjOffsets slot[3];  // adjacency of levels k-2, k-1, k rotate through these (index level % 3)
-  size_t hs, term0;    // half rings / corner-0 terms of the crease-free fast path
+  size_t hs, term0;    // half rings / corner-0 terms of the corner-class kernels
   size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
@@ -604,8 +604,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       if (g.sigk && L[k + 1].creases)
         g.sig1 = final ? outs[levels].crease_sharpness : adj_at(ws, y.slot[(k + 1) % 3], L[k + 1].E, true).sig;
       g.edges_k = outs[k + 1].edge_verts;
-      if (k >= 3 && !g.sigk) {
-        // crease-free, quad parent and grandparent: rings from corner classes
+      if (k >= 3) {
+        // quad parent and grandparent: rings from corner classes
         Lag2Step g2{};
         g2.s = g;
         g2.Vg = (int32_t)L[k - 2].V;
@@ -615,6 +615,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         g2.vhe_g = ag.vhe;
         g2.twin_g = ag.twin;
         g2.e2h_g = ag.e2h;
+        g2.bscan_g = g.bnd ? ag.bscan : nullptr;
         g2.hs = at<float>(ws, y.hs);
         g2.term0 = at<float>(ws, y.term0);
         SUBDIV_TIMED("cc_group", k, lag2_launch(LAG2_GROUP, g2, s));
@@ -733,6 +734,278 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
     SUBDIV_TIMED("bw_vertex", k, bw_launch(BW_VERTEX, b, s));
     g1 = b.g0;
   }
+  return SUBDIV_OK;
+}
+
+}  // extern "C"
+
+// ---- batches ------------------------------------------------------------
+namespace {
+
+struct BatchLayout {
+  size_t desc, tables, outtab, epre, bcount, ufv, uoff, uP, ucv, ucs, fvL, PL, uws;
+  size_t uws_bytes, total;
+  long long VU, FU, HU, CU, HL, VL;
+  bool general;
+  int order;
+};
+
+bool batch_layout(const subdiv_mesh *m, int n, int scheme, int levels, uint32_t flags, BatchLayout &b) {
+  b = BatchLayout{};
+  long long VU = 0, FU = 0, HU = 0, CU = 0;
+  int order = m[0].face_offsets ? 0 : m[0].face_order;
+  for (int i = 0; i < n; ++i) {
+    VU += m[i].num_vertices;
+    FU += m[i].num_faces;
+    HU += cage_H(&m[i]);
+    CU += m[i].num_creases;
+    const int oi = m[i].face_offsets ? 0 : m[i].face_order;
+    if (oi != order) order = 0;
+  }
+  const long long lim = 0x7fffffffLL - 16;
+  if (VU > lim || FU > lim || HU > lim || CU > lim) return false;
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, levels, VU, FU, HU, HU, HU, order, CU > 0 ? 1e30f : 0.f, CU, L);
+  if (!sizes_fit_int32(L, levels)) return false;
+  b.VU = VU;
+  b.FU = FU;
+  b.HU = HU;
+  b.CU = CU;
+  b.HL = L[levels].H;
+  b.VL = L[levels].V;
+  b.general = (order == 0);
+  b.order = order;
+  b.uws_bytes = subdiv_workspace_bound((int32_t)VU, (int32_t)FU, HU, (int32_t)CU, scheme, levels, flags);
+  if (b.uws_bytes == 0) return false;
+  Carver c;
+  b.desc = c.take(sizeof(BatchMesh) * (size_t)n);
+  b.tables = c.take(4 * 3 * (size_t)(levels + 1) * (n + 1));
+  b.outtab = c.take(sizeof(BatchOut) * (size_t)n);
+  b.epre = c.take(4 * (size_t)(n + 1));
+  b.bcount = c.take(4 * (size_t)n);
+  b.ufv = c.take(4 * HU);
+  b.uoff = b.general ? c.take(4 * (FU + 1)) : 0;
+  b.uP = c.take(12 * VU);
+  b.ucv = c.take(8 * (CU > 0 ? CU : 1));
+  b.ucs = c.take(4 * (CU > 0 ? CU : 1));
+  b.fvL = c.take(4 * b.HL);
+  b.PL = c.take(12 * b.VL);
+  b.uws = c.take(b.uws_bytes);
+  b.total = c.at + 256;
+  return true;
+}
+
+std::vector<BatchMesh> batch_descriptors(const subdiv_mesh *m, int n) {
+  std::vector<BatchMesh> d((size_t)n);
+  int vo = 0, fo = 0, ho = 0, co = 0;
+  for (int i = 0; i < n; ++i) {
+    BatchMesh &x = d[i];
+    x.fv = m[i].face_verts;
+    x.off = m[i].face_offsets;
+    x.order = m[i].face_offsets ? 0 : m[i].face_order;
+    x.P = m[i].positions;
+    x.cv = m[i].crease_verts;
+    x.cs = m[i].crease_sharpness;
+    x.V = m[i].num_vertices;
+    x.F = m[i].num_faces;
+    x.H = (int32_t)cage_H(&m[i]);
+    x.C = m[i].num_creases;
+    x.vofs = vo;
+    x.fofs = fo;
+    x.hofs = ho;
+    x.cofs = co;
+    vo += x.V;
+    fo += x.F;
+    ho += x.H;
+    co += x.C;
+  }
+  return d;
+}
+
+subdiv_mesh union_mesh(const BatchLayout &b, void *ws, int n_creases) {
+  subdiv_mesh u{};
+  u.num_vertices = (int32_t)b.VU;
+  u.num_faces = (int32_t)b.FU;
+  u.face_order = b.general ? 0 : b.order;
+  u.num_halfedges = (int32_t)b.HU;
+  u.face_offsets = b.general ? at<int32_t>(ws, b.uoff) : nullptr;
+  u.face_verts = at<int32_t>(ws, b.ufv);
+  u.positions = at<float>(ws, b.uP);
+  u.num_creases = n_creases;
+  u.crease_verts = n_creases ? at<int32_t>(ws, b.ucv) : nullptr;
+  u.crease_sharpness = n_creases ? at<float>(ws, b.ucs) : nullptr;
+  return u;
+}
+
+// Library-owned pinned staging for the per-call pointer tables of a batch:
+// a ring of slots, each reused only after the copy that used it completed.
+struct PinnedRing {
+  struct Slot {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
+  std::mutex mu;
+  Slot slots[8];
+  unsigned next = 0;
+};
+PinnedRing g_ring;
+
+hipError_t staged_upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_ring.mu);
+  PinnedRing::Slot &sl = g_ring.slots[g_ring.next++ % 8];
+  hipError_t err;
+  if (sl.pending && (err = hipEventSynchronize(sl.ev)) != hipSuccess) return err;
+  sl.pending = false;
+  if (sl.cap < bytes) {
+    if (sl.host && (err = hipHostFree(sl.host)) != hipSuccess) return err;
+    sl.host = nullptr;
+    sl.cap = 0;
+    const size_t cap = bytes < 65536 ? 65536 : bytes;
+    if ((err = hipHostMalloc(&sl.host, cap, hipHostMallocDefault)) != hipSuccess) return err;
+    sl.cap = cap;
+  }
+  if (!sl.ev && (err = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess) return err;
+  std::memcpy(sl.host, src, bytes);
+  if ((err = hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return err;
+  if ((err = hipEventRecord(sl.ev, s)) != hipSuccess) return err;
+  sl.pending = true;
+  return hipSuccess;
+}
+
+int check_batch_args(const subdiv_mesh *m, int n, int scheme, int levels) {
+  if (!m || n < 1 || n > SUBDIV_MAX_BATCH) return SUBDIV_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const int st = check_mesh_args(&m[i], scheme, levels);
+    if (st != SUBDIV_OK) return st;
+  }
+  return SUBDIV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags) {
+  if (check_batch_args(meshes, n, scheme, levels) != SUBDIV_OK) return 0;
+  BatchLayout b;
+  if (!batch_layout(meshes, n, scheme, levels, flags, b)) return 0;
+  return b.total;
+}
+
+int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags, void *ws,
+                      size_t ws_bytes, subdiv_batch_plan *bplan, subdiv_plan_info *plans, void *stream) {
+  if (!bplan || !plans || !ws) return SUBDIV_INVALID_ARG;
+  std::memset(bplan, 0, sizeof(*bplan));
+  int st = check_batch_args(meshes, n, scheme, levels);
+  if (st != SUBDIV_OK) return st;
+  if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;
+  BatchLayout b;
+  if (!batch_layout(meshes, n, scheme, levels, flags, b)) return SUBDIV_INVALID_ARG;
+  if (ws_bytes < b.total) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
+  SUBDIV_TRY(staged_upload(at<void>(ws, b.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
+  BatchUnion u{at<int32_t>(ws, b.ufv), b.general ? at<int32_t>(ws, b.uoff) : nullptr, at<int32_t>(ws, b.ucv),
+               at<float>(ws, b.ucs)};
+  long long items = b.HU;
+  items = (b.FU + 1 > items) ? b.FU + 1 : items;
+  items = (b.CU > items) ? b.CU : items;
+  SUBDIV_TRY(batch_concat_topology(at<BatchMesh>(ws, b.desc), n, u, items, s));
+  const subdiv_mesh um = union_mesh(b, ws, (int)b.CU);
+  void *uws = at<void>(ws, b.uws);
+  st = subdiv_plan(&um, scheme, levels, flags, uws, b.uws_bytes, &bplan->union_plan, stream);
+  if (st != SUBDIV_OK) return st;
+  // per-mesh edge and boundary counts of the cage, from the union's build
+  Sizes L0[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, 0, b.VU, b.FU, b.HU, b.HU, b.HU, 0, 0.f, b.CU, L0);
+  const Layout y0 = make_layout(scheme, 0, flags, L0, b.CU);
+  SUBDIV_TRY(batch_stats(at<BatchMesh>(ws, b.desc), n, at<int32_t>(uws, y0.ebase), at<int32_t>(uws, y0.bflag),
+                         bplan->union_plan.level[0].num_edges, at<int32_t>(ws, b.epre), at<int32_t>(ws, b.bcount),
+                         s));
+  std::vector<int32_t> epre((size_t)n + 1), bcount((size_t)n);
+  SUBDIV_TRY(hipMemcpyAsync(epre.data(), at<int32_t>(ws, b.epre), 4 * epre.size(), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipMemcpyAsync(bcount.data(), at<int32_t>(ws, b.bcount), 4 * bcount.size(), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipStreamSynchronize(s));
+  // per-mesh sizes (closed forms) and the prefix tables the gather reads
+  const int n1 = n + 1;
+  std::vector<int32_t> tab((size_t)3 * (levels + 1) * n1, 0);
+  int32_t *vpre = tab.data(), *fpre = vpre + (levels + 1) * n1, *epre_t = fpre + (levels + 1) * n1;
+  for (int i = 0; i < n; ++i) {
+    Sizes Li[SUBDIV_MAX_LEVELS + 1];
+    const int oi = meshes[i].face_offsets ? 0 : meshes[i].face_order;
+    level_sizes(scheme, levels, meshes[i].num_vertices, meshes[i].num_faces, cage_H(&meshes[i]),
+                epre[i + 1] - epre[i], bcount[i], oi, bplan->union_plan.max_sharpness, meshes[i].num_creases, Li);
+    subdiv_plan_info &p = plans[i];
+    std::memset(&p, 0, sizeof(p));
+    p.scheme = scheme;
+    p.levels = levels;
+    p.flags = flags;
+    p.max_sharpness = bplan->union_plan.max_sharpness;
+    for (int k = 0; k <= levels; ++k) {
+      subdiv_level_info &li = p.level[k];
+      li.num_vertices = Li[k].V;
+      li.num_edges = Li[k].E;
+      li.num_faces = Li[k].F;
+      li.num_halfedges = Li[k].H;
+      li.num_boundary_edges = Li[k].B;
+      li.face_order = Li[k].order;
+      vpre[k * n1 + i + 1] = vpre[k * n1 + i] + (int32_t)Li[k].V;
+      fpre[k * n1 + i + 1] = fpre[k * n1 + i] + (int32_t)Li[k].F;
+      epre_t[k * n1 + i + 1] = epre_t[k * n1 + i] + (int32_t)Li[k].E;
+    }
+  }
+  SUBDIV_TRY(hipMemcpyAsync(at<int32_t>(ws, b.tables), tab.data(), 4 * tab.size(), hipMemcpyHostToDevice, s));
+  SUBDIV_TRY(hipStreamSynchronize(s));
+  bplan->num_meshes = n;
+  bplan->scheme = scheme;
+  bplan->levels = levels;
+  bplan->flags = flags;
+  bplan->workspace_bytes = b.total;
+  bplan->priv_ws = ws;
+  static std::atomic<uint64_t> stamp{1};
+  bplan->priv_stamp = stamp++;
+  return SUBDIV_OK;
+}
+
+int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_plan *bplan, subdiv_level_out *outs,
+                        void *ws, size_t ws_bytes, void *stream) {
+  if (!bplan || !outs || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_batch_args(meshes, n, bplan->scheme, bplan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (bplan->priv_stamp == 0 || n != bplan->num_meshes || ws != bplan->priv_ws) return SUBDIV_STATE;
+  if (ws_bytes < bplan->workspace_bytes) return SUBDIV_WORKSPACE;
+  for (int i = 0; i < n; ++i)
+    if (!outs[i].face_verts || !outs[i].positions) return SUBDIV_INVALID_ARG;
+  BatchLayout b;
+  if (!batch_layout(meshes, n, bplan->scheme, bplan->levels, bplan->flags, b)) return SUBDIV_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // pointer tables: the meshes (positions may have moved) and the outputs
+  const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
+  std::vector<BatchOut> ot((size_t)n);
+  for (int i = 0; i < n; ++i) ot[i] = BatchOut{outs[i].face_verts, outs[i].positions};
+  SUBDIV_TRY(staged_upload(at<void>(ws, b.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
+  SUBDIV_TRY(staged_upload(at<void>(ws, b.outtab), ot.data(), sizeof(BatchOut) * ot.size(), s));
+  SUBDIV_TRY(batch_concat_positions(at<BatchMesh>(ws, b.desc), n, at<float>(ws, b.uP), b.VU, s));
+  const subdiv_mesh um = union_mesh(b, ws, (int)b.CU);
+  const int L = bplan->levels;
+  subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
+  uo[L].face_verts = at<int32_t>(ws, b.fvL);
+  uo[L].positions = at<float>(ws, b.PL);
+  st = subdiv_refine(&um, &bplan->union_plan, uo, at<void>(ws, b.uws), b.uws_bytes, stream);
+  if (st != SUBDIV_OK) return st;
+  BatchTables t{};
+  t.n = n;
+  t.L = L;
+  t.order = bplan->scheme == SUBDIV_CATMULL_CLARK ? 4 : 3;
+  t.has_f = bplan->scheme != SUBDIV_LOOP;
+  t.vpre = at<int32_t>(ws, b.tables);
+  t.fpre = t.vpre + (L + 1) * (n + 1);
+  t.epre = t.fpre + (L + 1) * (n + 1);
+  SUBDIV_TIMED("batch_extract", L,
+               batch_extract(t, at<int32_t>(ws, b.fvL), at<float>(ws, b.PL), at<BatchOut>(ws, b.outtab),
+                             bplan->union_plan.level[L].num_faces, bplan->union_plan.level[L].num_vertices, s));
   return SUBDIV_OK;
 }
 

@@ -195,11 +195,12 @@ hipError_t lag_launch(int which, const LagStep &c, hipStream_t s);
 // corner it occupies in its level-m faces (see cc_lag.hip).
 enum { LAG2_GROUP = 0, LAG2_COMBINE = 1, LAG2_OLDER = 2 };
 struct Lag2Step {
-  LagStep s;                 // the parent-level view (no creases)
+  LagStep s;                 // the parent-level view (creases: s.sigk, s.vcrk)
   int32_t Vg, Fg, Eg, VFg;   // grandparent sizes, VFg = Vg + Fg
   const int32_t *vhe_g;      // grandparent adjacency
   const int32_t *twin_g;
   const int32_t *e2h_g;
+  const int32_t *bscan_g;    // grandparent boundary-edge prefix (meshes with boundary)
   float *hs;                 // [2*Eg*3] half rings of the grandparent's edge points
   float *term0;              // [Fm*3] ring term of corner 0 of every level-m face
 };
@@ -216,6 +217,38 @@ struct BwdStep {
   float *coef;       // [V_k*4] scratch: vertex-rule coefficients (a, b, d, flags)
 };
 hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s);
+
+// ---- batches: meshes packed into one disjoint union cage ---------------
+struct BatchMesh {        // one mesh of a batch (device table entry)
+  const int32_t *fv;
+  const int32_t *off;     // nullptr for a uniform face order
+  int32_t order;
+  const float *P;
+  const int32_t *cv;
+  const float *cs;
+  int32_t V, F, H, C;
+  int32_t vofs, fofs, hofs, cofs;  // its first vertex / face / half-edge / crease in the union
+};
+struct BatchUnion {       // the union cage's buffers
+  int32_t *fv;
+  int32_t *off;           // nullptr when the union has a uniform order
+  int32_t *cv;
+  float *cs;
+};
+struct BatchTables {      // per level k = 0..L: prefix sums over the meshes of V, F, E ([(L+1)*(n+1)])
+  int32_t n, L, order, has_f;
+  const int32_t *vpre, *fpre, *epre;
+};
+struct BatchOut {
+  int32_t *fv;
+  float *P;
+};
+hipError_t batch_concat_topology(const BatchMesh *m, int n, const BatchUnion &u, long long items, hipStream_t s);
+hipError_t batch_concat_positions(const BatchMesh *m, int n, float *P, long long V, hipStream_t s);
+hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, long long E,
+                       int32_t *epre, int32_t *bcount, hipStream_t s);
+hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out, long long F,
+                         long long V, hipStream_t s);
 
 // Loop / sqrt(3) level steps (adjacency from a build of the same level).
 struct TriStep {

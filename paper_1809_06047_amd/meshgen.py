@@ -160,44 +160,50 @@ def icosphere(level: int):
 def geodesic_sphere(freq: int):
     """Class-I geodesic sphere: each icosahedron face split into freq^2
     triangles on a barycentric grid, vertices projected to the unit sphere.
-    F = 20 freq^2, V = 10 freq^2 + 2. freq = 2^L reproduces icosphere(L)'s counts."""
+    F = 20 freq^2, V = 10 freq^2 + 2. freq = 2^L reproduces icosphere(L)'s counts.
+
+    A grid point of face (A, B, C) at (i, j) has integer weights (n-i-j, i, j)
+    on those corners; points with equal weights on the 12 corners are one
+    vertex, numbered in order of first appearance (faces in order, i outer,
+    j inner). Its position is the weighted sum of its corners in ascending
+    corner order, normalised."""
     P0, F0 = icosahedron()
     n = int(freq)
     if n < 1:
         raise ValueError("freq must be >= 1")
-    key_to_id = {}
-    pos = []
-
-    def vertex(face, i, j):
-        # barycentric weights (n-i-j, i, j)/n over corners (A, B, C)
-        A, B, C = (int(x) for x in F0[face])
-        w = {}
-        for cid, k in ((A, n - i - j), (B, i), (C, j)):
-            if k:
-                w[cid] = w.get(cid, 0) + k
-        key = tuple(sorted(w.items()))
-        vid = key_to_id.get(key)
-        if vid is None:
-            p = sum(P0[c] * (k / n) for c, k in key)
-            p = p / np.linalg.norm(p)
-            vid = len(pos)
-            key_to_id[key] = vid
-            pos.append(p)
-        return vid
-
-    tris = []
-    for f in range(F0.shape[0]):
-        ids = {}
-        for i in range(n + 1):
-            for j in range(n + 1 - i):
-                ids[(i, j)] = vertex(f, i, j)
-        for i in range(n):
-            for j in range(n - i):
-                tris.append((ids[(i, j)], ids[(i + 1, j)], ids[(i, j + 1)]))
-                if i + j + 1 < n:
-                    tris.append((ids[(i + 1, j)], ids[(i + 1, j + 1)], ids[(i, j + 1)]))
-    P = np.array(pos, dtype=np.float64)
-    F = np.array(tris, dtype=np.int32)
+    I, J = np.array([(i, j) for i in range(n + 1) for j in range(n + 1 - i)], dtype=np.int64).T
+    lp = np.full((n + 2, n + 2), -1, np.int64)
+    lp[I, J] = np.arange(I.size)
+    nf, npt = F0.shape[0], I.size
+    W = np.zeros((nf, npt, 12), np.int64)
+    for f in range(nf):
+        A, B, C = (int(x) for x in F0[f])
+        W[f, :, A] += n - I - J
+        W[f, :, B] += I
+        W[f, :, C] += J
+    uniq, first, inv = np.unique(W.reshape(-1, 12), axis=0, return_index=True, return_inverse=True)
+    order = np.argsort(first, kind="stable")
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    ids = rank[inv.reshape(-1)].reshape(nf, npt)
+    w = uniq[order]
+    corner = np.argsort(w == 0, axis=1, kind="stable")[:, :3]  # nonzero corners first, ascending
+    rows = np.arange(w.shape[0])
+    p = np.zeros((w.shape[0], 3))
+    for k in range(3):
+        c = corner[:, k]
+        wk = w[rows, c]
+        p = np.where((wk > 0)[:, None], p + P0[c] * (wk / n)[:, None], p)
+    P = np.empty_like(p)
+    for r in range(p.shape[0]):
+        P[r] = p[r] / np.linalg.norm(p[r])
+    loc = []
+    for i in range(n):
+        for j in range(n - i):
+            loc.append((lp[i, j], lp[i + 1, j], lp[i, j + 1]))
+            if i + j + 1 < n:
+                loc.append((lp[i + 1, j], lp[i + 1, j + 1], lp[i, j + 1]))
+    F = ids[:, np.array(loc, np.int64)].reshape(-1, 3).astype(np.int32)
     return P, _orient_outward(P, F)
 
 
@@ -214,45 +220,39 @@ def merge_pairs(faces: np.ndarray, n_merges: int, rng: np.random.Generator):
     dropped. Triangle (a,b,c) + triangle (b,a,d) -> quad (a,d,b,c), which keeps
     counter-clockwise order. Returns (offsets, verts) in CSC form."""
     F = faces.shape[0]
-    owner = {}
-    for f in range(F):
-        for s in range(3):
-            owner[(int(faces[f, s]), int(faces[f, (s + 1) % 3]))] = (f, s)
+    nv = int(faces.max()) + 1
+    a = faces.reshape(-1).astype(np.int64)
+    b = np.roll(faces, -1, axis=1).reshape(-1).astype(np.int64)
+    key = a * nv + b                      # directed half-edge a -> b at slot 3f + s
+    srt = np.argsort(key)
     edges = _undirected_edges(faces)
     order = rng.permutation(edges.shape[0])
+    lo, hi = edges[:, 0].astype(np.int64), edges[:, 1].astype(np.int64)
+    h1 = srt[np.searchsorted(key[srt], lo * nv + hi)]  # lo -> hi
+    h2 = srt[np.searchsorted(key[srt], hi * nv + lo)]  # hi -> lo
     merged = np.zeros(F, dtype=bool)
-    quad_of = {}
     dropped = np.zeros(F, dtype=bool)
+    rowsv = np.concatenate([faces, np.full((F, 1), -1, np.int32)], 1)
     done = 0
     for ei in order:
         if done >= n_merges:
             break
-        lo, hi = int(edges[ei, 0]), int(edges[ei, 1])
-        f1, s1 = owner[(lo, hi)]
-        f2, s2 = owner[(hi, lo)]
+        f1, f2 = h1[ei] // 3, h2[ei] // 3
         if merged[f1] or merged[f2]:
             continue
         # f1 holds lo->hi at slot s1: (a=lo, b=hi, c); f2 holds hi->lo: (b, a, d)
-        a, b = lo, hi
-        c = int(faces[f1, (s1 + 2) % 3])
-        d = int(faces[f2, (s2 + 2) % 3])
-        quad = [a, d, b, c]
+        c = faces[f1, (h1[ei] % 3 + 2) % 3]
+        d = faces[f2, (h2[ei] % 3 + 2) % 3]
         keep, drop = (f1, f2) if f1 < f2 else (f2, f1)
-        quad_of[keep] = quad
+        rowsv[keep] = (lo[ei], d, hi[ei], c)
         dropped[drop] = True
         merged[f1] = merged[f2] = True
         done += 1
     if done != n_merges:
         raise RuntimeError(f"only {done} of {n_merges} merges possible")
-    offsets = [0]
-    verts = []
-    for f in range(F):
-        if dropped[f]:
-            continue
-        v = quad_of.get(f, faces[f].tolist())
-        verts.extend(int(x) for x in v)
-        offsets.append(len(verts))
-    return np.array(offsets, dtype=np.int32), np.array(verts, dtype=np.int32)
+    kept = rowsv[~dropped]
+    offsets = np.concatenate([[0], np.cumsum((kept >= 0).sum(1))]).astype(np.int32)
+    return offsets, kept[kept >= 0].astype(np.int32)
 
 
 def cut_holes(faces: np.ndarray, n_remove: int, rng: np.random.Generator) -> np.ndarray:
@@ -427,3 +427,23 @@ def poisson_trace(n_requests: int, qps: float, seed: int):
     scheme = np.where(rng.integers(0, 2, size=n_requests) == 0, "cc", "loop")
     levels = rng.integers(1, 5, size=n_requests)
     return t, faces, scheme, levels
+
+
+_SERVING_BASES = {}
+
+
+def serving_cage(target_faces: float, scheme: str, rng: np.random.Generator, sigma: float = 0.01) -> Mesh:
+    """Request cage of the serving trace. The topology of frequency
+    nu = max(2, round(sqrt(T/20))) -- the geodesic sphere and, for
+    Catmull-Clark, its merged triangle pairs and tagged creases -- is drawn
+    once per (nu, scheme) with the seed 1000 + nu and cached; each request
+    jitters its own copy of the positions by N(0, sigma)."""
+    freq = max(2, int(round(math.sqrt(float(target_faces) / 20.0))))
+    key = (freq, scheme)
+    base = _SERVING_BASES.get(key)
+    if base is None:
+        base = geodesic_cage(20 * freq * freq, scheme, np.random.default_rng(1000 + freq), sigma=0.0)
+        _SERVING_BASES[key] = base
+    return Mesh(positions=_jitter(base.positions, sigma, rng), verts=base.verts, offsets=base.offsets,
+                face_order=base.face_order, crease_verts=base.crease_verts, crease_sharp=base.crease_sharp,
+                name=base.name)

@@ -1,0 +1,72 @@
+"""Parity at the full workload sizes (slow): the 10k-vertex mixed cage to
+Catmull-Clark level 6 (56.6M faces), the 40k-vertex holed triangle cage to
+Loop and sqrt(3) level 5, and the cage-fitting gradient at Catmull-Clark
+level 4. Every output of every level is compared with the FP64 oracle."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_06047_amd import api
+from paper_1809_06047_amd import meshgen as G
+from tests.parity_util import POS_TOL, crease_table, level_edges, normwise_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _full(oracle_mod, mesh, scheme, levels, label):
+    t0 = time.time()
+    ref = oracle_mod.refine(mesh, scheme, levels)
+    print(f"[full] {label}: oracle {time.time() - t0:.1f} s", flush=True)
+    outs, r = api.refine(mesh, scheme, levels, keep="all", creases=True)
+    order = 4 if scheme == "cc" else 3
+    for k in range(1, levels + 1):
+        g = {key: v.cpu().numpy() for key, v in outs[k].items()}
+        o = ref[k]
+        assert np.array_equal(g["face_verts"], o.verts), f"{label} topology level {k}"
+        err = normwise_err(g["positions"], o.positions)
+        print(f"[full] {label} level {k}: F={o.num_faces} V={o.num_vertices} err {err:.2e}", flush=True)
+        assert err <= POS_TOL
+        if "crease_sharpness" in g:
+            sig = crease_table(o, level_edges(o.verts, order))
+            assert np.array_equal(g["crease_sharpness"], sig), f"{label} creases level {k}"
+        del g
+    del outs, r
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_cc_level6_mixed_cage(oracle_mod):
+    _full(oracle_mod, G.cc_cage(), "cc", 6, "cc L6")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
+def test_triangle_cage_level5(oracle_mod, scheme):
+    _full(oracle_mod, G.tri_cage(), scheme, 5, f"{scheme} L5")
+
+
+@pytest.mark.timeout(900)
+def test_cage_fitting_gradient_level4(oracle_mod):
+    """Loss = sum |P_4 - T|^2, T = level 4 of the cage perturbed by N(0, 0.05)
+    (same topology and creases); gradient = 2 R^T (P_4 - T)."""
+    m = G.cc_cage()
+    rng = np.random.default_rng(50)
+    pert = G.Mesh(**{**m.__dict__, "positions": (m.positions + rng.normal(0, 0.05, m.positions.shape)).astype(
+        np.float32)})
+    T = oracle_mod.refine(pert, "cc", 4)[4].positions
+    t0 = time.time()
+    lv = oracle_mod.refine(m, "cc", 4, want_R=True)
+    g = 2.0 * (lv[4].positions - T)
+    for k in range(4, 0, -1):
+        g = lv[k].R.T @ g
+    print(f"[full] gradient oracle {time.time() - t0:.1f} s", flush=True)
+    r = api.differentiable_refiner(m, 4)
+    P0 = torch.from_numpy(m.positions.copy()).cuda().requires_grad_(True)
+    Tg = torch.from_numpy(T.astype(np.float32)).cuda()
+    loss = ((api.SubdivFunction.apply(P0, r) - Tg) ** 2).sum()
+    loss.backward()
+    err = normwise_err(P0.grad.cpu().numpy(), g)
+    print(f"[full] gradient level 4: err {err:.2e}", flush=True)
+    assert err <= 1e-4

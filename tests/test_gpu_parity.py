@@ -52,6 +52,23 @@ def test_cc_mixed_cage_with_creases(oracle_mod):
 
 
 @pytest.mark.parametrize("cage", ["mixed", "holes"])
+def test_cc_creases_alive_on_deep_levels(oracle_mod, cage):
+    """Sharpness up to 7 keeps creases alive past level 3, so the
+    corner-class kernels of levels >= 3 apply the crease rules at interior,
+    boundary, dart, crease and corner vertices."""
+    rng = np.random.default_rng(16)
+    if cage == "mixed":
+        m = G.cc_cage(seed=16, level=2, crease_frac=0.2, smax=7.0)
+    else:
+        m = G.tri_cage(seed=17, level=2, hole_frac=0.05)
+        m.crease_verts, m.crease_sharp = G.tag_creases(m.offsets, m.verts, m.face_order, 90, 7.0, rng)
+    ref = oracle_mod.refine(m, "cc", 4)
+    alive = crease_table(ref[4], level_edges(ref[4].verts, 4))
+    assert (alive > 0).sum() > 0, "the cage must still carry creases at level 4"
+    _compare(m, "cc", 5, oracle_mod, label=f"deep-creases-{cage}")
+
+
+@pytest.mark.parametrize("cage", ["mixed", "holes"])
 def test_cc_rebuild_each_level_matches_carried_adjacency(oracle_mod, cage):
     """The paper's per-level mapped M M^T build (explicit kernels on every
     level) and the closed-form carry-over from the parent level give the same

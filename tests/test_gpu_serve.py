@@ -1,0 +1,56 @@
+"""Serving on the GPU: the continuous-batching server returns, for every
+request, bitwise the final level that a solo plan + refine of its cage gives,
+and the QPS sweep runs end to end on a short trace."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1809_06047_amd import api
+from paper_1809_06047_amd import meshgen as G
+from paper_1809_06047_amd import serve as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _trace(n, seed, tmax=3000.0):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        sc = "cc" if k % 2 == 0 else "loop"
+        T = float(np.exp(rng.uniform(np.log(100.0), np.log(tmax))))
+        reqs.append(S.Request(rid=k, arrival=float(k) * 1e-4, mesh=G.serving_cage(T, sc, rng), scheme=sc,
+                              levels=int(rng.integers(1, 4))))
+    return reqs
+
+
+def test_batched_server_outputs_equal_solo_refinement():
+    reqs = _trace(48, 21)
+    print(f"[serve] 48 requests, faces {[r.mesh.num_faces for r in reqs[:6]]}...", flush=True)
+    srv = S.Server(S.GpuBatchExecutor("cuda", 2), 8 * 2**30, slots=2, max_batch=16, keep_results=True)
+    st = srv.run(reqs)
+    assert st["rejected"] == 0 and st["batches"] < len(reqs)
+    torch.cuda.synchronize()
+    for r in reqs:
+        outs, _ = api.refine(r.mesh, r.scheme, r.levels)
+        solo = outs[r.levels]
+        assert torch.equal(r.result["face_verts"], solo["face_verts"]), r.rid
+        assert torch.equal(r.result["positions"], solo["positions"]), r.rid
+        assert r.final_faces == solo["face_verts"].numel() // (4 if r.scheme == "cc" else 3)
+
+
+def test_per_mesh_baseline_matches_batched():
+    reqs = _trace(12, 22)
+    base = [S.Request(rid=r.rid, arrival=r.arrival, mesh=r.mesh, scheme=r.scheme, levels=r.levels) for r in reqs]
+    S.Server(S.GpuBatchExecutor("cuda", 1), 4 * 2**30, slots=1, keep_results=True).run(reqs)
+    S.serve_per_mesh(base, keep_results=True)
+    for a, b in zip(reqs, base):
+        assert torch.equal(a.result["positions"], b.result["positions"]), a.rid
+        assert torch.equal(a.result["face_verts"], b.result["face_verts"]), a.rid
+
+
+def test_sweep_runs_end_to_end():
+    res = S.sweep(n_requests=32, factors=(1.0,), budget_gib=8.0, sat_requests=16, log=lambda s: print(s, flush=True))
+    (p,) = res["points"]
+    assert res["per_mesh_saturation_qps"] > 0
+    for side in ("batched", "per_mesh"):
+        assert p[side]["served"] == 32 and p[side]["p99_ms"] >= p[side]["p50_ms"] > 0
