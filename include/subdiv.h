@@ -54,7 +54,7 @@ enum {
 
 enum {
   SUBDIV_OK = 0,
-  SUBDIV_INVALID_ARG = -1,  /* null pointer, bad enum/level count, index out of range, size overflow */
+  SUBDIV_INVALID_ARG = -1,  /* null or misaligned pointer, bad enum/level count, index out of range, size overflow */
   SUBDIV_SCHEME_MESH = -2,  /* Loop / sqrt(3) given a face that is not a triangle */
   SUBDIV_NONMANIFOLD = -3,  /* edge with > 2 faces, a directed edge twice, or a vertex whose faces form > 1 fan */
   SUBDIV_DEGENERATE = -4,   /* face order < 3, repeated vertex in a face, or a vertex in no face */
@@ -84,7 +84,7 @@ typedef struct subdiv_mesh {
   int32_t num_halfedges;          /* H = nnz(M); must equal face_offsets[|f|] when face_offsets != NULL,
                                      ignored (= |f|*face_order) otherwise */
   const int32_t *face_offsets;    /* [|f|+1] column pointer of M (starts at 0, non-decreasing), or NULL */
-  const int32_t *face_verts;      /* [H] row indices of M, CCW per face */
+  const int32_t *face_verts;      /* [H] row indices of M, CCW per face; 16-byte aligned */
   const float *positions;         /* [|v|*3] row-major x,y,z */
   int32_t num_creases;            /* crease matrix C as a list (Sec. 3.3); Catmull-Clark only */
   const int32_t *crease_verts;    /* [2*num_creases] end points of crease edges */
@@ -123,7 +123,7 @@ typedef struct subdiv_plan_info {
  * sqrt(3)); positions has level[k].num_vertices*3 floats. Optional buffers
  * may be NULL. */
 typedef struct subdiv_level_out {
-  int32_t *face_verts;       /* [H_k] reduced M of level k (uniform order) */
+  int32_t *face_verts;       /* [H_k] reduced M of level k (uniform order); 16-byte aligned */
   float *positions;          /* [V_k*3] */
   int32_t *edge_verts;       /* optional [2*E_{k-1}]: (lo, hi) of the PARENT level's edges in id order */
   double *crease_sharpness;  /* optional [E_k]: sharpness per edge id of level k (0 = smooth);
@@ -186,6 +186,7 @@ typedef struct subdiv_batch_plan {
   size_t workspace_bytes;      /* the workspace size the batch was planned in */
   const void *priv_ws;         /* private: the planned workspace */
   uint64_t priv_stamp;
+  int32_t priv_gather[4];      /* private: launch sizes of the final gather */
 } subdiv_batch_plan;
 
 #define SUBDIV_MAX_BATCH 65536
@@ -195,8 +196,10 @@ typedef struct subdiv_batch_plan {
 size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags);
 
 /* Packs the n meshes into the union cage inside `ws`, plans it (validation,
- * adjacency, one host wait), and fills plans[i] with the sizes of every level
- * of mesh i (size reports only: they cannot be passed to subdiv_refine). */
+ * adjacency; waits for the stream to read back the union's counts and the
+ * per-mesh edge and boundary counts), and fills plans[i] with the sizes of
+ * every level of mesh i (size reports only: they cannot be passed to
+ * subdiv_refine). A batch of one plans the mesh itself (no union). */
 int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags, void *ws,
                       size_t ws_bytes, subdiv_batch_plan *bplan, subdiv_plan_info *plans, void *stream);
 
@@ -205,7 +208,8 @@ int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, 
  * crease_sharpness are not written). The meshes must be the planned ones
  * (positions may change); `ws` must be the planned workspace. Enqueues work
  * only (the pointer tables go to the device through library-owned pinned
- * host memory). */
+ * host memory). The union's final level is gathered into the outputs in
+ * contiguous segments; a batch of one is refined straight into outs[0]. */
 int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_plan *bplan, subdiv_level_out *outs,
                         void *ws, size_t ws_bytes, void *stream);
 

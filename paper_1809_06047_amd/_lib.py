@@ -54,7 +54,7 @@ class subdiv_stage_time(ctypes.Structure):
 class subdiv_batch_plan(ctypes.Structure):
     _fields_ = [("num_meshes", c_i32), ("scheme", c_i32), ("levels", c_i32), ("flags", c_u32),
                 ("union_plan", subdiv_plan_info), ("workspace_bytes", c_sz), ("priv_ws", c_vp),
-                ("priv_stamp", c_u64)]
+                ("priv_stamp", c_u64), ("priv_gather", c_i32 * 4)]
 
 
 # every function the header declares, with its signature

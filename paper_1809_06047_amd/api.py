@@ -261,11 +261,11 @@ class BatchRefiner:
             s = structs[i]
             s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
             s.face_order = 0 if m.offsets is not None else m.face_order
-            s.face_offsets = 8 if m.offsets is not None else None  # sizes only: never dereferenced
-            s.face_verts = s.positions = 8
+            s.face_offsets = 16 if m.offsets is not None else None  # sizes only: never dereferenced
+            s.face_verts = s.positions = 16
             s.num_creases = m.num_creases
             if m.num_creases:
-                s.crease_verts = s.crease_sharpness = 8
+                s.crease_verts = s.crease_sharpness = 16
         return int(lib.subdiv_batch_workspace_bound(structs, len(meshes), _lib.SCHEMES.get(scheme, scheme), levels,
                                                     flags))
 

@@ -107,49 +107,35 @@ __global__ void k_batch_boundary_counts(const int32_t *epre, int n, const int32_
 }
 
 // ---- gather the union's final level into each mesh's buffers ----------
-// local index of a vertex of the union's level L (see the file header)
-__device__ int local_vertex(const BatchTables &t, int u, int *mesh) {
-  const int n1 = t.n + 1;
-  for (int k = t.L - 1; k >= 0; --k) {
-    const int32_t *vp = t.vpre + k * n1, *fp = t.fpre + k * n1, *ep = t.epre + k * n1;
-    const int UV = vp[t.n], UF = t.has_f ? fp[t.n] : 0;
-    if (u < UV) continue;  // a vertex point keeps the index of its level-k vertex
-    if (u < UV + UF) {
-      const int f = u - UV;
-      const int i = seg_of(fp, n1, f);
-      *mesh = i;
-      return (vp[i + 1] - vp[i]) + (f - fp[i]);
-    }
-    const int e = u - UV - UF;
-    const int i = seg_of(ep, n1, e);
-    *mesh = i;
-    return (vp[i + 1] - vp[i]) + (t.has_f ? fp[i + 1] - fp[i] : 0) + (e - ep[i]);
-  }
-  const int i = seg_of(t.vpre, n1, u);
-  *mesh = i;
-  return u - t.vpre[i];
-}
-
-__global__ void k_extract_faces(BatchTables t, const int32_t *fvL, const BatchOut *out) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n1 = t.n + 1;
-  const int32_t *fpL = t.fpre + t.L * n1;
-  if (f >= fpL[t.n]) return;
-  const int i = seg_of(fpL, n1, f);
-  const int lf = f - fpL[i];
-  int32_t *dst = out[i].fv + (long long)t.order * lf;
-  for (int j = 0; j < t.order; ++j) {
-    int mesh;
-    dst[j] = local_vertex(t, fvL[(long long)t.order * f + j], &mesh);
+// Both gathers give every workgroup one chunk of kGather elements of one
+// segment, found by a binary search over the chunk prefix; inside the chunk
+// the copy is contiguous on both sides.
+// faces: the union faces of mesh i are contiguous; a corner u lies in block
+// b = the last block starting at or below u, and its local id is u + doff(b, i)
+__global__ void __launch_bounds__(kBlock) k_extract_faces(BatchTables t, const int32_t *fvL, const BatchOut *out) {
+  const int c = blockIdx.x;
+  const int i = seg_of(t.fch, t.n, c);
+  const long long f0 = (long long)t.fpre[i] + (long long)(c - t.fch[i]) * kGather;
+  const long long f1 = min(f0 + kGather, (long long)t.fpre[i + 1]);
+  const long long x0 = t.order * f0, x1 = t.order * f1, base = (long long)t.order * t.fpre[i];
+  const int32_t *doff = t.doff + i;
+  int32_t *dst = out[i].fv;
+  for (long long x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+    const int u = fvL[x];
+    dst[x - base] = u + doff[(long long)seg_of(t.ub, t.nblk, u) * t.n];
   }
 }
 
-__global__ void k_extract_positions(BatchTables t, const float *PL, const BatchOut *out) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= t.vpre[t.L * (t.n + 1) + t.n]) return;
-  int i;
-  const int x = local_vertex(t, u, &i);
-  st3(out[i].P, x, ld3(PL, u));
+// positions: segment (block b, mesh i) is one contiguous run on both sides
+__global__ void __launch_bounds__(kBlock) k_extract_positions(BatchTables t, const float *PL, const BatchOut *out) {
+  const int c = blockIdx.x;
+  const int sidx = seg_of(t.pch, t.nseg, c);
+  const int4 g = t.seg[sidx];  // (union start, mesh, local start, length)
+  const long long e0 = (long long)(c - t.pch[sidx]) * kGather;
+  const long long e1 = min(e0 + kGather, (long long)g.w);
+  const float *src = PL + 3ll * (g.x + e0);
+  float *dst = out[g.y].P + 3ll * (g.z + e0);
+  for (long long x = threadIdx.x; x < 3 * (e1 - e0); x += blockDim.x) dst[x] = src[x];
 }
 
 hipError_t batch_concat_topology(const BatchMesh *m, int n, const BatchUnion &u, long long items, hipStream_t s) {
@@ -172,10 +158,12 @@ hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const in
   return hipGetLastError();
 }
 
-hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out, long long F,
-                         long long V, hipStream_t s) {
-  hipLaunchKernelGGL(k_extract_faces, dim3(grid_for(F)), dim3(kBlock), 0, s, t, fvL, out);
-  hipLaunchKernelGGL(k_extract_positions, dim3(grid_for(V)), dim3(kBlock), 0, s, t, PL, out);
+hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out,
+                         int face_chunks, int vertex_chunks, hipStream_t s) {
+  if (face_chunks > 0)
+    hipLaunchKernelGGL(k_extract_faces, dim3(face_chunks), dim3(kBlock), 0, s, t, fvL, out);
+  if (vertex_chunks > 0)
+    hipLaunchKernelGGL(k_extract_positions, dim3(vertex_chunks), dim3(kBlock), 0, s, t, PL, out);
   return hipGetLastError();
 }
 

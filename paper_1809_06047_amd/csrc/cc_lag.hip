@@ -181,8 +181,9 @@ __global__ void __launch_bounds__(kBlock) k_lag_vertex(LagStep c) {
 // -------------------------------------------------------------- edge kernel
 template <int OM>
 __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= c.am.E) return;
+  const int eid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = eid < c.am.E;
+  const int e = valid ? eid : c.am.E - 1;  // every lane takes part in the staged store
   const Topo &tm = c.tm;
   const int Vm = tm.V, VFm = tm.V + tm.F;
   const int Vk = c.Vk, VFk = c.Vk + c.Fk;
@@ -198,14 +199,14 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
   const bool creases = c.sigk != nullptr;
   const int ra = a < bv ? 0 : 1;  // rank of (a, EP) among e's children
   const double sa = creases ? c.sigk[base + ra] : 0.0, sb = creases ? c.sigk[base + 1 - ra] : 0.0;
-  f3 ea, eb, S;
+  f3 ea, eb, S, ec[4];
   int s = -1, tn = -1;
   if (t < 0) {
     ea = mul3(0.5f, add3(pa, pEP));
     eb = mul3(0.5f, add3(pb, pEP));
     // boundary edge point vertex: 3/4 p + 1/8 (a + b)
     S = fma3(0.75f, pEP, mul3(0.125f, add3(pa, pb)));
-    st3(c.P1, VFk + base + 2, mul3(0.25f, add3(add3(pFPp, pEP), add3(fh, fhn))));
+    ec[2] = mul3(0.25f, add3(add3(pFPp, pEP), add3(fh, fhn)));
   } else {
     s = face_of<OM>(c, t);
     tn = he_next<OM>(tm, t);
@@ -215,8 +216,8 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
     eb = mul3(0.25f, add3(add3(pb, pEP), add3(fhn, ft)));
     const f3 ep_p = mul3(0.25f, add3(add3(pFPp, pEP), add3(fh, fhn)));
     const f3 ep_s = mul3(0.25f, add3(add3(pFPs, pEP), add3(ft, ftn)));
-    st3(c.P1, VFk + base + (pf < s ? 2 : 3), ep_p);
-    st3(c.P1, VFk + base + (pf < s ? 3 : 2), ep_s);
+    ec[pf < s ? 2 : 3] = ep_p;
+    ec[pf < s ? 3 : 2] = ep_s;
     // interior edge point vertex: valence 4, neighbours a, b, FP(p), FP(s)
     const f3 nb = add3(add3(pa, pb), add3(pFPp, pFPs));
     const f3 fs = add3(add3(fh, fhn), add3(ft, ftn));
@@ -245,10 +246,37 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
       eb = fma3(1.0f - w, eb, mul3(w * 0.5f, add3(pb, pEP)));
     }
   }
-  st3(c.P1, VFk + base + ra, ea);
-  st3(c.P1, VFk + base + 1 - ra, eb);
-  st3(c.P1, EP, S);
+  ec[ra] = ea;
+  ec[1 - ra] = eb;
   const int nchild = t < 0 ? 3 : 4;
+  {
+    // the children's edge points, VFk + base .. base + nchild - 1, are one
+    // contiguous run over the wave (base(e + 1) = base(e) + nchild(e)): they
+    // leave through LDS as runs of 64 consecutive dwords
+    __shared__ uint32_t stage[kBlock / 64][64 * 12];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    uint32_t *lds = stage[w];
+    const int base0 = __shfl(base, 0, 64);
+    const int end = __shfl(base + nchild, min(63, c.am.E - 1 - (eid - l)), 64);
+    const int off = 3 * (base - base0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < nchild) {
+        lds[off + 3 * r + 0] = __float_as_uint(ec[r].x);
+        lds[off + 3 * r + 1] = __float_as_uint(ec[r].y);
+        lds[off + 3 * r + 2] = __float_as_uint(ec[r].z);
+      }
+    __builtin_amdgcn_wave_barrier();
+    const int count = (eid - l < c.am.E) ? 3 * (end - base0) : 0;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(c.P1 + 3ll * (VFk + base0));
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+      const int g = 64 * t + l;
+      if (g < count) dst[g] = lds[g];
+    }
+  }
+  if (!valid) return;
+  st3(c.P1, EP, S);
   if (c.edges_k) {  // (lo, hi) of level-k edges, in id order
     int2 *o = reinterpret_cast<int2 *>(c.edges_k);
     o[base + ra] = make_int2(a, EP);
@@ -390,44 +418,85 @@ __global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
     kk[i][2] = base[ip] + 2 + (sp >= 0 && sp < p);
     kk[i][3] = base[ip] + (cv[i] > cv[ip]);
   }
-  if (valid) {
-    // face points of the four level-k children of p and the vertex point of FP_m(p)
+  // per-face outputs are contiguous over the wave (face p owns [16 p, 16 p + 16)
+  // of every level-k row array and 12 floats of face points): they leave
+  // through the wave's LDS slice as whole lines
+  __shared__ int4 stage[kBlock / 64][8 * 66];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const long long pw = (long long)blockIdx.x * blockDim.x + (w << 6);  // first face of the wave
+  const int nw = (int)min(64ll, (long long)L.tm.F - pw);               // faces of the wave
+  uint32_t *lds = reinterpret_cast<uint32_t *>(stage[w]);
+  {
+    // face points of the four level-k children of p
+    uint32_t v[12];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) st3(L.P1, Vk + 4 * p + i, f[i]);
+    for (int i = 0; i < 4; ++i) {
+      v[3 * i + 0] = __float_as_uint(f[i].x);
+      v[3 * i + 1] = __float_as_uint(f[i].y);
+      v[3 * i + 2] = __float_as_uint(f[i].z);
+    }
+    wave_store<12>(lds, v, reinterpret_cast<uint32_t *>(L.P1 + 3ll * (Vk + 4 * pw)), l, 12 * nw);
+  }
+  if (L.fvk) {  // level-k face table: corners (v_i, EP(e_i), FP, EP(e_{i-1})) of child i
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[4 * i + 0] = cv[i];
+      v[4 * i + 1] = VFm + e[i];
+      v[4 * i + 2] = FP;
+      v[4 * i + 3] = VFm + e[(i + 3) & 3];
+    }
+    wave_store<16>(lds, v, reinterpret_cast<uint32_t *>(L.fvk) + 16 * pw, l, 16 * nw);
+  }
+  if (L.ak.twin) {  // level-k twins and edge ids
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ip = (i + 3) & 3;
+      const int t = tw[i], tp = tw[ip];
+      const int tn = t < 0 ? -1 : ((t & ~3) | ((t + 1) & 3));
+      v[4 * i + 0] = t < 0 ? -1 : 4 * tn + 3;
+      v[4 * i + 1] = 4 * (4 * p + ((i + 1) & 3)) + 2;
+      v[4 * i + 2] = 4 * (4 * p + ip) + 1;
+      v[4 * i + 3] = tp < 0 ? -1 : 4 * tp;
+    }
+    wave_store<16>(lds, v, reinterpret_cast<uint32_t *>(L.ak.twin) + 16 * pw, l, 16 * nw);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[4 * i + r] = kk[i][r];
+    wave_store<16>(lds, v, reinterpret_cast<uint32_t *>(L.ak.eid) + 16 * pw, l, 16 * nw);
+    if (valid) L.ak.vhe[FP] = 4 * (4 * p) + 2;
+  }
+  if (valid) {
+    // vertex point of FP_m(p)
     const f3 sum = add3(add3(add3(pe[0], pe[1]), add3(pe[2], pe[3])), add3(add3(f[0], f[1]), add3(f[2], f[3])));
     st3(L.P1, FP, fma3(0.5f, pFP, mul3(1.0f / 16.0f, sum)));
-    if (L.fvk) {
-      int4 *o = reinterpret_cast<int4 *>(L.fvk) + 4ll * p;
+  }
+  if (L.fv1) {
+    // the 16 children rows of level k+1 (256 B per face) as int4: the wave
+    // stages 8 rows of its 64 faces at a time and stores them as whole
+    // 128-byte lines (8 faces x 8 rows per instruction). Stride 66 int4 keeps
+    // both the row-wise writes and the face-wise reads conflict-free.
+    int4 *o = reinterpret_cast<int4 *>(L.fv1);
+    const int cc[4][4] = {{cv[0], VFm + e[0], FP, VFm + e[3]},
+                          {cv[1], VFm + e[1], FP, VFm + e[0]},
+                          {cv[2], VFm + e[2], FP, VFm + e[1]},
+                          {cv[3], VFm + e[3], FP, VFm + e[2]}};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = make_int4(cv[i], VFm + e[i], FP, VFm + e[(i + 3) & 3]);
-    }
-    if (L.ak.twin) {
-      int4 *to = reinterpret_cast<int4 *>(L.ak.twin) + 4ll * p;
-      int4 *eo = reinterpret_cast<int4 *>(L.ak.eid) + 4ll * p;
+    for (int hf = 0; hf < 2; ++hf) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ip = (i + 3) & 3;
-        const int t = tw[i], tp = tw[ip];
-        const int tn = t < 0 ? -1 : ((t & ~3) | ((t + 1) & 3));
-        to[i] = make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * (4 * p + ((i + 1) & 3)) + 2, 4 * (4 * p + ip) + 1,
-                          tp < 0 ? -1 : 4 * tp);
-        eo[i] = make_int4(kk[i][0], kk[i][1], kk[i][2], kk[i][3]);
+      for (int x = 0; x < 8; ++x) {
+        const int i = (8 * hf + x) >> 2, r = (8 * hf + x) & 3;
+        stage[w][x * 66 + l] = make_int4(cc[i][r], VFk + kk[i][r], Vk + 4 * p + i, VFk + kk[i][(r + 3) & 3]);
       }
-      L.ak.vhe[FP] = 4 * (4 * p) + 2;
-    }
-    if (L.fv1) {
-      int4 *o = reinterpret_cast<int4 *>(L.fv1) + 16ll * p;
-      const int cc[4][4] = {{cv[0], VFm + e[0], FP, VFm + e[3]},
-                            {cv[1], VFm + e[1], FP, VFm + e[0]},
-                            {cv[2], VFm + e[2], FP, VFm + e[1]},
-                            {cv[3], VFm + e[3], FP, VFm + e[2]}};
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int fq = Vk + 4 * p + i;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          o[4 * i + r] = make_int4(cc[i][r], VFk + kk[i][r], fq, VFk + kk[i][(r + 3) & 3]);
+      for (int t = 0; t < 8; ++t) {
+        const int fl = 8 * t + (l >> 3), x = l & 7;
+        if (fl < nw) o[16 * (pw + fl) + 8 * hf + x] = stage[w][x * 66 + fl];
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   // ring terms of the level-m corners: edge point of the outgoing level-k edge + face point

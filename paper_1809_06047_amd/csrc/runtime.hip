@@ -312,6 +312,7 @@ Topo cage_topo(const subdiv_mesh *m, long long H, void *ws, const Layout &y) {
 
 int check_mesh_args(const subdiv_mesh *m, int scheme, int levels) {
   if (!m || !m->face_verts || !m->positions) return SUBDIV_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(m->face_verts) % 16 != 0) return SUBDIV_INVALID_ARG;  // read as int4 rows
   if (scheme < 0 || scheme > 2 || levels < 1 || levels > SUBDIV_MAX_LEVELS) return SUBDIV_INVALID_ARG;
   if (m->num_vertices < 1 || m->num_faces < 1) return SUBDIV_INVALID_ARG;
   if (!m->face_offsets && m->face_order != 3 && m->face_order != 4) return SUBDIV_INVALID_ARG;
@@ -487,6 +488,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts) return SUBDIV_STATE;
   const int scheme = plan->scheme, levels = plan->levels;
   if (!outs[levels].face_verts || !outs[levels].positions) return SUBDIV_INVALID_ARG;
+  for (int k = 1; k <= levels; ++k)  // face tables are written as int4 rows
+    if (reinterpret_cast<uintptr_t>(outs[k].face_verts) % 16 != 0) return SUBDIV_INVALID_ARG;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
@@ -750,6 +753,11 @@ struct BatchLayout {
   int order;
 };
 
+// blocks of the union's final vertex ids: V_0, then per level F_k and/or E_k
+int gather_blocks(int scheme, int levels) {
+  return 1 + levels * (scheme == SUBDIV_CATMULL_CLARK ? 2 : 1);
+}
+
 bool batch_layout(const subdiv_mesh *m, int n, int scheme, int levels, uint32_t flags, BatchLayout &b) {
   b = BatchLayout{};
   long long VU = 0, FU = 0, HU = 0, CU = 0;
@@ -779,7 +787,8 @@ bool batch_layout(const subdiv_mesh *m, int n, int scheme, int levels, uint32_t 
   if (b.uws_bytes == 0) return false;
   Carver c;
   b.desc = c.take(sizeof(BatchMesh) * (size_t)n);
-  b.tables = c.take(4 * 3 * (size_t)(levels + 1) * (n + 1));
+  const size_t nseg = (size_t)gather_blocks(scheme, levels) * n;
+  b.tables = c.take(16 * nseg + 4 * (nseg + 1 + (size_t)gather_blocks(scheme, levels) + 1 + nseg + 2 * ((size_t)n + 1)));
   b.outtab = c.take(sizeof(BatchOut) * (size_t)n);
   b.epre = c.take(4 * (size_t)(n + 1));
   b.bcount = c.take(4 * (size_t)n);
@@ -905,6 +914,20 @@ int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, 
   if (!batch_layout(meshes, n, scheme, levels, flags, b)) return SUBDIV_INVALID_ARG;
   if (ws_bytes < b.total) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  static std::atomic<uint64_t> stamp{1};
+  if (n == 1) {  // a batch of one is the mesh itself: no union, no gather
+    st = subdiv_plan(&meshes[0], scheme, levels, flags, at<void>(ws, b.uws), b.uws_bytes, &bplan->union_plan, stream);
+    if (st != SUBDIV_OK) return st;
+    plans[0] = bplan->union_plan;
+    bplan->num_meshes = 1;
+    bplan->scheme = scheme;
+    bplan->levels = levels;
+    bplan->flags = flags;
+    bplan->workspace_bytes = b.total;
+    bplan->priv_ws = ws;
+    bplan->priv_stamp = stamp++;
+    return SUBDIV_OK;
+  }
   const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
   SUBDIV_TRY(staged_upload(at<void>(ws, b.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
   BatchUnion u{at<int32_t>(ws, b.ufv), b.general ? at<int32_t>(ws, b.uoff) : nullptr, at<int32_t>(ws, b.ucv),
@@ -928,12 +951,10 @@ int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, 
   SUBDIV_TRY(hipMemcpyAsync(epre.data(), at<int32_t>(ws, b.epre), 4 * epre.size(), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipMemcpyAsync(bcount.data(), at<int32_t>(ws, b.bcount), 4 * bcount.size(), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
-  // per-mesh sizes (closed forms) and the prefix tables the gather reads
-  const int n1 = n + 1;
-  std::vector<int32_t> tab((size_t)3 * (levels + 1) * n1, 0);
-  int32_t *vpre = tab.data(), *fpre = vpre + (levels + 1) * n1, *epre_t = fpre + (levels + 1) * n1;
+  // per-mesh sizes (closed forms)
+  std::vector<Sizes> Lm((size_t)n * (levels + 1));
   for (int i = 0; i < n; ++i) {
-    Sizes Li[SUBDIV_MAX_LEVELS + 1];
+    Sizes *Li = &Lm[(size_t)i * (levels + 1)];
     const int oi = meshes[i].face_offsets ? 0 : meshes[i].face_order;
     level_sizes(scheme, levels, meshes[i].num_vertices, meshes[i].num_faces, cage_H(&meshes[i]),
                 epre[i + 1] - epre[i], bcount[i], oi, bplan->union_plan.max_sharpness, meshes[i].num_creases, Li);
@@ -951,21 +972,59 @@ int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, 
       li.num_halfedges = Li[k].H;
       li.num_boundary_edges = Li[k].B;
       li.face_order = Li[k].order;
-      vpre[k * n1 + i + 1] = vpre[k * n1 + i] + (int32_t)Li[k].V;
-      fpre[k * n1 + i + 1] = fpre[k * n1 + i] + (int32_t)Li[k].F;
-      epre_t[k * n1 + i + 1] = epre_t[k * n1 + i] + (int32_t)Li[k].E;
     }
   }
-  SUBDIV_TRY(hipMemcpyAsync(at<int32_t>(ws, b.tables), tab.data(), 4 * tab.size(), hipMemcpyHostToDevice, s));
-  SUBDIV_TRY(hipStreamSynchronize(s));
+  // the final gather's tables: block b of the union's level-L vertex ids
+  // lists the meshes in order; mesh i numbers its vertices by its segments
+  // of the blocks in block order
+  const bool has_f = scheme != SUBDIV_LOOP, has_e = scheme != SUBDIV_SQRT3;
+  const int nblk = gather_blocks(scheme, levels), nseg = nblk * n;
+  auto bsize = [&](int blk, int i) -> long long {
+    const Sizes *Li = &Lm[(size_t)i * (levels + 1)];
+    if (blk == 0) return Li[0].V;
+    const int k = (blk - 1) / ((int)has_f + (int)has_e), t = (blk - 1) % ((int)has_f + (int)has_e);
+    return (has_f && t == 0) ? Li[k].F : Li[k].E;
+  };
+  std::vector<int32_t> seg(4 * (size_t)nseg), pch((size_t)nseg + 1, 0), ub((size_t)nblk + 1, 0),
+      doff((size_t)nseg), fpre((size_t)n + 1, 0), fch((size_t)n + 1, 0);
+  std::vector<long long> loc((size_t)n, 0);
+  for (int blk = 0; blk < nblk; ++blk) {
+    long long pre = 0;
+    for (int i = 0; i < n; ++i) {
+      const long long len = bsize(blk, i), x = blk * (long long)n + i;
+      seg[4 * x + 0] = (int32_t)(ub[blk] + pre);
+      seg[4 * x + 1] = i;
+      seg[4 * x + 2] = (int32_t)loc[i];
+      seg[4 * x + 3] = (int32_t)len;
+      doff[x] = (int32_t)(loc[i] - ub[blk] - pre);
+      pch[x + 1] = pch[x] + (int32_t)((len + kGather - 1) / kGather);
+      loc[i] += len;
+      pre += len;
+    }
+    ub[blk + 1] = (int32_t)(ub[blk] + pre);
+  }
+  for (int i = 0; i < n; ++i) {
+    const long long FLi = Lm[(size_t)i * (levels + 1) + levels].F;
+    fpre[i + 1] = fpre[i] + (int32_t)FLi;
+    fch[i + 1] = fch[i] + (int32_t)((FLi + kGather - 1) / kGather);
+  }
+  if (ub[nblk] != bplan->union_plan.level[levels].num_vertices ||
+      fpre[n] != bplan->union_plan.level[levels].num_faces)
+    return SUBDIV_STATE;
+  std::vector<int32_t> tab;
+  tab.reserve(seg.size() + pch.size() + ub.size() + doff.size() + fpre.size() + fch.size());
+  for (const auto *v : {&seg, &pch, &ub, &doff, &fpre, &fch}) tab.insert(tab.end(), v->begin(), v->end());
+  SUBDIV_TRY(staged_upload(at<void>(ws, b.tables), tab.data(), 4 * tab.size(), s));
   bplan->num_meshes = n;
   bplan->scheme = scheme;
   bplan->levels = levels;
   bplan->flags = flags;
   bplan->workspace_bytes = b.total;
   bplan->priv_ws = ws;
-  static std::atomic<uint64_t> stamp{1};
   bplan->priv_stamp = stamp++;
+  bplan->priv_gather[0] = fch[n];
+  bplan->priv_gather[1] = pch[nseg];
+  bplan->priv_gather[2] = nblk;
   return SUBDIV_OK;
 }
 
@@ -977,10 +1036,17 @@ int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_pla
   if (bplan->priv_stamp == 0 || n != bplan->num_meshes || ws != bplan->priv_ws) return SUBDIV_STATE;
   if (ws_bytes < bplan->workspace_bytes) return SUBDIV_WORKSPACE;
   for (int i = 0; i < n; ++i)
-    if (!outs[i].face_verts || !outs[i].positions) return SUBDIV_INVALID_ARG;
+    if (!outs[i].face_verts || !outs[i].positions || reinterpret_cast<uintptr_t>(outs[i].face_verts) % 16 != 0)
+      return SUBDIV_INVALID_ARG;
   BatchLayout b;
   if (!batch_layout(meshes, n, bplan->scheme, bplan->levels, bplan->flags, b)) return SUBDIV_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 1) {  // the mesh itself, straight into its outputs
+    subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
+    uo[bplan->levels].face_verts = outs[0].face_verts;
+    uo[bplan->levels].positions = outs[0].positions;
+    return subdiv_refine(&meshes[0], &bplan->union_plan, uo, at<void>(ws, b.uws), b.uws_bytes, stream);
+  }
   // pointer tables: the meshes (positions may have moved) and the outputs
   const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
   std::vector<BatchOut> ot((size_t)n);
@@ -997,15 +1063,19 @@ int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_pla
   if (st != SUBDIV_OK) return st;
   BatchTables t{};
   t.n = n;
-  t.L = L;
   t.order = bplan->scheme == SUBDIV_CATMULL_CLARK ? 4 : 3;
-  t.has_f = bplan->scheme != SUBDIV_LOOP;
-  t.vpre = at<int32_t>(ws, b.tables);
-  t.fpre = t.vpre + (L + 1) * (n + 1);
-  t.epre = t.fpre + (L + 1) * (n + 1);
+  t.nblk = bplan->priv_gather[2];
+  t.nseg = t.nblk * n;
+  const int32_t *tb = at<int32_t>(ws, b.tables);
+  t.seg = reinterpret_cast<const int4 *>(tb);
+  t.pch = tb + 4ll * t.nseg;
+  t.ub = t.pch + t.nseg + 1;
+  t.doff = t.ub + t.nblk + 1;
+  t.fpre = t.doff + t.nseg;
+  t.fch = t.fpre + n + 1;
   SUBDIV_TIMED("batch_extract", L,
                batch_extract(t, at<int32_t>(ws, b.fvL), at<float>(ws, b.PL), at<BatchOut>(ws, b.outtab),
-                             bplan->union_plan.level[L].num_faces, bplan->union_plan.level[L].num_vertices, s));
+                             bplan->priv_gather[0], bplan->priv_gather[1], s));
   return SUBDIV_OK;
 }
 

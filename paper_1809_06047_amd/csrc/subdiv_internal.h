@@ -104,18 +104,28 @@ __device__ __forceinline__ f3 fma3(float s, f3 a, f3 b) { return f3{s * a.x + b.
 
 constexpr int kBlock = 256;
 
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD
-// b % 8), each with its own L2. Remap so that XCD x processes one contiguous
-// 1/8 of the index range: neighbouring faces / vertices / edges (which the
-// hierarchical index order of refined levels keeps spatially close) then
-// share one L2. A bijection on [0, gridDim.x) for any grid size.
-__device__ __forceinline__ int xcd_block() {
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q = nb >> 3, r = nb & 7;
-  const int x = b & 7, i = b >> 3;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+// Coalesced wave stores. A wave whose lane l owns the N dwords
+// dst[l*N .. l*N+N) of one contiguous run dst[0 .. 64 N) would store them as
+// N per-lane pieces spread over the whole run (one small request per lane
+// per instruction). They go through the wave's LDS slice `lds` (64 * (N|1)
+// dwords; the odd stride keeps the lane-wise writes conflict-free) and leave
+// as N instructions that each write 64 consecutive dwords. `count` = dwords
+// of the run that exist (a partial last wave).
+template <int N>
+__device__ __forceinline__ void wave_store(uint32_t *lds, const uint32_t (&v)[N], uint32_t *dst, int lane, int count) {
+  constexpr int S = N | 1;
+#pragma unroll
+  for (int k = 0; k < N; ++k) lds[lane * S + k] = v[k];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const int g = 64 * t + lane, src = g / N;
+    const uint32_t x = lds[src * S + (g - src * N)];
+    if (g < count) dst[g] = x;
+  }
+  __builtin_amdgcn_wave_barrier();
 }
-__device__ __forceinline__ int xcd_index() { return xcd_block() * blockDim.x + threadIdx.x; }
+
 inline unsigned grid_for(long long n, int block = kBlock) {
   long long g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -235,9 +245,20 @@ struct BatchUnion {       // the union cage's buffers
   int32_t *cv;
   float *cs;
 };
-struct BatchTables {      // per level k = 0..L: prefix sums over the meshes of V, F, E ([(L+1)*(n+1)])
-  int32_t n, L, order, has_f;
-  const int32_t *vpre, *fpre, *epre;
+// Gather of the union's final level L into the meshes' own buffers. The
+// union's level-L vertex ids are blocks [V_0 | F_0 | E_0 | F_1 | E_1 | ...]
+// (Catmull-Clark; Loop has no F blocks, sqrt(3) no E blocks), every block
+// listing the meshes in order; mesh i numbers its own level-L vertices by its
+// segments of the same blocks, in the same block order.
+constexpr int kGather = 1024;  // elements per workgroup of the gather kernels
+struct BatchTables {
+  int32_t n, order, nblk, nseg;  // meshes, face order, blocks, segments (nblk * n)
+  const int4 *seg;       // [nseg] (union start, mesh, local start, length), in union order
+  const int32_t *pch;    // [nseg+1] chunk prefix of the segments (kGather vertices per chunk)
+  const int32_t *ub;     // [nblk+1] union start of every block
+  const int32_t *doff;   // [nblk*n] local id - union id inside segment (block b, mesh i)
+  const int32_t *fpre;   // [n+1] union face prefix of level L
+  const int32_t *fch;    // [n+1] chunk prefix of the meshes' faces (kGather faces per chunk)
 };
 struct BatchOut {
   int32_t *fv;
@@ -247,8 +268,8 @@ hipError_t batch_concat_topology(const BatchMesh *m, int n, const BatchUnion &u,
 hipError_t batch_concat_positions(const BatchMesh *m, int n, float *P, long long V, hipStream_t s);
 hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, long long E,
                        int32_t *epre, int32_t *bcount, hipStream_t s);
-hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out, long long F,
-                         long long V, hipStream_t s);
+hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out,
+                         int face_chunks, int vertex_chunks, hipStream_t s);
 
 // Loop / sqrt(3) level steps (adjacency from a build of the same level).
 struct TriStep {

@@ -142,17 +142,20 @@ class Server:
     prepare(req), footprint_fn(reqs, scheme, levels) -> f(k) (bytes of the
     batch reqs[:k], non-decreasing in k, INF when it cannot be planned),
     launch(reqs, scheme, levels, slot) -> handle (may raise ExecutorOOM),
-    done(handle) -> bool, results(handle) -> list of per-request outputs."""
+    done(handle) -> bool, results(handle) -> list of per-request outputs
+    (called only when results are kept), retire(handle) (the batch's memory
+    may be released once the outputs taken from it are dropped)."""
 
     def __init__(self, executor, hbm_budget: int, slots: int = 2, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-                 keep_results: bool = False, idle_wait: float = 50e-6):
+                 keep_results: bool = False, idle_wait: float = 50e-6, max_batch_faces: int = 16 << 20):
         if slots < 1 or max_batch < 1 or hbm_budget <= 0:
             raise ValueError("slots, max_batch and hbm_budget must be positive")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
         self.max_batch = int(max_batch)
+        self.max_batch_faces = int(max_batch_faces)  # larger batches gain nothing: the GPU is busy anyway
         self.clock = clock
         self.sleep = sleep
         self.keep_results = keep_results
@@ -165,6 +168,8 @@ class Server:
         head = queue[0]
         key = (head.scheme, head.levels)
         cands = [r for r in queue if (r.scheme, r.levels) == key][: self._cap]
+        faces = np.cumsum([r.final_faces for r in cands])
+        cands = cands[: max(1, int(np.searchsorted(faces, self.max_batch_faces, side="right")))]
         f = self.ex.footprint_fn(cands, head.scheme, head.levels)
         if f(1) > avail:
             return None, f(1)
@@ -203,10 +208,11 @@ class Server:
             for s, b in enumerate(inflight):
                 if b is not None and self.ex.done(b.handle):
                     t = self.clock() - t0
-                    outs = self.ex.results(b.handle)
+                    outs = self.ex.results(b.handle) if self.keep_results else [None] * len(b.reqs)
+                    self.ex.retire(b.handle)
                     for r, o in zip(b.reqs, outs):
                         r.done = t
-                        r.result = o if self.keep_results else None
+                        r.result = o
                         if self.on_complete is not None:
                             self.on_complete(r)
                     used -= b.nbytes
@@ -282,48 +288,34 @@ def summarize(requests: List[Request], makespan: float) -> Dict:
 # the GPU executor and the per-mesh baseline
 # ---------------------------------------------------------------------------
 
-def _pack_upload(meshes, device):
-    """All cages of a batch in one int32 and one float32 upload; returns
-    DeviceMesh views into them."""
-    import torch
-    from .api import DeviceMesh
-    ints, flts, spans = [], [], []
-    io = fo = 0
-    for m in meshes:
-        parts_i = [np.ascontiguousarray(m.verts, np.int32).reshape(-1)]
-        if m.offsets is not None:
-            parts_i.append(np.ascontiguousarray(m.offsets, np.int32).reshape(-1))
-        if m.num_creases:
-            parts_i.append(np.ascontiguousarray(m.crease_verts, np.int32).reshape(-1))
-        parts_f = [np.ascontiguousarray(m.positions, np.float32).reshape(-1)]
-        if m.num_creases:
-            parts_f.append(np.ascontiguousarray(m.crease_sharp, np.float32).reshape(-1))
-        spans.append((io, [p.size for p in parts_i], fo, [p.size for p in parts_f]))
-        ints += parts_i
-        flts += parts_f
-        io += sum(p.size for p in parts_i)
-        fo += sum(p.size for p in parts_f)
-    di = torch.from_numpy(np.concatenate(ints)).to(device)
-    df = torch.from_numpy(np.concatenate(flts)).to(device)
-    out = []
-    for m, (i0, si, f0, sf) in zip(meshes, spans):
-        k = i0
-        verts = di[k:k + si[0]]
-        k += si[0]
-        offsets = None
-        if m.offsets is not None:
-            offsets = di[k:k + si[1]]
-            k += si[1]
-        cv = di[k:k + 2 * m.num_creases].view(-1, 2) if m.num_creases else None
-        pos = df[f0:f0 + sf[0]].view(-1, 3)
-        cs = df[f0 + sf[0]:f0 + sf[0] + sf[1]] if m.num_creases else None
-        out.append(DeviceMesh.from_tensors(verts, offsets, pos, cv, cs, m.face_order, getattr(m, "name", "")))
-    return out, (di, df)
+def _packed(mesh) -> tuple:
+    """One int32 array holding a cage's face table, column pointer, crease
+    pairs, positions and sharpness (float bits), every part starting on a
+    16-byte boundary; returns (array, part offsets in ints)."""
+    parts = [np.ascontiguousarray(mesh.verts, np.int32).reshape(-1)]
+    parts.append(None if mesh.offsets is None else np.ascontiguousarray(mesh.offsets, np.int32).reshape(-1))
+    parts.append(np.ascontiguousarray(mesh.crease_verts, np.int32).reshape(-1) if mesh.num_creases else None)
+    parts.append(np.ascontiguousarray(mesh.positions, np.float32).reshape(-1).view(np.int32))
+    parts.append(np.ascontiguousarray(mesh.crease_sharp, np.float32).reshape(-1).view(np.int32)
+                 if mesh.num_creases else None)
+    offs, chunks, at = [], [], 0
+    for x in parts:
+        if x is None:
+            offs.append(-1)
+            continue
+        offs.append(at)
+        pad = (-x.size) % 4
+        chunks.append(x)
+        if pad:
+            chunks.append(np.zeros(pad, np.int32))
+        at += x.size + pad
+    return np.concatenate(chunks), offs
 
 
 class GpuBatchExecutor:
     """Runs each batch through the library's batch entry points on its
-    slot's stream (all streams at the default priority)."""
+    slot's stream (all streams at the default priority): one upload of the
+    packed cages, one workspace, one allocation per output kind."""
 
     def __init__(self, device="cuda", slots: int = 2):
         import torch
@@ -336,14 +328,15 @@ class GpuBatchExecutor:
 
     def prepare(self, r: Request):
         m = r.mesh
+        r.meta["packed"] = _packed(m)
         s = self._lib.subdiv_mesh()
         s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
         s.face_order = 0 if m.offsets is not None else m.face_order
-        s.face_offsets = 8 if m.offsets is not None else None  # sizes only: never dereferenced
-        s.face_verts = s.positions = 8
+        s.face_offsets = 16 if m.offsets is not None else None  # sizes only: never dereferenced
+        s.face_verts = s.positions = 16
         s.num_creases = m.num_creases
         if m.num_creases:
-            s.crease_verts = s.crease_sharpness = 8
+            s.crease_verts = s.crease_sharpness = 16
         r.meta["shape"] = s
 
     def footprint_fn(self, reqs, scheme, levels):
@@ -358,26 +351,66 @@ class GpuBatchExecutor:
         return f
 
     def launch(self, reqs, scheme, levels, slot):
-        from .api import BatchRefiner
-        torch = self.torch
+        import ctypes
+        torch, L, lib = self.torch, self._lib, self.lib
         s = self.streams[slot]
+        n = len(reqs)
+        sid = L.SCHEMES[scheme]
         try:
             with torch.cuda.stream(s):
-                dms, keep = _pack_upload([r.mesh for r in reqs], self.device)
-                br = BatchRefiner(dms, scheme, levels, device=self.device)
-                br.plan(stream=s.cuda_stream)
-                outs = br.run(stream=s.cuda_stream)
+                host = np.concatenate([r.meta["packed"][0] for r in reqs])
+                dev = torch.from_numpy(host).to(self.device)
+                base = dev.data_ptr()
+                structs = (L.subdiv_mesh * n)()
+                at = 0
+                for k, r in enumerate(reqs):
+                    arr, offs = r.meta["packed"]
+                    structs[k] = r.meta["shape"]
+                    st = structs[k]  # a view into the array
+                    st.face_verts = base + 4 * (at + offs[0])
+                    st.face_offsets = None if offs[1] < 0 else base + 4 * (at + offs[1])
+                    st.crease_verts = None if offs[2] < 0 else base + 4 * (at + offs[2])
+                    st.positions = base + 4 * (at + offs[3])
+                    st.crease_sharpness = None if offs[4] < 0 else base + 4 * (at + offs[4])
+                    at += arr.size
+                ws_bytes = int(lib.subdiv_batch_workspace_bound(structs, n, sid, levels, 0))
+                if ws_bytes == 0:
+                    raise L.SubdivError(L.INVALID_ARG, "subdiv_batch_workspace_bound")
+                ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+                bplan = L.subdiv_batch_plan()
+                plans = (L.subdiv_plan_info * n)()
+                L.check(lib.subdiv_plan_batch(structs, n, sid, levels, 0, ctypes.c_void_p(ws.data_ptr()), ws_bytes,
+                                              ctypes.byref(bplan), plans, ctypes.c_void_p(s.cuda_stream)),
+                        "subdiv_plan_batch")
+                # outputs: one int32 and one float32 allocation, every face table 16-byte aligned
+                hs = [int(plans[k].level[levels].num_halfedges) for k in range(n)]
+                vs = [int(plans[k].level[levels].num_vertices) for k in range(n)]
+                hofs = np.concatenate([[0], np.cumsum([(h + 3) // 4 * 4 for h in hs])])
+                vofs = np.concatenate([[0], np.cumsum(vs)])
+                fv = torch.empty(int(hofs[-1]), dtype=torch.int32, device=self.device)
+                P = torch.empty((int(vofs[-1]), 3), dtype=torch.float32, device=self.device)
+                outs = (L.subdiv_level_out * n)()
+                for k in range(n):
+                    outs[k].face_verts = fv.data_ptr() + 4 * int(hofs[k])
+                    outs[k].positions = P.data_ptr() + 12 * int(vofs[k])
+                L.check(lib.subdiv_refine_batch(structs, n, ctypes.byref(bplan), outs, ctypes.c_void_p(ws.data_ptr()),
+                                                ws_bytes, ctypes.c_void_p(s.cuda_stream)), "subdiv_refine_batch")
                 ev = torch.cuda.Event()
                 ev.record(s)
         except torch.cuda.OutOfMemoryError as e:
             raise ExecutorOOM(str(e)) from e
-        return (br, keep, outs, ev)
+        return dict(ev=ev, keep=(dev, ws, fv, P), hofs=hofs, hs=hs, vofs=vofs)
 
     def done(self, h) -> bool:
-        return h[3].query()
+        return h["ev"].query()
 
     def results(self, h):
-        return h[2]
+        fv, P = h["keep"][2], h["keep"][3]
+        return [{"face_verts": fv[int(h["hofs"][k]):int(h["hofs"][k]) + h["hs"][k]],
+                 "positions": P[int(h["vofs"][k]):int(h["vofs"][k + 1])]} for k in range(len(h["hs"]))]
+
+    def retire(self, h):
+        h.clear()
 
 
 def serve_per_mesh(requests: List[Request], device="cuda", clock=time.perf_counter, sleep=time.sleep,

@@ -70,3 +70,6 @@ def test_plan_rejects_bad_arguments_without_device(lib):
     assert lib.subdiv_plan(ctypes.byref(m), 5, 1, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
     assert lib.subdiv_plan(ctypes.byref(m), 0, 0, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
     assert lib.subdiv_refine(ctypes.byref(m), ctypes.byref(info), None, None, 0, None) == _lib.INVALID_ARG
+    m.face_verts = 16 + 4  # face tables are read as int4 rows: 16-byte alignment is required
+    assert lib.subdiv_plan(ctypes.byref(m), 0, 1, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
+    assert lib.subdiv_workspace_bound(4, 1, 4, 0, 0, 1, 0) > 0  # sizes alone carry no pointers

@@ -56,9 +56,11 @@ class FakeExecutor:
         return self.clock() >= h["t"]
 
     def results(self, h):
+        return [dict(rid=r.rid, level=self.oracle.refine(r.mesh, r.scheme, r.levels)[-1]) for r in h["reqs"]]
+
+    def retire(self, h):
         self.busy[h["slot"]] = False
         self.inflight_bytes -= h["fp"]
-        return [dict(rid=r.rid, level=self.oracle.refine(r.mesh, r.scheme, r.levels)[-1]) for r in h["reqs"]]
 
 
 def _small_requests(n, seed=0, spacing=1e-3):
@@ -162,6 +164,19 @@ def test_oversized_request_is_rejected_and_others_served(oracle_mod):
     assert reqs[0].error is None and reqs[2].error is None
     s = S.summarize(reqs, st["makespan"])
     assert s["served"] == 2 and s["rejected"] == 1
+
+
+def test_face_cap_splits_batches(oracle_mod):
+    clock = FakeClock()
+    ex = FakeExecutor(clock, oracle_mod, slots=1)
+    m = G.cube()
+    reqs = [S.Request(rid=k, arrival=0.0, mesh=m, scheme="cc", levels=2) for k in range(10)]
+    faces = S.request_bytes(m, "cc", 2)[1]  # 96 faces per request
+    srv = S.Server(ex, 10**9, slots=1, clock=clock, sleep=clock.sleep, max_batch_faces=3 * faces + 1)
+    st = srv.run(reqs)
+    assert st["batch_sizes"] == [3, 3, 3, 1]
+    srv = S.Server(ex, 10**9, slots=1, clock=clock, sleep=clock.sleep, max_batch_faces=1)
+    assert srv.run([S.Request(rid=0, arrival=0.0, mesh=m, scheme="cc", levels=2)])["batch_sizes"] == [1]
 
 
 def test_out_of_memory_halves_the_batch(oracle_mod):
