@@ -39,6 +39,28 @@ HBM_PEAK_GBS = 8000.0
 # Per parent quad (V ~ F, E ~ 2F): 392 + 24 + 144 = 560 B = 35 B per refined face.
 BYTES_PER_UNIT = {"cc_group": ("F", 392), "cc_old_vertex": ("V", 24), "cc_edge_group": ("E", 72)}
 
+# HBM bytes per launch of the dominant kernel from the committed rocprofv3
+# counter passes (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
+# readings); reported only while the kernel sources are the ones measured.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cc_group_L5to6_mixed10k_traffic.json")
+
+
+def measured_traffic(stage, level):
+    import hashlib
+    try:
+        t = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if (t.get("stage"), t.get("level")) != (stage, level):
+        return None
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sources_sha256"]:
+        return None
+    return int(t["fetch_bytes"]) + int(t["write_bytes"])
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -160,7 +182,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dname, dlevel),
             "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_bytes_per_launch": per_unit * units,
         },

@@ -194,10 +194,18 @@ __global__ void k_build_faces(Topo t, int scheme, int32_t *nval, int32_t *hface_
   if (fault) atomicOr(&info->faults, fault);
 }
 
+// The kernels after the validation pass run in the same stream without a
+// host round trip; once any fault is recorded they do nothing (indices of an
+// invalid cage may be out of range), and the plan reports the fault.
+__device__ __forceinline__ bool faulted(const DeviceInfo *info) {
+  return *reinterpret_cast<const volatile uint32_t *>(&info->faults) != 0;
+}
+
 // 3. row view of M: half-edges leaving each vertex
-__global__ void k_build_incidence(Topo t, const int32_t *rowptr, int32_t *cursor, int32_t *inc) {
+__global__ void k_build_incidence(Topo t, const int32_t *rowptr, int32_t *cursor, int32_t *inc,
+                                  const DeviceInfo *info) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= t.H) return;
+  if (h >= t.H || faulted(info)) return;
   const int v = t.fv[h];
   const int pos = atomicAdd(&cursor[v], 1);
   inc[rowptr[v] + pos] = h;
@@ -221,7 +229,7 @@ template <int ORDER>
 __global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int32_t *cand, int32_t *twin,
                                int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= t.V) return;
+  if (v >= t.V || faulted(info)) return;
   const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
   uint32_t fault = 0;
   if (n == 0 || n > SUBDIV_MAX_VALENCE) {
@@ -302,7 +310,7 @@ __global__ void k_build_eid(Topo t, const int32_t *rowptr, const int32_t *inc, c
                             const int32_t *cntlo, const int32_t *ebase, const int32_t *twin, int32_t *eid,
                             int32_t *e2h, int32_t *bflag, DeviceInfo *info) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= t.V) return;
+  if (v >= t.V || faulted(info)) return;
   const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
   const int32_t *c = cand + 2 * r0;
   const int cnt = cntlo[v], base = ebase[v];
@@ -354,7 +362,7 @@ hipError_t build_adjacency(const Topo &t, int scheme, const BuildScratch &b, Adj
   hipError_t err;
   if ((err = launch_scan(b.nval, b.rowptr, t.V, b.partials, nullptr, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_build_incidence, dim3(grid_for(t.H)), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr,
-                     b.cursor, b.inc);
+                     b.cursor, b.inc, (const DeviceInfo *)info);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const unsigned gv = grid_for(t.V);
   if (t.order == 4)
@@ -392,7 +400,7 @@ __global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *in
                                 const int32_t *cv, const float *cs, double *sig, int32_t *sigcnt,
                                 DeviceInfo *info) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= C) return;
+  if (i >= C || faulted(info)) return;
   const int a = cv[2 * i], b = cv[2 * i + 1];
   const float s = cs[i];
   if (a < 0 || a >= t.V || b < 0 || b >= t.V || a == b || !(s >= 0.0f) || isinf(s)) {

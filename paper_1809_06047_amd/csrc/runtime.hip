@@ -431,12 +431,10 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   Topo t = cage_topo(mesh, H0, ws, y0);
   DeviceInfo *dinfo = at<DeviceInfo>(ws, y0.info);
   DeviceInfo hinfo{};
-  // phase A: validate faces and indices, valence
+  // validation of faces and indices, valence; then the adjacency, edge ids
+  // and creases, whose kernels do nothing once a fault is recorded: one
+  // read-back of the counts and faults for the whole build
   SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y0, s));
-  SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  SUBDIV_TRY(hipStreamSynchronize(s));
-  if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
-  // phase B: adjacency, edge ids, creases
   BuildScratch b = scratch0(ws, y0);
   Adj a0 = adj_at(ws, y0.adj0, H0, mesh->num_creases > 0);
   SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, a0, dinfo, s));
