@@ -19,6 +19,8 @@
 //      upper triangle), edge -> half-edge map, boundary flags (E == 1)
 // plus the crease matrix C placed onto edge ids (Sec. 3.3) and the device
 // exclusive scan used by every step.
+#include <climits>
+
 #include "subdiv_internal.h"
 
 namespace subdiv {
@@ -224,21 +226,115 @@ __device__ void sort_small(int32_t *a, int n) {
   }
 }
 
-// 4. per vertex: twins, boundary start, fan check, lower neighbours
+// Batcher's odd-even merge sort of N (a power of two) values held in
+// registers: the loops unroll into a fixed network of min/max pairs.
+template <int N>
+__device__ __forceinline__ void sort_net(int (&a)[N]) {
+#pragma unroll
+  for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i)
+          if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const int x = a[i + j], y = a[i + j + k];
+            a[i + j] = min(x, y);
+            a[i + j + k] = max(x, y);
+          }
+}
+
+constexpr int kRegValence = 8;  // rows up to this valence are handled in registers
+
+// 4. per vertex: twins, boundary start, fan check, lower neighbours.
+// Register path for valence <= kRegValence: the row and the end points of
+// its half-edges are loaded once, side by side, and every search runs on
+// registers.
 template <int ORDER>
-__global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int32_t *cand, int32_t *twin,
-                               int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= t.V || faulted(info)) return;
-  const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
-  uint32_t fault = 0;
-  if (n == 0 || n > SUBDIV_MAX_VALENCE) {
-    atomicOr(&info->faults, n == 0 ? FAULT_DEGENERATE : FAULT_INVALID_ARG);
-    vhe[v] = -1;
-    cntlo[v] = 0;
-    return;
+__device__ void vertex_row_regs(const Topo &t, int v, int r0, int n, int32_t *inc, int32_t *cand, int32_t *twin,
+                                int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
+  constexpr int R = kRegValence;
+  int hh[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) hh[i] = i < n ? inc[r0 + i] : INT_MAX;
+  sort_net<R>(hh);
+  int pv[R], ww[R], uu[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const bool ok = i < n;
+    const int nx = ok ? he_next<ORDER>(t, hh[i]) : 0;
+    pv[i] = ok ? he_prev<ORDER>(t, hh[i]) : 0;
+    ww[i] = ok ? t.fv[nx] : -1;     // h = v -> w
+    uu[i] = ok ? t.fv[pv[i]] : -2;  // prev(h) = u -> v
   }
-  atomicMax(&info->max_valence, n);
+  uint32_t fault = 0;
+  int start = hh[0], start_u = uu[0], nbnd = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i < n) {
+      int tw = -1, hits = 0;
+#pragma unroll
+      for (int m = 0; m < R; ++m)
+        if (uu[m] == ww[i]) {  // prev(row[m]) runs w -> v: the twin of v -> w
+          tw = pv[m];
+          ++hits;
+        }
+      if (hits > 1) fault |= FAULT_NONMANIFOLD;
+#pragma unroll
+      for (int m = 0; m < i; ++m)
+        if (ww[m] == ww[i]) fault |= FAULT_NONMANIFOLD;  // directed edge v->w twice
+      twin[hh[i]] = tw;
+      if (tw < 0) {
+        if (nbnd == 0) {
+          start = hh[i];
+          start_u = uu[i];
+        }
+        ++nbnd;
+      }
+      inc[r0 + i] = hh[i];  // the sorted row
+    }
+  }
+  if (nbnd > 1) fault |= FAULT_NONMANIFOLD;
+  vhe[v] = start;
+  // one fan: from the start, the next half-edge leaves v towards u = prev's source
+  int steps = 0, cu = start_u;
+  for (int it = 0; it < R + 1; ++it) {
+    ++steps;
+    if (steps > n) break;
+    int hn = -1, nu = 0;
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      if (ww[m] == cu) {
+        hn = hh[m];
+        nu = uu[m];
+      }
+    if (hn < 0 || hn == start) break;
+    cu = nu;
+  }
+  if (steps != n) fault |= FAULT_NONMANIFOLD;
+  // lower neighbours (one column of triu(E)), sorted and distinct
+  int c[2 * R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    c[2 * i] = (i < n && ww[i] < v) ? ww[i] : INT_MAX;
+    c[2 * i + 1] = (i < n && uu[i] >= 0 && uu[i] < v) ? uu[i] : INT_MAX;
+  }
+  sort_net<2 * R>(c);
+  int32_t *out = cand + 2 * r0;
+  int d = 0;
+#pragma unroll
+  for (int i = 0; i < 2 * R; ++i)
+    if (c[i] != INT_MAX && (i == 0 || c[i] != c[i - 1])) out[d++] = c[i];
+  cntlo[v] = d;
+  if (fault) atomicOr(&info->faults, fault);
+}
+
+// General path (any valence): the same steps on the row in global memory.
+template <int ORDER>
+__device__ void vertex_row_general(const Topo &t, int v, int r0, int n, int32_t *inc, int32_t *cand, int32_t *twin,
+                                   int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
+  uint32_t fault = 0;
   int32_t *row = inc + r0;
   sort_small(row, n);
   int start = row[0], nbnd = 0;
@@ -292,6 +388,23 @@ __global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int3
     if (i == 0 || c[i] != c[i - 1]) c[d++] = c[i];
   cntlo[v] = d;
   if (fault) atomicOr(&info->faults, fault);
+}
+
+template <int ORDER>
+__global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int32_t *cand, int32_t *twin,
+                               int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= t.V || faulted(info)) return;
+  const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
+  if (n == 0 || n > SUBDIV_MAX_VALENCE) {
+    atomicOr(&info->faults, n == 0 ? FAULT_DEGENERATE : FAULT_INVALID_ARG);
+    vhe[v] = -1;
+    cntlo[v] = 0;
+    return;
+  }
+  atomicMax(&info->max_valence, n);
+  if (n <= kRegValence) vertex_row_regs<ORDER>(t, v, r0, n, inc, cand, twin, vhe, cntlo, info);
+  else vertex_row_general<ORDER>(t, v, r0, n, inc, cand, twin, vhe, cntlo, info);
 }
 
 __device__ __forceinline__ int rank_of(const int32_t *c, int n, int x) {

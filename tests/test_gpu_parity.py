@@ -123,6 +123,31 @@ def test_general_polygon_cages(oracle_mod, n):
     _compare(_prism(n), "cc", 3, oracle_mod, label=f"prism{n}")
 
 
+def _bipyramid(n, closed=True):
+    """Two apexes over an n-gon ring (valence n at the apexes); the open
+    variant keeps only the upper fan, so its apex has valence n and the ring
+    is a boundary."""
+    a = 2 * np.pi * np.arange(n) / n
+    ring = np.stack([np.cos(a), np.sin(a), 0.1 * np.sin(3 * a)], 1)
+    P = np.concatenate([ring, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]]).astype(np.float32)
+    top, bot = n, n + 1
+    faces = [[i, (i + 1) % n, top] for i in range(n)]
+    if closed:
+        faces += [[(i + 1) % n, i, bot] for i in range(n)]
+    else:
+        P = P[:n + 1]
+    return G.Mesh(positions=P, verts=np.array(faces, np.int32).reshape(-1), face_order=3,
+                  name=f"bipyramid{n}" if closed else f"fan{n}")
+
+
+@pytest.mark.parametrize("scheme", ["cc", "loop", "sqrt3"])
+def test_high_valence_vertices(oracle_mod, scheme):
+    """Valence 12 at the apexes takes the general (memory) row path of the
+    cage build; the ring vertices (valence 4 or 3) take the register path."""
+    _compare(_bipyramid(12), scheme, 3, oracle_mod, label=f"bipyramid12-{scheme}")
+    _compare(_bipyramid(12, closed=False), scheme, 3, oracle_mod, label=f"fan12-{scheme}")
+
+
 def test_single_faces(oracle_mod):
     quad = G.Mesh(positions=np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0.5], [0, 1, 0]], np.float32),
                   verts=np.arange(4, dtype=np.int32), face_order=4, name="quad")
