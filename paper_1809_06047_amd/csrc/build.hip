@@ -428,26 +428,68 @@ __global__ void k_build_eid(Topo t, const int32_t *rowptr, const int32_t *inc, c
   const int32_t *c = cand + 2 * r0;
   const int cnt = cntlo[v], base = ebase[v];
   int nb = 0;
-  for (int i = 0; i < n; ++i) {
-    const int h = inc[r0 + i];
-    const int w = t.fv[he_next<ORDER>(t, h)];
-    if (w < v) {
-      const int e = base + rank_of(c, cnt, w);
-      eid[h] = e;
-      const int tw = twin[h];
-      e2h[e] = (tw >= 0 && tw < h) ? tw : h;
-      bflag[e] = tw < 0;
-      nb += tw < 0;
+  if (n <= kRegValence) {
+    // register path: the row, its end points, twins and the lower neighbours
+    // are loaded side by side; ranks are counted on registers
+    constexpr int R = kRegValence;
+    int hh[R], pv[R], ww[R], uu[R], cc[2 * R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const bool ok = i < n;
+      hh[i] = ok ? inc[r0 + i] : 0;
+      pv[i] = ok ? he_prev<ORDER>(t, hh[i]) : 0;
+      ww[i] = ok ? t.fv[he_next<ORDER>(t, hh[i])] : INT_MAX;
+      uu[i] = ok ? t.fv[pv[i]] : INT_MAX;
     }
-    const int hp = he_prev<ORDER>(t, h);
-    const int u = t.fv[hp];
-    if (u < v) {
-      const int e = base + rank_of(c, cnt, u);
-      eid[hp] = e;
-      if (twin[hp] < 0) {  // boundary edge u->v with no half-edge v->u
-        e2h[e] = hp;
-        bflag[e] = 1;
-        ++nb;
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) cc[j] = j < cnt ? c[j] : INT_MAX;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (ww[i] < v) {
+        int rk = 0;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) rk += cc[j] < ww[i];
+        const int e = base + rk, h = hh[i], tw = twin[h];
+        eid[h] = e;
+        e2h[e] = (tw >= 0 && tw < h) ? tw : h;
+        bflag[e] = tw < 0;
+        nb += tw < 0;
+      }
+      if (uu[i] < v) {
+        int rk = 0;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) rk += cc[j] < uu[i];
+        const int e = base + rk, hp = pv[i];
+        eid[hp] = e;
+        if (twin[hp] < 0) {  // boundary edge u->v with no half-edge v->u
+          e2h[e] = hp;
+          bflag[e] = 1;
+          ++nb;
+        }
+      }
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const int h = inc[r0 + i];
+      const int w = t.fv[he_next<ORDER>(t, h)];
+      if (w < v) {
+        const int e = base + rank_of(c, cnt, w);
+        eid[h] = e;
+        const int tw = twin[h];
+        e2h[e] = (tw >= 0 && tw < h) ? tw : h;
+        bflag[e] = tw < 0;
+        nb += tw < 0;
+      }
+      const int hp = he_prev<ORDER>(t, h);
+      const int u = t.fv[hp];
+      if (u < v) {
+        const int e = base + rank_of(c, cnt, u);
+        eid[hp] = e;
+        if (twin[hp] < 0) {  // boundary edge u->v with no half-edge v->u
+          e2h[e] = hp;
+          bflag[e] = 1;
+          ++nb;
+        }
       }
     }
   }
@@ -508,10 +550,11 @@ hipError_t build_bscan(const Topo &t, const BuildScratch &b, Adj &a, hipStream_t
 }
 
 // crease matrix C (Sec. 3.3) placed on edge ids: sig[eid] = sigma
-template <int ORDER>
-__global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *inc, const int32_t *eid, int C,
-                                const int32_t *cv, const float *cs, double *sig, int32_t *sigcnt,
-                                DeviceInfo *info) {
+// the crease matrix C placed onto edge ids: edge (lo, hi) is
+// ebase[hi] + rank of lo among hi's sorted lower neighbours
+__global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *cand, const int32_t *cntlo,
+                                const int32_t *ebase, int C, const int32_t *cv, const float *cs, double *sig,
+                                int32_t *sigcnt, DeviceInfo *info) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= C || faulted(info)) return;
   const int a = cv[2 * i], b = cv[2 * i + 1];
@@ -522,13 +565,9 @@ __global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *in
   }
   if (s == 0.0f) return;  // a smooth edge
   const int hi = a > b ? a : b, lo = a > b ? b : a;
-  int e = -1;
-  for (int r = rowptr[hi]; r < rowptr[hi + 1]; ++r) {
-    const int h = inc[r];
-    if (t.fv[he_next<ORDER>(t, h)] == lo) e = eid[h];
-    const int hp = he_prev<ORDER>(t, h);
-    if (t.fv[hp] == lo) e = eid[hp];
-  }
+  const int32_t *c = cand + 2 * rowptr[hi];
+  const int n = cntlo[hi], r = rank_of(c, n, lo);
+  const int e = (r < n && c[r] == lo) ? ebase[hi] + r : -1;
   if (e < 0 || atomicAdd(&sigcnt[e], 1) != 0) {
     atomicOr(&info->faults, FAULT_BAD_CREASE);
     return;
@@ -540,15 +579,9 @@ __global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *in
 hipError_t build_creases(const Topo &t, const BuildScratch &b, const Adj &a, int C, const int32_t *cv,
                          const float *cs, DeviceInfo *info, hipStream_t s) {
   if (C <= 0) return hipSuccess;
-#define SUBDIV_CR_ARGS                                                                                       \
-  t, (const int32_t *)b.rowptr, (const int32_t *)b.inc, (const int32_t *)a.eid, C, cv, cs, a.sig, b.sigcnt, info
-  if (t.order == 4)
-    hipLaunchKernelGGL(k_build_creases<4>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
-  else if (t.order == 3)
-    hipLaunchKernelGGL(k_build_creases<3>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
-  else
-    hipLaunchKernelGGL(k_build_creases<0>, dim3(grid_for(C)), dim3(kBlock), 0, s, SUBDIV_CR_ARGS);
-#undef SUBDIV_CR_ARGS
+  hipLaunchKernelGGL(k_build_creases, dim3(grid_for(C)), dim3(kBlock), 0, s, t, (const int32_t *)b.rowptr,
+                     (const int32_t *)b.cand, (const int32_t *)b.cntlo, (const int32_t *)b.ebase, C, cv, cs, a.sig,
+                     b.sigcnt, info);
   return hipGetLastError();
 }
 
