@@ -74,6 +74,8 @@ def parse():
                     help="requests of the serving trace (Poisson arrivals; 0 = skip the serving leg)")
     ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2",
                     help="arrival rates as multiples of the per-mesh-launch saturation rate")
+    ap.add_argument("--tri-levels", type=int, default=5,
+                    help="levels of the Loop and sqrt(3) legs on the holed triangle cage (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -189,11 +191,46 @@ def main():
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(stages.items())},
     }
+    if args.tri_levels > 0:
+        out["triangle_schemes"] = {sc: scheme_leg(G.tri_cage(), sc, args.tri_levels, max(3, args.steps // 4))
+                                   for sc in ("loop", "sqrt3")}
     if args.serve_requests > 0:
         out["serving"] = serving(args)
     if args.cpu_levels > 0:
         out["cpu_baseline"] = cpu_baseline(mesh, args.cpu_levels)
     print(json.dumps(out), flush=True)
+
+
+def scheme_leg(mesh, scheme, levels, steps):
+    """Loop / sqrt(3) on the holed triangle cage (icosphere level 6, 2% of the
+    faces removed as vertex-disjoint holes): plan + refine per step, like the
+    main workload; refined faces/s and the per-stage device time."""
+    import torch
+    from paper_1809_06047_amd import _lib, api
+    r = api.Refiner(mesh, scheme, levels)
+    r.plan()
+    r.run()
+    torch.cuda.synchronize()
+    faces = r.level_info(levels)["F"]
+    _lib.timing_enable(True)
+    _lib.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.plan()
+        r.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = _lib.timing_read()
+    _lib.timing_enable(False)
+    ms = (t1 - t0) * 1000.0 / steps
+    per_stage = {}
+    for (name, lvl), (_, tot) in stages.items():
+        per_stage[name] = per_stage.get(name, 0.0) + tot / steps
+    return {"workload": f"{scheme} levels 0->{levels} of the holed triangle cage (F={mesh.num_faces})",
+            "faces_out": faces, "ms_per_step": round(ms, 4), "refined_faces_per_s": round(faces / (ms / 1000.0), 1),
+            "device_ms_per_step": round(sum(per_stage.values()), 4),
+            "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(per_stage.items(), key=lambda kv: -kv[1])}}
 
 
 def serving(args):

@@ -56,7 +56,9 @@ enum {
   SUBDIV_OK = 0,
   SUBDIV_INVALID_ARG = -1,  /* null or misaligned pointer, bad enum/level count, index out of range, size overflow */
   SUBDIV_SCHEME_MESH = -2,  /* Loop / sqrt(3) given a face that is not a triangle */
-  SUBDIV_NONMANIFOLD = -3,  /* edge with > 2 faces, a directed edge twice, or a vertex whose faces form > 1 fan */
+  SUBDIV_NONMANIFOLD = -3,  /* edge with > 2 faces, a directed edge twice, a vertex whose faces form > 1 fan,
+                               or (Loop / sqrt(3), levels > 1) two triangles on the same three vertices, whose
+                               first refined level has edges on four faces */
   SUBDIV_DEGENERATE = -4,   /* face order < 3, repeated vertex in a face, or a vertex in no face */
   SUBDIV_BAD_CREASE = -5,   /* crease end points not an edge, sharpness < 0 or NaN, or an edge tagged twice */
   SUBDIV_WORKSPACE = -6,    /* workspace too small */

@@ -576,6 +576,21 @@ __global__ void k_build_creases(Topo t, const int32_t *rowptr, const int32_t *ca
   atomicMax(&info->max_sharp_bits, __float_as_uint(s));
 }
 
+// Two triangles on the same three vertices with opposite orientations are a
+// closed two-face component; refining it by Loop or sqrt(3) gives a level on
+// which edges are shared by more than two faces.
+__global__ void k_count_pillows(Topo t, const int32_t *twin, DeviceInfo *info) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= t.F || faulted(info)) return;
+  const int a = twin[3 * f], b = twin[3 * f + 1], c = twin[3 * f + 2];
+  if (a >= 0 && b >= 0 && c >= 0 && a / 3 == b / 3 && b / 3 == c / 3) atomicAdd(&info->num_pillows, 1);
+}
+
+hipError_t count_pillows(const Topo &t, const Adj &a, DeviceInfo *info, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_pillows, dim3(grid_for(t.F)), dim3(kBlock), 0, s, t, (const int32_t *)a.twin, info);
+  return hipGetLastError();
+}
+
 hipError_t build_creases(const Topo &t, const BuildScratch &b, const Adj &a, int C, const int32_t *cv,
                          const float *cs, DeviceInfo *info, hipStream_t s) {
   if (C <= 0) return hipSuccess;

@@ -152,6 +152,7 @@ struct Layout {
   // per-level regions
   AdjOffsets slot[3];  // adjacency of levels k-2, k-1, k rotate through these (index level % 3)
   size_t hs, term0;    // half rings / corner-0 terms of the corner-class kernels
+  size_t tbase;        // edge bases of the next level (triangle schemes with carried adjacency)
   size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
@@ -173,6 +174,11 @@ AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool crea
   a.vcr = creases ? c.take(16 * V) : 0;
   return a;
 }
+
+// Levels >= 1 are built from scratch by the generic mapped product when the
+// caller asks for it; otherwise every scheme carries each level's adjacency
+// over in closed form from the level it was refined from.
+bool rebuilds_levels(int, uint32_t flags) { return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0; }
 
 Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long long C0) {
   Layout y{};
@@ -211,11 +217,22 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       mF = L[k].F > mF ? L[k].F : mF;
       cr = cr || L[k].creases;
     }
-    const bool rebuild = scheme != SUBDIV_CATMULL_CLARK || (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL);
-    for (int s = 0; s < (rebuild ? 2 : 3); ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
-    if (!rebuild && levels >= 4) {
+    const bool rebuild = rebuilds_levels(scheme, flags);
+    const bool cc_carry = scheme == SUBDIV_CATMULL_CLARK && !rebuild;
+    for (int s = 0; s < (cc_carry ? 3 : 2); ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
+    if (cc_carry && levels >= 4) {
       y.hs = c.take(24 * mE);
       y.term0 = c.take(12 * mF);
+    }
+    if (!rebuild && scheme != SUBDIV_CATMULL_CLARK) {
+      // edge bases of the carried triangle levels (Loop: one entry per edge,
+      // sqrt(3): per face) of every level that is refined further
+      long long mX = 0;
+      for (int k = 0; k < levels - 1; ++k) {
+        const long long x = scheme == SUBDIV_LOOP ? L[k].E : L[k].F;
+        mX = x > mX ? x : mX;
+      }
+      y.tbase = c.take(4 * (mX + 1));
     }
     if (rebuild) {
       y.bnval = c.take(4 * (mV + 1));
@@ -440,9 +457,13 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, a0, dinfo, s));
   SUBDIV_TIMED("build", 0,
                build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+  const bool pillow_check = scheme != SUBDIV_CATMULL_CLARK && levels >= 2;
+  if (pillow_check) SUBDIV_TIMED("build", 0, count_pillows(t, a0, dinfo, s));
   SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
   if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
+  // a two-face component refined by Loop or sqrt(3) is not manifold after one level
+  if (pillow_check && hinfo.num_pillows > 0) return SUBDIV_NONMANIFOLD;
   float max_sharp;
   std::memcpy(&max_sharp, &hinfo.max_sharp_bits, 4);
   Sizes L[SUBDIV_MAX_LEVELS + 1];
@@ -496,7 +517,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
               plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
               L);
   const Layout y = make_layout(scheme, levels, plan->flags, L, mesh->num_creases);
-  const bool rebuild = scheme != SUBDIV_CATMULL_CLARK || (plan->flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL);
+  const bool rebuild = rebuilds_levels(scheme, plan->flags);
   Topo t = cage_topo(mesh, H0, ws, y);
   DeviceInfo *dinfo = at<DeviceInfo>(ws, y.info);
   const bool cr0 = mesh->num_creases > 0;
@@ -509,7 +530,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     SUBDIV_TIMED("build", 0,
                  build_creases(t, b, full, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
   }
-  if (L[0].B > 0) {
+  if (L[0].B > 0 && scheme != SUBDIV_LOOP) {  // boundary prefix: CC edge-point ids, sqrt(3) kept boundary edges
     BuildScratch b = scratch0(ws, y);
     SUBDIV_TIMED("bscan", 0, build_bscan(t, b, a, s));
   }
@@ -653,7 +674,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       SUBDIV_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(dinfo2), 0, sizeof(DeviceInfo) / 4, s));
       SUBDIV_TIMED("rebuild", k, build_faces(t, scheme, b, dinfo2, s));
       SUBDIV_TIMED("rebuild", k, build_adjacency(t, scheme, b, slot, dinfo2, s));
-      if (L[k].B > 0) SUBDIV_TIMED("bscan", k, build_bscan(t, b, slot, s));
+      if (L[k].B > 0 && scheme == SUBDIV_CATMULL_CLARK) SUBDIV_TIMED("bscan", k, build_bscan(t, b, slot, s));
       a = slot;
     }
     if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, a, outs[k + 1].edge_verts, s));
@@ -683,14 +704,28 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else {
-      TriStep c{t, a, P, fv1, P1};
+      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B};
+      const bool carry = !rebuild && !final;  // level k+1's adjacency in closed form
+      if (carry) {
+        c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, false);
+        c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
+        c.base = at<int32_t>(ws, y.tbase);
+      }
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
+        if (carry)
+          SUBDIV_TIMED("loop_scan", k, launch_scan(c.base, c.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
         SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
+        if (carry) a = c.a1;
       } else {
+        if (carry) {
+          SUBDIV_TIMED("sqrt3_count", k, tri_launch(SQRT3_COUNT, c, s));
+          SUBDIV_TIMED("sqrt3_scan", k, launch_scan(c.base, c.base, t.F, at<int32_t>(ws, y.partials), nullptr, s));
+        }
         SUBDIV_TIMED("sqrt3_face", k, tri_launch(SQRT3_FACE, c, s));
         SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, c, s));
+        if (carry) a = c.a1;
       }
     }
     // level k+1 becomes the input of the next step

@@ -24,7 +24,8 @@ struct DeviceInfo {
   int32_t num_boundary;       // boundary edges
   uint32_t max_sharp_bits;    // float bits of the largest crease sharpness (>= 0 so ordered as uint)
   int32_t max_valence;
-  int32_t pad[11];
+  int32_t num_pillows;        // triangles whose three twins lie in one face (two-face components)
+  int32_t pad[10];
 };
 
 // ---- one level's mesh matrix -------------------------------------------
@@ -159,6 +160,8 @@ hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceI
 // phase B: row view of M, twins, edge ids, edge -> half-edge map, boundary flags
 hipError_t build_adjacency(const Topo &t, int scheme, const BuildScratch &b, Adj &a, DeviceInfo *info,
                            hipStream_t s);
+// counts the triangles of a triangle mesh whose three twins lie in one face
+hipError_t count_pillows(const Topo &t, const Adj &a, DeviceInfo *info, hipStream_t s);
 hipError_t build_creases(const Topo &t, const BuildScratch &b, const Adj &a, int num_creases,
                          const int32_t *crease_verts, const float *crease_sharp, DeviceInfo *info, hipStream_t s);
 // boundary prefix of a built level (needs the DeviceInfo's E on device: passed as E)
@@ -271,15 +274,22 @@ hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const in
 hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out,
                          int face_chunks, int vertex_chunks, hipStream_t s);
 
-// Loop / sqrt(3) level steps (adjacency from a build of the same level).
+// Loop / sqrt(3) level steps. `a` is the adjacency of level k (from the
+// build of the cage, or carried over from the previous step). When level
+// k+1 is refined further, the step also writes level k+1's adjacency in
+// closed form into `a1` (twin, eid, e2h, vhe); `base` holds the edge bases of
+// level k+1's edges grouped by their higher end (counts, then their scan).
 struct TriStep {
   Topo t;
   Adj a;
   const float *P;
   int32_t *fv1;
   float *P1;
+  Adj a1;
+  int32_t *base;
+  int32_t nbnd;  // boundary edges of level k (sqrt(3): they keep ids 0 .. nbnd-1 on level k+1)
 };
-enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4 };
+enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
 hipError_t init_weight_tables();
 

@@ -75,19 +75,43 @@ __device__ __forceinline__ Ring ring3(const Topo &t, const Adj &a, const float *
 }
 
 // ------------------------------------------------------------------ Loop
+// Carried adjacency of the next level (App. B topology: children 4r+j, j<3,
+// = (v_j, E_j, E_{j-1}) and 4r+3 = (E_0, E_1, E_2), E_j = |v| + e_j).
+// Every edge of level k+1 has an edge point E_e as its higher end; its lower
+// neighbours, ascending, are lo(e), hi(e) and the edge points E_e' of the
+// edges e' < e that share a face with e (the set N(e), at most four). So the
+// edges with higher end E_e take ids base(e) .. base(e) + 1 + |{e' in N(e),
+// e' < e}|, base = exclusive scan of those counts over e, and
+//   (lo(e), E_e) -> base(e), (hi(e), E_e) -> base(e) + 1,
+//   (E_a, E_b), a < b -> base(b) + 2 + |{e' in N(b), e' < a}|.
+// N(e) is counted as a set (two faces may share more than one edge).
+__device__ __forceinline__ int lt_new(int x, int bound, int o1, int o2) {
+  return (x < bound && x != o1 && x != o2) ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= c.a.E) return;
   const int h = c.a.e2h[e];
-  const f3 pab = add3(ld3(c.P, c.t.fv[h]), ld3(c.P, c.t.fv[he_next<3>(c.t, h)]));
+  const int hn = he_next<3>(c.t, h), hp = he_prev<3>(c.t, h);
+  const f3 pab = add3(ld3(c.P, c.t.fv[h]), ld3(c.P, c.t.fv[hn]));
   const int t = c.a.twin[h];
   f3 ep;
   if (t < 0) ep = mul3(0.5f, pab);
   else {
-    const f3 pcd = add3(ld3(c.P, c.t.fv[he_prev<3>(c.t, h)]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
+    const f3 pcd = add3(ld3(c.P, c.t.fv[hp]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
     ep = fma3(0.375f, pab, mul3(0.125f, pcd));
   }
   st3(c.P1, c.t.V + e, ep);
+  if (c.base) {  // children of level k+1 with higher end E_e
+    const int n1 = c.a.eid[hn], n2 = c.a.eid[hp];
+    int cnt = 2 + (n1 < e) + (n2 < e);
+    if (t >= 0) {
+      cnt += lt_new(c.a.eid[he_next<3>(c.t, t)], e, n1, n2);
+      cnt += lt_new(c.a.eid[he_prev<3>(c.t, t)], e, n1, n2);
+    }
+    c.base[e] = cnt;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
@@ -104,6 +128,12 @@ __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
     S = fma3(1.0f - (float)n * beta, p, mul3(beta, R.sum));
   }
   st3(c.P1, v, S);
+  // an old vertex's half-edges at level k+1 are the first halves 3 (4r + j)
+  // of its level-k half-edges 3r + j, in the same order
+  if (c.a1.vhe) {
+    const int h0 = c.a.vhe[v];
+    c.a1.vhe[v] = 4 * h0 - h0 % 3;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
@@ -116,9 +146,87 @@ __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
   o[0] = make_int4(v0, e0, e2, v1);
   o[1] = make_int4(e1, e0, v2, e2);
   o[2] = make_int4(e1, e0, e1, e2);
+  if (!c.a1.twin) return;
+  // ---- carried adjacency of level k+1 (see above); h1(q, s) = 3 q + s
+  const int vv[3] = {v0, v1, v2};
+  int ed[3], tw[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    ed[j] = c.a.eid[3 * r + j];
+    tw[j] = c.a.twin[3 * r + j];
+  }
+  int32_t *tw1 = c.a1.twin + 12ll * r, *ei1 = c.a1.eid + 12ll * r;
+  const int q3 = 4 * r + 3;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+    const int t = tw[j], tp = tw[jp];
+    // child j = (v_j, E_j, E_{j-1}): v_j -> E_j is the first half of 3r+j; its
+    // twin E_j -> v_j is the last slot of the child of the face across e_j at v_j
+    tw1[3 * j + 0] = t < 0 ? -1 : 3 * (4 * (t / 3) + (t % 3 + 1) % 3) + 2;
+    tw1[3 * j + 1] = 3 * q3 + jp;                                           // E_j -> E_{j-1}
+    tw1[3 * j + 2] = tp < 0 ? -1 : 3 * (4 * (tp / 3) + tp % 3);           // E_{j-1} -> v_j
+    tw1[9 + j] = 3 * (4 * r + jn) + 1;                                      // centre: E_j -> E_{j+1}
+    ei1[3 * j + 0] = c.base[ed[j]] + (vv[j] > vv[jn]);
+    ei1[3 * j + 2] = c.base[ed[jp]] + (vv[j] > vv[jp]);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    // centre edge (E_{e_m}, E_{e_{m+1}}): child 3 slot m and child m+1 slot 1
+    const int mn = (m + 1) % 3, mo = (m + 2) % 3;
+    const int a = min(ed[m], ed[mn]), b = max(ed[m], ed[mn]), other = ed[mo];
+    const int hb = 3 * r + (ed[m] == b ? m : mn);  // b's half-edge in face r
+    const int tb = c.a.twin[hb];
+    int rank = 2 + (other < a);
+    if (tb >= 0) {
+      rank += lt_new(c.a.eid[he_next<3>(c.t, tb)], a, a, other);
+      rank += lt_new(c.a.eid[he_prev<3>(c.t, tb)], a, a, other);
+    }
+    const int id = c.base[b] + rank;
+    ei1[9 + m] = id;
+    ei1[3 * mn + 1] = id;
+    c.a1.e2h[id] = 3 * (4 * r + mn) + 1;  // the lower of its two half-edges
+  }
+  // edges owned by this face (its half-edge is the lower of the pair): the
+  // halves' owners and the canonical half-edge of the edge point
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int t = tw[j], jn = (j + 1) % 3;
+    if (t >= 0 && t < 3 * r + j) continue;
+    const int b0 = c.base[ed[j]];
+    c.a1.e2h[b0 + (vv[j] > vv[jn])] = 3 * (4 * r + j);          // (v_j, E_j): v_j -> E_j
+    c.a1.e2h[b0 + (vv[jn] > vv[j])] = 3 * (4 * r + jn) + 2;     // (v_{j+1}, E_j): E_j -> v_{j+1}
+    c.a1.vhe[c.t.V + ed[j]] = t < 0 ? 3 * (4 * r + jn) + 2      // boundary: E_j -> v_{j+1} starts the fan
+                                    : min(min(3 * (4 * r + j) + 1, 3 * (4 * r + jn) + 2), 3 * q3 + j);
+  }
 }
 
 // ------------------------------------------------------------------ sqrt(3)
+// Carried adjacency of the next level (App. A topology: child 3r+j =
+// (v_j, X_j, F_r) with X_j = F_s across an interior edge j, else v_{j+1};
+// F_r = |v| + r). The boundary edges (v_j, v_{j+1}) are the only edges of
+// level k+1 whose ends are both old vertices, so they come first in the
+// (hi, lo) order and keep their relative order: ids 0 .. B-1, i.e. the
+// level-k boundary prefix. Every other edge has a face point F_r as its
+// higher end; its lower neighbours, ascending, are the three corners of r
+// and the face points F_s of the neighbours s < r. With base = exclusive
+// scan of 3 + |{neighbours s < r}| over the faces:
+//   (v, F_r) -> B + base(r) + rank of v among r's corners,
+//   (F_x, F_m), x < m -> B + base(m) + 3 + |{neighbours s of m, s < x}|.
+__global__ void __launch_bounds__(kBlock) k_sqrt3_count(TriStep c) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= c.t.F) return;
+  int cnt = 3;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int t = c.a.twin[3 * r + j];
+    cnt += (t >= 0 && t / 3 < r);
+  }
+  c.base[r] = cnt;
+}
+
+__device__ __forceinline__ int rank3(int x, int a, int b) { return (x > a) + (x > b); }
+
 __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= c.t.F) return;
@@ -138,6 +246,61 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
     o[3 * j + 1] = tw[j] < 0 ? v[(j + 1) % 3] : V + tw[j] / 3;
     o[3 * j + 2] = V + r;
   }
+  if (!c.a1.twin) return;
+  // ---- carried adjacency of level k+1 (see above); h1(q, s) = 3 q + s
+  const int B = c.nbnd, br = B + c.base[r];
+  int nb[3];  // neighbour across edge j, -1 on the boundary
+#pragma unroll
+  for (int j = 0; j < 3; ++j) nb[j] = tw[j] < 0 ? -1 : tw[j] / 3;
+  int32_t *tw1 = c.a1.twin + 9ll * r, *ei1 = c.a1.eid + 9ll * r;
+  int vhe_fp = 9 * r + 2;  // F_r -> v_0; F_r is never on the boundary
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+    const int t = tw[j], tp = tw[jp];
+    const int rk_j = rank3(v[j], v[jn], v[jp]), rk_jn = rank3(v[jn], v[j], v[jp]);
+    // slot 2: F_r -> v_j; its twin v_j -> F_r is slot 1 of child j-1 (boundary
+    // edge j-1) or slot 0 of the child at v_j of the face across edge j-1
+    const int t2 = tp < 0 ? 9 * r + 3 * jp + 1 : 9 * (tp / 3) + 3 * (tp % 3);
+    tw1[3 * j + 2] = t2;
+    const int id2 = br + rk_j;
+    ei1[3 * j + 2] = id2;
+    c.a1.e2h[id2] = min(9 * r + 3 * j + 2, t2);
+    if (t < 0) {
+      // boundary edge j kept: v_j -> v_{j+1}, then v_{j+1} -> F_r
+      const int e = c.a.eid[3 * r + j];
+      const int idb = c.a.bscan ? c.a.bscan[e] : e;  // its rank among the boundary edges
+      tw1[3 * j + 0] = -1;
+      ei1[3 * j + 0] = idb;
+      c.a1.e2h[idb] = 9 * r + 3 * j;
+      tw1[3 * j + 1] = 9 * r + 3 * jn + 2;
+      ei1[3 * j + 1] = br + rk_jn;
+    } else {
+      const int s = t / 3, i = t % 3;  // t = s's half-edge v_{j+1} -> v_j
+      // slot 0: v_j -> F_s; twin F_s -> v_j is slot 2 of s's child at v_j
+      tw1[3 * j + 0] = 9 * s + 3 * ((i + 1) % 3) + 2;
+      const int w = c.t.fv[3 * s + (i + 2) % 3];  // the third corner of s
+      ei1[3 * j + 0] = B + c.base[s] + rank3(v[j], v[jn], w);
+      // slot 1: F_s -> F_r, the flipped edge; twin F_r -> F_s is slot 1 of s's child i
+      tw1[3 * j + 1] = 9 * s + 3 * i + 1;
+      int idf;
+      if (s < r) {
+        idf = br + 3 + (nb[0] >= 0 && nb[0] < s) + (nb[1] >= 0 && nb[1] < s) + (nb[2] >= 0 && nb[2] < s);
+        vhe_fp = min(vhe_fp, 9 * s + 3 * i + 1);
+      } else {
+        int k3 = 0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const int u = c.a.twin[3 * s + m];
+          k3 += (u >= 0 && u / 3 < r);
+        }
+        idf = B + c.base[s] + 3 + k3;
+        c.a1.e2h[idf] = 9 * r + 3 * j + 1;  // the lower of its two half-edges
+      }
+      ei1[3 * j + 1] = idf;
+    }
+  }
+  c.a1.vhe[V + r] = vhe_fp;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
@@ -154,6 +317,9 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
     S = fma3(1.0f - alpha, p, mul3(alpha / (float)n, R.sum));
   }
   st3(c.P1, v, S);
+  // an old vertex's half-edges at level k+1 are the first slots 3 (3r + j) of
+  // the children at its level-k half-edges 3r + j, in the same order
+  if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
 }
 
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s) {
@@ -169,6 +335,9 @@ hipError_t tri_launch(int which, const TriStep &c, hipStream_t s) {
       break;
     case SQRT3_FACE:
       hipLaunchKernelGGL(k_sqrt3_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      break;
+    case SQRT3_COUNT:
+      hipLaunchKernelGGL(k_sqrt3_count, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
       break;
     default:
       hipLaunchKernelGGL(k_sqrt3_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);

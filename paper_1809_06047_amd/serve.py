@@ -148,7 +148,7 @@ class Server:
 
     def __init__(self, executor, hbm_budget: int, slots: int = 2, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-                 keep_results: bool = False, idle_wait: float = 50e-6, max_batch_faces: int = 16 << 20):
+                 keep_results: bool = False, spin_window: float = 200e-6, max_batch_faces: int = 16 << 20):
         if slots < 1 or max_batch < 1 or hbm_budget <= 0:
             raise ValueError("slots, max_batch and hbm_budget must be positive")
         self.ex = executor
@@ -159,7 +159,7 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.keep_results = keep_results
-        self.idle_wait = idle_wait
+        self.spin_window = spin_window  # the last part of an idle gap is spent polling, not sleeping
         self.on_complete: Optional[Callable[[Request], None]] = None
         self.stats: Dict = {}
 
@@ -262,10 +262,12 @@ class Server:
                 st["peak_admitted_bytes"] = max(st["peak_admitted_bytes"], used)
                 progressed = True
             if not progressed:
-                wait = self.idle_wait
                 if i < n and not queue and all(b is None for b in inflight):
-                    wait = max(0.0, reqs[i].arrival - (self.clock() - t0))
-                self.sleep(min(wait, 1e-3) if wait > 0 else 0.0)
+                    # idle until the next arrival: sleep most of the gap, then spin
+                    gap = reqs[i].arrival - (self.clock() - t0)
+                    self.sleep(min(gap - self.spin_window, 1e-3) if gap > self.spin_window else 0.0)
+                else:
+                    self.sleep(0.0)  # poll the in-flight batches again right away
         st["makespan"] = self.clock() - t0
         self.stats = st
         return st
@@ -436,8 +438,9 @@ def serve_per_mesh(requests: List[Request], device="cuda", clock=time.perf_count
     reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
     t0 = clock()
     for r in reqs:
-        while clock() - t0 < r.arrival:
-            sleep(min(1e-3, max(0.0, r.arrival - (clock() - t0))))
+        while clock() - t0 < r.arrival:  # same idle policy as the server: sleep, then spin
+            gap = r.arrival - (clock() - t0)
+            sleep(min(gap - 200e-6, 1e-3) if gap > 200e-6 else 0.0)
         r.footprint, r.final_faces = request_bytes(r.mesh, r.scheme, r.levels)
         outs, _ = refine(r.mesh, r.scheme, r.levels, device=device)
         r.done = clock() - t0

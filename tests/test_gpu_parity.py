@@ -90,6 +90,46 @@ def test_cc_rebuild_each_level_matches_carried_adjacency(oracle_mod, cage):
 
 
 @pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
+@pytest.mark.parametrize("cage", ["icosphere", "holes", "fan"])
+def test_triangle_carried_adjacency_matches_rebuild(oracle_mod, cage, scheme):
+    """Loop and sqrt(3) levels carried over in closed form (counts, one scan,
+    twins and ids per face) against the per-level mapped M M^T build:
+    topology, edge enumeration and positions agree bit for bit (the carried
+    ring starts are the canonical ones the build picks)."""
+    m = {"icosphere": lambda: G.tri_cage(seed=18, level=2, hole_frac=0.0),
+         "holes": lambda: G.tri_cage(seed=19, level=2, hole_frac=0.08),
+         "fan": lambda: _bipyramid(12, closed=False)}[cage]()
+    _compare(m, scheme, 4, oracle_mod, label=f"{scheme}-carried-{cage}")
+    a, _ = _gpu(m, scheme, 4)
+    b, _ = _gpu(m, scheme, 4, flags=_lib.FLAG_REBUILD_EACH_LEVEL)
+    for k in range(1, 5):
+        for key in a[k]:
+            np.testing.assert_array_equal(a[k][key], b[k][key], err_msg=f"level {k} {key}")
+
+
+def _pillow():
+    """Two triangles on the same three vertices, opposite orientations: every
+    edge is shared by the same two faces."""
+    P = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    return G.Mesh(positions=P, verts=np.array([0, 1, 2, 0, 2, 1], np.int32), face_order=3, name="pillow")
+
+
+@pytest.mark.parametrize("scheme", ["cc", "loop", "sqrt3"])
+def test_two_faces_sharing_every_edge(oracle_mod, scheme):
+    """A pillow refines under Catmull-Clark at any depth; under Loop and
+    sqrt(3) its first level has edges on four faces, so only one level is
+    valid and the plan rejects deeper refinement as the oracle does."""
+    assert oracle_mod.status_of(_pillow(), scheme) == 0
+    if scheme == "cc":
+        _compare(_pillow(), scheme, 3, oracle_mod, label="pillow-cc")
+        return
+    _compare(_pillow(), scheme, 1, oracle_mod, label=f"pillow-{scheme}")
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.refine(_pillow(), scheme, 2)
+    assert api.plan_status(_pillow(), scheme, levels=2) == _lib.NONMANIFOLD
+
+
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
 def test_triangle_schemes_with_holes(oracle_mod, scheme):
     m = G.tri_cage(seed=13, level=3, hole_frac=0.02)
     _compare(m, scheme, 3, oracle_mod, label="holes")

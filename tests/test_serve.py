@@ -76,7 +76,7 @@ def _small_requests(n, seed=0, spacing=1e-3):
 
 def _server(ex, clock, budget=10**9, slots=2, max_batch=256, keep=True):
     return S.Server(ex, budget, slots=slots, max_batch=max_batch, clock=clock, sleep=clock.sleep,
-                    keep_results=keep, idle_wait=50e-6)
+                    keep_results=keep)
 
 
 def test_every_request_served_with_its_own_result(oracle_mod):
