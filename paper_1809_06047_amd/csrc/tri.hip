@@ -114,9 +114,40 @@ __global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
   }
 }
 
+// Edge-point vertex u = Vg + e of a refined level k: its ring lies in the
+// children of the two level-(k-1) faces of e. Its canonical half-edge
+// (the lowest outgoing one, or the boundary one) sits in the children of the
+// face r owning e and names e's slot j there; r's child rows hold v_j,
+// v_{j+1} and the edge points of r's other edges, the twin of v_j -> E_j
+// names the face s across e, whose centre child holds the other two.
+__device__ __forceinline__ f3 loop_ep_point(const TriStep &c, int u) {
+  const f3 p = ld3(c.P, u);
+  const int h0 = c.a.vhe[u], q = h0 / 3, r = q >> 2, cq = q & 3;
+  const int j = (h0 % 3 == 1) ? cq : (cq + 2) % 3;  // E_j -> E_{j-1} in child j, or E_j -> v_{j+1} in child j+1
+  const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+  const int32_t *rw = c.t.fv + 12ll * r;
+  const f3 pa = ld3(c.P, rw[3 * j]), pb = ld3(c.P, rw[3 * jn]);
+  const int tw = c.a.twin[12 * r + 3 * j];  // twin of v_j -> E_j
+  if (tw < 0) return fma3(0.75f, p, mul3(0.125f, add3(pa, pb)));
+  const f3 n1 = ld3(c.P, rw[9 + jn]), n2 = ld3(c.P, rw[9 + jp]);
+  const int qs = tw / 3, s = qs >> 2, i = ((qs & 3) + 2) % 3;  // e is edge i of s
+  const int32_t *sw = c.t.fv + 12ll * s + 9;
+  const f3 x = ld3(c.P, sw[(i + 1) % 3]), y = ld3(c.P, sw[(i + 2) % 3]);
+  const float beta = c_loop_beta[6];
+  return fma3(1.0f - 6.0f * beta, p, mul3(beta, add3(add3(pa, pb), add3(add3(n1, n2), add3(x, y)))));
+}
+
 __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
+  if (c.Vg > 0 && v >= c.Vg) {  // an edge point of the previous level: no ring walk
+    st3(c.P1, v, loop_ep_point(c, v));
+    if (c.a1.vhe) {
+      const int h0 = c.a.vhe[v];
+      c.a1.vhe[v] = 4 * h0 - h0 % 3;
+    }
+    return;
+  }
   const f3 p = ld3(c.P, v);
   const Ring R = ring3(c.t, c.a, c.P, v);
   f3 S;
@@ -137,15 +168,24 @@ __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= c.t.F) return;
+  // the 12-int rows of every face (children, and when carried their twins
+  // and edge ids) are contiguous over the wave: they leave through LDS
+  __shared__ uint32_t stage[kBlock / 64][64 * 13];
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = rid < c.t.F;
+  const int r = valid ? rid : c.t.F - 1;
+  const int l = threadIdx.x & 63;
+  uint32_t *lds = stage[threadIdx.x >> 6];
+  const long long rw = (long long)rid - l;             // first face of the wave
+  const int cnt = (int)min(64ll, (long long)c.t.F - rw) * 12;
   const int V = c.t.V;
   const int v0 = c.t.fv[3 * r], v1 = c.t.fv[3 * r + 1], v2 = c.t.fv[3 * r + 2];
   const int e0 = V + c.a.eid[3 * r], e1 = V + c.a.eid[3 * r + 1], e2 = V + c.a.eid[3 * r + 2];
-  int4 *o = reinterpret_cast<int4 *>(c.fv1 + 12ll * r);
-  o[0] = make_int4(v0, e0, e2, v1);
-  o[1] = make_int4(e1, e0, v2, e2);
-  o[2] = make_int4(e1, e0, e1, e2);
+  {
+    const uint32_t row[12] = {(uint32_t)v0, (uint32_t)e0, (uint32_t)e2, (uint32_t)v1, (uint32_t)e1, (uint32_t)e0,
+                              (uint32_t)v2, (uint32_t)e2, (uint32_t)e1, (uint32_t)e0, (uint32_t)e1, (uint32_t)e2};
+    wave_store<12>(lds, row, reinterpret_cast<uint32_t *>(c.fv1) + 12 * rw, l, cnt);
+  }
   if (!c.a1.twin) return;
   // ---- carried adjacency of level k+1 (see above); h1(q, s) = 3 q + s
   const int vv[3] = {v0, v1, v2};
@@ -155,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
     ed[j] = c.a.eid[3 * r + j];
     tw[j] = c.a.twin[3 * r + j];
   }
-  int32_t *tw1 = c.a1.twin + 12ll * r, *ei1 = c.a1.eid + 12ll * r;
+  uint32_t tw1[12], ei1[12];
   const int q3 = 4 * r + 3;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -185,8 +225,11 @@ __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
     const int id = c.base[b] + rank;
     ei1[9 + m] = id;
     ei1[3 * mn + 1] = id;
-    c.a1.e2h[id] = 3 * (4 * r + mn) + 1;  // the lower of its two half-edges
+    if (valid) c.a1.e2h[id] = 3 * (4 * r + mn) + 1;  // the lower of its two half-edges
   }
+  wave_store<12>(lds, tw1, reinterpret_cast<uint32_t *>(c.a1.twin) + 12 * rw, l, cnt);
+  wave_store<12>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 12 * rw, l, cnt);
+  if (!valid) return;
   // edges owned by this face (its half-edge is the lower of the pair): the
   // halves' owners and the canonical half-edge of the edge point
 #pragma unroll
@@ -228,8 +271,16 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_count(TriStep c) {
 __device__ __forceinline__ int rank3(int x, int a, int b) { return (x > a) + (x > b); }
 
 __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= c.t.F) return;
+  // the 9-int rows of every face (children, and when carried their twins and
+  // edge ids) are contiguous over the wave: they leave through LDS
+  __shared__ uint32_t stage[kBlock / 64][64 * 9];
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = rid < c.t.F;
+  const int r = valid ? rid : c.t.F - 1;
+  const int l = threadIdx.x & 63;
+  uint32_t *lds = stage[threadIdx.x >> 6];
+  const long long rw = (long long)rid - l;  // first face of the wave
+  const int cnt = (int)min(64ll, (long long)c.t.F - rw) * 9;
   const int V = c.t.V;
   int v[3], tw[3];
 #pragma unroll
@@ -237,14 +288,19 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
     v[j] = c.t.fv[3 * r + j];
     tw[j] = c.a.twin[3 * r + j];
   }
-  const f3 sum = add3(add3(ld3(c.P, v[0]), ld3(c.P, v[1])), ld3(c.P, v[2]));
-  st3(c.P1, V + r, mul3(1.0f / 3.0f, sum));
-  int *o = c.fv1 + 9ll * r;
+  if (valid) {
+    const f3 sum = add3(add3(ld3(c.P, v[0]), ld3(c.P, v[1])), ld3(c.P, v[2]));
+    st3(c.P1, V + r, mul3(1.0f / 3.0f, sum));
+  }
+  {
+    uint32_t row[9];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    o[3 * j + 0] = v[j];
-    o[3 * j + 1] = tw[j] < 0 ? v[(j + 1) % 3] : V + tw[j] / 3;
-    o[3 * j + 2] = V + r;
+    for (int j = 0; j < 3; ++j) {
+      row[3 * j + 0] = v[j];
+      row[3 * j + 1] = tw[j] < 0 ? v[(j + 1) % 3] : V + tw[j] / 3;
+      row[3 * j + 2] = V + r;
+    }
+    wave_store<9>(lds, row, reinterpret_cast<uint32_t *>(c.fv1) + 9 * rw, l, cnt);
   }
   if (!c.a1.twin) return;
   // ---- carried adjacency of level k+1 (see above); h1(q, s) = 3 q + s
@@ -252,7 +308,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
   int nb[3];  // neighbour across edge j, -1 on the boundary
 #pragma unroll
   for (int j = 0; j < 3; ++j) nb[j] = tw[j] < 0 ? -1 : tw[j] / 3;
-  int32_t *tw1 = c.a1.twin + 9ll * r, *ei1 = c.a1.eid + 9ll * r;
+  uint32_t tw1[9], ei1[9];
   int vhe_fp = 9 * r + 2;  // F_r -> v_0; F_r is never on the boundary
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -265,14 +321,14 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
     tw1[3 * j + 2] = t2;
     const int id2 = br + rk_j;
     ei1[3 * j + 2] = id2;
-    c.a1.e2h[id2] = min(9 * r + 3 * j + 2, t2);
+    if (valid) c.a1.e2h[id2] = min(9 * r + 3 * j + 2, t2);
     if (t < 0) {
       // boundary edge j kept: v_j -> v_{j+1}, then v_{j+1} -> F_r
       const int e = c.a.eid[3 * r + j];
       const int idb = c.a.bscan ? c.a.bscan[e] : e;  // its rank among the boundary edges
       tw1[3 * j + 0] = -1;
       ei1[3 * j + 0] = idb;
-      c.a1.e2h[idb] = 9 * r + 3 * j;
+      if (valid) c.a1.e2h[idb] = 9 * r + 3 * j;
       tw1[3 * j + 1] = 9 * r + 3 * jn + 2;
       ei1[3 * j + 1] = br + rk_jn;
     } else {
@@ -295,17 +351,41 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
           k3 += (u >= 0 && u / 3 < r);
         }
         idf = B + c.base[s] + 3 + k3;
-        c.a1.e2h[idf] = 9 * r + 3 * j + 1;  // the lower of its two half-edges
+        if (valid) c.a1.e2h[idf] = 9 * r + 3 * j + 1;  // the lower of its two half-edges
       }
       ei1[3 * j + 1] = idf;
     }
   }
-  c.a1.vhe[V + r] = vhe_fp;
+  wave_store<9>(lds, tw1, reinterpret_cast<uint32_t *>(c.a1.twin) + 9 * rw, l, cnt);
+  wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
+  if (valid) c.a1.vhe[V + r] = vhe_fp;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
+  if (c.Vg > 0 && v >= c.Vg) {
+    // face point F_r of the previous level: never on the boundary; its ring is
+    // r's corners and the face points across r's interior edges, all in the
+    // rows of r's three children (v_j, X_j, F_r)
+    const int r = v - c.Vg;
+    const int32_t *rw = c.t.fv + 9ll * r;
+    const f3 p = ld3(c.P, v);
+    f3 sum = add3(add3(ld3(c.P, rw[0]), ld3(c.P, rw[3])), ld3(c.P, rw[6]));
+    int n = 3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int x = rw[3 * j + 1];
+      if (x >= c.Vg) {
+        sum = add3(sum, ld3(c.P, x));
+        ++n;
+      }
+    }
+    const float alpha = c_sqrt3_alpha[n];
+    st3(c.P1, v, fma3(1.0f - alpha, p, mul3(alpha / (float)n, sum)));
+    if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
+    return;
+  }
   const f3 p = ld3(c.P, v);
   const Ring R = ring3(c.t, c.a, c.P, v);
   f3 S;
