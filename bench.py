@@ -70,9 +70,9 @@ def parse():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-levels", type=int, default=5, help="levels of the oracle sample (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=512,
+    ap.add_argument("--serve-requests", type=int, default=1024,
                     help="requests of the serving trace (Poisson arrivals; 0 = skip the serving leg)")
-    ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2",
+    ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2,1.5,2,3",
                     help="arrival rates as multiples of the per-mesh-launch saturation rate")
     ap.add_argument("--tri-levels", type=int, default=5,
                     help="levels of the Loop and sqrt(3) legs on the holed triangle cage (0 = skip)")

@@ -146,7 +146,7 @@ class Server:
     (called only when results are kept), retire(handle) (the batch's memory
     may be released once the outputs taken from it are dropped)."""
 
-    def __init__(self, executor, hbm_budget: int, slots: int = 2, max_batch: int = 256,
+    def __init__(self, executor, hbm_budget: int, slots: int = 1, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
                  keep_results: bool = False, spin_window: float = 200e-6, max_batch_faces: int = 16 << 20):
         if slots < 1 or max_batch < 1 or hbm_budget <= 0:
@@ -331,7 +331,7 @@ class GpuBatchExecutor:
     slot's stream (all streams at the default priority): one upload of the
     packed cages, one workspace, one allocation per output kind."""
 
-    def __init__(self, device="cuda", slots: int = 2, reserve_bytes: int = 0):
+    def __init__(self, device="cuda", slots: int = 1, reserve_bytes: int = 0):
         import torch
         from . import _lib
         self.torch = torch
@@ -472,8 +472,8 @@ def _retime(reqs: List[Request], base_times: np.ndarray, qps: float) -> List[Req
             for r, t in zip(reqs, base_times)]
 
 
-def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2), seed: int = 4, budget_gib: float = 64.0,
-          slots: int = 2, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
+def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), seed: int = 4, budget_gib: float = 64.0,
+          slots: int = 1, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
           log=print) -> Dict:
     """Measure the per-mesh-launch saturation rate, then serve the trace at
     each factor x that rate with the batched server and the baseline."""
@@ -524,10 +524,11 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2), seed: int = 4, b
 def main(argv=None):
     ap = argparse.ArgumentParser(description="continuous-batching refinement server: QPS sweep")
     ap.add_argument("--requests", type=int, default=4096)
-    ap.add_argument("--factors", default="0.5,0.8,1.0,1.2")
+    ap.add_argument("--factors", default="0.5,0.8,1.0,1.2,1.5,2,3")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=64.0)
-    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--slots", type=int, default=1,
+                    help="batches in flight at once (one: a second concurrent batch only slows the first)")
     ap.add_argument("--max-batch", type=int, default=256)
     a = ap.parse_args(argv)
     res = sweep(a.requests, tuple(float(x) for x in a.factors.split(",")), a.seed, a.budget_gib, a.slots,
