@@ -222,11 +222,14 @@ int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_pla
  * events, writes up to max_out entries aggregated by (stage, level) and
  * clears the records; it returns the number of entries written, or a
  * negative status. Stage names: "build" (cage adjacency), "rebuild" (per-level
- * generic build), "bscan", "cc_face", "cc_vertex", "cc_edge" (a level refined
- * from its own adjacency), "cc_group", "cc_old_vertex", "cc_edge_group" (a
- * Catmull-Clark level refined from its parent level's adjacency, one thread
- * per parent face / vertex / edge), "loop_edge", "loop_vertex", "loop_face",
- * "sqrt3_face", "sqrt3_vertex", "edge_export"; level = the level refined. */
+ * generic build), "bscan" (boundary prefix), "cc_face", "cc_vertex",
+ * "cc_edge" (a level refined from its own adjacency), "cc_group",
+ * "cc_old_vertex", "cc_ep_vertex", "cc_edge_group" (a Catmull-Clark level
+ * refined from its parent level's adjacency, one thread per parent face /
+ * vertex / edge), "loop_edge", "loop_scan", "loop_vertex", "loop_face",
+ * "sqrt3_count", "sqrt3_scan", "sqrt3_face", "sqrt3_vertex" (the scans give
+ * the next level's edge ids), "bw_coef", "bw_face", "bw_vertex" (adjoint),
+ * "batch_extract", "edge_export"; level = the level refined. */
 typedef struct subdiv_stage_time {
   char name[24];
   int32_t level;
