@@ -74,6 +74,8 @@ def parse():
                     help="requests of the serving trace (Poisson arrivals; 0 = skip the serving leg)")
     ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2,1.5,2,3",
                     help="arrival rates as multiples of the per-mesh-launch saturation rate")
+    ap.add_argument("--adjoint-levels", type=int, default=4,
+                    help="levels of the adjoint leg on the same cage (0 = skip)")
     ap.add_argument("--tri-levels", type=int, default=5,
                     help="levels of the Loop and sqrt(3) legs on the holed triangle cage (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -191,6 +193,8 @@ def main():
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(stages.items())},
     }
+    if args.adjoint_levels > 0:
+        out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
         out["triangle_schemes"] = {sc: scheme_leg(G.tri_cage(), sc, args.tri_levels, max(3, args.steps // 4))
                                    for sc in ("loop", "sqrt3")}
@@ -199,6 +203,16 @@ def main():
     if args.cpu_levels > 0:
         out["cpu_baseline"] = cpu_baseline(mesh, args.cpu_levels)
     print(json.dumps(out), flush=True)
+
+
+# algorithmic bytes of the triangle-scheme kernels of one level (no adjacency
+# carried, as on the last level): face kernels read the face's vertex and edge
+# (Loop) or twin (sqrt(3)) rows and write the children (Loop 4 x 12 B, sqrt(3)
+# 3 x 12 B) plus, for sqrt(3), the face point; the edge kernel reads its
+# half-edge and writes the edge point; the vertex kernel reads and writes one
+# position (positions are read once per level, counted here).
+TRI_BYTES_PER_UNIT = {"loop_face": ("F", 72), "loop_edge": ("E", 16), "loop_vertex": ("V", 24),
+                      "sqrt3_face": ("F", 72), "sqrt3_vertex": ("V", 24)}
 
 
 def scheme_leg(mesh, scheme, levels, steps):
@@ -227,10 +241,61 @@ def scheme_leg(mesh, scheme, levels, steps):
     per_stage = {}
     for (name, lvl), (_, tot) in stages.items():
         per_stage[name] = per_stage.get(name, 0.0) + tot / steps
+    last = levels - 1  # the last step: level L-1 -> L
+    roof = {}
+    for (name, lvl), (n, tot) in stages.items():
+        if lvl != last or name not in TRI_BYTES_PER_UNIT:
+            continue
+        unit, per_unit = TRI_BYTES_PER_UNIT[name]
+        nbytes = per_unit * r.level_info(last)[unit]
+        avg = tot / n
+        gbs = nbytes / (avg / 1000.0) / 1e9
+        roof[name] = {"avg_launch_ms": round(avg, 5), "algorithmic_bytes_per_launch": nbytes,
+                      "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return {"workload": f"{scheme} levels 0->{levels} of the holed triangle cage (F={mesh.num_faces})",
             "faces_out": faces, "ms_per_step": round(ms, 4), "refined_faces_per_s": round(faces / (ms / 1000.0), 1),
             "device_ms_per_step": round(sum(per_stage.values()), 4),
-            "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(per_stage.items(), key=lambda kv: -kv[1])}}
+            "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(per_stage.items(), key=lambda kv: -kv[1])},
+            f"last_step_roofline (level {last} -> {levels})": roof}
+
+
+def adjoint_leg(mesh, levels, steps):
+    """Cage-fitting gradient: Catmull-Clark level 4 of the 10k cage with its
+    state kept, then subdiv_backward (g_k = R_k^T g_{k+1}, level by level).
+    Per level the adjoint must read g_{k+1} and write g_k once: 12 (V_{k+1} +
+    V_k) bytes, reported for the largest level."""
+    import torch
+    from paper_1809_06047_amd import _lib, api
+    r = api.Refiner(mesh, "cc", levels, flags=_lib.FLAG_KEEP_STATE)
+    r.plan()
+    outs = r.run()
+    g = torch.randn_like(outs[levels]["positions"])
+    r.backward(g)
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    _lib.timing_read()
+    tf = tb = 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r.backward(g)
+        torch.cuda.synchronize()
+        tf += t1 - t0
+        tb += time.perf_counter() - t1
+    stages = _lib.timing_read()
+    _lib.timing_enable(False)
+    k = levels - 1
+    bw = sum(tot for (name, lvl), (_, tot) in stages.items() if name.startswith("bw_") and lvl == k) / steps
+    nbytes = 12 * (r.level_info(levels)["V"] + r.level_info(k)["V"])
+    gbs = nbytes / (bw / 1000.0) / 1e9
+    return {"workload": f"Catmull-Clark level {levels} of the 10k-vertex mixed cage, gradient w.r.t. the cage "
+                        f"(V_{levels}={r.level_info(levels)['V']})",
+            "ms_forward": round(tf * 1000.0 / steps, 4), "ms_backward": round(tb * 1000.0 / steps, 4),
+            f"backward_level_{levels}_to_{k}": {"device_ms": round(bw, 5), "algorithmic_bytes": nbytes,
+                                                 "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
 def serving(args):
