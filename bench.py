@@ -193,6 +193,7 @@ def main():
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(stages.items())},
     }
+    out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
     if args.adjoint_levels > 0:
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
@@ -257,6 +258,33 @@ def scheme_leg(mesh, scheme, levels, steps):
             "device_ms_per_step": round(sum(per_stage.values()), 4),
             "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(per_stage.items(), key=lambda kv: -kv[1])},
             f"last_step_roofline (level {last} -> {levels})": roof}
+
+
+def static_leg(mesh, levels, steps):
+    """Static topology on the main workload: the plan keeps every level's
+    state; after one full subdiv_refine, subdiv_refine_positions re-evaluates
+    P_6 = R_5 ... R_0 P_0 for moved cage positions, writing positions only."""
+    import torch
+    from paper_1809_06047_amd import _lib, api
+    r = api.Refiner(mesh, "cc", levels, flags=_lib.FLAG_KEEP_STATE)
+    r.plan()
+    r.run()
+    r.run_positions()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.run_positions()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        r.run()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    faces = r.level_info(levels)["F"]
+    ms_pos = (t1 - t0) * 1000.0 / steps
+    return {"workload": f"Catmull-Clark levels 0->{levels}, positions only with the topology kept",
+            "ms_per_eval": round(ms_pos, 4), "refined_faces_per_s": round(faces / (ms_pos / 1000.0), 1),
+            "ms_per_full_refine_same_plan": round((t2 - t1) * 1000.0 / steps, 4)}
 
 
 def adjoint_leg(mesh, levels, steps):

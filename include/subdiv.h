@@ -171,6 +171,20 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* Static topology (Sec. 3.6: P_L = R_{L-1} ... R_0 P_0 with every R_k fixed
+ * by topology and creases). Re-evaluates the positions of a Catmull-Clark
+ * refinement planned with SUBDIV_FLAG_KEEP_STATE, after one completed
+ * subdiv_refine with the same plan, cage topology and workspace, for the
+ * cage positions now in mesh->positions. The operators are applied
+ * matrix-free by the same stencil kernels as subdiv_refine, reading the kept
+ * face tables, adjacency and sharpness; nothing but positions is written, so
+ * the result equals subdiv_refine's positions bit for bit. outs[k].positions
+ * as in subdiv_refine (the final level is required; other fields are
+ * ignored). Enqueues work only. Returns SUBDIV_STATE for a plan that does not
+ * keep its state or a different workspace. */
+int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
+                            size_t ws_bytes, void *stream);
+
 /* ---- batches of uneven meshes (one scheme and level count per batch) ---
  * The meshes are packed into one disjoint union cage and refined together:
  * every stage runs as one launch over all meshes of the batch. Each mesh's

@@ -118,6 +118,7 @@ class Refiner:
         if self.plan_info.workspace_bytes > self.ws_bytes:
             raise _lib.SubdivError(_lib.WORKSPACE, "workspace bound below the planned size")
         self._alloc_outputs()
+        self._state_ready = False  # a new plan: the next run rebuilds the kept state
         return self.plan_info
 
     def level_info(self, k):
@@ -159,6 +160,18 @@ class Refiner:
         check(st, "subdiv_refine")
         return self.outs
 
+    def run_positions(self, stream=None):
+        """Static topology: refine the cage's current positions again with the
+        kept state of the last run (plan with FLAG_KEEP_STATE, Catmull-Clark);
+        only the position outputs are written. Enqueues work only."""
+        lib = load()
+        s = current_stream_handle(self.dmesh.device) if stream is None else stream
+        st = lib.subdiv_refine_positions(ctypes.byref(self.dmesh.struct), ctypes.byref(self.plan_info),
+                                         self._outs_struct, ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                         ctypes.c_void_p(s))
+        check(st, "subdiv_refine_positions")
+        return self.outs
+
     @property
     def final(self):
         return self.outs[self.levels]
@@ -189,7 +202,9 @@ class SubdivFunction(torch.autograd.Function):
     def forward(ctx, P0: torch.Tensor, refiner: "Refiner"):
         P0c = P0.detach().contiguous()
         refiner.dmesh.set_positions(P0c)
-        outs = refiner.run()
+        # the topology is fixed: after the first run only positions are recomputed
+        outs = refiner.run_positions() if getattr(refiner, "_state_ready", False) else refiner.run()
+        refiner._state_ready = True
         ctx.refiner = refiner
         ctx.keep = P0c
         return outs[refiner.levels]["positions"].clone()

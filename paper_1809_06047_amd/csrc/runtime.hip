@@ -219,7 +219,9 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     }
     const bool rebuild = rebuilds_levels(scheme, flags);
     const bool cc_carry = scheme == SUBDIV_CATMULL_CLARK && !rebuild;
-    for (int s = 0; s < (cc_carry ? 3 : 2); ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
+    // rotating adjacency slots; with the state kept every level has its own region instead
+    const int nslots = cc_carry ? ((flags & SUBDIV_FLAG_KEEP_STATE) ? 0 : 3) : 2;
+    for (int s = 0; s < nslots; ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
     if (cc_carry && levels >= 4) {
       y.hs = c.take(24 * mE);
       y.term0 = c.take(12 * mF);
@@ -359,6 +361,106 @@ hipError_t build_level0_faces(const subdiv_mesh *m, int scheme, const Topo &t, v
     if ((err = launch_fill_i32(b.sigcnt, 0, t.H, s)) != hipSuccess) return err;
   }
   return build_faces(t, scheme, b, info, s);
+}
+
+// Catmull-Clark with the adjacency carried over in closed form: step 0 on
+// the cage adjacency, steps k >= 1 from the parent level's adjacency. Level
+// k's own adjacency is written during step k when a later step or the
+// adjoint reads it. With SUBDIV_FLAG_KEEP_STATE every level keeps its face
+// table, adjacency and sharpness in its own region (y.keep[k]); otherwise
+// three slots rotate. positions_only re-evaluates the positions of a
+// refinement whose state is kept (static topology): only positions are
+// written, every other array is read from the kept state.
+int refine_cc_carried(const subdiv_mesh *mesh, const subdiv_level_out *outs, void *ws, const Layout &y,
+                      const Sizes *L, int levels, uint32_t flags, Topo t, Adj a, const float *P, bool positions_only,
+                      hipStream_t s) {
+  (void)mesh;
+  const bool keep = (flags & SUBDIV_FLAG_KEEP_STATE) != 0;
+  auto level_adj = [&](int k, bool creases) -> Adj {
+    return adj_at(ws, keep ? y.keep[k] : y.slot[k % 3], L[k].E, creases);
+  };
+  const bool emit = !positions_only;
+  const bool final0 = (levels == 1);
+  CCStep c{};
+  c.t = t;
+  c.a = a;
+  c.P = P;
+  c.fv1 = (final0 && emit) ? outs[1].face_verts : nullptr;
+  c.P1 = outs[1].positions ? outs[1].positions : at<float>(ws, y.mP[1]);
+  c.has_bnd = L[0].B > 0;
+  c.creases = L[0].creases && a.sig != nullptr;
+  c.creases1 = c.creases && L[1].creases;
+  if (c.creases1 && emit) c.a1.sig = final0 ? outs[1].crease_sharpness : level_adj(1, true).sig;
+  if (outs[1].edge_verts && emit) SUBDIV_TIMED("edge_export", 0, launch_edge_export(t, a, outs[1].edge_verts, s));
+  SUBDIV_TIMED("cc_face", 0, cc_launch(CC_FACE, c, s));
+  SUBDIV_TIMED("cc_vertex", 0, cc_launch(CC_VERTEX, c, s));
+  SUBDIV_TIMED("cc_edge", 0, cc_launch(CC_EDGE, c, s));
+  if (!final0 && c.a1.sig && outs[1].crease_sharpness)
+    SUBDIV_TRY(hipMemcpyAsync(outs[1].crease_sharpness, c.a1.sig, 8 * L[1].E, hipMemcpyDeviceToDevice, s));
+  Topo tm = t;
+  Adj am = a;
+  Adj ag{};  // grandparent adjacency (levels >= 1 only)
+  const double *sig_cur = (c.creases1 && !final0) ? level_adj(1, true).sig : nullptr;
+  P = c.P1;
+  for (int k = 1; k < levels; ++k) {
+    const bool final = (k == levels - 1);
+    const Adj slotk = level_adj(k, L[k].creases);
+    LagStep g{};
+    g.tm = tm;
+    g.am = am;
+    g.bnd = L[0].B > 0;
+    g.Vk = (int32_t)L[k].V;
+    g.Fk = (int32_t)L[k].F;
+    g.Ek = (int32_t)L[k].E;
+    g.Pk = P;
+    g.sigk = L[k].creases ? sig_cur : nullptr;
+    g.vcrk = (g.sigk && emit) ? slotk.vcr : nullptr;
+    g.P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
+    g.fv1 = (final && emit) ? outs[levels].face_verts : nullptr;
+    if (emit) g.fvk = keep ? slotk.fv : (outs[k].face_verts ? outs[k].face_verts : (final ? nullptr : slotk.fv));
+    if (emit && (!final || keep)) {  // level k's adjacency: read by step k+1 or by the adjoint
+      g.ak = slotk;
+      g.ak.fv = nullptr;
+      g.ak.sig = nullptr;
+      g.ak.vcr = nullptr;
+      if (!g.bnd) g.ak.bscan = nullptr;
+    }
+    if (emit && g.sigk && L[k + 1].creases)
+      g.sig1 = final ? outs[levels].crease_sharpness : level_adj(k + 1, true).sig;
+    g.edges_k = emit ? outs[k + 1].edge_verts : nullptr;
+    if (k >= 3) {
+      // quad parent and grandparent: rings from corner classes
+      Lag2Step g2{};
+      g2.s = g;
+      g2.Vg = (int32_t)L[k - 2].V;
+      g2.Fg = (int32_t)L[k - 2].F;
+      g2.Eg = (int32_t)L[k - 2].E;
+      g2.VFg = g2.Vg + g2.Fg;
+      g2.vhe_g = ag.vhe;
+      g2.twin_g = ag.twin;
+      g2.e2h_g = ag.e2h;
+      g2.bscan_g = g.bnd ? ag.bscan : nullptr;
+      g2.hs = at<float>(ws, y.hs);
+      g2.term0 = at<float>(ws, y.term0);
+      SUBDIV_TIMED("cc_group", k, lag2_launch(LAG2_GROUP, g2, s));
+      SUBDIV_TIMED("cc_ep_vertex", k, lag2_launch(LAG2_COMBINE, g2, s));
+      SUBDIV_TIMED("cc_old_vertex", k, lag2_launch(LAG2_OLDER, g2, s));
+    } else {
+      SUBDIV_TIMED("cc_group", k, lag_launch(LAG_GROUP, g, s));
+      SUBDIV_TIMED("cc_old_vertex", k, lag_launch(LAG_VERTEX, g, s));
+    }
+    SUBDIV_TIMED("cc_edge_group", k, lag_launch(LAG_EDGE, g, s));
+    if (emit && keep && outs[k].face_verts)
+      SUBDIV_TRY(hipMemcpyAsync(outs[k].face_verts, slotk.fv, 4 * L[k].H, hipMemcpyDeviceToDevice, s));
+    if (!final && g.sig1 && outs[k + 1].crease_sharpness)
+      SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, g.sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
+    tm = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, emit ? g.fvk : slotk.fv};
+    ag = am;
+    am = slotk;
+    sig_cur = emit ? g.sig1 : ((!final && L[k + 1].creases) ? level_adj(k + 1, true).sig : nullptr);
+    P = g.P1;
+  }
+  return SUBDIV_OK;
 }
 
 }  // namespace
@@ -536,128 +638,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   }
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
-  if (plan->flags & SUBDIV_FLAG_KEEP_STATE) {
-    // ---- Catmull-Clark keeping every level's adjacency for subdiv_backward:
-    // each level's kernels emit the next level's adjacency in closed form
-    for (int k = 0; k < levels; ++k) {
-      const bool final = (k == levels - 1);
-      const Adj ak = (k == 0) ? a : adj_at(ws, y.keep[k], L[k].E, L[k].creases);
-      CCStep c{};
-      c.t = t;
-      c.a = ak;
-      c.P = P;
-      c.P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
-      c.has_bnd = L[0].B > 0;
-      c.creases = L[k].creases && ak.sig != nullptr;
-      c.creases1 = c.creases && L[k + 1].creases;
-      if (!final) {
-        c.a1 = adj_at(ws, y.keep[k + 1], L[k + 1].E, L[k + 1].creases);
-        c.fv1 = c.a1.fv;
-        c.a1.fv = nullptr;
-        c.a1.vcr = nullptr;
-        if (!c.creases1) c.a1.sig = nullptr;
-      } else {
-        c.fv1 = outs[levels].face_verts;
-        if (c.creases1) c.a1.sig = outs[levels].crease_sharpness;
-      }
-      if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, ak, outs[k + 1].edge_verts, s));
-      SUBDIV_TIMED("cc_face", k, cc_launch(CC_FACE, c, s));
-      SUBDIV_TIMED("cc_vertex", k, cc_launch(CC_VERTEX, c, s));
-      SUBDIV_TIMED("cc_edge", k, cc_launch(CC_EDGE, c, s));
-      if (!final && outs[k + 1].face_verts)
-        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].face_verts, c.fv1, 4 * L[k + 1].H, hipMemcpyDeviceToDevice, s));
-      if (!final && c.a1.sig && outs[k + 1].crease_sharpness)
-        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.a1.sig, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
-      t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, 4, nullptr, nullptr, c.fv1};
-      P = c.P1;
-    }
-    return SUBDIV_OK;
-  }
-  if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
-    // ---- Catmull-Clark, adjacency carried over in closed form ------------
-    // step 0 on the cage adjacency; steps k >= 1 from the parent level's
-    // adjacency (level k's own adjacency is written only when step k+1 needs it)
-    const bool final0 = (levels == 1);
-    CCStep c{};
-    c.t = t;
-    c.a = a;
-    c.P = P;
-    c.fv1 = final0 ? outs[1].face_verts : nullptr;
-    c.P1 = outs[1].positions ? outs[1].positions : at<float>(ws, y.mP[1]);
-    c.has_bnd = L[0].B > 0;
-    c.creases = L[0].creases && a.sig != nullptr;
-    c.creases1 = c.creases && L[1].creases;
-    if (c.creases1)
-      c.a1.sig = final0 ? outs[1].crease_sharpness : adj_at(ws, y.slot[1 % 3], L[1].E, true).sig;
-    if (outs[1].edge_verts) SUBDIV_TIMED("edge_export", 0, launch_edge_export(t, a, outs[1].edge_verts, s));
-    SUBDIV_TIMED("cc_face", 0, cc_launch(CC_FACE, c, s));
-    SUBDIV_TIMED("cc_vertex", 0, cc_launch(CC_VERTEX, c, s));
-    SUBDIV_TIMED("cc_edge", 0, cc_launch(CC_EDGE, c, s));
-    if (!final0 && c.a1.sig && outs[1].crease_sharpness)
-      SUBDIV_TRY(hipMemcpyAsync(outs[1].crease_sharpness, c.a1.sig, 8 * L[1].E, hipMemcpyDeviceToDevice, s));
-    Topo tm = t;
-    Adj am = a;
-    Adj ag{};  // grandparent adjacency (levels >= 1 only)
-    const double *sig_cur = c.creases1 ? c.a1.sig : nullptr;
-    P = c.P1;
-    for (int k = 1; k < levels; ++k) {
-      const bool final = (k == levels - 1);
-      const Adj slotk = adj_at(ws, y.slot[k % 3], L[k].E, L[k].creases);
-      LagStep g{};
-      g.tm = tm;
-      g.am = am;
-      g.bnd = L[0].B > 0;
-      g.Vk = (int32_t)L[k].V;
-      g.Fk = (int32_t)L[k].F;
-      g.Ek = (int32_t)L[k].E;
-      g.Pk = P;
-      g.sigk = L[k].creases ? sig_cur : nullptr;
-      g.vcrk = g.sigk ? slotk.vcr : nullptr;
-      g.P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
-      g.fv1 = final ? outs[levels].face_verts : nullptr;
-      g.fvk = outs[k].face_verts ? outs[k].face_verts : (final ? nullptr : slotk.fv);
-      if (!final) {  // step k+1 refines level k from this adjacency
-        g.ak = slotk;
-        g.ak.fv = nullptr;
-        g.ak.sig = nullptr;
-        g.ak.vcr = nullptr;
-        if (!g.bnd) g.ak.bscan = nullptr;
-      }
-      if (g.sigk && L[k + 1].creases)
-        g.sig1 = final ? outs[levels].crease_sharpness : adj_at(ws, y.slot[(k + 1) % 3], L[k + 1].E, true).sig;
-      g.edges_k = outs[k + 1].edge_verts;
-      if (k >= 3) {
-        // quad parent and grandparent: rings from corner classes
-        Lag2Step g2{};
-        g2.s = g;
-        g2.Vg = (int32_t)L[k - 2].V;
-        g2.Fg = (int32_t)L[k - 2].F;
-        g2.Eg = (int32_t)L[k - 2].E;
-        g2.VFg = g2.Vg + g2.Fg;
-        g2.vhe_g = ag.vhe;
-        g2.twin_g = ag.twin;
-        g2.e2h_g = ag.e2h;
-        g2.bscan_g = g.bnd ? ag.bscan : nullptr;
-        g2.hs = at<float>(ws, y.hs);
-        g2.term0 = at<float>(ws, y.term0);
-        SUBDIV_TIMED("cc_group", k, lag2_launch(LAG2_GROUP, g2, s));
-        SUBDIV_TIMED("cc_ep_vertex", k, lag2_launch(LAG2_COMBINE, g2, s));
-        SUBDIV_TIMED("cc_old_vertex", k, lag2_launch(LAG2_OLDER, g2, s));
-      } else {
-        SUBDIV_TIMED("cc_group", k, lag_launch(LAG_GROUP, g, s));
-        SUBDIV_TIMED("cc_old_vertex", k, lag_launch(LAG_VERTEX, g, s));
-      }
-      SUBDIV_TIMED("cc_edge_group", k, lag_launch(LAG_EDGE, g, s));
-      if (!final && g.sig1 && outs[k + 1].crease_sharpness)
-        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, g.sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
-      tm = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, g.fvk};
-      ag = am;
-      am = slotk;
-      sig_cur = g.sig1;
-      P = g.P1;
-    }
-    return SUBDIV_OK;
-  }
+  if (scheme == SUBDIV_CATMULL_CLARK && !rebuild)
+    return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
@@ -733,6 +715,28 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     P = P1;
   }
   return SUBDIV_OK;
+}
+
+int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs,
+                            void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
+  const int levels = plan->levels;
+  if (!outs[levels].positions) return SUBDIV_INVALID_ARG;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(plan->scheme, levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
+  const Topo t = cage_topo(mesh, H0, ws, y);
+  const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
+  return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, mesh->positions, true, s);
 }
 
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,

@@ -77,3 +77,31 @@ def test_backward_without_keep_state_is_rejected():
     with pytest.raises(_lib.SubdivError) as e:
         r.backward(torch.zeros((r.level_info(2)["V"], 3), device="cuda"))
     assert e.value.status == _lib.STATE
+
+
+@pytest.mark.parametrize("cage", ["mixed_creases", "holes"])
+def test_refine_positions_equals_full_refine(oracle_mod, cage):
+    """Static topology: with the state kept, new cage positions refined by
+    subdiv_refine_positions (positions only) give bit for bit the positions
+    of a full subdiv_refine of the moved cage, at every level, and match the
+    oracle."""
+    if cage == "mixed_creases":
+        m = G.cc_cage(seed=31, level=2, crease_frac=0.1, smax=6.0)
+    else:
+        m = G.tri_cage(seed=32, level=2, hole_frac=0.06)
+    L = 4
+    r = api.Refiner(m, "cc", L, flags=_lib.FLAG_KEEP_STATE, keep="all")
+    r.plan()
+    r.run()
+    rng = np.random.default_rng(33)
+    moved = G.Mesh(**{**m.__dict__, "positions": (m.positions + rng.normal(0, 0.05, m.positions.shape)).astype(
+        np.float32)})
+    r.dmesh.set_positions(torch.from_numpy(moved.positions.copy()).cuda())
+    outs = r.run_positions()
+    torch.cuda.synchronize()
+    got = [None] + [outs[k]["positions"].cpu().numpy() for k in range(1, L + 1)]
+    full, _ = api.refine(moved, "cc", L, keep="all")
+    ref = oracle_mod.refine(moved, "cc", L)
+    for k in range(1, L + 1):
+        np.testing.assert_array_equal(got[k], full[k]["positions"].cpu().numpy(), err_msg=f"level {k}")
+        assert normwise_err(got[k], ref[k].positions) <= POS_TOL
