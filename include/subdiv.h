@@ -253,6 +253,10 @@ typedef struct subdiv_stage_time {
 
 void subdiv_timing_enable(int on);
 int subdiv_timing_read(subdiv_stage_time *out, int max_out);
+/* Restrict the timing to one stage name and level (level < 0: every level),
+ * so that only its kernels get an event pair; NULL or "" times every stage
+ * again. Process-wide, like subdiv_timing_enable. */
+void subdiv_timing_select(const char *stage, int level);
 
 /* HIP error text of the last SUBDIV_HIP status on this thread ("" if none). */
 const char *subdiv_last_error(void);

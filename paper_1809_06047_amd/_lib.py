@@ -76,6 +76,7 @@ SIGNATURES = {
     "subdiv_refine_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.POINTER(subdiv_batch_plan),
                                            ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
     "subdiv_timing_enable": (None, [ctypes.c_int]),
+    "subdiv_timing_select": (None, [ctypes.c_char_p, ctypes.c_int]),
     "subdiv_timing_read": (ctypes.c_int, [ctypes.POINTER(subdiv_stage_time), ctypes.c_int]),
     "subdiv_last_error": (ctypes.c_char_p, []),
     "subdiv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -113,6 +114,11 @@ class SubdivError(RuntimeError):
 
 def timing_enable(on: bool = True):
     load().subdiv_timing_enable(1 if on else 0)
+
+
+def timing_select(stage=None, level: int = -1):
+    """Time only `stage` at `level` (-1: every level); None times every stage."""
+    load().subdiv_timing_select(stage.encode() if stage else None, int(level))
 
 
 def timing_read(max_out: int = 512):

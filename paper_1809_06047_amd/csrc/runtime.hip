@@ -37,9 +37,18 @@ std::atomic<bool> g_timing{false};
 std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
-hipEvent_t timing_begin(hipStream_t s) {
+// optional selection: only one stage (and level) is timed, so that the event
+// pairs of the other stages do not sit between the kernels
+std::atomic<bool> g_tsel_on{false};
+char g_tsel_name[24] = "";
+int g_tsel_level = -1;
+
+hipEvent_t timing_begin(const char *name, int level, hipStream_t s) {
   if (!g_timing.load(std::memory_order_relaxed)) return nullptr;
   std::lock_guard<std::mutex> lock(g_tmu);
+  if (g_tsel_on.load(std::memory_order_relaxed) &&
+      (std::strcmp(name, g_tsel_name) != 0 || (g_tsel_level >= 0 && level != g_tsel_level)))
+    return nullptr;
   hipEvent_t e = nullptr;
   if (!g_pool.empty()) {
     e = g_pool.back();
@@ -75,7 +84,7 @@ void timing_end(hipEvent_t a, const char *name, int level, hipStream_t s) {
 
 #define SUBDIV_TIMED(name, level, expr)          \
   do {                                           \
-    hipEvent_t _ta = timing_begin(s);            \
+    hipEvent_t _ta = timing_begin(name, level, s); \
     hipError_t _e = (expr);                      \
     if (_e != hipSuccess) return hip_fail(_e);   \
     timing_end(_ta, name, level, s);             \
@@ -471,6 +480,20 @@ extern "C" {
 int subdiv_version(void) { return 1000; }
 
 void subdiv_timing_enable(int on) { g_timing.store(on != 0); }
+
+void subdiv_timing_select(const char *stage, int level) {
+  std::lock_guard<std::mutex> lock(g_tmu);
+  if (!stage || !*stage) {
+    g_tsel_on.store(false);
+    g_tsel_name[0] = 0;
+    g_tsel_level = -1;
+    return;
+  }
+  std::strncpy(g_tsel_name, stage, sizeof(g_tsel_name) - 1);
+  g_tsel_name[sizeof(g_tsel_name) - 1] = 0;
+  g_tsel_level = level;
+  g_tsel_on.store(true);
+}
 
 int subdiv_timing_read(subdiv_stage_time *out, int max_out) {
   if (!out || max_out < 0) return SUBDIV_INVALID_ARG;

@@ -485,14 +485,15 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), s
     reserve_bytes = int(min(budget_gib, 8.0) * 2**30) // max(1, slots)
     reserve(device, reserve_bytes)
     ex = GpuBatchExecutor(device, slots, reserve_bytes)
-    # warm-up: one request of every (scheme, levels) group, both paths
+    # warm-up of both paths: one request of every (scheme, levels) group and
+    # the head of the trace, all arriving at once
     seen, warm = set(), []
     for r in trace:
         if (r.scheme, r.levels) not in seen:
             seen.add((r.scheme, r.levels))
             warm.append(r)
-    wb = _retime(warm, np.zeros(len(warm)), 1.0)
-    Server(ex, int(budget_gib * 2**30), slots, max_batch).run(wb)
+    warm += trace[:min(64, n_requests)]
+    Server(ex, int(budget_gib * 2**30), slots, max_batch).run(_retime(warm, np.zeros(len(warm)), 1.0))
     serve_per_mesh(_retime(warm, np.zeros(len(warm)), 1.0), device)
     # saturation of the baseline: everything arrives at t = 0
     ns = min(n_requests, sat_requests or n_requests)
