@@ -1,5 +1,7 @@
-// One Catmull-Clark level on gfx950: eval (face, edge and vertex points,
-// boundary repair, creases) fused with the build of the next level.
+// One Catmull-Clark level on gfx950 from the adjacency of the same level:
+// the cage step, and every step when levels are rebuilt on request. Eval
+// (face, edge and vertex points, boundary repair, creases), the face table
+// of the next level and the inherited sharpness of its edges.
 //
 // Rules (Sec. 3.1 / 3.2): face point f_r = mapped M^T P (eq:spla_fp); edge
 // point 1/4 (p_k + p_l + f_r + f_s) with f_r, f_s = F(k,l), F(l,k) (eq:F);
@@ -10,17 +12,12 @@
 //
 // Topology of level k+1 (Sec. 3.2 "Topology refinement"): child j of face r
 // is (v_j, |v|+|f|+e(v_j,v_j+1), |v|+r, |v|+|f|+e(v_j-1,v_j)) at index
-// col_ptr[r] + j, i.e. child index == parent half-edge index h.
-//
-// Next-level build in closed form. Every edge of level k+1 has an edge
-// point as its higher end, so its lower neighbours are, ascending:
-// lo(e), hi(e), then the face points of the (one or two) faces of e. The
-// upper triangle of E_{k+1} is therefore enumerated by
-//     base(e) = sum_{e' < e} (2 + faces(e')) = 4 e - (boundary edges before e)
-// plus a rank in {0,1,2,3}. Twins of the 4 child half-edges of h follow from
-// twin(h) and twin(prev(h)). This replaces the symbolic pass and the mapped
-// product at every level after the cage (whose adjacency comes from the
-// generic build) and produces the same canonical ids bit for bit.
+// col_ptr[r] + j, i.e. child index == parent half-edge index h. Every edge of
+// level k+1 has an edge point as its higher end, so its lower neighbours are,
+// ascending, lo(e), hi(e), then the face points of the (one or two) faces of
+// e: the children of edge e have ids base(e) + rank, base(e) = 4 e -
+// (boundary edges before e). The next level's own adjacency is carried over
+// in closed form by the parent-level kernels (cc_lag.hip).
 #include "subdiv_internal.h"
 
 namespace subdiv {
@@ -56,51 +53,17 @@ __global__ void __launch_bounds__(kBlock) k_cc_face(CCStep c) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) out[j] = make_int4(v[j], VF + e[j], V + r, VF + e[(j + 3) & 3]);
     }
-    if (c.a1.twin) {
-      const int4 tq = reinterpret_cast<const int4 *>(c.a.twin)[r];
-      const int tw[4] = {tq.x, tq.y, tq.z, tq.w};
-      int base[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) base[j] = edge_base(c, e[j]);
-      int4 *tout = reinterpret_cast<int4 *>(c.a1.twin) + 4ll * r;
-      int4 *eout = reinterpret_cast<int4 *>(c.a1.eid) + 4ll * r;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int jp = (j + 3) & 3;
-        const int t = tw[j], tp = tw[jp];
-        const int tn = t < 0 ? -1 : ((t & ~3) | ((t + 1) & 3));  // next(t)
-        tout[j] = make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * (4 * r + ((j + 1) & 3)) + 2, 4 * (4 * r + jp) + 1,
-                            tp < 0 ? -1 : 4 * tp);
-        const int s = t < 0 ? -1 : (t >> 2), sp = tp < 0 ? -1 : (tp >> 2);
-        eout[j] = make_int4(base[j] + (v[j] > v[(j + 1) & 3]), base[j] + 2 + (s >= 0 && s < r),
-                            base[jp] + 2 + (sp >= 0 && sp < r), base[jp] + (v[j] > v[jp]));
-      }
-      c.a1.vhe[V + r] = 4 * (4 * r) + 2;
-    }
   } else {
     // general polygons (a cage with a column pointer) and triangle cages
     const int b = face_begin<ORDER>(c.t, r), en = face_end<ORDER>(c.t, r), n = en - b;
     f3 acc{0.f, 0.f, 0.f};
     for (int h = b; h < en; ++h) acc = add3(acc, ld3(c.P, c.t.fv[h]));
     st3(c.P1, V + r, mul3(1.0f / (float)n, acc));
-    for (int h = b; h < en; ++h) {
-      const int hp = (h == b) ? en - 1 : h - 1;
-      const int hn = (h + 1 == en) ? b : h + 1;
-      if (c.fv1)
+    if (c.fv1)
+      for (int h = b; h < en; ++h) {
+        const int hp = (h == b) ? en - 1 : h - 1;
         reinterpret_cast<int4 *>(c.fv1)[h] = make_int4(c.t.fv[h], VF + c.a.eid[h], V + r, VF + c.a.eid[hp]);
-      if (c.a1.twin) {
-        const int t = c.a.twin[h], tp = c.a.twin[hp];
-        const int tn = t < 0 ? -1 : he_next<ORDER>(c.t, t);
-        reinterpret_cast<int4 *>(c.a1.twin)[h] =
-            make_int4(t < 0 ? -1 : 4 * tn + 3, 4 * hn + 2, 4 * hp + 1, tp < 0 ? -1 : 4 * tp);
-        const int s = t < 0 ? -1 : he_face<ORDER>(c.t, t), sp = tp < 0 ? -1 : he_face<ORDER>(c.t, tp);
-        const int bj = edge_base(c, c.a.eid[h]), bp = edge_base(c, c.a.eid[hp]);
-        const int vj = c.t.fv[h], vn = c.t.fv[hn], vp = c.t.fv[hp];
-        reinterpret_cast<int4 *>(c.a1.eid)[h] = make_int4(bj + (vj > vn), bj + 2 + (s >= 0 && s < r),
-                                                          bp + 2 + (sp >= 0 && sp < r), bp + (vj > vp));
       }
-    }
-    if (c.a1.twin) c.a1.vhe[V + r] = 4 * b + 2;
   }
 }
 
@@ -169,7 +132,6 @@ __global__ void __launch_bounds__(kBlock) k_cc_vertex(CCStep c) {
   }
   st3(c.P1, v, S);
   if (c.creases) c.a.vcr[v] = make_int4(k, ce0, ce1, 0);
-  if (c.a1.twin) c.a1.vhe[v] = 4 * h0;
 }
 
 // ---------------------------------------------------------------- edges
@@ -198,32 +160,10 @@ __global__ void __launch_bounds__(kBlock) k_cc_edge(CCStep c) {
     }
   }
   st3(c.P1, V + F + e, ep);
-  if (!c.a1.e2h && !c.a1.sig) return;
+  if (!c.sig1) return;
   const int base = edge_base(c, e);
   const int nchild = t < 0 ? 3 : 4;
-  if (c.a1.e2h) {
-    const int hx0 = 4 * h, hx1 = 4 * hn + 3;  // a->ep in child h, ep->b in child next(h)
-    c.a1.e2h[base + 0] = a < b ? hx0 : hx1;
-    c.a1.e2h[base + 1] = a < b ? hx1 : hx0;
-    if (t < 0) {
-      c.a1.e2h[base + 2] = 4 * h + 1;
-      c.a1.vhe[V + F + e] = hx1;  // boundary vertex: its boundary half-edge
-    } else {
-      const int s = he_face<ORDER>(c.t, t);
-      c.a1.e2h[base + (r < s ? 2 : 3)] = 4 * h + 1;
-      c.a1.e2h[base + (r < s ? 3 : 2)] = 4 * t + 1;
-      // an interior vertex starts its ring at its lowest outgoing half-edge,
-      // as the generic build does, so both builds sum rings in one order
-      const int tn = he_next<ORDER>(c.t, t);
-      const int m0 = min(4 * h + 1, 4 * hn + 3), m1 = min(4 * t + 1, 4 * tn + 3);
-      c.a1.vhe[V + F + e] = min(m0, m1);
-    }
-    if (c.has_bnd) {
-      const int b2 = 2 * c.a.bscan[e];
-      for (int i = 0; i < nchild; ++i) c.a1.bscan[base + i] = b2 + (t < 0 ? (i < 2 ? i : 2) : 0);
-    }
-  }
-  if (c.a1.sig) {
+  {
     double s_lo = 0.0, s_hi = 0.0;
     if (sj > 0.0) {
       const int lo = a < b ? a : b, hi = a < b ? b : a;
@@ -233,9 +173,9 @@ __global__ void __launch_bounds__(kBlock) k_cc_edge(CCStep c) {
       s_lo = chaikin(si, sj);
       s_hi = chaikin(sk, sj);
     }
-    c.a1.sig[base + 0] = s_lo;
-    c.a1.sig[base + 1] = s_hi;
-    for (int i = 2; i < nchild; ++i) c.a1.sig[base + i] = 0.0;
+    c.sig1[base + 0] = s_lo;
+    c.sig1[base + 1] = s_hi;
+    for (int i = 2; i < nchild; ++i) c.sig1[base + i] = 0.0;
   }
 }
 

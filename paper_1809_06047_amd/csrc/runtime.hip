@@ -399,13 +399,13 @@ int refine_cc_carried(const subdiv_mesh *mesh, const subdiv_level_out *outs, voi
   c.has_bnd = L[0].B > 0;
   c.creases = L[0].creases && a.sig != nullptr;
   c.creases1 = c.creases && L[1].creases;
-  if (c.creases1 && emit) c.a1.sig = final0 ? outs[1].crease_sharpness : level_adj(1, true).sig;
+  if (c.creases1 && emit) c.sig1 = final0 ? outs[1].crease_sharpness : level_adj(1, true).sig;
   if (outs[1].edge_verts && emit) SUBDIV_TIMED("edge_export", 0, launch_edge_export(t, a, outs[1].edge_verts, s));
   SUBDIV_TIMED("cc_face", 0, cc_launch(CC_FACE, c, s));
   SUBDIV_TIMED("cc_vertex", 0, cc_launch(CC_VERTEX, c, s));
   SUBDIV_TIMED("cc_edge", 0, cc_launch(CC_EDGE, c, s));
-  if (!final0 && c.a1.sig && outs[1].crease_sharpness)
-    SUBDIV_TRY(hipMemcpyAsync(outs[1].crease_sharpness, c.a1.sig, 8 * L[1].E, hipMemcpyDeviceToDevice, s));
+  if (!final0 && c.sig1 && outs[1].crease_sharpness)
+    SUBDIV_TRY(hipMemcpyAsync(outs[1].crease_sharpness, c.sig1, 8 * L[1].E, hipMemcpyDeviceToDevice, s));
   Topo tm = t;
   Adj am = a;
   Adj ag{};  // grandparent adjacency (levels >= 1 only)
@@ -693,19 +693,18 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       c.has_bnd = L[k].B > 0;
       c.creases = L[k].creases && a.sig != nullptr;
       c.creases1 = L[k + 1].creases != 0;
-      Adj a1{};  // only the inherited sharpness is carried over: the next level is rebuilt
+      // only the inherited sharpness is carried over: the next level is rebuilt
       if (!final) {
-        if (c.creases1) a1.sig = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, true).sig;
+        if (c.creases1) c.sig1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, true).sig;
       } else if (c.creases1 && outs[k + 1].crease_sharpness) {
-        a1.sig = outs[k + 1].crease_sharpness;
+        c.sig1 = outs[k + 1].crease_sharpness;
       }
-      c.a1 = a1;
-      if (!c.creases) c.a1.sig = nullptr;
+      if (!c.creases) c.sig1 = nullptr;
       SUBDIV_TIMED("cc_face", k, cc_launch(CC_FACE, c, s));
       SUBDIV_TIMED("cc_vertex", k, cc_launch(CC_VERTEX, c, s));
       SUBDIV_TIMED("cc_edge", k, cc_launch(CC_EDGE, c, s));
-      if (!final && c.a1.sig && outs[k + 1].crease_sharpness)
-        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.a1.sig, 8 * L[k + 1].E, hipMemcpyDeviceToDevice,
+      if (!final && c.sig1 && outs[k + 1].crease_sharpness)
+        SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice,
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else {

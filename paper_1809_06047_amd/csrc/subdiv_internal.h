@@ -175,10 +175,10 @@ struct CCStep {
   const float *P;   // [V*3]
   int32_t *fv1;     // [4H] refined M
   float *P1;        // [(V+F+E)*3]
-  Adj a1;           // adjacency of level k+1 (output; twin == nullptr => final level, not emitted)
+  double *sig1;     // [E_{k+1}] inherited sharpness of level k+1 (null: not written)
   bool has_bnd;     // level k has boundary edges (bscan valid)
   bool creases;     // level k may have creases (a.sig, a.vcr valid)
-  bool creases1;    // level k+1 may have creases (a1.sig to be written)
+  bool creases1;    // level k+1 may have creases
 };
 enum { CC_FACE = 0, CC_VERTEX = 1, CC_EDGE = 2 };
 // one of the three kernels of a Catmull-Clark level (launch in this order)
