@@ -47,10 +47,16 @@ hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s) {
 
 // ------------------------------------------------------------------- scan
 // Block-wide scans: 256 threads x 8 items. A wave-64 inclusive scan with
-// cross-lane shuffles, then the 4 wave totals through LDS.
+// cross-lane shuffles, then the 4 wave totals through LDS. Inputs of at most
+// kScanSmall items are scanned by one 1024-thread block in a single launch
+// (a few tiles with a running carry): the plan of a cage and the small levels
+// are bound by launch latency, not by the scan's bytes.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanOneThreads = 1024;
+constexpr int kScanOneTile = kScanOneThreads * 16;
+constexpr long long kScanSmall = 2ll * kScanOneTile;
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -62,16 +68,18 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Exclusive scan of one value per thread across the block; *total = block sum.
+// Exclusive scan of one value per thread across a block of NT threads;
+// *total = block sum.
+template <int NT = kScanThreads>
 __device__ __forceinline__ int block_excl_scan(int x, int *total) {
-  __shared__ int wsum[kScanThreads / 64];
+  __shared__ int wsum[NT / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int incl = wave_incl_scan(x);
   if (lane == 63) wsum[wid] = incl;
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kScanThreads / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     const int s = wsum[w];
     off += (w < wid) ? s : 0;
     tot += s;
@@ -141,6 +149,36 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t *in, 
   }
 }
 
+// one block: the whole scan of n <= kScanSmall items (in may equal out: every
+// tile is read into registers before it is written)
+__global__ void __launch_bounds__(kScanOneThreads) k_scan_one(const int32_t *in, int32_t *out, long long n,
+                                                              int32_t *total_dst) {
+  constexpr int kI = kScanOneTile / kScanOneThreads;
+  int carry = 0;
+  for (long long t0 = 0; t0 < n; t0 += kScanOneTile) {
+    const long long base = t0 + (long long)threadIdx.x * kI;
+    int v[kI];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kI; ++i) {
+      v[i] = (base + i < n) ? in[base + i] : 0;
+      s += v[i];
+    }
+    int tot;
+    int off = block_excl_scan<kScanOneThreads>(s, &tot) + carry;
+#pragma unroll
+    for (int i = 0; i < kI; ++i) {
+      if (base + i < n) out[base + i] = off;
+      off += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    out[n] = carry;
+    if (total_dst) *total_dst = carry;
+  }
+}
+
 long long scan_partials_ints(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 hipError_t launch_scan(const int32_t *in, int32_t *out, long long n, int32_t *partials, int32_t *total_dst,
@@ -149,6 +187,10 @@ hipError_t launch_scan(const int32_t *in, int32_t *out, long long n, int32_t *pa
   if (nb <= 1) {
     hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const int32_t *)nullptr, 0ll,
                        total_dst);
+    return hipGetLastError();
+  }
+  if (n <= kScanSmall) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneThreads), 0, s, in, out, n, total_dst);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);

@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
       const int g = 64 * t + l;
-      if (g < count) dst[g] = lds[g];
+      if (g < count) stream_store(dst + g, lds[g]);
     }
   }
   if (!valid) return;
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int fl = 8 * t + (l >> 3), x = l & 7;
-        if (fl < nw) o[16 * (pw + fl) + 8 * hf + x] = stage[w][x * 66 + fl];
+        if (fl < nw) stream_store4(o + 16 * (pw + fl) + 8 * hf + x, stage[w][x * 66 + fl]);
       }
       __builtin_amdgcn_wave_barrier();
     }

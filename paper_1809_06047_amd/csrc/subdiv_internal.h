@@ -105,13 +105,24 @@ __device__ __forceinline__ f3 fma3(float s, f3 a, f3 b) { return f3{s * a.x + b.
 
 constexpr int kBlock = 256;
 
+// Stores of the large output streams (face tables, staged point rows) are
+// non-temporal: each line is written once and is not read again by the
+// kernel that writes it, so it should not displace the rows the kernel
+// gathers from L2.
+__device__ __forceinline__ void stream_store(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void stream_store4(int4 *p, int4 v) {
+  const v4i32 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<v4i32 *>(p));
+}
+
 // Coalesced wave stores. A wave whose lane l owns the N dwords
 // dst[l*N .. l*N+N) of one contiguous run dst[0 .. 64 N) would store them as
 // N per-lane pieces spread over the whole run (one small request per lane
 // per instruction). They go through the wave's LDS slice `lds` (64 * (N|1)
 // dwords; the odd stride keeps the lane-wise writes conflict-free) and leave
 // as N instructions that each write 64 consecutive dwords. `count` = dwords
-// of the run that exist (a partial last wave).
+// of the run that exist (a partial last wave). The stores are non-temporal.
 template <int N>
 __device__ __forceinline__ void wave_store(uint32_t *lds, const uint32_t (&v)[N], uint32_t *dst, int lane, int count) {
   constexpr int S = N | 1;
@@ -122,7 +133,7 @@ __device__ __forceinline__ void wave_store(uint32_t *lds, const uint32_t (&v)[N]
   for (int t = 0; t < N; ++t) {
     const int g = 64 * t + lane, src = g / N;
     const uint32_t x = lds[src * S + (g - src * N)];
-    if (g < count) dst[g] = x;
+    if (g < count) stream_store(dst + g, x);
   }
   __builtin_amdgcn_wave_barrier();
 }
