@@ -664,6 +664,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   if (scheme == SUBDIV_CATMULL_CLARK && !rebuild)
     return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
+  Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -682,6 +683,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       if (L[k].B > 0 && scheme == SUBDIV_CATMULL_CLARK) SUBDIV_TIMED("bscan", k, build_bscan(t, b, slot, s));
       a = slot;
     }
+    const Adj ak = a;
     if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, a, outs[k + 1].edge_verts, s));
     if (scheme == SUBDIV_CATMULL_CLARK) {
       CCStep c{};
@@ -708,7 +710,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else {
-      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0};
+      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev};
       const bool carry = !rebuild && !final;  // level k+1's adjacency in closed form
       if (carry) {
         c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, false);
@@ -719,6 +721,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
         if (carry)
           SUBDIV_TIMED("loop_scan", k, launch_scan(c.base, c.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
+        // the vertex step walks level k-1's adjacency, whose slot the carried
+        // face step overwrites with level k+1's: it runs first
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
         SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
         if (carry) a = c.a1;
@@ -727,14 +731,17 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
           SUBDIV_TIMED("sqrt3_count", k, tri_launch(SQRT3_COUNT, c, s));
           SUBDIV_TIMED("sqrt3_scan", k, launch_scan(c.base, c.base, t.F, at<int32_t>(ws, y.partials), nullptr, s));
         }
-        SUBDIV_TIMED("sqrt3_face", k, tri_launch(SQRT3_FACE, c, s));
+        // the vertex step reads level k-1's adjacency, whose slot the carried
+        // face step overwrites with level k+1's: it runs first
         SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, c, s));
+        SUBDIV_TIMED("sqrt3_face", k, tri_launch(SQRT3_FACE, c, s));
         if (carry) a = c.a1;
       }
     }
     // level k+1 becomes the input of the next step
     t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, L[k + 1].order, nullptr, nullptr, fv1};
     P = P1;
+    aprev = ak;
   }
   return SUBDIV_OK;
 }

@@ -74,6 +74,56 @@ __device__ __forceinline__ Ring ring3(const Topo &t, const Adj &a, const float *
   return R;
 }
 
+// The old vertices v < Vg of a refined level k keep their rings from level
+// k-1: their level-k half-edges are the first slots of the children at their
+// level-(k-1) half-edges, in the same rotation order, and the neighbour along
+// each is a point of level k named by that level-(k-1) half-edge (Loop: the
+// edge point Vg + eid; sqrt(3): the face point Vg + face across it). So the
+// ring is walked on level k-1, whose rows are a third or a quarter as many,
+// visiting the same neighbours in the same order (the sums are the same
+// bits). sqrt(3) fixes boundary vertices, so there only the boundary test is
+// kept (the same half-edges end the walk on both levels).
+__device__ __forceinline__ Ring ring_prev_loop(const TriStep &c, int v) {
+  const Adj &a = c.ap;
+  const int h0 = a.vhe[v];
+  Ring R{{0.f, 0.f, 0.f}, 0, c.Vg + a.eid[h0], -1};
+  int h = h0;
+  while (true) {
+    R.sum = add3(R.sum, ld3(c.P, c.Vg + a.eid[h]));
+    ++R.faces;
+    const int hp = he_prev<3>(c.t, h);
+    const int tw = a.twin[hp];
+    if (tw < 0) {
+      R.ub = c.Vg + a.eid[hp];
+      R.sum = add3(R.sum, ld3(c.P, R.ub));
+      break;
+    }
+    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+  return R;
+}
+
+__device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
+  const Adj &a = c.ap;
+  const int h0 = a.vhe[v];
+  Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
+  int h = h0;
+  while (true) {
+    const int ts = a.twin[h];
+    if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + ts / 3));
+    ++R.faces;
+    const int tw = a.twin[he_prev<3>(c.t, h)];
+    if (tw < 0) {
+      R.ub = 0;  // on the boundary: the vertex stays where it is
+      break;
+    }
+    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+  return R;
+}
+
 // ------------------------------------------------------------------ Loop
 // Carried adjacency of the next level (App. B topology: children 4r+j, j<3,
 // = (v_j, E_j, E_{j-1}) and 4r+3 = (E_0, E_1, E_2), E_j = |v| + e_j).
@@ -149,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
     return;
   }
   const f3 p = ld3(c.P, v);
-  const Ring R = ring3(c.t, c.a, c.P, v);
+  const Ring R = c.Vg > 0 ? ring_prev_loop(c, v) : ring3(c.t, c.a, c.P, v);
   f3 S;
   if (R.ub >= 0) {
     S = fma3(0.75f, p, mul3(0.125f, add3(ld3(c.P, R.w0), ld3(c.P, R.ub))));
@@ -387,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
     return;
   }
   const f3 p = ld3(c.P, v);
-  const Ring R = ring3(c.t, c.a, c.P, v);
+  const Ring R = c.Vg > 0 ? ring_prev_sqrt3(c, v) : ring3(c.t, c.a, c.P, v);
   f3 S;
   if (R.ub >= 0) {
     S = p;
