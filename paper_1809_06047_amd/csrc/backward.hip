@@ -83,54 +83,109 @@ __device__ __forceinline__ void edge_coef(const BwdStep &c, int h, float &m, flo
   u = (1.0f - l) * 0.25f;
 }
 
-// adjoint of the face points, divided by the face order
+// Per face: the adjoint of its face point, divided by the face order, and
+// then every half-edge's share of its origin's gather. Half-edge h (u -> w)
+// carries the terms of g_u that come with the edge (u, w) and the face of h:
+//   term(h) = b_w gV_w + m_e gE_e + gf_q (+ d_w gV_w when u is c1/c2 of w),
+// so the vertex kernel adds one 12-byte term per ring step instead of
+// gathering six arrays at every step.
 template <int ORDER>
 __global__ void __launch_bounds__(kBlock) k_bw_face(BwdStep c) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= c.t.F) return;
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int V = c.t.V, F = c.t.F;
-  const int b = face_begin<ORDER>(c.t, r), en = face_end<ORDER>(c.t, r);
-  f3 g = ld3(c.g1, V + r);
   const float4 *coef = reinterpret_cast<const float4 *>(c.coef);
-  for (int h = b; h < en; ++h) {
-    float m, u;
-    edge_coef(c, h, m, u);
-    if (u != 0.0f) g = fma3(u, ld3(c.g1, V + F + c.a.eid[h]), g);
-    const int w = c.t.fv[h];
-    const float bw = coef[w].y;
-    if (bw != 0.0f) g = fma3(bw, ld3(c.g1, w), g);
+  if (F <= 0) return;
+  if constexpr (ORDER > 0) {
+    // uniform faces: the corners and edges are loaded once, and the terms of
+    // the wave's faces (contiguous) leave through LDS as whole lines
+    __shared__ uint32_t stage[kBlock / 64][64 * (3 * ORDER | 1)];
+    const bool valid = rid < F;
+    const int r = valid ? rid : F - 1;
+    const int l = threadIdx.x & 63;
+    const long long rw = (long long)rid - l;  // first face of the wave
+    const int cnt = (int)min(64ll, (long long)F - rw) * 3 * ORDER;
+    int w[ORDER];
+    float4 cw[ORDER];
+    f3 gw[ORDER], ge[ORDER];
+    float m[ORDER], u[ORDER];
+    f3 g = ld3(c.g1, V + r);
+#pragma unroll
+    for (int i = 0; i < ORDER; ++i) {
+      const int h = ORDER * r + i;
+      w[i] = c.t.fv[h];
+      cw[i] = coef[w[i]];
+      gw[i] = ld3(c.g1, w[i]);
+      ge[i] = ld3(c.g1, V + F + c.a.eid[h]);
+      edge_coef(c, h, m[i], u[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < ORDER; ++i) {
+      if (u[i] != 0.0f) g = fma3(u[i], ge[i], g);
+      if (cw[i].y != 0.0f) g = fma3(cw[i].y, gw[i], g);
+    }
+    const f3 gq = mul3(1.0f / (float)ORDER, g);
+    uint32_t out[3 * ORDER];
+#pragma unroll
+    for (int i = 0; i < ORDER; ++i) {
+      const int h = ORDER * r + i, n = (i + 1) % ORDER;  // h runs from w[i] to w[n]
+      f3 t = add3(fma3(cw[n].y, gw[n], mul3(m[i], ge[i])), gq);
+      const bool bedge = c.a.twin[h] < 0;
+      const bool cedge = c.a.sig && c.a.sig[c.a.eid[h]] > 0.0 && !(__float_as_int(cw[n].w) & 1);
+      if (bedge || cedge) t = fma3(cw[n].z, gw[n], t);  // w[i] is c1/c2 of w[n]
+      out[3 * i + 0] = __float_as_uint(t.x);
+      out[3 * i + 1] = __float_as_uint(t.y);
+      out[3 * i + 2] = __float_as_uint(t.z);
+    }
+    wave_store<3 * ORDER>(stage[threadIdx.x >> 6], out, reinterpret_cast<uint32_t *>(c.term) + 3 * ORDER * rw, l,
+                          cnt);
+  } else {
+    if (rid >= F) return;
+    const int r = rid;
+    const int b = face_begin<ORDER>(c.t, r), en = face_end<ORDER>(c.t, r);
+    f3 g = ld3(c.g1, V + r);
+    for (int h = b; h < en; ++h) {
+      float m, u;
+      edge_coef(c, h, m, u);
+      if (u != 0.0f) g = fma3(u, ld3(c.g1, V + F + c.a.eid[h]), g);
+      const float bw = coef[c.t.fv[h]].y;
+      if (bw != 0.0f) g = fma3(bw, ld3(c.g1, c.t.fv[h]), g);
+    }
+    const f3 gq = mul3(1.0f / (float)(en - b), g);
+    for (int h = b; h < en; ++h) {
+      const int w = c.t.fv[he_next<ORDER>(c.t, h)];
+      const float4 cw = coef[w];
+      const f3 gw = ld3(c.g1, w);
+      float m, u;
+      edge_coef(c, h, m, u);
+      f3 t = add3(fma3(cw.y, gw, mul3(m, ld3(c.g1, V + F + c.a.eid[h]))), gq);
+      const bool bedge = c.a.twin[h] < 0;
+      const bool cedge = c.a.sig && c.a.sig[c.a.eid[h]] > 0.0 && !(__float_as_int(cw.w) & 1);
+      if (bedge || cedge) t = fma3(cw.z, gw, t);  // u is c1/c2 of w
+      st3(c.term, h, t);
+    }
   }
-  st3(c.gf, r, mul3(1.0f / (float)(en - b), g));
 }
 
-// adjoint of the whole level at every vertex
+// adjoint of the whole level at every vertex: its own vertex rule plus the
+// terms of its outgoing half-edges, and on a boundary the incoming boundary
+// edge (u -> v), whose half-edge belongs to u
 template <int ORDER>
 __global__ void __launch_bounds__(kBlock) k_bw_vertex(BwdStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   const int V = c.t.V, F = c.t.F;
   const float4 *coef = reinterpret_cast<const float4 *>(c.coef);
-  const float4 cv = coef[v];
-  f3 g = mul3(cv.x, ld3(c.g1, v));
+  f3 g = mul3(coef[v].x, ld3(c.g1, v));
   const int h0 = c.a.vhe[v];
   int h = h0, n = 0;
   while (true) {
-    const int w = c.t.fv[he_next<ORDER>(c.t, h)];
-    const float4 cw = coef[w];
-    const f3 gw = ld3(c.g1, w);
-    float m, u;
-    edge_coef(c, h, m, u);
-    g = fma3(cw.y, gw, g);                                   // v is a neighbour in w's smooth rule
-    g = fma3(m, ld3(c.g1, V + F + c.a.eid[h]), g);          // edge point of (v, w)
-    g = add3(g, ld3(c.gf, he_face<ORDER>(c.t, h)));         // face point of the face of h
-    const bool bedge = c.a.twin[h] < 0;
-    const bool cedge = c.a.sig && c.a.sig[c.a.eid[h]] > 0.0 && !(__float_as_int(cw.w) & 1);
-    if (bedge || cedge) g = fma3(cw.z, gw, g);               // v is c1/c2 of w
+    g = add3(g, ld3(c.term, h));
     ++n;
     const int hp = he_prev<ORDER>(c.t, h);
     const int t = c.a.twin[hp];
     if (t < 0) {
-      // last edge (u -> v) of a boundary fan: neighbour u, a boundary edge
+      // neighbour u of the last, boundary edge: v is in u's smooth rule (b_u),
+      // takes half of the edge point, and is one of u's two boundary neighbours
       const int uu = c.t.fv[hp];
       const float4 cu = coef[uu];
       const f3 gu = ld3(c.g1, uu);

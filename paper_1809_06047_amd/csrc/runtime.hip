@@ -167,7 +167,7 @@ struct Layout {
   size_t mfv[2], mP[2];
   // SUBDIV_FLAG_KEEP_STATE: adjacency of every level 1..L-1 and the backward scratch
   AdjOffsets keep[SUBDIV_MAX_LEVELS + 1];
-  size_t bg[2], bgf, bcoef;
+  size_t bg[2], bterm, bcoef;
   size_t total;
 };
 
@@ -262,15 +262,15 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     }
   }
   if (flags & SUBDIV_FLAG_KEEP_STATE) {
-    long long gV = L[0].V, gF = L[0].F;
+    long long gV = L[0].V, gH = L[0].H;
     for (int k = 1; k < levels; ++k) {
       y.keep[k] = carve_adj(c, L[k].V, L[k].E, L[k].H, L[k].creases != 0, true);
-      gF = L[k].F > gF ? L[k].F : gF;
+      gH = L[k].H > gH ? L[k].H : gH;
     }
     for (int k = 1; k <= levels; ++k) gV = L[k].V > gV ? L[k].V : gV;
     y.bg[0] = c.take(12 * gV);
     y.bg[1] = c.take(12 * gV);
-    y.bgf = c.take(12 * gF);
+    y.bterm = c.take(12 * gH);
     y.bcoef = c.take(16 * gV);
   }
   y.total = c.at + 256;
@@ -796,7 +796,7 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
     }
     b.g1 = g1;
     b.g0 = (k == 0) ? grad_in : at<float>(ws, y.bg[k & 1]);
-    b.gf = at<float>(ws, y.bgf);
+    b.term = at<float>(ws, y.bterm);
     b.coef = at<float>(ws, y.bcoef);
     SUBDIV_TIMED("bw_coef", k, bw_launch(BW_COEF, b, s));
     SUBDIV_TIMED("bw_face", k, bw_launch(BW_FACE, b, s));

@@ -237,7 +237,7 @@ struct BwdStep {
   Adj a;             // its adjacency (twin, eid, vhe; sig when the level may carry creases)
   const float *g1;   // [V_{k+1}*3] gradient w.r.t. the positions of level k+1
   float *g0;         // [V_k*3] gradient w.r.t. the positions of level k
-  float *gf;         // [F_k*3] scratch: face-point adjoints divided by the face order
+  float *term;       // [H_k*3] scratch: each half-edge's share of its origin's gradient
   float *coef;       // [V_k*4] scratch: vertex-rule coefficients (a, b, d, flags)
 };
 hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s);
