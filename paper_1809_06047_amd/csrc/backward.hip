@@ -31,11 +31,44 @@ struct BwdCoef {
   int flags;  // bit 0: boundary vertex
 };
 
-// forward vertex-rule coefficients of every level-k vertex (ring walk)
+__device__ __forceinline__ BwdCoef smooth_or_blend(int n, int k, double ssum) {
+  const float fn = (float)n;
+  const float sa = 1.0f - 2.0f / fn, sb = 1.0f / (fn * fn);
+  if (k >= 2) {
+    const double s = ssum / (double)k;
+    const float l = s >= 1.0 ? 1.0f : (float)s;
+    return BwdCoef{(1.0f - l) * sa + l * (k == 2 ? 0.75f : 1.0f), (1.0f - l) * sb, k == 2 ? l * 0.125f : 0.0f, 0};
+  }
+  return BwdCoef{sa, sb, 0.0f, 0};
+}
+
+// forward vertex-rule coefficients of every level-k vertex. On a level
+// refined from quads, the face points of level k-1 are interior, of valence
+// 4 and on no crease; an edge point EP(e) has valence 4 unless e is a
+// boundary edge, and its only possible creases are the two halves of e, the
+// level-k edges base(e) and base(e) + 1 (base(e) = 4 e - boundary edges
+// before e). Only the older vertices walk their ring.
 template <int ORDER>
 __global__ void __launch_bounds__(kBlock) k_bw_coef(BwdStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
+  float4 *out = reinterpret_cast<float4 *>(c.coef);
+  if (c.Vp > 0 && v >= c.Vp) {
+    BwdCoef co{0.5f, 0.0625f, 0.0f, 0};  // valence 4, smooth
+    if (v >= c.Vp + c.Fp) {
+      if (c.a.twin[c.a.vhe[v]] < 0) {
+        co = BwdCoef{0.75f, 0.0f, 0.125f, 1};
+      } else if (c.a.sig) {
+        const int e = v - c.Vp - c.Fp;
+        const int base = 4 * e - (c.bscan_p ? c.bscan_p[e] : 0);
+        const double s0 = c.a.sig[base], s1 = c.a.sig[base + 1];
+        const int k = (s0 > 0.0) + (s1 > 0.0);
+        if (k == 2) co = smooth_or_blend(4, 2, s0 + s1);
+      }
+    }
+    out[v] = make_float4(co.a, co.b, co.d, __int_as_float(co.flags));
+    return;
+  }
   const int h0 = c.a.vhe[v];
   const bool bnd = c.a.twin[h0] < 0;
   BwdCoef co;
@@ -58,17 +91,9 @@ __global__ void __launch_bounds__(kBlock) k_bw_coef(BwdStep c) {
       if (t < 0 || t == h0 || n >= SUBDIV_MAX_VALENCE) break;
       h = t;
     }
-    const float fn = (float)n;
-    const float sa = 1.0f - 2.0f / fn, sb = 1.0f / (fn * fn);
-    if (k >= 2) {
-      const double s = ssum / (double)k;
-      const float l = s >= 1.0 ? 1.0f : (float)s;
-      co = BwdCoef{(1.0f - l) * sa + l * (k == 2 ? 0.75f : 1.0f), (1.0f - l) * sb, k == 2 ? l * 0.125f : 0.0f, 0};
-    } else {
-      co = BwdCoef{sa, sb, 0.0f, 0};
-    }
+    co = smooth_or_blend(n, k, ssum);
   }
-  reinterpret_cast<float4 *>(c.coef)[v] = make_float4(co.a, co.b, co.d, __int_as_float(co.flags));
+  out[v] = make_float4(co.a, co.b, co.d, __int_as_float(co.flags));
 }
 
 __device__ __forceinline__ void edge_coef(const BwdStep &c, int h, float &m, float &u) {
@@ -176,6 +201,15 @@ __global__ void __launch_bounds__(kBlock) k_bw_vertex(BwdStep c) {
   const int V = c.t.V, F = c.t.F;
   const float4 *coef = reinterpret_cast<const float4 *>(c.coef);
   f3 g = mul3(coef[v].x, ld3(c.g1, v));
+  if (c.Vp > 0 && v >= c.Vp && v < c.Vp + c.Fp) {
+    // face point of level-k-1 face p: its half-edges are slot 2 of p's four
+    // children, in ring order from its canonical start (child 0)
+    const float *tp = c.term + 48ll * (v - c.Vp);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g = add3(g, ld3(tp, 4 * i + 2));
+    st3(c.g0, v, g);
+    return;
+  }
   const int h0 = c.a.vhe[v];
   int h = h0, n = 0;
   while (true) {

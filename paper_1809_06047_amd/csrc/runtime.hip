@@ -794,6 +794,12 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
       b.a = adj_at(ws, y.keep[k], L[k].E, L[k].creases);
       b.t = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, b.a.fv};
     }
+    if (k >= 2) {  // level k-1 is all quads
+      const Adj ap = adj_at(ws, y.keep[k - 1], L[k - 1].E, false);
+      b.Vp = (int32_t)L[k - 1].V;
+      b.Fp = (int32_t)L[k - 1].F;
+      b.bscan_p = L[k - 1].B > 0 ? ap.bscan : nullptr;
+    }
     b.g1 = g1;
     b.g0 = (k == 0) ? grad_in : at<float>(ws, y.bg[k & 1]);
     b.term = at<float>(ws, y.bterm);

@@ -239,6 +239,12 @@ struct BwdStep {
   float *g0;         // [V_k*3] gradient w.r.t. the positions of level k
   float *term;       // [H_k*3] scratch: each half-edge's share of its origin's gradient
   float *coef;       // [V_k*4] scratch: vertex-rule coefficients (a, b, d, flags)
+  // levels k >= 2 (refined from a quad level k-1): the sizes of level k-1,
+  // whose face and edge points are the level-k vertices [Vp, Vp+Fp) and
+  // [Vp+Fp, V_k), and its boundary prefix (nullptr without a boundary);
+  // Vp = 0 on the levels below
+  int32_t Vp, Fp;
+  const int32_t *bscan_p;
 };
 hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s);
 

@@ -18,10 +18,26 @@ def _oracle_RT(oracle_mod, mesh, levels, g):
     return g, lv
 
 
-@pytest.mark.parametrize("case", ["mixed_creases", "torus", "grid_boundary", "prism"])
+def _grid_with_creases(seed):
+    """Open quad grid with creases tagged on interior and boundary edges."""
+    rng = np.random.default_rng(seed)
+    m = G.grid_patch(6, 5, z_fn=lambda x, y: rng.normal(0, 0.3, x.shape))
+    cv, cs = G.tag_creases(None, m.verts, 4, 14, 4.0, rng)
+    m.crease_verts, m.crease_sharp = cv, cs
+    return m
+
+
+@pytest.mark.parametrize("case", ["mixed_creases", "deep_creases", "grid_creases", "torus", "grid_boundary", "prism"])
 def test_adjoint_equals_oracle_transpose(oracle_mod, case):
+    """Levels k >= 2 take the corner-class coefficient and face-point paths
+    (creases on the halves of edge points, boundary edge points); the cases
+    with four levels carry creases through two such levels."""
     if case == "mixed_creases":
         m, L = G.cc_cage(seed=21, level=2), 3
+    elif case == "deep_creases":
+        m, L = G.cc_cage(seed=24, level=2), 4
+    elif case == "grid_creases":
+        m, L = _grid_with_creases(23), 4
     elif case == "torus":
         m, L = G.torus_cage(n=8), 3
     elif case == "grid_boundary":
