@@ -561,7 +561,19 @@ __global__ void __launch_bounds__(kBlock) k_lag2_combine(Lag2Step c) {
   st3(L.P1, EPg, S);
 }
 
-// level-g vertices: walk the ring on level g, summing the corner terms
+// level-g vertices: the sum of the corner terms over their ring on level g.
+// When level g was itself refined from quads, its face and interior edge
+// points have their four ring half-edges in closed form, listed in the order
+// the walk would visit them from the canonical start (so the sums are the
+// same bits):
+//   face point of quad p':  the slot-2 half-edges 16 p' + 2, + 6, + 10, + 14;
+//   edge point of e' = (a, b): with a one of e''s half-edges whose child
+//     carries the start, an = next(a), the twin of child a's slot 0 is slot 3
+//     of child bn = next(b) on the other side: 4a+1, 4bn+3, 4b+1, 4an+3.
+// Only the older vertices, and boundary edge points, walk.
+__device__ __forceinline__ int quad_next(int h) { return (h & ~3) | ((h + 1) & 3); }
+__device__ __forceinline__ int quad_prev(int h) { return (h & ~3) | ((h + 3) & 3); }
+
 __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.Vg) return;
@@ -585,21 +597,53 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
       ssum += s;
     }
   };
-  while (true) {
-    sum = add3(sum, term0[h]);
-    ++n;
-    hlast = h;
-    if (creases) crease(L.am.eid[4 * h]);
-    const int hp = (h & 3) == 0 ? h + 3 : h - 1;
-    const int t = c.twin_g[hp];
-    if (t < 0) {
-      bnd = true;
-      break;
+  int ring[4];
+  bool closed = false;
+  if (c.Vq > 0 && v >= c.Vq) {
+    if (v < c.Vq + c.Fq) {  // face point: never on a crease or the boundary
+      const int b = 16 * (v - c.Vq) + 2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sum = add3(sum, term0[b + 4 * i]);
+      n = 4;
+      hlast = b + 12;
+    } else {
+      const int a = (h0 & 3) == 1 ? (h0 >> 2) : quad_prev(h0 >> 2);
+      const int tw = c.twin_g[4 * a];
+      if (tw >= 0) {  // interior edge point
+        const int bn = tw >> 2, b = quad_prev(bn);
+        const int cyc[4] = {4 * a + 1, 4 * bn + 3, 4 * b + 1, 4 * quad_next(a) + 3};
+        const int s0 = (h0 & 3) == 1 ? 0 : 3;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ring[j] = cyc[(s0 + j) & 3];
+        closed = true;
+      }
     }
-    if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
-    h = t;
   }
-  if (creases && bnd) crease(L.am.eid[4 * hlast + 3]);  // the incoming boundary edge
+  if (closed) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sum = add3(sum, term0[ring[j]]);
+      if (creases) crease(L.am.eid[4 * ring[j]]);
+    }
+    n = 4;
+    hlast = ring[3];
+  } else if (n == 0) {
+    while (true) {
+      sum = add3(sum, term0[h]);
+      ++n;
+      hlast = h;
+      if (creases) crease(L.am.eid[4 * h]);
+      const int hp = (h & 3) == 0 ? h + 3 : h - 1;
+      const int t = c.twin_g[hp];
+      if (t < 0) {
+        bnd = true;
+        break;
+      }
+      if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
+      h = t;
+    }
+    if (creases && bnd) crease(L.am.eid[4 * hlast + 3]);  // the incoming boundary edge
+  }
   const f3 p = ld3(L.Pk, v);
   f3 S;
   if (bnd) {

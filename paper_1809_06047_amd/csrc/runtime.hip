@@ -445,6 +445,10 @@ int refine_cc_carried(const subdiv_mesh *mesh, const subdiv_level_out *outs, voi
       g2.Fg = (int32_t)L[k - 2].F;
       g2.Eg = (int32_t)L[k - 2].E;
       g2.VFg = g2.Vg + g2.Fg;
+      if (k >= 4) {  // level g = k-2 was itself refined from quads
+        g2.Vq = (int32_t)L[k - 3].V;
+        g2.Fq = (int32_t)L[k - 3].F;
+      }
       g2.vhe_g = ag.vhe;
       g2.twin_g = ag.twin;
       g2.e2h_g = ag.e2h;

@@ -221,6 +221,8 @@ enum { LAG2_GROUP = 0, LAG2_COMBINE = 1, LAG2_OLDER = 2 };
 struct Lag2Step {
   LagStep s;                 // the parent-level view (creases: s.sigk, s.vcrk)
   int32_t Vg, Fg, Eg, VFg;   // grandparent sizes, VFg = Vg + Fg
+  int32_t Vq, Fq;            // sizes of the level below g when it is all quads (else 0): the
+                             // level-g vertices [Vq, Vq+Fq) are its face points, the rest its edge points
   const int32_t *vhe_g;      // grandparent adjacency
   const int32_t *twin_g;
   const int32_t *e2h_g;
