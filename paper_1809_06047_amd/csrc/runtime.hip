@@ -714,7 +714,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else {
-      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev};
+      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev,
+                k >= 2 ? (int32_t)L[k - 2].V : 0};
       const bool carry = !rebuild && !final;  // level k+1's adjacency in closed form
       if (carry) {
         c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, false);

@@ -309,6 +309,7 @@ struct TriStep {
   int32_t nbnd;  // boundary edges of level k (sqrt(3): they keep ids 0 .. nbnd-1 on level k+1)
   int32_t Vg;    // levels >= 1: vertices of the level k was refined from (its old vertices); 0 on the cage
   Adj ap;        // levels >= 1: adjacency of that level (twin, eid, vhe), where the old vertices' rings are walked
+  int32_t Vq;    // levels >= 2: vertices of level k-2 (the old vertices v >= Vq are its edge / face points)
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);

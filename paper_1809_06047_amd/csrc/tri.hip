@@ -83,10 +83,43 @@ __device__ __forceinline__ Ring ring3(const Topo &t, const Adj &a, const float *
 // visiting the same neighbours in the same order (the sums are the same
 // bits). sqrt(3) fixes boundary vertices, so there only the boundary test is
 // kept (the same half-edges end the walk on both levels).
+//
+// One level further down, an old vertex that was itself new on level k-1
+// has its level-(k-1) ring in closed form, listed here in walk order from its
+// canonical start (so again the same bits):
+//   Loop, edge point u of edge j of face r (edge i of the face s across): the
+//     six half-edges slot 1 of child j of r, slot 2 of child i+1 of s, slot i
+//     of s's centre child, slot 1 of child i of s, slot 2 of child j+1 of r,
+//     slot j of r's centre child (h1(q, slot) = 3 q + slot, children 4 r + c);
+//     the start is the first of these or the fifth;
+//   sqrt(3), face point of face r: slot 2 of r's child j (F_r -> v_j) and the
+//     twin of slot 1 of that child (F_r -> F_s in the child of the face s
+//     across edge j), alternating over j; the start is slot 2 of child 0 or
+//     one of those twins. Only interior edge / face points take this form.
 __device__ __forceinline__ Ring ring_prev_loop(const TriStep &c, int v) {
   const Adj &a = c.ap;
   const int h0 = a.vhe[v];
   Ring R{{0.f, 0.f, 0.f}, 0, c.Vg + a.eid[h0], -1};
+  if (c.Vq > 0 && v >= c.Vq) {
+    const int q = h0 / 3, r = q >> 2, cq = q & 3;
+    const bool first = (h0 % 3 == 1);  // else slot 2 of child j+1
+    const int j = first ? cq : (cq + 2) % 3;
+    const int tw = a.twin[12 * r + 3 * j];  // v_j -> E_j: slot 2 of child i+1 of s
+    if (tw >= 0) {
+      const int qs = tw / 3, s = qs >> 2, i = ((qs & 3) + 2) % 3;
+      const int jn = (j + 1) % 3, in = (i + 1) % 3;
+      const int cyc[6] = {12 * r + 3 * j + 1, 12 * s + 3 * in + 2, 12 * s + 9 + i,
+                          12 * s + 3 * i + 1, 12 * r + 3 * jn + 2, 12 * r + 9 + j};
+      const int p0 = first ? 0 : 4;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int x = p0 + t;
+        R.sum = add3(R.sum, ld3(c.P, c.Vg + a.eid[cyc[x < 6 ? x : x - 6]]));
+      }
+      R.faces = 6;
+      return R;
+    }
+  }
   int h = h0;
   while (true) {
     R.sum = add3(R.sum, ld3(c.P, c.Vg + a.eid[h]));
@@ -108,6 +141,27 @@ __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
   const Adj &a = c.ap;
   const int h0 = a.vhe[v];
   Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
+  if (c.Vq > 0 && v >= c.Vq) {
+    const int r = v - c.Vq;
+    const int *tr = a.twin + 9ll * r;
+    const int t1[3] = {tr[1], tr[4], tr[7]}, t2[3] = {tr[2], tr[5], tr[8]};
+    // slot 1 of a child whose edge is interior pairs with slot 1 of the child of s
+    if (t1[0] % 3 == 1 && t1[1] % 3 == 1 && t1[2] % 3 == 1) {
+      int p0 = 0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (h0 == t1[j]) p0 = 2 * j + 1;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int x = p0 + t < 6 ? p0 + t : p0 + t - 6, j = x >> 1;
+        // across F_r -> v_j: the face holding v_j -> F_r; across F_r -> F_s: r's child j
+        const int face = (x & 1) ? 3 * r + j : t2[j] / 3;
+        R.sum = add3(R.sum, ld3(c.P, c.Vg + face));
+      }
+      R.faces = 6;
+      return R;
+    }
+  }
   int h = h0;
   while (true) {
     const int ts = a.twin[h];
