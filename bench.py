@@ -347,11 +347,22 @@ def static_leg(mesh, levels, steps):
         r.run()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # general vertex data: five channels (a UV pair and an RGB colour), three
+    # channels per pass through the same kernels
+    data = torch.rand((mesh.num_vertices, 5), device="cuda")
+    out = r.run_vertex_data(data)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(steps):
+        r.run_vertex_data(data, out=out)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
     faces = r.level_info(levels)["F"]
     ms_pos = (t1 - t0) * 1000.0 / steps
     return {"workload": f"Catmull-Clark levels 0->{levels}, positions only with the topology kept",
             "ms_per_eval": round(ms_pos, 4), "refined_faces_per_s": round(faces / (ms_pos / 1000.0), 1),
-            "ms_per_full_refine_same_plan": round((t2 - t1) * 1000.0 / steps, 4)}
+            "ms_per_full_refine_same_plan": round((t2 - t1) * 1000.0 / steps, 4),
+            "ms_per_vertex_data_eval_5_channels": round((t4 - t3) * 1000.0 / steps, 4)}
 
 
 def adjoint_leg(mesh, levels, steps):

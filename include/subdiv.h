@@ -185,6 +185,24 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
 int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                             size_t ws_bytes, void *stream);
 
+/* General vertex data: UVs, colours, any number of channels (Sec. 3.6:
+ * refinement is linear in the vertex data and every channel goes through the
+ * same R_{L-1} ... R_0, fixed by topology and creases). Refines data
+ * ([V_0*dim] device floats, row-major: vertex v's channels at v*dim) into
+ * out ([V_L*dim] device floats, caller-owned, overwritten), dim >= 1. The
+ * state requirements are those of subdiv_refine_positions (a Catmull-Clark
+ * plan with SUBDIV_FLAG_KEEP_STATE, one completed subdiv_refine with the same
+ * plan, cage topology and workspace). Channels go three at a time through
+ * the kernels of subdiv_refine_positions: channels 3c..3c+2 of out equal, bit
+ * for bit, the positions it writes for those three channels as cage
+ * positions (channels past dim read as zero). Between calls the workspace
+ * holds nothing of the data (the slices use the adjoint's scratch, so a
+ * pending subdiv_backward on the same workspace must be ordered before).
+ * Enqueues work only. Returns SUBDIV_INVALID_ARG for dim < 1 or a null
+ * pointer, SUBDIV_STATE as subdiv_refine_positions. */
+int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *data, int dim,
+                              float *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- batches of uneven meshes (one scheme and level count per batch) ---
  * The meshes are packed into one disjoint union cage and refined together:
  * every stage runs as one launch over all meshes of the batch. Each mesh's

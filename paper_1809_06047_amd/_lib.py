@@ -66,6 +66,8 @@ SIGNATURES = {
                                      ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
     "subdiv_refine_positions": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                                ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_refine_vertex_data": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
+                                                 c_vp, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
     "subdiv_backward": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, c_vp,
                                        c_vp, c_sz, c_vp]),
     "subdiv_batch_workspace_bound": (c_sz, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int,

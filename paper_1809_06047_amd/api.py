@@ -172,6 +172,31 @@ class Refiner:
         check(st, "subdiv_refine_positions")
         return self.outs
 
+    def run_vertex_data(self, data: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """General vertex data ([V_0, dim] float32 on the device, any dim >= 1:
+        UVs, colours, ...) refined with the kept state of the last run, like
+        run_positions (plan with FLAG_KEEP_STATE, Catmull-Clark); returns
+        [V_L, dim]. Enqueues work only."""
+        lib = load()
+        d = self.dmesh
+        dev = torch.device(d.device)
+        same_dev = data.device.type == dev.type and (dev.index is None or data.device.index == dev.index)
+        if data.dim() != 2 or data.shape[0] != d.V or data.dtype != torch.float32 or not same_dev:
+            raise ValueError(f"vertex data must be a [{d.V}, dim] float32 tensor on {d.device}")
+        data = data.contiguous()
+        dim = int(data.shape[1])
+        VL = self.plan_info.level[self.levels].num_vertices
+        if out is None:
+            out = torch.empty((VL, dim), dtype=torch.float32, device=d.device)
+        elif tuple(out.shape) != (VL, dim) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous [{VL}, {dim}] float32 tensor")
+        s = current_stream_handle(d.device) if stream is None else stream
+        st = lib.subdiv_refine_vertex_data(ctypes.byref(d.struct), ctypes.byref(self.plan_info),
+                                           ctypes.c_void_p(data.data_ptr()), dim, ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.c_void_p(s))
+        check(st, "subdiv_refine_vertex_data")
+        return out
+
     @property
     def final(self):
         return self.outs[self.levels]

@@ -45,6 +45,37 @@ hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s) {
   return launch_fill_i32(reinterpret_cast<int32_t *>(p), 0, nbytes / 4, s);
 }
 
+// Vertex data of `dim` channels, row-major [V*dim]: three channels at a time
+// go through the position kernels as a [V*3] array. pack: channels c0..c0+2
+// (those past dim read as zero); unpack: back into their columns.
+__global__ void k_pack3(const float *data, int dim, int c0, long long n3, float *slice) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n3) return;
+  const long long v = x / 3;
+  const int c = c0 + (int)(x - 3 * v);
+  slice[x] = c < dim ? data[v * dim + c] : 0.0f;
+}
+
+__global__ void k_unpack3(const float *slice, int dim, int c0, long long n3, float *out) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n3) return;
+  const long long v = x / 3;
+  const int c = c0 + (int)(x - 3 * v);
+  if (c < dim) out[v * dim + c] = slice[x];
+}
+
+hipError_t launch_pack3(const float *data, int dim, int c0, long long V, float *slice, hipStream_t s) {
+  if (V <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack3, dim3(grid_for(3 * V)), dim3(kBlock), 0, s, data, dim, c0, 3 * V, slice);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack3(const float *slice, int dim, int c0, long long V, float *out, hipStream_t s) {
+  if (V <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack3, dim3(grid_for(3 * V)), dim3(kBlock), 0, s, slice, dim, c0, 3 * V, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------- scan
 // Block-wide scans: 256 threads x 8 items. A wave-64 inclusive scan with
 // cross-lane shuffles, then the 4 wave totals through LDS. Inputs of at most

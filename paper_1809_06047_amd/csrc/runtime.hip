@@ -773,6 +773,40 @@ int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *pla
   return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, mesh->positions, true, s);
 }
 
+int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *data, int dim,
+                              float *out, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !data || !out || !ws || dim < 1) return SUBDIV_INVALID_ARG;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int levels = plan->levels;
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(plan->scheme, levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
+  const Topo t = cage_topo(mesh, H0, ws, y);
+  const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
+  // the adjoint's two gradient buffers (each [max_k V_k * 3]) carry the cage
+  // slice and the final slice; the levels in between use the usual buffers
+  float *slice0 = at<float>(ws, y.bg[0]), *sliceL = at<float>(ws, y.bg[1]);
+  subdiv_mesh m = *mesh;
+  m.positions = slice0;
+  subdiv_level_out outs[SUBDIV_MAX_LEVELS + 1] = {};
+  outs[levels].positions = sliceL;
+  for (int c0 = 0; c0 < dim; c0 += 3) {
+    SUBDIV_TRY(launch_pack3(data, dim, c0, L[0].V, slice0, s));
+    if ((st = refine_cc_carried(&m, outs, ws, y, L, levels, plan->flags, t, a, slice0, true, s)) != SUBDIV_OK)
+      return st;
+    SUBDIV_TRY(launch_unpack3(sliceL, dim, c0, L[levels].V, out, s));
+  }
+  return SUBDIV_OK;
+}
+
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream) {
   if (!plan || !grad_out || !grad_in || !ws) return SUBDIV_INVALID_ARG;
