@@ -196,6 +196,8 @@ def main():
     # timed region: steps two deep (TwoDeep); events around the dominant kernel
     # only, so that the event pairs of the other stages do not sit between the
     # kernels of the step
+    for _ in range(2):  # both refiners' outputs allocated for stream R again
+        pipe.step()
     _lib.timing_select(dname, dlevel)
     _lib.timing_enable(True)
     _lib.timing_read()
@@ -300,6 +302,9 @@ def scheme_leg(mesh, scheme, levels, steps):
     torch.cuda.synchronize()
     stages = _lib.timing_read()
     _lib.timing_enable(False)
+    for _ in range(2):  # both refiners' outputs allocated for stream R before the timed steps
+        pipe.step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()  # timed steps, two deep: no events
     for _ in range(steps):
         pipe.step()
