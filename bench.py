@@ -260,6 +260,7 @@ def main():
                        "the timed steps carry events around the dominant kernel only",
     }
     out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
+    out["selective"] = selective_leg(mesh, 4, 2, 2, max(3, args.steps // 4))
     if args.adjoint_levels > 0:
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
@@ -368,6 +369,44 @@ def static_leg(mesh, levels, steps):
             "ms_per_eval": round(ms_pos, 4), "refined_faces_per_s": round(faces / (ms_pos / 1000.0), 1),
             "ms_per_full_refine_same_plan": round((t2 - t1) * 1000.0 / steps, 4),
             "ms_per_vertex_data_eval_5_channels": round((t4 - t3) * 1000.0 / steps, 4)}
+
+
+def selective_leg(mesh, base_level, rings, extra_levels, steps):
+    """Selective subdivision (Sec. 3.4) on the main cage refined to
+    `base_level` (all quads, 3.5 M faces at level 4): the region `rings`
+    face rings around its extraordinary vertices (valence != 4) is extracted
+    and refined `extra_levels` further, against refining the whole level."""
+    import torch
+    from paper_1809_06047_amd import api
+    outs, _ = api.refine(mesh, "cc", base_level)
+    fv, P = outs[base_level]["face_verts"], outs[base_level]["positions"]
+    dm = api.DeviceMesh.from_tensors(fv, None, P, None, None, 4, name=f"cc-l{base_level}")
+    whole = api.Refiner(dm, "cc", extra_levels)
+    whole.plan()
+    reg = api.extract_region(whole, None, rings)
+    part = api.Refiner(reg["mesh"], "cc", extra_levels)
+    part.plan()
+    torch.cuda.synchronize()
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000.0 / steps
+
+    ms_extract = timed(lambda: api.extract_region(whole, None, rings))  # select (one read-back) + extract
+    ms_region = timed(lambda: (part.plan(), part.run()))
+    ms_whole = timed(lambda: (whole.plan(), whole.run()))
+    return {"workload": f"Catmull-Clark level {base_level} of the 10k cage ({dm.F} quads), region {rings} rings "
+                        f"around the extraordinary vertices, refined {extra_levels} more levels",
+            "region_faces": reg["mesh"].F, "region_vertices": reg["mesh"].V, "whole_faces": dm.F,
+            "ms_select_and_extract": round(ms_extract, 4), "ms_region_plan_refine": round(ms_region, 4),
+            "ms_whole_plan_refine": round(ms_whole, 4),
+            "region_faces_out": part.level_info(extra_levels)["F"],
+            "whole_faces_out": whole.level_info(extra_levels)["F"]}
 
 
 def adjoint_leg(mesh, levels, steps):

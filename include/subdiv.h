@@ -171,6 +171,55 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- selective subdivision: extraction of a region (Sec. 3.4) ----------
+ * x_0 marks the seed vertices; q_i = M^T x_i marks the faces with a marked
+ * corner and x_{i+1} = M q_i their corners, for i < rings. The extraction
+ * M' = X M X-ring keeps the faces of q_{rings-1} and the vertices of x_rings
+ * (the identity with unselected rows / columns deleted), P' = X P. Survivors
+ * keep their relative order: the extracted vertex of rank r is the r-th
+ * selected cage vertex, faces keep their corners in cyclic order. Creases
+ * whose edge is an edge of an extracted face are kept (endpoints renumbered,
+ * same sharpness); the rest are dropped. The extraction is a cage like any
+ * other: plan and refine it with its own workspace.
+ * Both calls need the cage's successful subdiv_plan (any scheme) with the
+ * same mesh and workspace, whose level-0 region holds the selection between
+ * the two calls (a later subdiv_plan into the workspace replaces it). */
+typedef struct subdiv_selection {
+  int32_t num_vertices;   /* V' of the extraction (0: nothing selected) */
+  int32_t num_faces;      /* F' */
+  int32_t num_halfedges;  /* H' */
+  int32_t num_creases;    /* C' */
+  int32_t face_order;     /* the cage's uniform order (3 or 4), or 0: the extraction has a column pointer */
+  int32_t rings;
+  uint64_t priv_stamp;    /* private: the plan it was made with */
+  const void *priv_ws;
+} subdiv_selection;
+
+/* Caller-allocated device buffers of the extraction, sized from a selection. */
+typedef struct subdiv_extraction {
+  int32_t *face_offsets;     /* [F'+1] when face_order == 0, else unused */
+  int32_t *face_verts;       /* [H'] extracted vertex ids */
+  float *positions;          /* [V'*3] copies of the selected cage positions */
+  int32_t *crease_verts;     /* [2*C'] (may be NULL when C' = 0) */
+  float *crease_sharpness;   /* [C'] */
+  int32_t *vertex_map;       /* [V'] cage id of every extracted vertex, or NULL */
+  int32_t *face_map;         /* [F'] cage id of every extracted face, or NULL */
+} subdiv_extraction;
+
+/* Selection: seed is a [V] device byte mask (non-zero = selected) or NULL for
+ * the extraordinary vertices, those whose valence n = M 1 (eq:vo: incident
+ * faces) is not 4 (on an open cage this includes the boundary). rings >= 1.
+ * Reads back the extraction's sizes into *sel (one synchronisation of the
+ * stream). Returns SUBDIV_STATE without the cage's plan in this workspace. */
+int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings, void *ws,
+                  size_t ws_bytes, subdiv_selection *sel, void *stream);
+
+/* Extraction into the caller's buffers; enqueues work only. An empty
+ * selection writes nothing. Returns SUBDIV_STATE when sel was not made with
+ * this plan and workspace, SUBDIV_INVALID_ARG for a missing buffer. */
+int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const subdiv_selection *sel,
+                   const subdiv_extraction *out, void *ws, size_t ws_bytes, void *stream);
+
 /* Static topology (Sec. 3.6: P_L = R_{L-1} ... R_0 P_0 with every R_k fixed
  * by topology and creases). Re-evaluates the positions of a Catmull-Clark
  * refinement planned with SUBDIV_FLAG_KEEP_STATE, after one completed

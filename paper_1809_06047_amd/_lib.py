@@ -51,6 +51,16 @@ class subdiv_stage_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("level", c_i32), ("launches", c_i32), ("total_ms", ctypes.c_double)]
 
 
+class subdiv_selection(ctypes.Structure):
+    _fields_ = [("num_vertices", c_i32), ("num_faces", c_i32), ("num_halfedges", c_i32), ("num_creases", c_i32),
+                ("face_order", c_i32), ("rings", c_i32), ("priv_stamp", c_u64), ("priv_ws", c_vp)]
+
+
+class subdiv_extraction(ctypes.Structure):
+    _fields_ = [("face_offsets", c_vp), ("face_verts", c_vp), ("positions", c_vp), ("crease_verts", c_vp),
+                ("crease_sharpness", c_vp), ("vertex_map", c_vp), ("face_map", c_vp)]
+
+
 class subdiv_batch_plan(ctypes.Structure):
     _fields_ = [("num_meshes", c_i32), ("scheme", c_i32), ("levels", c_i32), ("flags", c_u32),
                 ("union_plan", subdiv_plan_info), ("workspace_bytes", c_sz), ("priv_ws", c_vp),
@@ -70,6 +80,11 @@ SIGNATURES = {
                                                  c_vp, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
     "subdiv_backward": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, c_vp,
                                        c_vp, c_sz, c_vp]),
+    "subdiv_select": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, ctypes.c_int,
+                                     c_vp, c_sz, ctypes.POINTER(subdiv_selection), c_vp]),
+    "subdiv_extract": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
+                                      ctypes.POINTER(subdiv_selection), ctypes.POINTER(subdiv_extraction), c_vp, c_sz,
+                                      c_vp]),
     "subdiv_batch_workspace_bound": (c_sz, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              c_u32]),
     "subdiv_plan_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int, c_u32,

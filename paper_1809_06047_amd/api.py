@@ -258,6 +258,50 @@ def refine(mesh, scheme, levels: int, flags: int = 0, keep: str = "final", edges
     return outs, r
 
 
+def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int = 1, stream=None) -> Dict:
+    """Selective subdivision (Sec. 3.4): the region around the seed vertices
+    of `r`'s cage (planned with r.plan()), `rings` face rings deep, as a cage
+    of its own. seed: [V] uint8/bool device mask, or None for the
+    extraordinary vertices (valence != 4). Returns the extracted arrays, the
+    maps back to the cage and a DeviceMesh of the extraction ("mesh", None
+    when nothing is selected). Synchronises once (the sizes)."""
+    lib = load()
+    d = r.dmesh
+    s = current_stream_handle(d.device) if stream is None else stream
+    seed_ptr = None
+    if seed is not None:
+        if seed.shape != (d.V,) or seed.dtype not in (torch.uint8, torch.bool) or not seed.is_cuda:
+            raise ValueError(f"seed must be a [{d.V}] uint8 or bool device tensor")
+        seed = seed.to(torch.uint8).contiguous()
+        seed_ptr = ctypes.c_void_p(seed.data_ptr())
+    sel = _lib.subdiv_selection()
+    check(lib.subdiv_select(ctypes.byref(d.struct), ctypes.byref(r.plan_info), seed_ptr, int(rings),
+                            ctypes.c_void_p(r.ws.data_ptr()), r.ws_bytes, ctypes.byref(sel), ctypes.c_void_p(s)),
+          "subdiv_select")
+    V1, F1, H1, C1, order = sel.num_vertices, sel.num_faces, sel.num_halfedges, sel.num_creases, sel.face_order
+    dev = d.device
+    out = {"positions": torch.empty((V1, 3), dtype=torch.float32, device=dev),
+           "face_verts": torch.empty(H1, dtype=torch.int32, device=dev),
+           "face_offsets": (torch.empty if F1 else torch.zeros)(F1 + 1, dtype=torch.int32, device=dev)
+           if order == 0 else None,
+           "crease_verts": torch.empty((C1, 2), dtype=torch.int32, device=dev) if C1 else None,
+           "crease_sharpness": torch.empty(C1, dtype=torch.float32, device=dev) if C1 else None,
+           "vertex_map": torch.empty(V1, dtype=torch.int32, device=dev),
+           "face_map": torch.empty(F1, dtype=torch.int32, device=dev)}
+    e = _lib.subdiv_extraction()
+    for k in ("positions", "face_verts", "face_offsets", "crease_verts", "vertex_map", "face_map"):
+        if out[k] is not None and out[k].numel():
+            setattr(e, k, out[k].data_ptr())
+    if out["crease_sharpness"] is not None:
+        e.crease_sharpness = out["crease_sharpness"].data_ptr()
+    check(lib.subdiv_extract(ctypes.byref(d.struct), ctypes.byref(r.plan_info), ctypes.byref(sel), ctypes.byref(e),
+                             ctypes.c_void_p(r.ws.data_ptr()), r.ws_bytes, ctypes.c_void_p(s)), "subdiv_extract")
+    out["mesh"] = None if V1 == 0 else DeviceMesh.from_tensors(
+        out["face_verts"], out["face_offsets"], out["positions"], out["crease_verts"], out["crease_sharpness"],
+        order if order else 0, name=f"{d.name}-region")
+    return out
+
+
 def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
     """Status subdiv_plan reports for this cage (0 = accepted)."""
     try:

@@ -271,10 +271,12 @@ __global__ void k_build_faces(Topo t, int scheme, int32_t *nval, int32_t *hface_
 
 // The kernels after the validation pass run in the same stream without a
 // host round trip; once any fault is recorded they do nothing (indices of an
-// invalid cage may be out of range), and the plan reports the fault.
-__device__ __forceinline__ bool faulted(const DeviceInfo *info) {
-  return *reinterpret_cast<const volatile uint32_t *>(&info->faults) != 0;
-}
+// invalid cage may be out of range), and the plan reports the fault. The
+// faults that matter were recorded by earlier kernels of the stream, whose
+// writes every later kernel sees, so a plain (cached, uniform) load is
+// enough; a volatile one sent every lane's load to memory and made a large
+// cage's build twice as slow.
+__device__ __forceinline__ bool faulted(const DeviceInfo *info) { return info->faults != 0; }
 
 // 3. row view of M: half-edges leaving each vertex
 __global__ void k_build_incidence(Topo t, const int32_t *rowptr, int32_t *cursor, int32_t *inc,
@@ -467,15 +469,21 @@ template <int ORDER>
 __global__ void k_build_vertex(Topo t, const int32_t *rowptr, int32_t *inc, int32_t *cand, int32_t *twin,
                                int32_t *vhe, int32_t *cntlo, DeviceInfo *info) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= t.V || faulted(info)) return;
-  const int r0 = rowptr[v], n = rowptr[v + 1] - r0;
+  const bool live = v < t.V && !faulted(info);
+  const int r0 = live ? rowptr[v] : 0, n = live ? rowptr[v + 1] - r0 : 0;
+  // the largest valence: reduced over the wave first, one atomic per wave
+  // (one per vertex on a single word serialises a large cage's build)
+  int vmax = n;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) vmax = max(vmax, __shfl_xor(vmax, o, 64));
+  if ((threadIdx.x & 63) == 0 && vmax > 0) atomicMax(&info->max_valence, vmax);
+  if (!live) return;
   if (n == 0 || n > SUBDIV_MAX_VALENCE) {
     atomicOr(&info->faults, n == 0 ? FAULT_DEGENERATE : FAULT_INVALID_ARG);
     vhe[v] = -1;
     cntlo[v] = 0;
     return;
   }
-  atomicMax(&info->max_valence, n);
   if (n <= kRegValence) vertex_row_regs<ORDER>(t, v, r0, n, inc, cand, twin, vhe, cntlo, info);
   else vertex_row_general<ORDER>(t, v, r0, n, inc, cand, twin, vhe, cntlo, info);
 }

@@ -157,6 +157,7 @@ struct Layout {
   size_t nval, rowptr, cursor, inc, cand, cntlo, ebase, bflag, sigcnt, partials0;
   size_t hface0;
   AdjOffsets adj0;
+  size_t sel_x[2], sel_q, sel_vnew, sel_fnew, sel_onew, sel_flag, sel_cnew, sel_totals;  // selective extraction
   size_t level0_end;
   // per-level regions
   AdjOffsets slot[3];  // adjacency of levels k-2, k-1, k rotate through these (index level % 3)
@@ -208,6 +209,16 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   y.hface0 = c.take(4 * H0);
   // level-0 adjacency: edge-indexed arrays sized by H0 >= E0
   y.adj0 = carve_adj(c, V0, H0, H0, C0 > 0, false);
+  const long long F0 = L[0].F;
+  y.sel_x[0] = c.take(4 * V0);
+  y.sel_x[1] = c.take(4 * V0);
+  y.sel_q = c.take(4 * F0);
+  y.sel_vnew = c.take(4 * (V0 + 1));
+  y.sel_fnew = c.take(4 * (F0 + 1));
+  y.sel_onew = c.take(4 * (F0 + 1));
+  y.sel_flag = c.take(4 * ((F0 > H0 ? F0 : H0) + 1));
+  y.sel_cnew = c.take(4 * (H0 + 1));
+  y.sel_totals = c.take(16);
   y.level0_end = c.at;
   // everything below may depend on the level count and on E0
   long long maxn = 1;
@@ -309,6 +320,21 @@ BuildScratch scratch0(void *ws, const Layout &y) {
   b.sigcnt = at<int32_t>(ws, y.sigcnt);
   b.partials = at<int32_t>(ws, y.partials0);
   return b;
+}
+
+SelectScratch select_scratch(void *ws, const Layout &y) {
+  SelectScratch w{};
+  w.x[0] = at<int32_t>(ws, y.sel_x[0]);
+  w.x[1] = at<int32_t>(ws, y.sel_x[1]);
+  w.q = at<int32_t>(ws, y.sel_q);
+  w.vnew = at<int32_t>(ws, y.sel_vnew);
+  w.fnew = at<int32_t>(ws, y.sel_fnew);
+  w.onew = at<int32_t>(ws, y.sel_onew);
+  w.flag = at<int32_t>(ws, y.sel_flag);
+  w.cnew = at<int32_t>(ws, y.sel_cnew);
+  w.partials = at<int32_t>(ws, y.partials0);
+  w.totals = at<int32_t>(ws, y.sel_totals);
+  return w;
 }
 
 BuildScratch scratch_rebuild(void *ws, const Layout &y) {
@@ -804,6 +830,68 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
       return st;
     SUBDIV_TRY(launch_unpack3(sliceL, dim, c0, L[levels].V, out, s));
   }
+  return SUBDIV_OK;
+}
+
+int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings, void *ws,
+                  size_t ws_bytes, subdiv_selection *sel, void *stream) {
+  if (!sel) return SUBDIV_INVALID_ARG;
+  std::memset(sel, 0, sizeof(*sel));
+  if (!plan || !ws || !mesh || rings < 1) return SUBDIV_INVALID_ARG;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(plan->scheme, plan->levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(plan->scheme, plan->levels, plan->flags, L, mesh->num_creases);
+  const Topo t = cage_topo(mesh, H0, ws, y);
+  const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0);
+  const SelectScratch w = select_scratch(ws, y);
+  SUBDIV_TRY(select_region(t, a, w, seed, at<int32_t>(ws, y.nval), rings, s));
+  int32_t tot[4];
+  SUBDIV_TRY(hipMemcpyAsync(tot, w.totals, sizeof(tot), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipStreamSynchronize(s));
+  sel->num_vertices = tot[0];
+  sel->num_faces = tot[1];
+  sel->num_halfedges = t.order > 0 ? tot[1] * t.order : tot[2];
+  sel->num_creases = tot[3];
+  sel->face_order = t.order;
+  sel->rings = rings;
+  sel->priv_stamp = plan->priv_stamp;
+  sel->priv_ws = ws;
+  return SUBDIV_OK;
+}
+
+int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const subdiv_selection *sel,
+                   const subdiv_extraction *out, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !sel || !out || !ws || !mesh) return SUBDIV_INVALID_ARG;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws ||
+      sel->priv_stamp != plan->priv_stamp || sel->priv_ws != ws)
+    return SUBDIV_STATE;
+  int st = check_mesh_args(mesh, plan->scheme, plan->levels);
+  if (st != SUBDIV_OK) return st;
+  if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
+  if (sel->num_vertices == 0) return SUBDIV_OK;
+  if (!out->face_verts || !out->positions || (sel->face_order == 0 && !out->face_offsets) ||
+      (sel->num_creases > 0 && (!out->crease_verts || !out->crease_sharpness)))
+    return SUBDIV_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(plan->scheme, plan->levels, mesh->num_vertices, mesh->num_faces, H0, plan->level[0].num_edges,
+              plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
+              L);
+  const Layout y = make_layout(plan->scheme, plan->levels, plan->flags, L, mesh->num_creases);
+  const Topo t = cage_topo(mesh, H0, ws, y);
+  const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0);
+  ExtractOut o{out->face_verts, out->face_offsets, out->face_map, out->vertex_map, out->crease_verts,
+               out->positions, out->crease_sharpness, sel->num_faces, sel->num_creases};
+  SUBDIV_TRY(extract_region(t, a, select_scratch(ws, y), sel->rings, mesh->positions, o, s));
   return SUBDIV_OK;
 }
 

@@ -253,6 +253,27 @@ struct BwdStep {
 };
 hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s);
 
+// ---- selective subdivision: extraction of a region of a cage ------------
+struct SelectScratch {
+  int32_t *x[2];               // [V] vertex flags, alternating over the rings (the last in x[rings & 1])
+  int32_t *q;                  // [F] face flags
+  int32_t *vnew, *fnew, *onew; // [V+1], [F+1], [F+1] exclusive scans: new vertex / face ids, corner offsets
+  int32_t *flag;               // [max(F, H)+1] corner counts of a general cage, then crease flags
+  int32_t *cnew;               // [H+1] crease ids
+  int32_t *partials;           // scan partials (max(V, H) items)
+  int32_t *totals;             // [4] V', F', H' (general cages), C'
+};
+struct ExtractOut {
+  int32_t *fv, *off, *fmap, *vmap, *cv;
+  float *P, *cs;
+  int32_t F, C;
+};
+// flags and scans; totals are left on the device for one read-back
+hipError_t select_region(const Topo &t, const Adj &a, const SelectScratch &w, const uint8_t *seed,
+                         const int32_t *valence, int rings, hipStream_t s);
+hipError_t extract_region(const Topo &t, const Adj &a, const SelectScratch &w, int rings, const float *P,
+                          const ExtractOut &o, hipStream_t s);
+
 // ---- batches: meshes packed into one disjoint union cage ---------------
 struct BatchMesh {        // one mesh of a batch (device table entry)
   const int32_t *fv;
