@@ -109,36 +109,20 @@ def cpu_baseline(mesh, levels):
 
 
 class TwoDeep:
-    """Steps run two deep. Step i is planned on stream P into its own
-    workspace (two refiners alternate) while step i-1 still refines on stream
-    R; its refinement then queues on R behind step i-1's. Every step
-    validates, builds and refines its cage in full: the overlap only fills
-    the time the host spends waiting for the plan's read-back. A plan waits
-    for the refinement that last used its workspace. Both streams have the
-    default priority."""
+    """Steps two deep through api.StreamingRefiner: step i is planned on a
+    second stream, into the second of two workspaces, while step i-1 still
+    refines; every step validates, builds and refines its cage in full."""
 
     def __init__(self, dmesh, levels, scheme="cc"):
-        import torch
         from paper_1809_06047_amd import api
-        self.torch = torch
-        self.rs = [api.Refiner(dmesh, scheme, levels) for _ in range(2)]
-        self.P, self.R = torch.cuda.Stream(), torch.cuda.Stream()
-        self.done = [None, None]
-        self.i = 0
+        self.dmesh = dmesh
+        self.sr = api.StreamingRefiner(scheme, levels)
+        for _ in range(2):  # both slots' refiners exist from the start
+            self.sr.step(dmesh)
+        self.rs = [self.sr.refiner(0), self.sr.refiner(1)]
 
     def step(self):
-        torch = self.torch
-        j = self.i & 1
-        r = self.rs[j]
-        if self.done[j] is not None:
-            self.P.wait_event(self.done[j])
-        with torch.cuda.stream(self.R):  # outputs are allocated for, and written on, R
-            r.plan(stream=self.P.cuda_stream)
-            r.run(stream=self.R.cuda_stream)
-            e = torch.cuda.Event()
-            e.record(self.R)
-        self.done[j] = e
-        self.i += 1
+        self.sr.step(self.dmesh)
 
 
 def main():
