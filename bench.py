@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -245,6 +247,7 @@ def main():
     }
     out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
     out["selective"] = selective_leg(mesh, 4, 2, 2, max(3, args.steps // 4))
+    out["reorder"] = reorder_leg(mesh, args.levels, max(5, args.steps // 2))
     if args.adjoint_levels > 0:
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
@@ -353,6 +356,43 @@ def static_leg(mesh, levels, steps):
             "ms_per_eval": round(ms_pos, 4), "refined_faces_per_s": round(faces / (ms_pos / 1000.0), 1),
             "ms_per_full_refine_same_plan": round((t2 - t1) * 1000.0 / steps, 4),
             "ms_per_vertex_data_eval_5_channels": round((t4 - t3) * 1000.0 / steps, 4)}
+
+
+def reorder_leg(mesh, levels, steps, seed=5):
+    """Mesh reordering (Sec. 4.5): the main cage with its vertices and faces
+    in a seeded random order, and that cage after reverse Cuthill-McKee,
+    refined to `levels` (plan + refine per step, one at a time), beside the
+    cage in its generated order."""
+    import torch
+    from paper_1809_06047_amd import api
+    from paper_1809_06047_amd import meshgen as G
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(mesh.num_vertices)  # old -> new
+    inv = np.argsort(p)
+    faces = [[int(p[v]) for v in f] for f in mesh.face_list()]
+    faces = [faces[i] for i in rng.permutation(len(faces))]
+    offs = np.concatenate([[0], np.cumsum([len(f) for f in faces])]).astype(np.int32)
+    shuffled = G.Mesh(positions=np.asarray(mesh.positions)[inv], verts=np.array([v for f in faces for v in f], np.int32),
+                      offsets=offs, crease_verts=p[np.asarray(mesh.crease_verts)].astype(np.int32),
+                      crease_sharp=mesh.crease_sharp, name="shuffled")
+    t0 = time.perf_counter()
+    rcm, _, _ = api.rcm_reorder(shuffled)
+    ms_rcm_host = (time.perf_counter() - t0) * 1000.0
+    out = {"workload": f"Catmull-Clark levels 0->{levels}: the 10k cage as generated, with vertices and faces "
+                       f"shuffled (seed {seed}), and the shuffled cage after reverse Cuthill-McKee",
+           "ms_rcm_order_host": round(ms_rcm_host, 3)}
+    for name, m in (("generated", mesh), ("shuffled", shuffled), ("rcm_of_shuffled", rcm)):
+        r = api.Refiner(api.DeviceMesh(m, "cuda"), "cc", levels)
+        r.plan()
+        r.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r.plan()
+            r.run()
+        torch.cuda.synchronize()
+        out[f"ms_per_step_{name}"] = round((time.perf_counter() - t0) * 1000.0 / steps, 4)
+    return out
 
 
 def selective_leg(mesh, base_level, rings, extra_levels, steps):

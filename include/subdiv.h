@@ -171,6 +171,21 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- mesh reordering (Sec. 4.5) --------------------------------------------
+ * Reverse Cuthill-McKee on the cage's vertex graph, for locality of the rows
+ * and columns of M in memory. HOST pointers: face_offsets ([F+1], or NULL
+ * for a uniform face_order) and face_verts ([H]) as in subdiv_mesh;
+ * vertex_perm [V] and face_perm [F] receive new id -> old id. Each connected
+ * component starts at its unvisited vertex of smallest degree (distinct
+ * neighbours; smaller id first), a dequeued vertex appends its unvisited
+ * neighbours by increasing (degree, id), and the sequence is reversed. Faces
+ * are ordered by the smallest new id among their corners (their first
+ * non-zero), then by old id; applying the permutations (corners renumbered,
+ * cyclic order kept) is the caller's. Runs on the host, synchronously.
+ * Returns SUBDIV_INVALID_ARG for sizes, pointers or indices out of range. */
+int subdiv_rcm_order(int32_t num_vertices, int32_t num_faces, const int32_t *face_offsets, int32_t face_order,
+                     const int32_t *face_verts, int32_t *vertex_perm, int32_t *face_perm);
+
 /* ---- selective subdivision: extraction of a region (Sec. 3.4) ----------
  * x_0 marks the seed vertices; q_i = M^T x_i marks the faces with a marked
  * corner and x_{i+1} = M q_i their corners, for i < rings. The extraction

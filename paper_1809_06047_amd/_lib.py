@@ -80,6 +80,7 @@ SIGNATURES = {
                                                  c_vp, ctypes.c_int, c_vp, c_vp, c_sz, c_vp]),
     "subdiv_backward": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, c_vp,
                                        c_vp, c_sz, c_vp]),
+    "subdiv_rcm_order": (ctypes.c_int, [c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "subdiv_select": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, ctypes.c_int,
                                      c_vp, c_sz, ctypes.POINTER(subdiv_selection), c_vp]),
     "subdiv_extract": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),

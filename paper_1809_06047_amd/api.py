@@ -302,6 +302,38 @@ def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int
     return out
 
 
+def rcm_reorder(mesh):
+    """Mesh reordering (Sec. 4.5) of a host cage (meshgen.Mesh): the library's
+    reverse Cuthill-McKee permutations applied to it. Returns (reordered
+    mesh, vertex_perm, face_perm), perms mapping new id -> old id."""
+    from . import meshgen
+    lib = load()
+    V, F = mesh.num_vertices, mesh.num_faces
+    verts = np.ascontiguousarray(mesh.verts, np.int32)
+    offs = None if mesh.offsets is None else np.ascontiguousarray(mesh.offsets, np.int32)
+    vperm = np.empty(V, np.int32)
+    fperm = np.empty(F, np.int32)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    check(lib.subdiv_rcm_order(V, F, ptr(offs), 0 if offs is not None else int(mesh.face_order), ptr(verts),
+                               ptr(vperm), ptr(fperm)), "subdiv_rcm_order")
+    newid = np.empty(V, np.int32)
+    newid[vperm] = np.arange(V, dtype=np.int32)
+    if offs is None:
+        k = int(mesh.face_order)
+        nverts = newid[verts.reshape(F, k)[fperm]].reshape(-1)
+        noffs = None
+    else:
+        sizes = np.diff(offs)[fperm]
+        noffs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        idx = np.concatenate([np.arange(offs[f], offs[f + 1]) for f in fperm])
+        nverts = newid[verts[idx]]
+    cv = None if mesh.crease_verts is None else newid[np.asarray(mesh.crease_verts, np.int32)]
+    out = meshgen.Mesh(positions=np.asarray(mesh.positions)[vperm], verts=nverts.astype(np.int32), offsets=noffs,
+                       face_order=mesh.face_order if offs is None else 0, crease_verts=cv,
+                       crease_sharp=mesh.crease_sharp, name=f"{mesh.name}-rcm")
+    return out, vperm, fperm
+
+
 def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
     """Status subdiv_plan reports for this cage (0 = accepted)."""
     try:
