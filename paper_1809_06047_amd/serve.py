@@ -327,20 +327,35 @@ def _packed(mesh) -> tuple:
 
 
 class GpuBatchExecutor:
-    """Runs each batch through the library's batch entry points on its
-    slot's stream (all streams at the default priority): one upload of the
-    packed cages, one workspace, one allocation per output kind."""
+    """Runs each batch through the library's batch entry points (all streams
+    at the default priority): one upload of the packed cages, one workspace,
+    one allocation per output kind.
 
-    def __init__(self, device="cuda", slots: int = 1, reserve_bytes: int = 0):
+    one_refine_stream=False: every slot plans and refines on its own stream.
+    one_refine_stream=True: plans go to a plan stream and every refinement to
+    one refine stream, so with two slots the next batch is uploaded and
+    planned while the previous one refines, and its refinement queues behind
+    it instead of running beside it. A batch's cage upload and workspace are
+    allocated for the plan stream and its outputs for the refine stream; all
+    of them are released only after the batch has retired."""
+
+    def __init__(self, device="cuda", slots: int = 1, reserve_bytes: int = 0, one_refine_stream: bool = False):
         import torch
         from . import _lib
         self.torch = torch
         self._lib = _lib
         self.lib = _lib.load()
         self.device = torch.device(device)
-        self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
-        for s in self.streams:
-            reserve(self.device, reserve_bytes, s)
+        self.one_refine_stream = one_refine_stream
+        if one_refine_stream:
+            self.plan_stream = torch.cuda.Stream(self.device)
+            self.refine_stream = torch.cuda.Stream(self.device)
+            for s in (self.plan_stream, self.refine_stream):
+                reserve(self.device, reserve_bytes, s)
+        else:
+            self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
+            for s in self.streams:
+                reserve(self.device, reserve_bytes, s)
 
     def prepare(self, r: Request):
         m = r.mesh
@@ -369,7 +384,10 @@ class GpuBatchExecutor:
     def launch(self, reqs, scheme, levels, slot):
         import ctypes
         torch, L, lib = self.torch, self._lib, self.lib
-        s = self.streams[slot]
+        if self.one_refine_stream:
+            s, rs = self.plan_stream, self.refine_stream
+        else:
+            s = rs = self.streams[slot]
         n = len(reqs)
         sid = L.SCHEMES[scheme]
         try:
@@ -398,6 +416,8 @@ class GpuBatchExecutor:
                 L.check(lib.subdiv_plan_batch(structs, n, sid, levels, 0, ctypes.c_void_p(ws.data_ptr()), ws_bytes,
                                               ctypes.byref(bplan), plans, ctypes.c_void_p(s.cuda_stream)),
                         "subdiv_plan_batch")
+            # (the plan read back on s: its work is done before the refinement below starts)
+            with torch.cuda.stream(rs):
                 # outputs: one int32 and one float32 allocation, every face table 16-byte aligned
                 hs = [int(plans[k].level[levels].num_halfedges) for k in range(n)]
                 vs = [int(plans[k].level[levels].num_vertices) for k in range(n)]
@@ -410,9 +430,9 @@ class GpuBatchExecutor:
                     outs[k].face_verts = fv.data_ptr() + 4 * int(hofs[k])
                     outs[k].positions = P.data_ptr() + 12 * int(vofs[k])
                 L.check(lib.subdiv_refine_batch(structs, n, ctypes.byref(bplan), outs, ctypes.c_void_p(ws.data_ptr()),
-                                                ws_bytes, ctypes.c_void_p(s.cuda_stream)), "subdiv_refine_batch")
+                                                ws_bytes, ctypes.c_void_p(rs.cuda_stream)), "subdiv_refine_batch")
                 ev = torch.cuda.Event()
-                ev.record(s)
+                ev.record(rs)
         except torch.cuda.OutOfMemoryError as e:
             raise ExecutorOOM(str(e)) from e
         return dict(ev=ev, keep=(dev, ws, fv, P), hofs=hofs, hs=hs, vofs=vofs)
@@ -473,10 +493,13 @@ def _retime(reqs: List[Request], base_times: np.ndarray, qps: float) -> List[Req
 
 
 def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), seed: int = 4, budget_gib: float = 64.0,
-          slots: int = 1, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
-          log=print) -> Dict:
+          slots: int = 2, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
+          log=print, one_refine_stream: bool = True) -> Dict:
     """Measure the per-mesh-launch saturation rate, then serve the trace at
-    each factor x that rate with the batched server and the baseline."""
+    each factor x that rate with the batched server and the baseline. By
+    default two batches are in flight: the next one is uploaded and planned
+    while the previous one refines, and refinements run one after the other
+    on one stream."""
     import torch
     trace = make_trace(n_requests, seed=seed, qps=1.0)
     base_t = np.array([r.arrival for r in trace])
@@ -484,7 +507,7 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), s
     # large request needs (one segment per stream they use)
     reserve_bytes = int(min(budget_gib, 8.0) * 2**30) // max(1, slots)
     reserve(device, reserve_bytes)
-    ex = GpuBatchExecutor(device, slots, reserve_bytes)
+    ex = GpuBatchExecutor(device, slots, reserve_bytes, one_refine_stream=one_refine_stream)
     # warm-up of both paths: one request of every (scheme, levels) group and
     # the head of the trace, all arriving at once
     seen, warm = set(), []

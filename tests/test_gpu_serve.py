@@ -23,10 +23,15 @@ def _trace(n, seed, tmax=3000.0):
     return reqs
 
 
-def test_batched_server_outputs_equal_solo_refinement():
+@pytest.mark.parametrize("one_refine_stream", [False, True])
+def test_batched_server_outputs_equal_solo_refinement(one_refine_stream):
+    """Two batches in flight, each on its own stream or (two deep) planned on
+    a plan stream while the previous one refines on the shared refine stream."""
     reqs = _trace(48, 21)
-    print(f"[serve] 48 requests, faces {[r.mesh.num_faces for r in reqs[:6]]}...", flush=True)
-    srv = S.Server(S.GpuBatchExecutor("cuda", 2), 8 * 2**30, slots=2, max_batch=16, keep_results=True)
+    print(f"[serve] 48 requests, one refine stream {one_refine_stream}, "
+          f"faces {[r.mesh.num_faces for r in reqs[:6]]}...", flush=True)
+    srv = S.Server(S.GpuBatchExecutor("cuda", 2, one_refine_stream=one_refine_stream), 8 * 2**30, slots=2,
+                   max_batch=16, keep_results=True)
     st = srv.run(reqs)
     assert st["rejected"] == 0 and st["batches"] < len(reqs)
     torch.cuda.synchronize()
