@@ -73,3 +73,32 @@ def test_plan_rejects_bad_arguments_without_device(lib):
     m.face_verts = 16 + 4  # face tables are read as int4 rows: 16-byte alignment is required
     assert lib.subdiv_plan(ctypes.byref(m), 0, 1, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
     assert lib.subdiv_workspace_bound(4, 1, 4, 0, 0, 1, 0) > 0  # sizes alone carry no pointers
+
+
+def test_later_entry_points_reject_bad_arguments_without_device(lib):
+    """Vertex data, selection, extraction and the backward check their
+    arguments and the plan's state on the host before any device work."""
+    info = _lib.subdiv_plan_info()   # never planned: stamp 0
+    info.levels = 1                  # so that the mesh arguments pass and the state is what fails
+    m = _lib.subdiv_mesh()
+    m.num_vertices, m.num_faces, m.face_order = 4, 1, 4
+    m.face_verts = m.positions = 16  # never dereferenced
+    ws = ctypes.c_void_p(256)
+    assert lib.subdiv_refine_vertex_data(ctypes.byref(m), ctypes.byref(info), ws, 0, ws, ws, 1, None) == \
+        _lib.INVALID_ARG                                          # dim < 1
+    assert lib.subdiv_refine_vertex_data(ctypes.byref(m), ctypes.byref(info), ws, 2, ws, ws, 1, None) == \
+        _lib.STATE                                                # no kept state
+    sel = _lib.subdiv_selection()
+    assert lib.subdiv_select(ctypes.byref(m), ctypes.byref(info), None, 1, ws, 1, None, None) == _lib.INVALID_ARG
+    assert lib.subdiv_select(ctypes.byref(m), ctypes.byref(info), None, 0, ws, 1, ctypes.byref(sel), None) == \
+        _lib.INVALID_ARG                                          # rings < 1
+    assert lib.subdiv_select(ctypes.byref(m), ctypes.byref(info), None, 1, ws, 1, ctypes.byref(sel), None) == \
+        _lib.STATE                                                # not planned
+    assert sel.num_vertices == 0
+    ext = _lib.subdiv_extraction()
+    assert lib.subdiv_extract(ctypes.byref(m), ctypes.byref(info), ctypes.byref(sel), None, ws, 1, None) == \
+        _lib.INVALID_ARG
+    assert lib.subdiv_extract(ctypes.byref(m), ctypes.byref(info), ctypes.byref(sel), ctypes.byref(ext), ws, 1,
+                              None) == _lib.STATE
+    assert lib.subdiv_backward(ctypes.byref(m), ctypes.byref(info), ws, ws, ws, 1, None) == _lib.STATE
+    assert lib.subdiv_refine_positions(ctypes.byref(m), ctypes.byref(info), None, ws, 1, None) == _lib.INVALID_ARG
