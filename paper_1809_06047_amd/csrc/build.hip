@@ -47,7 +47,7 @@ hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s) {
 
 // Vertex data of `dim` channels, row-major [V*dim]: three channels at a time
 // go through the position kernels as a [V*3] array. pack: channels c0..c0+2
-// (those past dim read as zero); unpack: back into their columns.
+// (those past dim read as zero).
 __global__ void k_pack3(const float *data, int dim, int c0, long long n3, float *slice) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n3) return;
@@ -56,23 +56,28 @@ __global__ void k_pack3(const float *data, int dim, int c0, long long n3, float 
   slice[x] = c < dim ? data[v * dim + c] : 0.0f;
 }
 
-__global__ void k_unpack3(const float *slice, int dim, int c0, long long n3, float *out) {
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n3) return;
-  const long long v = x / 3;
-  const int c = c0 + (int)(x - 3 * v);
-  if (c < dim) out[v * dim + c] = slice[x];
-}
-
 hipError_t launch_pack3(const float *data, int dim, int c0, long long V, float *slice, hipStream_t s) {
   if (V <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack3, dim3(grid_for(3 * V)), dim3(kBlock), 0, s, data, dim, c0, 3 * V, slice);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack3(const float *slice, int dim, int c0, long long V, float *out, hipStream_t s) {
+// channels c0 .. c0+ncols-1 (ncols <= 6) of out from two [V*3] arrays
+// holding channels c0..c0+2 and c0+3..c0+5: one lane per output value, so
+// when the group spans every channel each row is written whole, by
+// consecutive lanes
+__global__ void k_unpack6(const float *a, const float *b, int dim, int c0, int ncols, long long n, float *out) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const long long v = x / ncols;
+  const int c = (int)(x - v * ncols);
+  out[v * dim + c0 + c] = c < 3 ? a[3 * v + c] : b[3 * v + c - 3];
+}
+
+hipError_t launch_unpack6(const float *a, const float *b, int dim, int c0, int ncols, long long V, float *out,
+                          hipStream_t s) {
   if (V <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unpack3, dim3(grid_for(3 * V)), dim3(kBlock), 0, s, slice, dim, c0, 3 * V, out);
+  hipLaunchKernelGGL(k_unpack6, dim3(grid_for(V * ncols)), dim3(kBlock), 0, s, a, b, dim, c0, ncols, V * ncols, out);
   return hipGetLastError();
 }
 

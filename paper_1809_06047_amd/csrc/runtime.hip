@@ -817,18 +817,25 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
   const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
   const Topo t = cage_topo(mesh, H0, ws, y);
   const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
-  // the adjoint's two gradient buffers (each [max_k V_k * 3]) carry the cage
-  // slice and the final slice; the levels in between use the usual buffers
-  float *slice0 = at<float>(ws, y.bg[0]), *sliceL = at<float>(ws, y.bg[1]);
+  // Scratch of the adjoint: its term buffer ([max_k H_k * 3] >= [V_0 * 3])
+  // carries the cage slice, its two gradient buffers (each [max_k V_k * 3])
+  // the final slices of two groups of three channels; the levels in between
+  // use the usual buffers. Six channels at a time are then written into out
+  // by one kernel, whole rows when dim <= 6.
+  float *slice0 = at<float>(ws, y.bterm);
+  float *sliceL[2] = {at<float>(ws, y.bg[0]), at<float>(ws, y.bg[1])};
   subdiv_mesh m = *mesh;
   m.positions = slice0;
   subdiv_level_out outs[SUBDIV_MAX_LEVELS + 1] = {};
-  outs[levels].positions = sliceL;
-  for (int c0 = 0; c0 < dim; c0 += 3) {
-    SUBDIV_TRY(launch_pack3(data, dim, c0, L[0].V, slice0, s));
-    if ((st = refine_cc_carried(&m, outs, ws, y, L, levels, plan->flags, t, a, slice0, true, s)) != SUBDIV_OK)
-      return st;
-    SUBDIV_TRY(launch_unpack3(sliceL, dim, c0, L[levels].V, out, s));
+  for (int c0 = 0; c0 < dim; c0 += 6) {
+    for (int g = 0; g < 2 && c0 + 3 * g < dim; ++g) {
+      SUBDIV_TRY(launch_pack3(data, dim, c0 + 3 * g, L[0].V, slice0, s));
+      outs[levels].positions = sliceL[g];
+      if ((st = refine_cc_carried(&m, outs, ws, y, L, levels, plan->flags, t, a, slice0, true, s)) != SUBDIV_OK)
+        return st;
+    }
+    const int ncols = dim - c0 < 6 ? dim - c0 : 6;
+    SUBDIV_TRY(launch_unpack6(sliceL[0], sliceL[1], dim, c0, ncols, L[levels].V, out, s));
   }
   return SUBDIV_OK;
 }

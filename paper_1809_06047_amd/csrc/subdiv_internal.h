@@ -146,9 +146,10 @@ inline unsigned grid_for(long long n, int block = kBlock) {
 // ---- launchers (each returns hipGetLastError() of its launches) --------
 hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s);
-// channels c0..c0+2 of [V*dim] vertex data to and from a [V*3] array
+// channels c0..c0+2 of [V*dim] vertex data into a [V*3] array; up to six back
 hipError_t launch_pack3(const float *data, int dim, int c0, long long V, float *slice, hipStream_t s);
-hipError_t launch_unpack3(const float *slice, int dim, int c0, long long V, float *out, hipStream_t s);
+hipError_t launch_unpack6(const float *a, const float *b, int dim, int c0, int ncols, long long V, float *out,
+                          hipStream_t s);
 // exclusive scan of n ints into out[0..n] (out[n] = total); partials needs scan_partials_ints(n) ints;
 // when total_dst != nullptr the total is also stored there.
 long long scan_partials_ints(long long n);
