@@ -66,18 +66,41 @@ hipError_t launch_pack3(const float *data, int dim, int c0, long long V, float *
 // holding channels c0..c0+2 and c0+3..c0+5: one lane per output value, so
 // when the group spans every channel each row is written whole, by
 // consecutive lanes
-__global__ void k_unpack6(const float *a, const float *b, int dim, int c0, int ncols, long long n, float *out) {
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// The group width is a template argument and the index 32-bit when it fits,
+// so the row/column split is a multiply by a constant, not a 64-bit divide.
+template <int NC, typename I>
+__global__ void k_unpack6(const float *__restrict__ a, const float *__restrict__ b, int dim, int c0, I n,
+                          float *__restrict__ out) {
+  const I x = (I)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
-  const long long v = x / ncols;
-  const int c = (int)(x - v * ncols);
-  out[v * dim + c0 + c] = c < 3 ? a[3 * v + c] : b[3 * v + c - 3];
+  const I v = x / NC;
+  const int c = (int)(x - v * NC);
+  const float y = c < 3 ? a[3 * v + c] : b[3 * v + c - 3];
+  __builtin_nontemporal_store(y, out + (long long)v * dim + c0 + c);
+}
+
+template <int NC>
+static void unpack_t(const float *a, const float *b, int dim, int c0, long long V, float *out, hipStream_t s) {
+  const long long n = V * NC;
+  if (n <= 0xffffffffll)
+    hipLaunchKernelGGL((k_unpack6<NC, uint32_t>), dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, dim, c0, (uint32_t)n,
+                       out);
+  else
+    hipLaunchKernelGGL((k_unpack6<NC, long long>), dim3(grid_for(n)), dim3(kBlock), 0, s, a, b, dim, c0, n, out);
 }
 
 hipError_t launch_unpack6(const float *a, const float *b, int dim, int c0, int ncols, long long V, float *out,
                           hipStream_t s) {
   if (V <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unpack6, dim3(grid_for(V * ncols)), dim3(kBlock), 0, s, a, b, dim, c0, ncols, V * ncols, out);
+  switch (ncols) {
+    case 1: unpack_t<1>(a, b, dim, c0, V, out, s); break;
+    case 2: unpack_t<2>(a, b, dim, c0, V, out, s); break;
+    case 3: unpack_t<3>(a, b, dim, c0, V, out, s); break;
+    case 4: unpack_t<4>(a, b, dim, c0, V, out, s); break;
+    case 5: unpack_t<5>(a, b, dim, c0, V, out, s); break;
+    case 6: unpack_t<6>(a, b, dim, c0, V, out, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

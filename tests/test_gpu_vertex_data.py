@@ -70,3 +70,21 @@ def test_vertex_data_rejects_bad_calls():
     with pytest.raises(_lib.SubdivError) as e:
         plain.run_vertex_data(torch.zeros((m.num_vertices, 2), device="cuda"))
     assert e.value.status == _lib.STATE
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3, 4, 6, 8, 13])
+def test_vertex_data_every_group_width(dim):
+    """Channel j holds position coordinate j mod 3 scaled by 2^(j div 3), an
+    exact scaling: every output column is that coordinate of the refined
+    positions, scaled the same way, bit for bit. The dims cover the last
+    group of one to six channels."""
+    m = G.cc_cage(seed=24, level=2)
+    r = _kept(m, 3)
+    P = torch.from_numpy(m.positions).cuda()
+    data = torch.stack([P[:, j % 3] * 2.0 ** (j // 3) for j in range(dim)], 1).contiguous()
+    print(f"[vertex data] group widths, dim={dim}", flush=True)
+    got = r.run_vertex_data(data)
+    torch.cuda.synchronize()
+    ref = r.final["positions"]
+    for j in range(dim):
+        assert torch.equal(got[:, j], ref[:, j % 3] * 2.0 ** (j // 3)), j
