@@ -260,14 +260,20 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# algorithmic bytes of the triangle-scheme kernels of one level (no adjacency
-# carried, as on the last level): face kernels read the face's vertex and edge
-# (Loop) or twin (sqrt(3)) rows and write the children (Loop 4 x 12 B, sqrt(3)
-# 3 x 12 B) plus, for sqrt(3), the face point; the edge kernel reads its
-# half-edge and writes the edge point; the vertex kernel reads and writes one
-# position (positions are read once per level, counted here).
-TRI_BYTES_PER_UNIT = {"loop_face": ("F", 72), "loop_edge": ("E", 16), "loop_vertex": ("V", 24),
-                      "sqrt3_face": ("F", 72), "sqrt3_vertex": ("V", 24)}
+# algorithmic bytes of the last step's triangle-scheme kernels (no adjacency
+# carried), from the sizes of level k = L-1 and of level m = L-2:
+#   Loop (computed from level m): the face kernel reads a level-m face's
+#   vertex and edge rows (24 B) and writes its 16 grandchildren (192 B); the
+#   edge kernel reads the edge's half-edge (4 B), reads and writes the vertex
+#   point of its edge point (24 B) and writes the edge points of level k's
+#   edges (12 B each); the vertex kernel reads and writes the positions of
+#   level m's vertices (24 B);
+#   sqrt(3): the face kernel reads the face's vertex and twin rows and writes
+#   the 3 children (36 B) and the face point; the vertex kernel reads and
+#   writes one position.
+TRI_BYTES = {"loop_face": lambda k, m: 216 * m["F"], "loop_edge": lambda k, m: 12 * k["E"] + 28 * m["E"],
+             "loop_vertex": lambda k, m: 24 * m["V"],
+             "sqrt3_face": lambda k, m: 72 * k["F"], "sqrt3_vertex": lambda k, m: 24 * k["V"]}
 
 
 def scheme_leg(mesh, scheme, levels, steps):
@@ -305,10 +311,9 @@ def scheme_leg(mesh, scheme, levels, steps):
     last = levels - 1  # the last step: level L-1 -> L
     roof = {}
     for (name, lvl), (n, tot) in stages.items():
-        if lvl != last or name not in TRI_BYTES_PER_UNIT:
+        if lvl != last or name not in TRI_BYTES:
             continue
-        unit, per_unit = TRI_BYTES_PER_UNIT[name]
-        nbytes = per_unit * r.level_info(last)[unit]
+        nbytes = TRI_BYTES[name](r.level_info(last), r.level_info(last - 1))
         avg = tot / n
         gbs = nbytes / (avg / 1000.0) / 1e9
         roof[name] = {"avg_launch_ms": round(avg, 5), "algorithmic_bytes_per_launch": nbytes,

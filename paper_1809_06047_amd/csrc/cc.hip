@@ -23,8 +23,11 @@
 namespace subdiv {
 
 __device__ __forceinline__ double chaikin(double si, double sj) {
-  // max(1/4 (si + 3 sj) - 1, 0) in this exact operation order, no contraction
-  const double t = __dadd_rn(__dmul_rn(0.25, __dadd_rn(si, __dmul_rn(3.0, sj))), -1.0);
+  // max(1/4 (si + 3 sj) - 1, 0) in this exact operation order; the pragma keeps
+  // the compiler from fusing a product and a sum (HIP's __dadd_rn and
+  // __dmul_rn are plain operators, which it may contract)
+#pragma clang fp contract(off)
+  const double t = 0.25 * (si + 3.0 * sj) - 1.0;
   return t > 0.0 ? t : 0.0;
 }
 

@@ -32,7 +32,8 @@
 namespace subdiv {
 
 __device__ __forceinline__ double chaikin_lag(double si, double sj) {
-  const double t = __dadd_rn(__dmul_rn(0.25, __dadd_rn(si, __dmul_rn(3.0, sj))), -1.0);
+#pragma clang fp contract(off)
+  const double t = 0.25 * (si + 3.0 * sj) - 1.0;  // this operation order, no fused multiply-add
   return t > 0.0 ? t : 0.0;
 }
 

@@ -46,6 +46,26 @@ hipError_t init_weight_tables() {
   return hipSuccess;
 }
 
+// Loop's edge-point stencil and the stencils of the vertex points of edge
+// points, with every product and sum rounded on its own: the pragma keeps
+// the compiler from fusing them into multiply-adds, whose placement it picks
+// per kernel. The per-level kernels and the last step from two levels down
+// evaluate them from different index paths and give the same bits.
+__device__ __forceinline__ f3 lin2(float s, f3 a, float t, f3 b) {
+#pragma clang fp contract(off)
+  return f3{s * a.x + t * b.x, s * a.y + t * b.y, s * a.z + t * b.z};
+}
+// 3/8 (sum of the edge's ends) + 1/8 (sum of the opposite corners)
+__device__ __forceinline__ f3 loop_edge_pt(f3 ends, f3 opp) { return lin2(0.375f, ends, 0.125f, opp); }
+// boundary vertex: 3/4 p + 1/8 (sum of its two boundary neighbours)
+__device__ __forceinline__ f3 loop_bnd_pt(f3 p, f3 nb) { return lin2(0.75f, p, 0.125f, nb); }
+// interior vertex of valence 6 (every edge point of a refined level)
+__device__ __forceinline__ f3 loop_v6_pt(f3 p, f3 ring) {
+#pragma clang fp contract(off)
+  const float beta = c_loop_beta[6];
+  return lin2(1.0f - 6.0f * beta, p, beta, ring);
+}
+
 // ring walk around v: sum of the neighbours, count of faces, boundary ends
 struct Ring {
   f3 sum;
@@ -204,7 +224,7 @@ __global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
   if (t < 0) ep = mul3(0.5f, pab);
   else {
     const f3 pcd = add3(ld3(c.P, c.t.fv[hp]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
-    ep = fma3(0.375f, pab, mul3(0.125f, pcd));
+    ep = loop_edge_pt(pab, pcd);
   }
   st3(c.P1, c.t.V + e, ep);
   if (c.base) {  // children of level k+1 with higher end E_e
@@ -232,13 +252,12 @@ __device__ __forceinline__ f3 loop_ep_point(const TriStep &c, int u) {
   const int32_t *rw = c.t.fv + 12ll * r;
   const f3 pa = ld3(c.P, rw[3 * j]), pb = ld3(c.P, rw[3 * jn]);
   const int tw = c.a.twin[12 * r + 3 * j];  // twin of v_j -> E_j
-  if (tw < 0) return fma3(0.75f, p, mul3(0.125f, add3(pa, pb)));
+  if (tw < 0) return loop_bnd_pt(p, add3(pa, pb));
   const f3 n1 = ld3(c.P, rw[9 + jn]), n2 = ld3(c.P, rw[9 + jp]);
   const int qs = tw / 3, s = qs >> 2, i = ((qs & 3) + 2) % 3;  // e is edge i of s
   const int32_t *sw = c.t.fv + 12ll * s + 9;
   const f3 x = ld3(c.P, sw[(i + 1) % 3]), y = ld3(c.P, sw[(i + 2) % 3]);
-  const float beta = c_loop_beta[6];
-  return fma3(1.0f - 6.0f * beta, p, mul3(beta, add3(add3(pa, pb), add3(add3(n1, n2), add3(x, y)))));
+  return loop_v6_pt(p, add3(add3(pa, pb), add3(add3(n1, n2), add3(x, y))));
 }
 
 __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
@@ -504,6 +523,167 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
   // an old vertex's half-edges at level k+1 are the first slots 3 (3r + j) of
   // the children at its level-k half-edges 3r + j, in the same order
   if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
+}
+
+// ------------------------------------------------------- Loop, last step
+// Level k+1 computed from level m = k-1, the level that level k was refined
+// from. With E_j = |v_m| + e_j for the edges e_j of a level-m face
+// r = (v_0, v_1, v_2):
+//   level-k children of r: 4r+j = (v_j, E_j, E_{j-1}), 4r+3 = (E_0, E_1, E_2);
+//   level-k edge ids: the carried form of the face kernel above, on level m;
+//   level-(k+1) children of a level-k face q = (w_0, w_1, w_2) with edges
+//     (x_0, x_1, x_2): 4q+i = (w_i, V_k + x_i, V_k + x_{i-1}),
+//     4q+3 = (V_k + x_0, V_k + x_1, V_k + x_2). So r's sixteen grandchildren
+//     are the rows 16r .. 16r+15 of level k+1: 48 ints per level-m face.
+// Every level-k edge has an edge point E_e as its higher end, and the edges
+// with higher end E_e take the ids base(e) .. base(e+1)-1; one lane per
+// level-m edge e therefore writes the level-(k+1) edge points of a run of
+// ids, and the runs of a wave are contiguous. With e = (a, b) in face r,
+// whose other edges are ra (at a) and rb (at b), and in the face s across,
+// whose other edges are sa and sb, the level-k edges with higher end E_e and
+// their opposite corners are
+//   (a, E_e): E_ra and E_sa;          (b, E_e): E_rb and E_sb;
+//   (E_ra, E_e): a and E_rb;          (E_rb, E_e): b and E_ra;  likewise in s;
+// the vertex point of E_e (valence 6, or a boundary vertex between a and b)
+// takes the same points. Sums keep the operand grouping of the per-level
+// kernels above (two-term sums commute) and the stencils are the same
+// uncontracted ones, so both give the same bits.
+__global__ void __launch_bounds__(kBlock) k_loopl_face(LoopLag c) {
+  __shared__ int4 stage[kBlock / 64][64 * 13];
+  const int F = c.tm.F;
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = rid < F ? rid : F - 1;  // every lane takes part in the staged store
+  const int l = threadIdx.x & 63;
+  int4 *lds = stage[threadIdx.x >> 6];
+  const long long rw = (long long)rid - l;                 // first face of the wave
+  const int cnt = (int)min(64ll, (long long)F - rw) * 12;  // int4s of the wave's run
+  const int Vm = c.tm.V, Vk = c.Vk;
+  int v[3], ed[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    v[j] = c.tm.fv[3 * r + j];
+    ed[j] = c.am.eid[3 * r + j];
+  }
+  int xk[12];  // level-k edge ids of the children's half-edges, 3 (q - 4r) + slot
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+    xk[3 * j + 0] = c.base[ed[j]] + (v[j] > v[jn]);
+    xk[3 * j + 2] = c.base[ed[jp]] + (v[j] > v[jp]);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    // centre edge (E_{e_m}, E_{e_{m+1}}): child 3 slot m and child m+1 slot 1
+    const int mn = (m + 1) % 3, mo = (m + 2) % 3;
+    const int a = min(ed[m], ed[mn]), b = max(ed[m], ed[mn]), other = ed[mo];
+    const int tb = c.am.twin[3 * r + (ed[m] == b ? m : mn)];
+    int rank = 2 + (other < a);
+    if (tb >= 0) {
+      rank += lt_new(c.am.eid[he_next<3>(c.tm, tb)], a, a, other);
+      rank += lt_new(c.am.eid[he_prev<3>(c.tm, tb)], a, a, other);
+    }
+    xk[9 + m] = xk[3 * mn + 1] = c.base[b] + rank;
+  }
+  const int E0 = Vm + ed[0], E1 = Vm + ed[1], E2 = Vm + ed[2];
+  const int wk[12] = {v[0], E0, E2, v[1], E1, E0, v[2], E2, E1, E0, E1, E2};
+  int out[48];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out[12 * q + 3 * i + 0] = wk[3 * q + i];
+      out[12 * q + 3 * i + 1] = Vk + xk[3 * q + i];
+      out[12 * q + 3 * i + 2] = Vk + xk[3 * q + (i + 2) % 3];
+      out[12 * q + 9 + i] = Vk + xk[3 * q + i];
+    }
+  }
+  // 12 int4 per lane, leaving through LDS as 12 instructions of 64 int4
+#pragma unroll
+  for (int x = 0; x < 12; ++x) lds[13 * l + x] = make_int4(out[4 * x], out[4 * x + 1], out[4 * x + 2], out[4 * x + 3]);
+  __builtin_amdgcn_wave_barrier();
+  int4 *dst = reinterpret_cast<int4 *>(c.fv2) + 12 * rw;
+#pragma unroll
+  for (int t = 0; t < 12; ++t) {
+    const int g = 64 * t + l, src = g / 12;
+    const int4 x = lds[13 * src + (g - 12 * src)];
+    if (g < cnt) stream_store4(dst + g, x);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_loopl_edge(LoopLag c) {
+  __shared__ uint32_t stage[kBlock / 64][64 * 18];
+  const int E = c.am.E;
+  const int eid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = eid < E ? eid : E - 1;  // every lane takes part in the staged stores
+  const int l = threadIdx.x & 63;
+  uint32_t *lds = stage[threadIdx.x >> 6];
+  const int Vm = c.tm.V, Vk = c.Vk;
+  const int h = c.am.e2h[e], r = h / 3, j = h - 3 * r;
+  const int jn = j == 2 ? 0 : j + 1, jp = j == 0 ? 2 : j - 1;
+  const int a = c.tm.fv[h], b = c.tm.fv[3 * r + jn];
+  const int ra = c.am.eid[3 * r + jp], rb = c.am.eid[3 * r + jn];
+  const int t = c.am.twin[h];
+  const f3 pa = ld3(c.Pk, a), pb = ld3(c.Pk, b), pE = ld3(c.Pk, Vm + e);
+  const f3 pra = ld3(c.Pk, Vm + ra), prb = ld3(c.Pk, Vm + rb);
+  const int base = c.base[e];
+  const int base0 = __shfl(base, 0, 64);
+  const int off = 3 * (base - base0);
+  auto put = [&](int slot, f3 p) {
+    lds[off + 3 * slot + 0] = __float_as_uint(p.x);
+    lds[off + 3 * slot + 1] = __float_as_uint(p.y);
+    lds[off + 3 * slot + 2] = __float_as_uint(p.z);
+  };
+  const int lo_slot = a < b ? 0 : 1;  // (a, E_e) is base + 0 when a is the lower old end
+  f3 S;
+  int n;
+  if (t < 0) {
+    S = loop_bnd_pt(pE, add3(pa, pb));
+    put(lo_slot, mul3(0.5f, add3(pa, pE)));
+    put(1 - lo_slot, mul3(0.5f, add3(pb, pE)));
+    n = 2;
+    if (ra < e) put(2 + (rb < ra), loop_edge_pt(add3(pra, pE), add3(pa, prb)));
+    if (rb < e) put(2 + (ra < rb), loop_edge_pt(add3(prb, pE), add3(pb, pra)));
+    n += (ra < e) + (rb < e);
+  } else {
+    const int s = t / 3, i = t - 3 * s;  // t = s's half-edge b -> a
+    const int sa = c.am.eid[3 * s + (i == 2 ? 0 : i + 1)], sb = c.am.eid[3 * s + (i == 0 ? 2 : i - 1)];
+    const f3 psa = ld3(c.Pk, Vm + sa), psb = ld3(c.Pk, Vm + sb);
+    S = loop_v6_pt(pE, add3(add3(pa, pb), add3(add3(pra, prb), add3(psa, psb))));
+    put(lo_slot, loop_edge_pt(add3(pa, pE), add3(pra, psa)));
+    put(1 - lo_slot, loop_edge_pt(add3(pb, pE), add3(prb, psb)));
+    // the lower neighbours E_x, x < e, ranked among N(e) = {ra, rb, sa, sb}
+    auto rank = [&](int x) { return (ra < x) + (rb < x) + (sa < x) + (sb < x); };
+    if (ra < e) put(2 + rank(ra), loop_edge_pt(add3(pra, pE), add3(pa, prb)));
+    if (rb < e) put(2 + rank(rb), loop_edge_pt(add3(prb, pE), add3(pb, pra)));
+    if (sa < e) put(2 + rank(sa), loop_edge_pt(add3(psa, pE), add3(pa, psb)));
+    if (sb < e) put(2 + rank(sb), loop_edge_pt(add3(psb, pE), add3(pb, psa)));
+    n = 2 + (ra < e) + (rb < e) + (sa < e) + (sb < e);
+  }
+  __builtin_amdgcn_wave_barrier();
+  {
+    const int end = min(__shfl(base + n, min(63, E - 1 - (eid - l)), 64), c.Ek);
+    const int count = (eid - l < E) ? 3 * (end - base0) : 0;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vk + base0));
+#pragma unroll
+    for (int x = 0; x < 18; ++x) {
+      const int g = 64 * x + l;
+      if (g < count) stream_store(dst + g, lds[g]);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  {
+    const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
+    const int count = 3 * (int)min(64ll, (long long)E - (eid - l));
+    wave_store<3>(lds, row, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vm + eid - l)), l, count);
+  }
+}
+
+hipError_t loop_lag_launch(int which, const LoopLag &c, hipStream_t s) {
+  if (which == LOOP_LAG_FACE)
+    hipLaunchKernelGGL(k_loopl_face, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_loopl_edge, dim3(grid_for(c.am.E)), dim3(kBlock), 0, s, c);
+  return hipGetLastError();
 }
 
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s) {
