@@ -268,12 +268,14 @@ def main():
 #   point of its edge point (24 B) and writes the edge points of level k's
 #   edges (12 B each); the vertex kernel reads and writes the positions of
 #   level m's vertices (24 B);
-#   sqrt(3): the face kernel reads the face's vertex and twin rows and writes
-#   the 3 children (36 B) and the face point; the vertex kernel reads and
-#   writes one position.
+#   sqrt(3) (computed from level m): the face kernel reads a level-m face's
+#   vertex and twin rows (24 B), writes its 9 grandchildren (108 B) and the
+#   face points of its 3 children (36 B), and reads and writes the vertex
+#   point of its face point (24 B); the vertex kernel reads and writes the
+#   positions of level m's vertices.
 TRI_BYTES = {"loop_face": lambda k, m: 216 * m["F"], "loop_edge": lambda k, m: 12 * k["E"] + 28 * m["E"],
              "loop_vertex": lambda k, m: 24 * m["V"],
-             "sqrt3_face": lambda k, m: 72 * k["F"], "sqrt3_vertex": lambda k, m: 24 * k["V"]}
+             "sqrt3_face": lambda k, m: 192 * m["F"], "sqrt3_vertex": lambda k, m: 24 * m["V"]}
 
 
 def scheme_leg(mesh, scheme, levels, steps):

@@ -696,10 +696,10 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
   Topo tprev{};  // mesh matrix of level k-1
-  // Loop's last step from level levels-2 (no adjacency of level levels-1):
-  // when that level is a refined one and the caller wants no edge list of
-  // level levels-1
-  const bool loop_lag = scheme == SUBDIV_LOOP && !rebuild && levels >= 3 && !outs[levels].edge_verts;
+  // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
+  // levels-1): when that level is a refined one and the caller wants no edge
+  // list of level levels-1
+  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !outs[levels].edge_verts;
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -744,10 +744,10 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, c.sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice,
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
-    } else if (loop_lag && final) {
+    } else if (tri_lag && final) {
       // level k+1 from level m = k-1: `a` and `tprev` are level m's (the step
-      // before carried nothing), its edge bases are in tbase
-      const LoopLag g{tprev, a, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E, fv1, P1};
+      // before carried nothing); Loop's edge bases of level m are in tbase
+      const TriLag g{tprev, a, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E, fv1, P1};
       TriStep o{};  // the old vertices (level m's) walk their level-m rings
       o.t = tprev;
       o.P = P;
@@ -755,19 +755,28 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       o.Vg = (int32_t)L[k - 1].V;
       o.ap = a;
       o.Vq = (int32_t)L[k - 2].V;
-      SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
-      SUBDIV_TIMED("loop_edge", k, loop_lag_launch(LOOP_LAG_EDGE, g, s));
-      SUBDIV_TIMED("loop_face", k, loop_lag_launch(LOOP_LAG_FACE, g, s));
+      if (scheme == SUBDIV_LOOP) {
+        SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
+        SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
+        SUBDIV_TIMED("loop_face", k, tri_lag_launch(LAG_LOOP_FACE, g, s));
+      } else {
+        SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, o, s));
+        SUBDIV_TIMED("sqrt3_face", k, tri_lag_launch(LAG_SQRT3_FACE, g, s));
+      }
     } else {
       TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev,
                 k >= 2 ? (int32_t)L[k - 2].V : 0};
-      const bool before_lag = loop_lag && k == levels - 2;  // only the edge bases of level k are needed next
+      // before the last step from level k: Loop still needs level k's edge
+      // bases; nothing is carried, and level k+1's face table is only written
+      // for the caller
+      const bool before_lag = tri_lag && k == levels - 2;
       const bool carry = !rebuild && !final && !before_lag;  // level k+1's adjacency in closed form
       if (carry) {
         c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, false);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
       }
-      if (carry || before_lag) c.base = at<int32_t>(ws, y.tbase);
+      if (carry || (before_lag && scheme == SUBDIV_LOOP)) c.base = at<int32_t>(ws, y.tbase);
+      if (before_lag && !outs[k + 1].face_verts) c.fv1 = nullptr;
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
         if (c.base)
@@ -775,9 +784,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         // the vertex step walks level k-1's adjacency, whose slot the carried
         // face step overwrites with level k+1's: it runs first
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
-        // before the last step from level k, level k+1's face table is only
-        // written for the caller
-        if (!before_lag || outs[k + 1].face_verts) SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
+        if (c.fv1) SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
         if (carry) a = c.a1;
       } else {
         if (carry) {

@@ -339,22 +339,22 @@ struct TriStep {
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
 
-// Last Loop step k -> k+1 computed from level m = k-1 (which level k was
-// refined from): its faces, edges and adjacency are a quarter the size of
-// level k's, and level k's are closed-form functions of them, so level k's
-// adjacency is never written.
-struct LoopLag {
+// Last Loop or sqrt(3) step k -> k+1 computed from level m = k-1 (which
+// level k was refined from): its faces, edges and adjacency are a quarter
+// (a third) the size of level k's, and level k's are closed-form functions of
+// them, so level k's adjacency is never written.
+struct TriLag {
   Topo tm;               // level m (triangles)
   Adj am;                // level m: twin, eid, e2h (E = |e_m|)
-  const int32_t *base;   // [E_m + 1] first level-k edge id with higher end EP(e), per level-m edge
+  const int32_t *base;   // Loop: [E_m + 1] first level-k edge id with higher end EP(e), per level-m edge
   const float *Pk;       // level-k positions [V_k]
-  int32_t Vk;            // V_k = V_m + E_m
-  int32_t Ek;            // E_k = base[E_m]
-  int32_t *fv2;          // level k+1 face table [48 F_m]
-  float *P2;             // level k+1 positions [V_k + E_k]
+  int32_t Vk;            // V_k = V_m + E_m (Loop), V_m + F_m (sqrt(3))
+  int32_t Ek;            // Loop: E_k = base[E_m]
+  int32_t *fv2;          // level k+1 face table (Loop [48 F_m], sqrt(3) [27 F_m])
+  float *P2;             // level k+1 positions [V_{k+1}]
 };
-enum { LOOP_LAG_FACE = 0, LOOP_LAG_EDGE = 1 };
-hipError_t loop_lag_launch(int which, const LoopLag &c, hipStream_t s);
+enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
+hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);
 hipError_t init_weight_tables();
 
 }  // namespace subdiv

@@ -66,6 +66,15 @@ __device__ __forceinline__ f3 loop_v6_pt(f3 p, f3 ring) {
   return lin2(1.0f - 6.0f * beta, p, beta, ring);
 }
 
+// sqrt(3) interior vertex: (1 - alpha_n) p + alpha_n / n (sum of the n
+// neighbours), uncontracted like the Loop stencils (the face point of a
+// refined level is evaluated by two kernels)
+__device__ __forceinline__ f3 sqrt3_pt(f3 p, f3 ring, int n) {
+#pragma clang fp contract(off)
+  const float alpha = c_sqrt3_alpha[n];
+  return lin2(1.0f - alpha, p, alpha / (float)n, ring);
+}
+
 // ring walk around v: sum of the neighbours, count of faces, boundary ends
 struct Ring {
   f3 sum;
@@ -415,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
     const f3 sum = add3(add3(ld3(c.P, v[0]), ld3(c.P, v[1])), ld3(c.P, v[2]));
     st3(c.P1, V + r, mul3(1.0f / 3.0f, sum));
   }
-  {
+  if (c.fv1) {  // (before the last step from level k, only the caller wants it)
     uint32_t row[9];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -504,8 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
         ++n;
       }
     }
-    const float alpha = c_sqrt3_alpha[n];
-    st3(c.P1, v, fma3(1.0f - alpha, p, mul3(alpha / (float)n, sum)));
+    st3(c.P1, v, sqrt3_pt(p, sum, n));
     if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
     return;
   }
@@ -548,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
 // takes the same points. Sums keep the operand grouping of the per-level
 // kernels above (two-term sums commute) and the stencils are the same
 // uncontracted ones, so both give the same bits.
-__global__ void __launch_bounds__(kBlock) k_loopl_face(LoopLag c) {
+__global__ void __launch_bounds__(kBlock) k_loopl_face(TriLag c) {
   __shared__ int4 stage[kBlock / 64][64 * 13];
   const int F = c.tm.F;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -610,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_loopl_face(LoopLag c) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_loopl_edge(LoopLag c) {
+__global__ void __launch_bounds__(kBlock) k_loopl_edge(TriLag c) {
   __shared__ uint32_t stage[kBlock / 64][64 * 18];
   const int E = c.am.E;
   const int eid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -678,11 +686,97 @@ __global__ void __launch_bounds__(kBlock) k_loopl_edge(LoopLag c) {
   }
 }
 
-hipError_t loop_lag_launch(int which, const LoopLag &c, hipStream_t s) {
-  if (which == LOOP_LAG_FACE)
+// ----------------------------------------------------- sqrt(3), last step
+// Level k+1 from level m = k-1. With twin t_j of the half-edge v_j -> v_{j+1}
+// of a level-m face r and X_j = F_s across an interior edge j (t_j = 3s + i),
+// else v_{j+1}, level k's child q = 3r + j = (v_j, X_j, F_r) has, across its
+//   edge 0 (v_j -> X_j): s's child at v_j, 3s + (i+1) mod 3, or the boundary;
+//   edge 1 (X_j -> F_r): s's child i, i.e. face t_j, or r's child j+1 when
+//     edge j is on the boundary;
+//   edge 2 (F_r -> v_j): face t_{j-1} across edge j-1, or r's child j-1.
+// So per level-m face r one lane writes r's nine grandchildren (rows
+// 9r .. 9r+8 of level k+1: (w_i, face point across edge i or w_{i+1},
+// face point of q)), the face points of r's three children and the vertex
+// point of F_r (r's corners and the face points across its interior edges).
+// The sums are those of the per-level kernels, in the same order.
+__global__ void __launch_bounds__(kBlock) k_sqrt3l_face(TriLag c) {
+  __shared__ uint32_t stage[kBlock / 64][64 * 27];
+  const int F = c.tm.F;
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = rid < F ? rid : F - 1;  // every lane takes part in the staged stores
+  const int l = threadIdx.x & 63;
+  uint32_t *lds = stage[threadIdx.x >> 6];
+  const long long rw = (long long)rid - l;  // first face of the wave
+  const int nw = (int)min(64ll, (long long)F - rw);
+  const int Vm = c.tm.V, Vk = c.Vk;
+  int v[3], tw[3], X[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    v[j] = c.tm.fv[3 * r + j];
+    tw[j] = c.am.twin[3 * r + j];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) X[j] = tw[j] < 0 ? v[(j + 1) % 3] : Vm + tw[j] / 3;
+  const int Fr = Vm + r;
+  f3 pv[3], pX[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) pv[j] = ld3(c.Pk, v[j]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) pX[j] = tw[j] < 0 ? pv[(j + 1) % 3] : ld3(c.Pk, X[j]);
+  const f3 pF = ld3(c.Pk, Fr);
+  {
+    uint32_t row[27];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+      const int t = tw[j], tp = tw[jp];
+      const int q = Vk + 3 * r + j;  // face point of level-k face 3r + j
+      const int y0 = t < 0 ? X[j] : Vk + 3 * (t / 3) + (t % 3 + 1) % 3;
+      const int y1 = Vk + (t < 0 ? 3 * r + jn : t);
+      const int y2 = Vk + (tp < 0 ? 3 * r + jp : tp);
+      const int w[3] = {v[j], X[j], Fr}, y[3] = {y0, y1, y2};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        row[9 * j + 3 * i + 0] = w[i];
+        row[9 * j + 3 * i + 1] = y[i];
+        row[9 * j + 3 * i + 2] = q;
+      }
+    }
+    wave_store<27>(lds, row, reinterpret_cast<uint32_t *>(c.fv2) + 27 * rw, l, 27 * nw);
+  }
+  {
+    uint32_t fp[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const f3 f = mul3(1.0f / 3.0f, add3(add3(pv[j], pX[j]), pF));
+      fp[3 * j + 0] = __float_as_uint(f.x);
+      fp[3 * j + 1] = __float_as_uint(f.y);
+      fp[3 * j + 2] = __float_as_uint(f.z);
+    }
+    wave_store<9>(lds, fp, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vk + 3 * rw)), l, 9 * nw);
+  }
+  {
+    f3 sum = add3(add3(pv[0], pv[1]), pv[2]);
+    int n = 3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (tw[j] >= 0) {
+        sum = add3(sum, pX[j]);
+        ++n;
+      }
+    const f3 S = sqrt3_pt(pF, sum, n);
+    const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
+    wave_store<3>(lds, row, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vm + rw)), l, 3 * nw);
+  }
+}
+
+hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s) {
+  if (which == LAG_LOOP_FACE)
     hipLaunchKernelGGL(k_loopl_face, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
-  else
+  else if (which == LAG_LOOP_EDGE)
     hipLaunchKernelGGL(k_loopl_edge, dim3(grid_for(c.am.E)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_sqrt3l_face, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
   return hipGetLastError();
 }
 

@@ -241,13 +241,14 @@ def test_status_codes_match_oracle(oracle_mod):
             assert got != 0
 
 
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
 @pytest.mark.parametrize("levels", [3, 4])
 @pytest.mark.parametrize("cage", ["icosphere", "holes", "fan", "bipyramid", "grid"])
-def test_loop_last_step_from_two_levels_down(oracle_mod, cage, levels):
-    """Without an edge list of level L-1, Loop's last step runs from level
-    L-2 (the level L-1 was refined from) and level L-1's adjacency is never
-    built. The final level equals the per-level path (asked for the edge
-    list) bit for bit and the oracle within tolerance; asking for every
+def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
+    """Without an edge list of level L-1, the last Loop or sqrt(3) step runs
+    from level L-2 (the level L-1 was refined from) and level L-1's adjacency
+    is never built. The final level equals the per-level path (asked for the
+    edge list) bit for bit and the oracle within tolerance; asking for every
     level's face table as well changes nothing."""
     rng = np.random.default_rng(21)
     m = {"icosphere": lambda: G.tri_cage(seed=18, level=2, hole_frac=0.0),
@@ -256,16 +257,16 @@ def test_loop_last_step_from_two_levels_down(oracle_mod, cage, levels):
          "bipyramid": lambda: _bipyramid(9),
          "grid": lambda: G.grid_patch(7, 5, tri=True, z_fn=lambda x, y: rng.normal(0, 0.2, x.shape))}[cage]()
     L = levels
-    print(f"[parity] loop last step from level {L - 2}: {m.name} L={L}", flush=True)
-    outs, _ = api.refine(m, "loop", L)
+    print(f"[parity] {scheme} last step from level {L - 2}: {m.name} L={L}", flush=True)
+    outs, _ = api.refine(m, scheme, L)
     lag = {k: v.cpu().numpy() for k, v in outs[L].items()}
-    per, _ = api.refine(m, "loop", L, edges=True)
+    per, _ = api.refine(m, scheme, L, edges=True)
     np.testing.assert_array_equal(lag["face_verts"], per[L]["face_verts"].cpu().numpy())
     np.testing.assert_array_equal(lag["positions"], per[L]["positions"].cpu().numpy())
-    ref = oracle_mod.refine(m, "loop", L)
+    ref = oracle_mod.refine(m, scheme, L)
     np.testing.assert_array_equal(lag["face_verts"], ref[L].verts)
     assert normwise_err(lag["positions"], ref[L].positions) <= POS_TOL
-    every, _ = api.refine(m, "loop", L, keep="all")
+    every, _ = api.refine(m, scheme, L, keep="all")
     for k in range(1, L + 1):
         np.testing.assert_array_equal(every[k]["face_verts"].cpu().numpy(), ref[k].verts, err_msg=f"level {k}")
         assert normwise_err(every[k]["positions"].cpu().numpy(), ref[k].positions) <= POS_TOL
