@@ -695,6 +695,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
+  Adj aprev2{};  // adjacency of level k-2
   Topo tprev{};  // mesh matrix of level k-1
   // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
   // levels-1): when that level is a refined one and the caller wants no edge
@@ -755,6 +756,10 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       o.Vg = (int32_t)L[k - 1].V;
       o.ap = a;
       o.Vq = (int32_t)L[k - 2].V;
+      // level m-1's adjacency is still in place (step k-1 carried nothing):
+      // the older vertices walk there
+      o.app = aprev2;
+      o.Vr = k >= 3 ? (int32_t)L[k - 3].V : 0;
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
         SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
@@ -800,6 +805,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     }
     // level k+1 becomes the input of the next step
     tprev = t;
+    aprev2 = aprev;
     t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, L[k + 1].order, nullptr, nullptr, fv1};
     P = P1;
     aprev = ak;

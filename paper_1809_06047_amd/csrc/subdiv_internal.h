@@ -335,6 +335,8 @@ struct TriStep {
   int32_t Vg;    // levels >= 1: vertices of the level k was refined from (its old vertices); 0 on the cage
   Adj ap;        // levels >= 1: adjacency of that level (twin, eid, vhe), where the old vertices' rings are walked
   int32_t Vq;    // levels >= 2: vertices of level k-2 (the old vertices v >= Vq are its edge / face points)
+  Adj app;       // when set (twin != nullptr): adjacency of level k-2, where the rings of v < Vq are walked
+  int32_t Vr;    // with app: vertices of level k-3 (0 when level k-2 is the cage)
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);

@@ -83,6 +83,36 @@ struct Ring {
   int ub;  // start of the last incoming boundary half-edge, -1 if interior
 };
 
+// The fan of half-edges leaving a vertex, from h0 in rotation order, up to
+// kFan of them: only the dependent twin loads run in sequence here, and the
+// caller then issues every neighbour gather at once. Returns the count, or -1
+// when the fan is longer (the caller walks it one step at a time); hb = the
+// last half-edge when the fan ends at the boundary, else -1. Entries past the
+// count repeat the last half-edge, so loads through them stay in bounds.
+constexpr int kFan = 8;
+__device__ __forceinline__ int fan3(const int32_t *twin, int h0, int (&hs)[kFan], int &hb) {
+  int n = 0, h = h0;
+  bool go = true;
+  hb = -1;
+#pragma unroll
+  for (int i = 0; i < kFan; ++i) {
+    hs[i] = h;
+    if (go) {
+      n = i + 1;
+      const int tw = twin[h % 3 == 0 ? h + 2 : h - 1];
+      if (tw < 0) {
+        hb = h;
+        go = false;
+      } else if (tw == h0) {
+        go = false;
+      } else {
+        h = tw;
+      }
+    }
+  }
+  return go ? -1 : n;
+}
+
 __device__ __forceinline__ Ring ring3(const Topo &t, const Adj &a, const float *P, int v) {
   const int h0 = a.vhe[v];
   Ring R{{0.f, 0.f, 0.f}, 0, t.fv[he_next<3>(t, h0)], -1};
@@ -149,6 +179,22 @@ __device__ __forceinline__ Ring ring_prev_loop(const TriStep &c, int v) {
       return R;
     }
   }
+  int hs[kFan], hb;
+  const int n = fan3(a.twin, h0, hs, hb);
+  if (n > 0) {
+    f3 pt[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + a.eid[hs[i]]);
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n) R.sum = add3(R.sum, pt[i]);
+    R.faces = n;
+    if (hb >= 0) {
+      R.ub = c.Vg + a.eid[he_prev<3>(c.t, hb)];
+      R.sum = add3(R.sum, ld3(c.P, R.ub));
+    }
+    return R;
+  }
   int h = h0;
   while (true) {
     R.sum = add3(R.sum, ld3(c.P, c.Vg + a.eid[h]));
@@ -191,12 +237,155 @@ __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
       return R;
     }
   }
+  int hs[kFan], hb;
+  const int n = fan3(a.twin, h0, hs, hb);
+  if (n > 0) {
+    int ts[kFan];
+    f3 pt[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) ts[i] = a.twin[hs[i]];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + (ts[i] >= 0 ? ts[i] / 3 : 0));
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
+    R.faces = n;
+    if (hb >= 0) R.ub = 0;  // on the boundary: the vertex stays where it is
+    return R;
+  }
   int h = h0;
   while (true) {
     const int ts = a.twin[h];
     if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + ts / 3));
     ++R.faces;
     const int tw = a.twin[he_prev<3>(c.t, h)];
+    if (tw < 0) {
+      R.ub = 0;  // on the boundary: the vertex stays where it is
+      break;
+    }
+    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+  return R;
+}
+
+// Two levels down. An old vertex v < V_{k-2} of level k has the same ring
+// on level k-2, k-1 and k: the first-slot map takes a half-edge leaving v on
+// one level to the half-edge leaving v in the child at it on the next (Loop
+// h -> 4h - h mod 3, sqrt(3) h -> 3h), keeping the rotation order and the
+// boundary. So the walk (and, for the points born on level k-2, the closed
+// form) runs on level k-2's rows, a sixteenth (a ninth) of level k's, and
+// only the neighbour lookups touch level k-1: along the image h' of h the
+// neighbour is the level-k point named by h' (Loop: Vg + eid(h'); sqrt(3):
+// the face point Vg + (face across h')). Same neighbours, same order, same
+// bits as the walk one level down.
+__device__ __forceinline__ Ring ring_prev2_loop(const TriStep &c, int v) {
+  const Adj &x = c.app;
+  const int32_t *eid1 = c.ap.eid;
+  auto nb = [&](int h) { return c.Vg + eid1[4 * h - h % 3]; };
+  const int h0 = x.vhe[v];
+  Ring R{{0.f, 0.f, 0.f}, 0, nb(h0), -1};
+  if (c.Vr > 0 && v >= c.Vr) {
+    const int q = h0 / 3, r = q >> 2, cq = q & 3;
+    const bool first = (h0 % 3 == 1);
+    const int j = first ? cq : (cq + 2) % 3;
+    const int tw = x.twin[12 * r + 3 * j];
+    if (tw >= 0) {
+      const int qs = tw / 3, s = qs >> 2, i = ((qs & 3) + 2) % 3;
+      const int jn = (j + 1) % 3, in = (i + 1) % 3;
+      const int cyc[6] = {12 * r + 3 * j + 1, 12 * s + 3 * in + 2, 12 * s + 9 + i,
+                          12 * s + 3 * i + 1, 12 * r + 3 * jn + 2, 12 * r + 9 + j};
+      const int p0 = first ? 0 : 4;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int y = p0 + t;
+        R.sum = add3(R.sum, ld3(c.P, nb(cyc[y < 6 ? y : y - 6])));
+      }
+      R.faces = 6;
+      return R;
+    }
+  }
+  int hs[kFan], hb;
+  const int n = fan3(x.twin, h0, hs, hb);
+  if (n > 0) {
+    f3 pt[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, nb(hs[i]));
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n) R.sum = add3(R.sum, pt[i]);
+    R.faces = n;
+    if (hb >= 0) {
+      R.ub = c.Vg + eid1[4 * hb - hb % 3 + 2];
+      R.sum = add3(R.sum, ld3(c.P, R.ub));
+    }
+    return R;
+  }
+  int h = h0;
+  while (true) {
+    R.sum = add3(R.sum, ld3(c.P, nb(h)));
+    ++R.faces;
+    const int hp = he_prev<3>(c.t, h);
+    const int tw = x.twin[hp];
+    if (tw < 0) {
+      R.ub = c.Vg + eid1[4 * h - h % 3 + 2];  // the incoming half-edge of the child at h
+      R.sum = add3(R.sum, ld3(c.P, R.ub));
+      break;
+    }
+    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+  return R;
+}
+
+__device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
+  const Adj &x = c.app;
+  const int32_t *twin1 = c.ap.twin;
+  const int h0 = x.vhe[v];
+  Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
+  if (c.Vr > 0 && v >= c.Vr) {
+    const int r = v - c.Vr;
+    const int *tr = x.twin + 9ll * r;
+    const int t1[3] = {tr[1], tr[4], tr[7]};
+    if (t1[0] % 3 == 1 && t1[1] % 3 == 1 && t1[2] % 3 == 1) {
+      int p0 = 0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (h0 == t1[j]) p0 = 2 * j + 1;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int y = p0 + t < 6 ? p0 + t : p0 + t - 6, j = y >> 1;
+        // the ring's half-edges alternate F_r -> v_j (slot 2 of r's child j)
+        // and F_r -> F_s (the twin of its slot 1); all interior
+        const int he = (y & 1) ? t1[j] : 9 * r + 3 * j + 2;
+        R.sum = add3(R.sum, ld3(c.P, c.Vg + twin1[3 * he] / 3));
+      }
+      R.faces = 6;
+      return R;
+    }
+  }
+  int hs[kFan], hb;
+  const int n = fan3(x.twin, h0, hs, hb);
+  if (n > 0) {
+    int ts[kFan];
+    f3 pt[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) ts[i] = twin1[3 * hs[i]];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + (ts[i] >= 0 ? ts[i] / 3 : 0));
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
+    R.faces = n;
+    if (hb >= 0) R.ub = 0;
+    return R;
+  }
+  int h = h0;
+  while (true) {
+    const int ts = twin1[3 * h];
+    if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + ts / 3));
+    ++R.faces;
+    const int tw = x.twin[he_prev<3>(c.t, h)];
     if (tw < 0) {
       R.ub = 0;  // on the boundary: the vertex stays where it is
       break;
@@ -281,7 +470,9 @@ __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
     return;
   }
   const f3 p = ld3(c.P, v);
-  const Ring R = c.Vg > 0 ? ring_prev_loop(c, v) : ring3(c.t, c.a, c.P, v);
+  const Ring R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
+                 : (c.app.twin && v < c.Vq) ? ring_prev2_loop(c, v)
+                                            : ring_prev_loop(c, v);
   f3 S;
   if (R.ub >= 0) {
     S = fma3(0.75f, p, mul3(0.125f, add3(ld3(c.P, R.w0), ld3(c.P, R.ub))));
@@ -518,7 +709,9 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
     return;
   }
   const f3 p = ld3(c.P, v);
-  const Ring R = c.Vg > 0 ? ring_prev_sqrt3(c, v) : ring3(c.t, c.a, c.P, v);
+  const Ring R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
+                 : (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v)
+                                            : ring_prev_sqrt3(c, v);
   f3 S;
   if (R.ub >= 0) {
     S = p;
