@@ -168,7 +168,8 @@ struct Layout {
   size_t mfv[2], mP[2];
   // SUBDIV_FLAG_KEEP_STATE: adjacency of every level 1..L-1 and the backward scratch
   AdjOffsets keep[SUBDIV_MAX_LEVELS + 1];
-  size_t bg[2], bterm, bcoef;
+  size_t bg[2], bterm;
+  size_t kcoef[SUBDIV_MAX_LEVELS + 1];  // kept state: the adjoint's vertex-rule coefficients of level k
   size_t total;
 };
 
@@ -282,7 +283,7 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     y.bg[0] = c.take(12 * gV);
     y.bg[1] = c.take(12 * gV);
     y.bterm = c.take(12 * gH);
-    y.bcoef = c.take(16 * gV);
+    for (int k = 0; k < levels; ++k) y.kcoef[k] = c.take(16 * L[k].V);
   }
   y.total = c.at + 256;
   return y;
@@ -654,6 +655,12 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   return SUBDIV_OK;
 }
 
+}  // extern "C"
+namespace {
+int keep_bw_coefs(const subdiv_mesh *mesh, void *ws, const Layout &y, const Sizes *L, int levels, hipStream_t s);
+}
+extern "C" {
+
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream) {
   if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
@@ -691,8 +698,11 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   }
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
-  if (scheme == SUBDIV_CATMULL_CLARK && !rebuild)
-    return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
+  if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
+    if ((st = refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s)) != SUBDIV_OK)
+      return st;
+    return (plan->flags & SUBDIV_FLAG_KEEP_STATE) ? keep_bw_coefs(mesh, ws, y, L, levels, s) : SUBDIV_OK;
+  }
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
   Adj aprev2{};  // adjacency of level k-2
@@ -938,6 +948,45 @@ int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const 
   return SUBDIV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The adjoint's view of level k of a kept state: topology, adjacency, the
+// parent level's sizes for the closed-form classes, and the coefficients.
+BwdStep bwd_level(const subdiv_mesh *mesh, void *ws, const Layout &y, const Sizes *L, long long H0, int k) {
+  BwdStep b{};
+  if (k == 0) {
+    b.t = cage_topo(mesh, H0, ws, y);
+    b.a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
+  } else {
+    b.a = adj_at(ws, y.keep[k], L[k].E, L[k].creases);
+    b.t = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, b.a.fv};
+  }
+  if (k >= 2) {  // level k-1 is all quads
+    const Adj ap = adj_at(ws, y.keep[k - 1], L[k - 1].E, false);
+    b.Vp = (int32_t)L[k - 1].V;
+    b.Fp = (int32_t)L[k - 1].F;
+    b.bscan_p = L[k - 1].B > 0 ? ap.bscan : nullptr;
+  }
+  b.coef = at<float>(ws, y.kcoef[k]);
+  return b;
+}
+
+// The vertex-rule coefficients depend on the topology and the creases only:
+// they are part of the kept state, written once by the refinement that
+// builds it and read by every backward pass after it.
+int keep_bw_coefs(const subdiv_mesh *mesh, void *ws, const Layout &y, const Sizes *L, int levels, hipStream_t s) {
+  const long long H0 = cage_H(mesh);
+  for (int k = 0; k < levels; ++k) {
+    const BwdStep b = bwd_level(mesh, ws, y, L, H0, k);
+    SUBDIV_TIMED("bw_coef", k, bw_launch(BW_COEF, b, s));
+  }
+  return SUBDIV_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream) {
   if (!plan || !grad_out || !grad_in || !ws) return SUBDIV_INVALID_ARG;
@@ -956,25 +1005,10 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
   const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
   const float *g1 = grad_out;
   for (int k = levels - 1; k >= 0; --k) {
-    BwdStep b{};
-    if (k == 0) {
-      b.t = cage_topo(mesh, H0, ws, y);
-      b.a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
-    } else {
-      b.a = adj_at(ws, y.keep[k], L[k].E, L[k].creases);
-      b.t = Topo{(int32_t)L[k].V, (int32_t)L[k].F, (int32_t)L[k].H, 4, nullptr, nullptr, b.a.fv};
-    }
-    if (k >= 2) {  // level k-1 is all quads
-      const Adj ap = adj_at(ws, y.keep[k - 1], L[k - 1].E, false);
-      b.Vp = (int32_t)L[k - 1].V;
-      b.Fp = (int32_t)L[k - 1].F;
-      b.bscan_p = L[k - 1].B > 0 ? ap.bscan : nullptr;
-    }
+    BwdStep b = bwd_level(mesh, ws, y, L, H0, k);  // coefficients from the refinement that kept the state
     b.g1 = g1;
     b.g0 = (k == 0) ? grad_in : at<float>(ws, y.bg[k & 1]);
     b.term = at<float>(ws, y.bterm);
-    b.coef = at<float>(ws, y.bcoef);
-    SUBDIV_TIMED("bw_coef", k, bw_launch(BW_COEF, b, s));
     SUBDIV_TIMED("bw_face", k, bw_launch(BW_FACE, b, s));
     SUBDIV_TIMED("bw_vertex", k, bw_launch(BW_VERTEX, b, s));
     g1 = b.g0;
