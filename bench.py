@@ -112,8 +112,9 @@ def cpu_baseline(mesh, levels):
 
 class TwoDeep:
     """Steps two deep through api.StreamingRefiner: step i is planned on a
-    second stream, into the second of two workspaces, while step i-1 still
-    refines; every step validates, builds and refines its cage in full."""
+    third stream, into the second of two workspaces, while step i-1 still
+    refines, and refines on its slot's stream beside step i-1; every step
+    validates, builds and refines its cage in full."""
 
     def __init__(self, dmesh, levels, scheme="cc"):
         from paper_1809_06047_amd import api
@@ -205,6 +206,8 @@ def main():
     units = info[dlevel - 1][unit_key]  # one thread per element of the parent level
     avg_ms = total_ms / launches
     achieved = per_unit * units / (avg_ms / 1000.0) / 1e9
+    alone_ms = all_stages[(dname, dlevel)][1] / all_stages[(dname, dlevel)][0]
+    alone_gbs = per_unit * units / (alone_ms / 1000.0) / 1e9
 
     out = {
         "metric": METRIC,
@@ -226,7 +229,7 @@ def main():
             "faces_out": faces_out,
             "vertices_out": info[L]["V"],
             "step": "subdiv_plan + subdiv_refine (dynamic topology), steps two deep: the plan of a step "
-                    "overlaps the refinement of the one before",
+                    "and its refinement (on its slot's stream) overlap the refinement of the one before",
             "ms_per_step_one_at_a_time": round(ms_serial, 4),
         },
         "roofline": {
@@ -239,6 +242,11 @@ def main():
             "traffic": measured_traffic(dname, dlevel),
             "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_bytes_per_launch": per_unit * units,
+            # the timed steps run two deep, so the other slot's small levels and
+            # plan share the GPU with this kernel; the same kernel in the
+            # calibration steps, one step at a time on one stream:
+            "alone": {"avg_launch_ms": round(alone_ms, 5), "achieved": round(alone_gbs, 1),
+                      "frac": round(alone_gbs / HBM_PEAK_GBS, 4)},
         },
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / calib, 4) for k, v in sorted(all_stages.items())},

@@ -346,20 +346,23 @@ def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
 class StreamingRefiner:
     """Cages with changing topology, refined one after the other, two deep:
     the plan of cage i (into its own workspace, on a plan stream) overlaps
-    the refinement of cage i-1 (on the refine stream), so the GPU does not
-    idle while the host waits for a plan's read-back. Every cage is still
-    validated, built and refined in full. step() returns the cage's output
-    dicts (as Refiner.run) and an event recorded after its refinement; the
-    tensors are ready once the event has completed. A slot's refiner is
-    reused while the cage is the same DeviceMesh, and its plan waits for the
-    refinement that last used its workspace. Both streams have the default
-    priority."""
+    the refinement of cage i-1, so the GPU does not idle while the host waits
+    for a plan's read-back. Each of the two slots (workspace, outputs) has
+    its own refine stream, so cage i's refinement also runs beside cage
+    i-1's: the launch-bound small levels of one fill the gaps of the other's
+    HBM-bound last level. Every cage is still validated, built and refined
+    in full. step() returns the cage's output dicts (as Refiner.run) and an
+    event recorded after its refinement; the tensors are ready once the
+    event has completed. A slot's refiner is reused while the cage is the
+    same DeviceMesh, its plan waits for the refinement that last used its
+    workspace, and its refinements run in order on its stream. All streams
+    have the default priority."""
 
     def __init__(self, scheme, levels: int, flags: int = 0, keep: str = "final", device="cuda"):
         self.scheme, self.levels, self.flags, self.keep = scheme, int(levels), int(flags), keep
         dev = torch.device(device)
         self.plan_stream = torch.cuda.Stream(dev)
-        self.refine_stream = torch.cuda.Stream(dev)
+        self.refine_streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
         self.slots: List[Optional[Refiner]] = [None, None]
         self.done: List[Optional[torch.cuda.Event]] = [None, None]
         self.i = 0
@@ -370,17 +373,18 @@ class StreamingRefiner:
     def step(self, dmesh: "DeviceMesh"):
         j = self.i & 1
         r = self.slots[j]
+        rs = self.refine_streams[j]
         if self.done[j] is not None:
             self.plan_stream.wait_event(self.done[j])
         if r is None or r.dmesh is not dmesh:
-            with torch.cuda.stream(self.refine_stream):
+            with torch.cuda.stream(rs):
                 r = Refiner(dmesh, self.scheme, self.levels, self.flags, self.keep)
             self.slots[j] = r
-        with torch.cuda.stream(self.refine_stream):  # outputs are allocated for, and written on, this stream
+        with torch.cuda.stream(rs):  # the slot's outputs are allocated for, and written on, its stream
             r.plan(stream=self.plan_stream.cuda_stream)
-            outs = r.run(stream=self.refine_stream.cuda_stream)
+            outs = r.run(stream=rs.cuda_stream)
             ev = torch.cuda.Event()
-            ev.record(self.refine_stream)
+            ev.record(rs)
         self.done[j] = ev
         self.i += 1
         return outs, ev

@@ -1,7 +1,8 @@
 """Cages with changing topology streamed two deep (api.StreamingRefiner: the
-plan of one cage overlaps the refinement of the previous one, on two streams
-and two workspaces): every step's output equals refining that cage alone,
-bit for bit."""
+plan of one cage overlaps the refinement of the previous one, and the two
+slots' refinements run side by side on their own streams, each with its own
+workspace): every step's output equals refining that cage alone, bit for
+bit."""
 import numpy as np
 import pytest
 import torch
