@@ -592,14 +592,16 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
   auto crease = [&](int em) {
     const int x = lag_base(L, em);
     const double s = L.sigk[x];
-    if (s > 0.0) {
-      if (kc == 0) { cv0 = VFm + em; ce0 = x; } else if (kc == 1) { cv1 = VFm + em; ce1 = x; }
-      ++kc;
-      ssum += s;
-    }
+    const bool on = s > 0.0;
+    // selects, not branches: branches here were turned into a two-slot array
+    // indexed by kc, which lived in scratch memory
+    cv0 = (on && kc == 0) ? VFm + em : cv0;
+    ce0 = (on && kc == 0) ? x : ce0;
+    cv1 = (on && kc == 1) ? VFm + em : cv1;
+    ce1 = (on && kc == 1) ? x : ce1;
+    kc += on;
+    ssum += on ? s : 0.0;
   };
-  int ring[4];
-  bool closed = false;
   if (c.Vq > 0 && v >= c.Vq) {
     if (v < c.Vq + c.Fq) {  // face point: never on a crease or the boundary
       const int b = 16 * (v - c.Vq) + 2;
@@ -613,22 +615,60 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
       if (tw >= 0) {  // interior edge point
         const int bn = tw >> 2, b = quad_prev(bn);
         const int cyc[4] = {4 * a + 1, 4 * bn + 3, 4 * b + 1, 4 * quad_next(a) + 3};
-        const int s0 = (h0 & 3) == 1 ? 0 : 3;
+        // from the start: cyc[0..3], or cyc[3], cyc[0..2] (static indices: the
+        // cycle stays in registers)
+        const bool at0 = (h0 & 3) == 1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ring[j] = cyc[(s0 + j) & 3];
-        closed = true;
+        for (int j = 0; j < 4; ++j) {
+          const int hj = at0 ? cyc[j] : cyc[(j + 3) & 3];
+          sum = add3(sum, term0[hj]);
+          if (creases) crease(L.am.eid[4 * hj]);
+          hlast = hj;
+        }
+        n = 4;
       }
     }
   }
-  if (closed) {
+  if (n == 0) {
+    // the fan first (only the twin loads in sequence), then every term at once
+    constexpr int kFan = 8;
+    int hs[kFan];
+    bool go = true;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      sum = add3(sum, term0[ring[j]]);
-      if (creases) crease(L.am.eid[4 * ring[j]]);
+    for (int i = 0; i < kFan; ++i) {
+      hs[i] = h;  // past the end: repeats the last half-edge (loads stay in bounds)
+      if (go) {
+        n = i + 1;
+        const int t = c.twin_g[(h & 3) == 0 ? h + 3 : h - 1];
+        if (t < 0) {
+          bnd = true;
+          go = false;
+        } else if (t == h0) {
+          go = false;
+        } else {
+          h = t;
+        }
+      }
     }
-    n = 4;
-    hlast = ring[3];
-  } else if (n == 0) {
+    if (!go) {
+      f3 tv[kFan];
+#pragma unroll
+      for (int i = 0; i < kFan; ++i) tv[i] = term0[hs[i]];
+#pragma unroll
+      for (int i = 0; i < kFan; ++i)
+        if (i < n) {
+          sum = add3(sum, tv[i]);
+          if (creases) crease(L.am.eid[4 * hs[i]]);
+          hlast = hs[i];
+        }
+      if (creases && bnd) crease(L.am.eid[4 * hlast + 3]);  // the incoming boundary edge
+    } else {  // a longer fan: walk it one step at a time
+      n = 0;
+      bnd = false;
+      h = h0;
+    }
+  }
+  if (n == 0) {
     while (true) {
       sum = add3(sum, term0[h]);
       ++n;
