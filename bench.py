@@ -80,6 +80,9 @@ def parse():
                     help="levels of the adjoint leg on the same cage (0 = skip)")
     ap.add_argument("--tri-levels", type=int, default=5,
                     help="levels of the Loop and sqrt(3) legs on the holed triangle cage (0 = skip)")
+    ap.add_argument("--no-side-legs", action="store_true",
+                    help="skip the static-topology, selective, reorder and adjoint legs (for kernel profiles: "
+                         "the Catmull-Clark kernels then come from full refinements of the headline workload only)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -253,10 +256,11 @@ def main():
         "stages_note": "stage times from untimed calibration steps with an event pair around every stage; "
                        "the timed steps carry events around the dominant kernel only",
     }
-    out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
-    out["selective"] = selective_leg(mesh, 4, 2, 2, max(3, args.steps // 4))
-    out["reorder"] = reorder_leg(mesh, args.levels, max(5, args.steps // 2))
-    if args.adjoint_levels > 0:
+    if not args.no_side_legs:
+        out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
+        out["selective"] = selective_leg(mesh, 4, 2, 2, max(3, args.steps // 4))
+        out["reorder"] = reorder_leg(mesh, args.levels, max(5, args.steps // 2))
+    if args.adjoint_levels > 0 and not args.no_side_legs:
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
         out["triangle_schemes"] = {sc: scheme_leg(G.tri_cage(), sc, args.tri_levels, max(3, args.steps // 4))
