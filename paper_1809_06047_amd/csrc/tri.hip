@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
 // kernels above (two-term sums commute) and the stencils are the same
 // uncontracted ones, so both give the same bits.
 __global__ void __launch_bounds__(kBlock) k_loopl_face(TriLag c) {
-  __shared__ int4 stage[kBlock / 64][64 * 13];
+  __shared__ int4 stage[kBlock / 64][32 * 13];
   const int F = c.tm.F;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = rid < F ? rid : F - 1;  // every lane takes part in the staged store
@@ -798,16 +798,25 @@ __global__ void __launch_bounds__(kBlock) k_loopl_face(TriLag c) {
       out[12 * q + 9 + i] = Vk + xk[3 * q + i];
     }
   }
-  // 12 int4 per lane, leaving through LDS as 12 instructions of 64 int4
+  // 12 int4 per lane, leaving through LDS: half the wave's faces at a time
+  // (half the LDS, twice the occupancy), 6 instructions of 64 int4 (1 KB
+  // contiguous) per half
 #pragma unroll
-  for (int x = 0; x < 12; ++x) lds[13 * l + x] = make_int4(out[4 * x], out[4 * x + 1], out[4 * x + 2], out[4 * x + 3]);
-  __builtin_amdgcn_wave_barrier();
-  int4 *dst = reinterpret_cast<int4 *>(c.fv2) + 12 * rw;
+  for (int hf = 0; hf < 2; ++hf) {
+    if ((l >> 5) == hf) {
 #pragma unroll
-  for (int t = 0; t < 12; ++t) {
-    const int g = 64 * t + l, src = g / 12;
-    const int4 x = lds[13 * src + (g - 12 * src)];
-    if (g < cnt) stream_store4(dst + g, x);
+      for (int x = 0; x < 12; ++x)
+        lds[13 * (l & 31) + x] = make_int4(out[4 * x], out[4 * x + 1], out[4 * x + 2], out[4 * x + 3]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    int4 *dst = reinterpret_cast<int4 *>(c.fv2) + 12 * (rw + 32 * hf);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int g = 64 * t + l, src = g / 12;
+      const int4 x = lds[13 * src + (g - 12 * src)];
+      if (g + 384 * hf < cnt) stream_store4(dst + g, x);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
