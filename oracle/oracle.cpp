@@ -36,7 +36,10 @@
 //   * sqrt(3): boundary half-edges are not flipped and emit (v_j, v_j+1, f_r);
 //     boundary vertices stay fixed.
 //   * Loop/sqrt(3) valence n = number of distinct neighbours.
-//   * Creases (Catmull-Clark only): k = incident edges with sigma > 0,
+//   * Creases (Catmull-Clark and Loop; the paper gives them for
+//     Catmull-Clark, and Loop takes the same rules on its own smooth
+//     points, with Loop's edge point as the "smooth" edge value; sqrt(3)
+//     rejects them): k = incident edges with sigma > 0,
 //     s = mean of their sigma. Edge: sigma >= 1 -> midpoint, else blend
 //     (1-sigma) smooth + sigma midpoint. Vertex: k <= 1 smooth, k == 2 crease
 //     rule 3/4 p + 1/8 (a + b), k >= 3 corner p; s >= 1 -> sharp rule, else
@@ -345,26 +348,72 @@ struct Evaluator {
     return L.fv[he_prev(L, f, h)];
   }
 
+  // Crease vertices overwrite the smooth vertex points out[0..V): crease
+  // valency k (eq:CC_crease_valency) and vertex sharpness s, the mean of the
+  // incident creases' sigma (eq:CC_crease_vsharpness); k == 2 takes the
+  // crease rule 3/4 p + 1/8 (the two crease neighbours), k >= 3 the corner
+  // rule p, blended with the smooth point when s < 1. Boundary vertices keep
+  // the boundary rule. The same rules serve Catmull-Clark and Loop.
+  void crease_vertices(const std::vector<T>& P, std::vector<T>& out) const {
+    const int V = L.nv, E = A.ne;
+    std::vector<int> k(V, 0);
+    std::vector<double> ssum(V, 0.0);
+    std::vector<std::vector<int>> cnb(V);
+    for (int e = 0; e < E; ++e)
+      if (sig[e] > 0.0) {
+        for (int end = 0; end < 2; ++end) {
+          const int v = end ? A.e_hi[e] : A.e_lo[e];
+          const int w = end ? A.e_lo[e] : A.e_hi[e];
+          k[v]++;
+          ssum[v] += sig[e];
+          cnb[v].push_back(w);
+        }
+      }
+    for (int v = 0; v < V; ++v) {
+      if (A.bnd.size(v) > 0 || k[v] < 2) continue;
+      T sharp;
+      if (k[v] == 2) {
+        acc(sharp, 0.75, P[v]);
+        acc(sharp, 0.125, P[cnb[v][0]]);
+        acc(sharp, 0.125, P[cnb[v][1]]);
+      } else {
+        acc(sharp, 1.0, P[v]);
+      }
+      const double s = ssum[v] / k[v];
+      if (s >= 1.0) {
+        out[v] = sharp;
+      } else {
+        T blend;
+        acc(blend, 1.0 - s, out[v]);
+        acc(blend, s, sharp);
+        out[v] = blend;
+      }
+    }
+  }
+
+  // An interior crease edge's point: sigma >= 1 the midpoint, 0 < sigma < 1
+  // (1 - sigma) smooth + sigma midpoint.
+  void crease_edge(double s, const T& smooth, const T& pa, const T& pb, T& ep) const {
+    if (s >= 1.0) {
+      acc(ep, 0.5, pa);
+      acc(ep, 0.5, pb);
+    } else if (s > 0.0) {
+      T mid;
+      acc(mid, 0.5, pa);
+      acc(mid, 0.5, pb);
+      acc(ep, 1.0 - s, smooth);
+      acc(ep, s, mid);
+    } else {
+      ep = smooth;
+    }
+  }
+
   std::vector<T> run(const std::vector<T>& P) const {
     const int V = L.nv, F = L.nf(), E = A.ne;
     std::vector<T> out;
     if (scheme == CATMULL_CLARK) {
       const std::vector<T> f = face_points(P);
       out.resize((size_t)V + F + E);
-      // crease valency k and vertex sharpness s (eq:CC_crease_valency, eq:CC_crease_vsharpness)
-      std::vector<int> k(V, 0);
-      std::vector<double> ssum(V, 0.0);
-      std::vector<std::vector<int>> cnb(V);
-      for (int e = 0; e < E; ++e)
-        if (sig[e] > 0.0) {
-          for (int end = 0; end < 2; ++end) {
-            const int v = end ? A.e_hi[e] : A.e_lo[e];
-            const int w = end ? A.e_lo[e] : A.e_hi[e];
-            k[v]++;
-            ssum[v] += sig[e];
-            cnb[v].push_back(w);
-          }
-        }
       // vertex points (eq:pos_update split as s1 + s2 + s3)
       for (int v = 0; v < V; ++v) {
         T& S = out[v];
@@ -379,27 +428,7 @@ struct Evaluator {
         for (const int* w = A.nbrs.begin(v); w != A.nbrs.end(v); ++w) acc(S, 1.0 / (n * n), P[*w]);  // s2
         for (const int* r = A.vfaces.begin(v); r != A.vfaces.end(v); ++r) acc(S, 1.0 / (n * n), f[*r]);  // s3
       }
-      // crease vertices overwrite the smooth result
-      for (int v = 0; v < V; ++v) {
-        if (A.bnd.size(v) > 0 || k[v] < 2) continue;
-        T sharp;
-        if (k[v] == 2) {
-          acc(sharp, 0.75, P[v]);
-          acc(sharp, 0.125, P[cnb[v][0]]);
-          acc(sharp, 0.125, P[cnb[v][1]]);
-        } else {
-          acc(sharp, 1.0, P[v]);
-        }
-        const double s = ssum[v] / k[v];
-        if (s >= 1.0) {
-          out[v] = sharp;
-        } else {
-          T blend;
-          acc(blend, 1.0 - s, out[v]);
-          acc(blend, s, sharp);
-          out[v] = blend;
-        }
-      }
+      crease_vertices(P, out);
       for (int r = 0; r < F; ++r) out[(size_t)V + r] = f[r];
       // edge points
       for (int e = 0; e < E; ++e) {
@@ -415,19 +444,7 @@ struct Evaluator {
         acc(smooth, 0.25, P[b]);
         acc(smooth, 0.25, f[A.he_face[A.e_he0[e]]]);
         acc(smooth, 0.25, f[A.he_face[A.e_he1[e]]]);
-        const double s = sig[e];
-        if (s >= 1.0) {
-          acc(ep, 0.5, P[a]);
-          acc(ep, 0.5, P[b]);
-        } else if (s > 0.0) {
-          T mid;
-          acc(mid, 0.5, P[a]);
-          acc(mid, 0.5, P[b]);
-          acc(ep, 1.0 - s, smooth);
-          acc(ep, s, mid);
-        } else {
-          ep = smooth;
-        }
+        crease_edge(sig[e], smooth, P[a], P[b], ep);
       }
     } else if (scheme == LOOP) {
       out.resize((size_t)V + E);
@@ -445,6 +462,7 @@ struct Evaluator {
         acc(S, 1.0 - n * beta, P[v]);
         for (const int* w = A.nbrs.begin(v); w != A.nbrs.end(v); ++w) acc(S, beta, P[*w]);
       }
+      crease_vertices(P, out);  // the crease rules of Catmull-Clark, applied to Loop's points
       for (int e = 0; e < E; ++e) {
         T& ep = out[(size_t)V + e];
         const int a = A.e_lo[e], b = A.e_hi[e];
@@ -453,10 +471,12 @@ struct Evaluator {
           acc(ep, 0.5, P[b]);
           continue;
         }
-        acc(ep, 0.375, P[a]);
-        acc(ep, 0.375, P[b]);
-        acc(ep, 0.125, P[opposite(A.e_he0[e])]);
-        acc(ep, 0.125, P[opposite(A.e_he1[e])]);
+        T smooth;
+        acc(smooth, 0.375, P[a]);
+        acc(smooth, 0.375, P[b]);
+        acc(smooth, 0.125, P[opposite(A.e_he0[e])]);
+        acc(smooth, 0.125, P[opposite(A.e_he1[e])]);
+        crease_edge(sig[e], smooth, P[a], P[b], ep);
       }
     } else {  // SQRT3
       const std::vector<T> f = face_points(P);
@@ -478,6 +498,37 @@ struct Evaluator {
   }
 };
 
+// Crease inheritance (Chaikin variant): crease edge e = (lo, hi) has the
+// children (lo, m) and (hi, m), m = first_ep + e its edge point, with the
+// sharpness of the rule at each end; children of sharpness 0 are dropped.
+// Sorted by (hi, lo) like the edge ids.
+void inherit_creases(int V, int first_ep, const Adjacency& A, const std::vector<double>& sig, Result& R) {
+  const int E = A.ne;
+  std::vector<int> k(V, 0);
+  std::vector<std::vector<int>> ce(V);
+  for (int e = 0; e < E; ++e)
+    if (sig[e] > 0.0) {
+      k[A.e_lo[e]]++;
+      k[A.e_hi[e]]++;
+      ce[A.e_lo[e]].push_back(e);
+      ce[A.e_hi[e]].push_back(e);
+    }
+  for (int e = 0; e < E; ++e) {
+    if (!(sig[e] > 0.0)) continue;
+    const int m = first_ep + e;
+    for (int end = 0; end < 2; ++end) {
+      const int v = end ? A.e_hi[e] : A.e_lo[e];
+      double si = sig[e];
+      if (k[v] == 2) si = sig[ce[v][0] == e ? ce[v][1] : ce[v][0]];
+      const double sc = chaikin(si, sig[e]);
+      if (sc > 0.0) R.creases.push_back(Crease{v, m, sc});  // lo = v < hi = m
+    }
+  }
+  std::sort(R.creases.begin(), R.creases.end(), [](const Crease& x, const Crease& y) {
+    return x.hi != y.hi ? x.hi < y.hi : x.lo < y.lo;
+  });
+}
+
 // Topology of the refined mesh and inherited creases.
 void refine_topology(int scheme, const Level& L, const Adjacency& A, const std::vector<double>& sig, Result& R) {
   const int V = L.nv, F = L.nf(), H = L.nh(), E = A.ne;
@@ -497,30 +548,7 @@ void refine_topology(int scheme, const Level& L, const Adjacency& A, const std::
         q[2] = V + r;
         q[3] = V + F + A.he_eid[hp];
       }
-    // crease inheritance (Chaikin variant); children (lo, m) and (hi, m)
-    std::vector<int> k(V, 0);
-    std::vector<std::vector<int>> ce(V);
-    for (int e = 0; e < E; ++e)
-      if (sig[e] > 0.0) {
-        k[A.e_lo[e]]++;
-        k[A.e_hi[e]]++;
-        ce[A.e_lo[e]].push_back(e);
-        ce[A.e_hi[e]].push_back(e);
-      }
-    for (int e = 0; e < E; ++e) {
-      if (!(sig[e] > 0.0)) continue;
-      const int m = V + F + e;
-      for (int end = 0; end < 2; ++end) {
-        const int v = end ? A.e_hi[e] : A.e_lo[e];
-        double si = sig[e];
-        if (k[v] == 2) si = sig[ce[v][0] == e ? ce[v][1] : ce[v][0]];
-        const double sc = chaikin(si, sig[e]);
-        if (sc > 0.0) R.creases.push_back(Crease{v, m, sc});  // lo = v < hi = m
-      }
-    }
-    std::sort(R.creases.begin(), R.creases.end(), [](const Crease& x, const Crease& y) {
-      return x.hi != y.hi ? x.hi < y.hi : x.lo < y.lo;
-    });
+    inherit_creases(V, V + F, A, sig, R);
   } else if (scheme == LOOP) {
     O.nv = V + E;
     O.off.resize((size_t)4 * F + 1);
@@ -541,6 +569,7 @@ void refine_topology(int scheme, const Level& L, const Adjacency& A, const std::
       t[1] = e[1];
       t[2] = e[2];
     }
+    inherit_creases(V, V, A, sig, R);
   } else {
     O.nv = V + F;
     O.off.resize((size_t)3 * F + 1);
@@ -587,7 +616,7 @@ void* oracle_step(int scheme, int nv, int nf, const int* off, const int* fv, con
     if (scheme != CATMULL_CLARK) {
       for (int f = 0; f < nf; ++f)
         if (L.off[f + 1] - L.off[f] != 3) faults |= F_SCHEME_MESH;
-      if (nc > 0) faults |= F_INVALID_ARG;  // creases: Catmull-Clark only
+      if (nc > 0 && scheme == SQRT3) faults |= F_INVALID_ARG;  // creases: Catmull-Clark and Loop
     }
   }
   Adjacency A;

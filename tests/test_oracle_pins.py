@@ -504,6 +504,78 @@ def test_chaikin_on_closed_crease_loop(oracle_mod):
     assert lv[3].crease_sharp.size == 0
 
 
+def _tet_with_creases(sigma):
+    t = G.tetrahedron()
+    e = G.mesh_edges(None, t.verts, 3).astype(np.int32)
+    return G.Mesh(positions=t.positions, verts=t.verts, face_order=3, crease_verts=e,
+                  crease_sharp=np.full(len(e), sigma, np.float32))
+
+
+def test_loop_infinitely_sharp_tetrahedron(oracle_mod):
+    """Loop with every edge of a tetrahedron sharp beyond the levels (the
+    Catmull-Clark crease rules applied to Loop's points): each corner has
+    three creases and stays exactly where it is; crease edge points are
+    midpoints and crease vertices take 3/4 p + 1/8 (two crease neighbours),
+    so every crease vertex stays on its edge line; every other new point is
+    a Loop combination of points of one face, so it stays in that face's
+    plane. A dropped crease term would pull points off the surface."""
+    L = 3
+    lv = oracle_mod.refine(_tet_with_creases(10.0), "loop", L)
+    t = G.tetrahedron()
+    P0 = t.positions.astype(np.float64)
+    for k in range(1, L + 1):
+        np.testing.assert_array_equal(lv[k].positions[:4], P0)
+        assert np.all(lv[k].crease_sharp == 10.0 - k)
+        assert lv[k].crease_sharp.size == 6 * 2 ** k
+    planes = []
+    for f in t.face_list():
+        a, b, c = P0[f]
+        n = np.cross(b - a, c - a)
+        planes.append((n / np.linalg.norm(n), a))
+    P = lv[L].positions
+    d = np.min(np.stack([np.abs((P - a) @ n) for n, a in planes]), axis=0)
+    assert d.max() < 1e-14
+    # crease vertices of the last level lie on the cage's edge lines
+    on_edge = lambda p, a, b: np.linalg.norm(np.cross(p - a, b - a)) / np.linalg.norm(b - a)
+    edges = G.mesh_edges(None, t.verts, 3)
+    for lo, hi in lv[L].crease_verts:
+        for v in (lo, hi):
+            assert min(on_edge(P[v], P0[a], P0[b]) for a, b in edges) < 1e-14
+
+
+def test_loop_creases_zero_sigma_is_smooth_and_chaikin(oracle_mod):
+    """Loop with sharpness 0 everywhere is smooth Loop; a closed crease loop
+    of constant sigma (every end point has two creases) halves into children
+    of sigma - 1, level after level (the rule of Sec. 3.3)."""
+    np.testing.assert_array_equal(oracle_mod.refine(_tet_with_creases(0.0), "loop", 2)[2].positions,
+                                  oracle_mod.refine(G.tetrahedron(), "loop", 2)[2].positions)
+    # the equator of an octahedron: four edges, each end point on two of them
+    P = np.array([[1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float32)
+    F = [[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4], [1, 0, 5], [2, 1, 5], [3, 2, 5], [0, 3, 5]]
+    ring = np.array([[0, 1], [1, 2], [2, 3], [0, 3]], np.int32)
+    m = G.Mesh(positions=P, verts=np.array(F, np.int32).reshape(-1), face_order=3, crease_verts=ring,
+               crease_sharp=np.full(4, 2.5, np.float32))
+    lv = oracle_mod.refine(m, "loop", 3)
+    assert lv[1].crease_sharp.size == 8 and np.all(lv[1].crease_sharp == 1.5)
+    assert lv[2].crease_sharp.size == 16 and np.all(lv[2].crease_sharp == 0.5)
+    assert lv[3].crease_sharp.size == 0
+    # a sharp equator keeps the equator's points in the plane z = 0 (crease
+    # rules only read points of the loop), and the crease points of level 1
+    # are the midpoints of the square's edges or the 3/4, 1/8 rule of its corners
+    sharp = G.Mesh(positions=P, verts=m.verts, face_order=3, crease_verts=ring, crease_sharp=np.full(4, 5.0, np.float32))
+    s1 = oracle_mod.refine(sharp, "loop", 1)[1]
+    np.testing.assert_allclose(s1.positions[0], [0.75, 0, 0], atol=1e-15)       # 3/4 p + 1/8 (p1 + p3)
+    eq = [v for v in np.unique(s1.crease_verts)]
+    assert np.all(np.abs(s1.positions[eq, 2]) < 1e-15)
+
+
+def test_loop_semisharp_blend_is_linear_in_sigma(oracle_mod):
+    smooth = oracle_mod.refine(G.tetrahedron(), "loop", 1)[1].positions
+    sharp = oracle_mod.refine(_tet_with_creases(1.0), "loop", 1)[1].positions
+    half = oracle_mod.refine(_tet_with_creases(0.5), "loop", 1)[1].positions
+    np.testing.assert_allclose(half, 0.5 * (smooth + sharp), atol=1e-15)
+
+
 def test_semisharp_blend_is_linear_in_sigma(oracle_mod):
     """Fractional sharpness (0 < sigma < 1) blends the smooth and sharp
     results linearly (reading of the DeRose rules the paper defers to; the
@@ -607,5 +679,6 @@ def test_status_codes(oracle_mod):
     t = G.tetrahedron()
     tc = G.Mesh(positions=t.positions, verts=t.verts, face_order=3, crease_verts=np.array([[0, 1]], np.int32),
                 crease_sharp=np.array([1.0], np.float32))
-    assert oracle_mod.status_of(tc, "loop") == -1                                    # creases: CC only
+    assert oracle_mod.status_of(tc, "loop") == 0                                     # creases: CC and Loop
+    assert oracle_mod.status_of(tc, "sqrt3") == -1                                   # not sqrt(3)
     assert oracle_mod.status_of(G.cube(), "cc") == 0
