@@ -89,7 +89,9 @@ typedef struct subdiv_mesh {
   const int32_t *face_offsets;    /* [|f|+1] column pointer of M (starts at 0, non-decreasing), or NULL */
   const int32_t *face_verts;      /* [H] row indices of M, CCW per face; 16-byte aligned */
   const float *positions;         /* [|v|*3] row-major x,y,z */
-  int32_t num_creases;            /* crease matrix C as a list (Sec. 3.3); Catmull-Clark only */
+  int32_t num_creases;            /* crease matrix C as a list (Sec. 3.3); Catmull-Clark and Loop
+                                     (Loop takes the same crease rules on its own points);
+                                     sqrt(3) returns SUBDIV_INVALID_ARG */
   const int32_t *crease_verts;    /* [2*num_creases] end points of crease edges */
   const float *crease_sharpness;  /* [num_creases] sharpness sigma >= 0 (0 = smooth edge) */
 } subdiv_mesh;

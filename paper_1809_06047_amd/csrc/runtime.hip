@@ -108,7 +108,7 @@ struct Sizes {
 // Closed-form counts of the refined levels (index rules of Sec. 3.2, App. A, App. B).
 void level_sizes(int scheme, int levels, long long V0, long long F0, long long H0, long long E0, long long B0,
                  int order0, float max_sharp, long long C0, Sizes *L) {
-  L[0] = Sizes{V0, E0, F0, H0, B0, order0, (scheme == SUBDIV_CATMULL_CLARK && C0 > 0 && max_sharp > 0.f) ? 1 : 0};
+  L[0] = Sizes{V0, E0, F0, H0, B0, order0, (scheme != SUBDIV_SQRT3 && C0 > 0 && max_sharp > 0.f) ? 1 : 0};
   for (int k = 0; k < levels; ++k) {
     const Sizes &a = L[k];
     Sizes b{};
@@ -247,16 +247,7 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       y.hs = c.take(24 * mE);
       y.term0 = c.take(12 * mF);
     }
-    if (!rebuild && scheme != SUBDIV_CATMULL_CLARK) {
-      // edge bases of the carried triangle levels (Loop: one entry per edge,
-      // sqrt(3): per face) of every level that is refined further
-      long long mX = 0;
-      for (int k = 0; k < levels - 1; ++k) {
-        const long long x = scheme == SUBDIV_LOOP ? L[k].E : L[k].F;
-        mX = x > mX ? x : mX;
-      }
-      y.tbase = c.take(4 * (mX + 1));
-    }
+
     if (rebuild) {
       y.bnval = c.take(4 * (mV + 1));
       y.browptr = c.take(4 * (mV + 1));
@@ -272,6 +263,19 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       y.mfv[s] = c.take(4 * mH);
       y.mP[s] = c.take(12 * mV);
     }
+  }
+  if (scheme != SUBDIV_CATMULL_CLARK && levels >= 1) {
+    // edge bases of the triangle levels (Loop: one entry per edge, sqrt(3):
+    // per face) of every level that is refined further, and with Loop
+    // creases on the last level refined, of that level too (its bases give
+    // the ids of the inherited sharpness)
+    long long mX = 0;
+    const int last = (scheme == SUBDIV_LOOP && L[levels - 1].creases) ? levels : levels - 1;
+    for (int k = 0; k < last; ++k) {
+      const long long x = scheme == SUBDIV_LOOP ? L[k].E : L[k].F;
+      mX = x > mX ? x : mX;
+    }
+    y.tbase = c.take(4 * (mX + 1));
   }
   if (flags & SUBDIV_FLAG_KEEP_STATE) {
     long long gV = L[0].V, gH = L[0].H;
@@ -374,7 +378,7 @@ int check_mesh_args(const subdiv_mesh *m, int scheme, int levels) {
   if (m->face_offsets && m->num_halfedges < 3) return SUBDIV_INVALID_ARG;
   if (m->num_creases < 0 || (m->num_creases > 0 && (!m->crease_verts || !m->crease_sharpness)))
     return SUBDIV_INVALID_ARG;
-  if (m->num_creases > 0 && scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;
+  if (m->num_creases > 0 && scheme == SUBDIV_SQRT3) return SUBDIV_INVALID_ARG;  // creases: CC and Loop
   return SUBDIV_OK;
 }
 
@@ -710,7 +714,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
   // levels-1): when that level is a refined one and the caller wants no edge
   // list of level levels-1
-  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !outs[levels].edge_verts;
+  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !outs[levels].edge_verts &&
+                       !L[levels - 1].creases;  // (the last step from level levels-2 has no crease rules)
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -786,11 +791,16 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       // for the caller
       const bool before_lag = tri_lag && k == levels - 2;
       const bool carry = !rebuild && !final && !before_lag;  // level k+1's adjacency in closed form
+      // Loop creases of level k, and whether level k+1 inherits any
+      const bool lcr = scheme == SUBDIV_LOOP && L[k].creases && a.sig && a.vcr;
+      double *sig1 = nullptr;
+      if (lcr && L[k + 1].creases)
+        sig1 = final ? outs[k + 1].crease_sharpness : adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, true).sig;
       if (carry) {
-        c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, false);
+        c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases != 0);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
       }
-      if (carry || (before_lag && scheme == SUBDIV_LOOP)) c.base = at<int32_t>(ws, y.tbase);
+      if (carry || (before_lag && scheme == SUBDIV_LOOP) || sig1) c.base = at<int32_t>(ws, y.tbase);
       if (before_lag && !outs[k + 1].face_verts) c.fv1 = nullptr;
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
@@ -800,6 +810,12 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         // face step overwrites with level k+1's: it runs first
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
         if (c.fv1) SUBDIV_TIMED("loop_face", k, tri_launch(LOOP_FACE, c, s));
+        if (lcr) {
+          if (sig1) SUBDIV_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(sig1), 0, 2 * L[k + 1].E, s));
+          SUBDIV_TIMED("loop_crease", k, loop_crease_launch(c, sig1, s));
+          if (!final && sig1 && outs[k + 1].crease_sharpness)
+            SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].crease_sharpness, sig1, 8 * L[k + 1].E, hipMemcpyDeviceToDevice, s));
+        }
         if (carry) a = c.a1;
       } else {
         if (carry) {
@@ -1164,6 +1180,7 @@ int check_batch_args(const subdiv_mesh *m, int n, int scheme, int levels) {
   for (int i = 0; i < n; ++i) {
     const int st = check_mesh_args(&m[i], scheme, levels);
     if (st != SUBDIV_OK) return st;
+    if (m[i].num_creases > 0 && scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;  // batches: CC creases
   }
   return SUBDIV_OK;
 }

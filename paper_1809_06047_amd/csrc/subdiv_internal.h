@@ -340,6 +340,10 @@ struct TriStep {
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
+// Loop creases of level k (c.a.sig, c.a.vcr): crease and corner vertices over
+// the smooth vertex points, then (sig1 != nullptr, with c.base) the
+// inherited sharpness of level k+1's edges into sig1 (cleared by the caller)
+hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s);
 
 // Last Loop or sqrt(3) step k -> k+1 computed from level m = k-1 (which
 // level k was refined from): its faces, edges and adjacency are a quarter

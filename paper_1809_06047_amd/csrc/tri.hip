@@ -424,6 +424,15 @@ __global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
     const f3 pcd = add3(ld3(c.P, c.t.fv[hp]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
     ep = loop_edge_pt(pab, pcd);
   }
+  if (t >= 0 && c.a.sig) {  // a crease edge: Loop's edge point blended with the midpoint
+    const double sg = c.a.sig[e];
+    if (sg >= 1.0) {
+      ep = mul3(0.5f, pab);
+    } else if (sg > 0.0) {
+      const float w = (float)sg;
+      ep = lin2(1.0f - w, ep, 0.5f * w, pab);
+    }
+  }
   st3(c.P1, c.t.V + e, ep);
   if (c.base) {  // children of level k+1 with higher end E_e
     const int n1 = c.a.eid[hn], n2 = c.a.eid[hp];
@@ -724,6 +733,96 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
   // an old vertex's half-edges at level k+1 are the first slots 3 (3r + j) of
   // the children at its level-k half-edges 3r + j, in the same order
   if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
+}
+
+// ------------------------------------------------------------ Loop creases
+// The paper gives crease rules for Catmull-Clark (Sec. 3.3); Loop takes the
+// same rules on its own points: a crease edge's point blends Loop's edge
+// point with the midpoint (above); a vertex with k >= 2 incident crease
+// edges takes the crease rule 3/4 p + 1/8 (its two crease neighbours)
+// (k = 2) or stays (k >= 3), blended with its smooth point by the mean
+// sharpness when that is below 1 (boundary vertices keep the boundary rule);
+// the two halves of a crease edge inherit sharpness by the Chaikin rule.
+__device__ __forceinline__ double chaikin_tri(double si, double sj) {
+#pragma clang fp contract(off)
+  const double t = 0.25 * (si + 3.0 * sj) - 1.0;  // this operation order, no fused multiply-add
+  return t > 0.0 ? t : 0.0;
+}
+
+// Per level-k vertex, after the smooth vertex points: crease valency and the
+// first two incident creases (kept for the inheritance), then the crease or
+// corner rule over the smooth point. The walk visits every incident edge
+// (the outgoing half-edges, and the incoming boundary one).
+__global__ void __launch_bounds__(kBlock) k_loop_crease_vertex(TriStep c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c.t.V) return;
+  const Adj &a = c.a;
+  int k = 0, cv0 = -1, cv1 = -1, ce0 = -1, ce1 = -1;
+  double ssum = 0.0;
+  auto crease = [&](int e, int w) {
+    const double sg = a.sig[e];
+    const bool on = sg > 0.0;
+    cv0 = (on && k == 0) ? w : cv0;
+    ce0 = (on && k == 0) ? e : ce0;
+    cv1 = (on && k == 1) ? w : cv1;
+    ce1 = (on && k == 1) ? e : ce1;
+    k += on;
+    ssum += on ? sg : 0.0;
+  };
+  const int h0 = a.vhe[v];
+  int h = h0, n = 0;
+  bool bnd = false;
+  while (true) {
+    crease(a.eid[h], c.t.fv[he_next<3>(c.t, h)]);
+    ++n;
+    const int hp = he_prev<3>(c.t, h);
+    const int tw = a.twin[hp];
+    if (tw < 0) {  // the incoming boundary half-edge u -> v ends the fan
+      bnd = true;
+      crease(a.eid[hp], c.t.fv[hp]);
+      break;
+    }
+    if (tw == h0 || n >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+  a.vcr[v] = make_int4(k, ce0, ce1, 0);
+  if (bnd || k < 2) return;
+  const f3 p = ld3(c.P, v);
+  const f3 sharp = k == 2 ? loop_bnd_pt(p, add3(ld3(c.P, cv0), ld3(c.P, cv1))) : p;
+  const double sm = ssum / (double)k;
+  if (sm >= 1.0) {
+    st3(c.P1, v, sharp);
+  } else {
+    const float w = (float)sm;
+    st3(c.P1, v, lin2(1.0f - w, ld3(c.P1, v), w, sharp));
+  }
+}
+
+// Per level-k crease edge e = (lo, hi): its children (lo, E_e) and (hi, E_e)
+// are the level-(k+1) edges base(e) and base(e) + 1; each end takes
+// sigma_i = the other crease's sharpness when the end has exactly two
+// creases, else e's own. The caller has cleared sig1.
+__global__ void __launch_bounds__(kBlock) k_loop_crease_edge(TriStep c, double *sig1) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c.a.E) return;
+  const double sg = c.a.sig[e];
+  if (!(sg > 0.0)) return;
+  const int h = c.a.e2h[e];
+  const int x = c.t.fv[h], y = c.t.fv[he_next<3>(c.t, h)];
+  const int b = c.base[e];
+#pragma unroll
+  for (int end = 0; end < 2; ++end) {
+    const int v = end ? max(x, y) : min(x, y);
+    const int4 q = c.a.vcr[v];
+    const double si = q.x == 2 ? c.a.sig[q.y == e ? q.z : q.y] : sg;
+    sig1[b + end] = chaikin_tri(si, sg);
+  }
+}
+
+hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s) {
+  hipLaunchKernelGGL(k_loop_crease_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+  if (sig1) hipLaunchKernelGGL(k_loop_crease_edge, dim3(grid_for(c.a.E)), dim3(kBlock), 0, s, c, sig1);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------- Loop, last step
