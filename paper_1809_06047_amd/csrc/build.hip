@@ -148,12 +148,28 @@ __device__ __forceinline__ int block_excl_scan(int x, int *total) {
   return off + incl - x;
 }
 
+// A thread's 8 consecutive items as two 16-byte loads when they are all in
+// range and the array is 16-byte aligned (VEC), else one by one.
+template <bool VEC>
+__device__ __forceinline__ void load8(const int32_t *in, long long base, long long n, int (&v)[kScanItems]) {
+  if (VEC && base + kScanItems <= n) {
+    const int4 a = reinterpret_cast<const int4 *>(in + base)[0], b = reinterpret_cast<const int4 *>(in + base)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? in[base + i] : 0;
+  }
+}
+
+template <bool VEC>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t *in, long long n, int32_t *partials) {
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  load8<VEC>(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += in[base + i];
+  for (int i = 0; i < kScanItems; ++i) s += v[i];
   int tot;
   block_excl_scan(s, &tot);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -183,23 +199,33 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_partials(int32_t *partial
   if (threadIdx.x == 0) partials[nb] = carry;
 }
 
+template <bool VEC>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t *in, int32_t *out, long long n,
                                                             const int32_t *partials, long long nb,
                                                             int32_t *total_dst) {
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
   int v[kScanItems];
+  load8<VEC>(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0;
-    s += v[i];
-  }
+  for (int i = 0; i < kScanItems; ++i) s += v[i];
   int tot;
   int off = block_excl_scan(s, &tot) + (partials ? partials[blockIdx.x] : 0);
+  if (VEC && base + kScanItems <= n) {
+    int o[kScanItems];
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) out[base + i] = off;
-    off += v[i];
+    for (int i = 0; i < kScanItems; ++i) {
+      o[i] = off;
+      off += v[i];
+    }
+    reinterpret_cast<int4 *>(out + base)[0] = make_int4(o[0], o[1], o[2], o[3]);
+    reinterpret_cast<int4 *>(out + base)[1] = make_int4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < n) out[base + i] = off;
+      off += v[i];
+    }
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
     const int total = partials ? partials[nb] : off;
@@ -244,18 +270,28 @@ hipError_t launch_scan(const int32_t *in, int32_t *out, long long n, int32_t *pa
                        hipStream_t s) {
   const long long nb = (n + kScanTile - 1) / kScanTile;
   if (nb <= 1) {
-    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const int32_t *)nullptr, 0ll,
-                       total_dst);
+    hipLaunchKernelGGL(k_scan_apply<false>, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const int32_t *)nullptr,
+                       0ll, total_dst);
     return hipGetLastError();
   }
   if (n <= kScanSmall) {
     hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneThreads), 0, s, in, out, n, total_dst);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
+  const bool vec = reinterpret_cast<uintptr_t>(in) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  if (vec) {
+    hipLaunchKernelGGL(k_scan_reduce<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
+  } else {
+    hipLaunchKernelGGL(k_scan_reduce<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
+  }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
-                     (const int32_t *)partials, nb, total_dst);
+  if (vec) {
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const int32_t *)partials, nb, total_dst);
+  } else {
+    hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const int32_t *)partials, nb, total_dst);
+  }
   return hipGetLastError();
 }
 
