@@ -270,11 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
     __builtin_amdgcn_wave_barrier();
     const int count = (eid - l < c.am.E) ? 3 * (end - base0) : 0;
     uint32_t *dst = reinterpret_cast<uint32_t *>(c.P1 + 3ll * (VFk + base0));
-#pragma unroll
-    for (int t = 0; t < 12; ++t) {
-      const int g = 64 * t + l;
-      if (g < count) stream_store(dst + g, lds[g]);
-    }
+    run_store(lds, dst, count, l);
   }
   if (!valid) return;
   st3(c.P1, EP, S);

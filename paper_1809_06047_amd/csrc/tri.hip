@@ -973,11 +973,7 @@ __global__ void __launch_bounds__(kBlock) k_loopl_edge(TriLag c) {
     const int end = min(__shfl(base + n, min(63, E - 1 - (eid - l)), 64), c.Ek);
     const int count = (eid - l < E) ? 3 * (end - base0) : 0;
     uint32_t *dst = reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vk + base0));
-#pragma unroll
-    for (int x = 0; x < 18; ++x) {
-      const int g = 64 * x + l;
-      if (g < count) stream_store(dst + g, lds[g]);
-    }
+    run_store(lds, dst, count, l);
   }
   __builtin_amdgcn_wave_barrier();
   {
