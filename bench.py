@@ -485,11 +485,13 @@ def adjoint_leg(mesh, levels, steps):
         t1 = time.perf_counter()
         r.backward(g)
         torch.cuda.synchronize()
+        tf += t1 - t0
+        tb += time.perf_counter() - t1
+    for _ in range(steps):  # the full refinement (which the fitting loop runs once)
+        torch.cuda.synchronize()
         t2 = time.perf_counter()
         r.run()
         torch.cuda.synchronize()
-        tf += t1 - t0
-        tb += t2 - t1
         tr += time.perf_counter() - t2
     k = levels - 1
     bw = sum(tot for (name, lvl), (_, tot) in stages.items() if name.startswith("bw_") and lvl == k) / steps

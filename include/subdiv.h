@@ -76,8 +76,9 @@ enum {
 #define SUBDIV_FLAG_REBUILD_EACH_LEVEL 1u /* rebuild E/F from M at every level (generic M M^T path)
                                              instead of carrying them over in closed form */
 #define SUBDIV_FLAG_KEEP_STATE 2u         /* keep every level's topology in the workspace for
-                                             subdiv_backward (subdiv_refine also writes the
-                                             adjoint's per-vertex rule coefficients there) */
+                                             subdiv_backward (whose first call after a
+                                             subdiv_refine also writes the adjoint's per-vertex
+                                             rule coefficients there) */
 
 /* ---- inputs ----------------------------------------------------------- */
 typedef struct subdiv_mesh {

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -291,6 +292,31 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   }
   y.total = c.at + 256;
   return y;
+}
+
+// The vertex-rule coefficients depend on the topology and the creases only,
+// so they are fixed by the plan: the first backward pass with a plan's
+// workspace writes them into the kept state, and every later one with the
+// same plan (same stamp) reads them. Callers that keep the state only for
+// positions-only or vertex-data evaluation never pay for them.
+std::mutex g_coef_mu;
+std::unordered_map<const void *, uint64_t> g_coef_stamp;  // workspace -> plan whose coefficients it holds
+
+bool coefs_held(const void *ws, uint64_t stamp) {
+  std::lock_guard<std::mutex> lock(g_coef_mu);
+  const auto it = g_coef_stamp.find(ws);
+  return it != g_coef_stamp.end() && it->second == stamp;
+}
+
+void coefs_mark(const void *ws, uint64_t stamp) {
+  std::lock_guard<std::mutex> lock(g_coef_mu);
+  g_coef_stamp[ws] = stamp;
+}
+
+// a refinement that keeps the state writes it anew (the workspace may be new memory)
+void coefs_forget(const void *ws) {
+  std::lock_guard<std::mutex> lock(g_coef_mu);
+  g_coef_stamp.erase(ws);
 }
 
 template <class T>
@@ -659,12 +685,6 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   return SUBDIV_OK;
 }
 
-}  // extern "C"
-namespace {
-int keep_bw_coefs(const subdiv_mesh *mesh, void *ws, const Layout &y, const Sizes *L, int levels, hipStream_t s);
-}
-extern "C" {
-
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream) {
   if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
@@ -703,9 +723,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
   if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
-    if ((st = refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s)) != SUBDIV_OK)
-      return st;
-    return (plan->flags & SUBDIV_FLAG_KEEP_STATE) ? keep_bw_coefs(mesh, ws, y, L, levels, s) : SUBDIV_OK;
+    if (plan->flags & SUBDIV_FLAG_KEEP_STATE) coefs_forget(ws);
+    return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
   }
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
   Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
@@ -988,9 +1007,7 @@ BwdStep bwd_level(const subdiv_mesh *mesh, void *ws, const Layout &y, const Size
   return b;
 }
 
-// The vertex-rule coefficients depend on the topology and the creases only:
-// they are part of the kept state, written once by the refinement that
-// builds it and read by every backward pass after it.
+// (the coefficients of a plan are computed on its first backward pass)
 int keep_bw_coefs(const subdiv_mesh *mesh, void *ws, const Layout &y, const Sizes *L, int levels, hipStream_t s) {
   const long long H0 = cage_H(mesh);
   for (int k = 0; k < levels; ++k) {
@@ -1019,9 +1036,13 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
               plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
               L);
   const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
+  if (!coefs_held(ws, plan->priv_stamp)) {
+    if ((st = keep_bw_coefs(mesh, ws, y, L, levels, s)) != SUBDIV_OK) return st;
+    coefs_mark(ws, plan->priv_stamp);
+  }
   const float *g1 = grad_out;
   for (int k = levels - 1; k >= 0; --k) {
-    BwdStep b = bwd_level(mesh, ws, y, L, H0, k);  // coefficients from the refinement that kept the state
+    BwdStep b = bwd_level(mesh, ws, y, L, H0, k);  // the plan's kept coefficients
     b.g1 = g1;
     b.g0 = (k == 0) ? grad_in : at<float>(ws, y.bg[k & 1]);
     b.term = at<float>(ws, y.bterm);

@@ -121,3 +121,37 @@ def test_refine_positions_equals_full_refine(oracle_mod, cage):
     for k in range(1, L + 1):
         np.testing.assert_array_equal(got[k], full[k]["positions"].cpu().numpy(), err_msg=f"level {k}")
         assert normwise_err(got[k], ref[k].positions) <= POS_TOL
+
+
+def test_backward_coefficients_once_per_plan():
+    """The adjoint's vertex-rule coefficients are written by the first
+    backward after a keep-state refinement and reused after it: the gradient
+    is the same bits after a positions-only forward, after a second full
+    refinement (which clears them) and after a new plan of another cage in
+    the same refiner slot."""
+    import torch
+    m = G.cc_cage(seed=24, level=2)
+    r = api.differentiable_refiner(m, 3)
+    r.run()
+    g = torch.from_numpy(np.random.default_rng(8).normal(0, 1, (r.level_info(3)["V"], 3)).astype(np.float32)).cuda()
+    a = r.backward(g).cpu().numpy()
+    b = r.backward(g).cpu().numpy()
+    r.run_positions()
+    c = r.backward(g).cpu().numpy()
+    r.run()
+    d = r.backward(g).cpu().numpy()
+    for x in (b, c, d):
+        np.testing.assert_array_equal(a, x)
+    # a new plan (another cage with the same counts would reuse nothing): the
+    # coefficients are computed again for it
+    m2 = _grid_with_creases(23)
+    r2 = api.differentiable_refiner(m2, 3)
+    r2.run()
+    g2 = torch.ones((r2.level_info(3)["V"], 3), dtype=torch.float32, device="cuda")
+    e = r2.backward(g2).cpu().numpy()
+    r2.plan()
+    r2.run()
+    f = r2.backward(g2).cpu().numpy()
+    np.testing.assert_array_equal(e, f)
+    # every row of R sums to one, so a gradient of ones sums to the refined vertex count
+    assert abs(float(e.sum()) - 3 * r2.level_info(3)["V"]) <= 1e-3 * 3 * r2.level_info(3)["V"]
