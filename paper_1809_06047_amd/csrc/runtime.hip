@@ -230,16 +230,21 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   }
   y.partials = c.take(4 * (scan_partials_ints(maxn) + 8));
   if (levels >= 2) {
-    long long mV = 0, mE = 0, mH = 0, mF = 0;
+    const bool rebuild = rebuilds_levels(scheme, flags);
+    // Loop's last step from level levels-2 never holds level levels-1's
+    // adjacency or face table in the workspace (only its positions)
+    const bool loop_lag = scheme == SUBDIV_LOOP && !rebuild && levels >= 3 && !L[levels - 1].creases;
+    const int top = loop_lag ? levels - 1 : levels;  // levels 1 .. top-1 have adjacency slots and face tables
+    long long mV = 0, mE = 0, mH = 0, mF = 0, mVp = 0;
     bool cr = false;
-    for (int k = 1; k < levels; ++k) {
+    for (int k = 1; k < top; ++k) {
       mV = L[k].V > mV ? L[k].V : mV;
       mE = L[k].E > mE ? L[k].E : mE;
       mH = L[k].H > mH ? L[k].H : mH;
       mF = L[k].F > mF ? L[k].F : mF;
       cr = cr || L[k].creases;
     }
-    const bool rebuild = rebuilds_levels(scheme, flags);
+    for (int k = 1; k < levels; ++k) mVp = L[k].V > mVp ? L[k].V : mVp;
     const bool cc_carry = scheme == SUBDIV_CATMULL_CLARK && !rebuild;
     // rotating adjacency slots; with the state kept every level has its own region instead
     const int nslots = cc_carry ? ((flags & SUBDIV_FLAG_KEEP_STATE) ? 0 : 3) : 2;
@@ -261,8 +266,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       y.bsigcnt = c.take(4 * mH);
     }
     for (int s = 0; s < 2; ++s) {
-      y.mfv[s] = c.take(4 * mH);
-      y.mP[s] = c.take(12 * mV);
+      y.mfv[s] = c.take(4 * (mH > 0 ? mH : 1));
+      y.mP[s] = c.take(12 * mVp);
     }
   }
   if (scheme != SUBDIV_CATMULL_CLARK && levels >= 1) {
@@ -733,8 +738,10 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
   // levels-1): when that level is a refined one and the caller wants no edge
   // list of level levels-1
-  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !outs[levels].edge_verts &&
-                       !L[levels - 1].creases;  // (the last step from level levels-2 has no crease rules)
+  // (the last step from level levels-2 has no crease rules; Loop's writes
+  // the edge list of level levels-1 itself, sqrt(3)'s does not)
+  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases &&
+                       (scheme == SUBDIV_LOOP || !outs[levels].edge_verts);
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -754,7 +761,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       a = slot;
     }
     const Adj ak = a;
-    if (outs[k + 1].edge_verts) SUBDIV_TIMED("edge_export", k, launch_edge_export(t, a, outs[k + 1].edge_verts, s));
+    if (outs[k + 1].edge_verts && !(tri_lag && final))  // (the last step from level k-1 writes them itself)
+      SUBDIV_TIMED("edge_export", k, launch_edge_export(t, a, outs[k + 1].edge_verts, s));
     if (scheme == SUBDIV_CATMULL_CLARK) {
       CCStep c{};
       c.t = t;
@@ -782,7 +790,8 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
     } else if (tri_lag && final) {
       // level k+1 from level m = k-1: `a` and `tprev` are level m's (the step
       // before carried nothing); Loop's edge bases of level m are in tbase
-      const TriLag g{tprev, a, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E, fv1, P1};
+      const TriLag g{tprev, a, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E, fv1, P1,
+                     outs[k + 1].edge_verts};
       TriStep o{};  // the old vertices (level m's) walk their level-m rings
       o.t = tprev;
       o.P = P;

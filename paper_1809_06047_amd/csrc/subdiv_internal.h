@@ -379,6 +379,7 @@ struct TriLag {
   int32_t Ek;            // Loop: E_k = base[E_m]
   int32_t *fv2;          // level k+1 face table (Loop [48 F_m], sqrt(3) [27 F_m])
   float *P2;             // level k+1 positions [V_{k+1}]
+  int32_t *edges;        // Loop, optional: (lo, hi) of level k's edges in id order [2 E_k]
 };
 enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);

@@ -14,6 +14,7 @@
 //         index |v| + i).
 // beta_n and alpha_n are evaluated once on the host in FP64 and rounded to
 // FP32 into constant memory: no device cosine decides a weight.
+#include <climits>
 #include <cmath>
 #include <mutex>
 
@@ -967,6 +968,24 @@ __global__ void __launch_bounds__(kBlock) k_loopl_edge(TriLag c) {
     if (sa < e) put(2 + rank(sa), loop_edge_pt(add3(psa, pE), add3(pa, psb)));
     if (sb < e) put(2 + rank(sb), loop_edge_pt(add3(psb, pE), add3(pb, psa)));
     n = 2 + (ra < e) + (rb < e) + (sa < e) + (sb < e);
+  }
+  if (c.edges && eid < E) {
+    // level k's edges with higher end E_e, in id order: (lo, E_e), (hi, E_e),
+    // then (E_x, E_e) for x in N(e), x < e, ascending
+    int2 *o = reinterpret_cast<int2 *>(c.edges) + base;
+    const int hiE = Vm + e;
+    o[0] = make_int2(min(a, b), hiE);
+    o[1] = make_int2(max(a, b), hiE);
+    int x[4] = {ra, rb, t < 0 ? INT_MAX : c.am.eid[3 * (t / 3) + ((t % 3) == 2 ? 0 : (t % 3) + 1)],
+                t < 0 ? INT_MAX : c.am.eid[3 * (t / 3) + ((t % 3) == 0 ? 2 : (t % 3) - 1)]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (x[i] >= e) continue;
+      int rk = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rk += (j != i && x[j] < x[i]);
+      o[2 + rk] = make_int2(Vm + x[i], hiE);
+    }
   }
   __builtin_amdgcn_wave_barrier();
   {

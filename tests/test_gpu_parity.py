@@ -245,11 +245,12 @@ def test_status_codes_match_oracle(oracle_mod):
 @pytest.mark.parametrize("levels", [3, 4])
 @pytest.mark.parametrize("cage", ["icosphere", "holes", "fan", "bipyramid", "grid"])
 def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
-    """Without an edge list of level L-1, the last Loop or sqrt(3) step runs
-    from level L-2 (the level L-1 was refined from) and level L-1's adjacency
-    is never built. The final level equals the per-level path (asked for the
-    edge list) bit for bit and the oracle within tolerance; asking for every
-    level's face table as well changes nothing."""
+    """The last Loop or sqrt(3) step runs from level L-2 (the level L-1 was
+    refined from) and level L-1's adjacency is never built. The final level
+    equals the per-level path (the per-level build) bit for bit and the
+    oracle within tolerance; asking for every level's face table as well
+    changes nothing; Loop's last step also writes level L-1's edge list
+    (sqrt(3) takes the per-level path when it is asked for)."""
     rng = np.random.default_rng(21)
     m = {"icosphere": lambda: G.tri_cage(seed=18, level=2, hole_frac=0.0),
          "holes": lambda: G.tri_cage(seed=19, level=2, hole_frac=0.08),
@@ -260,7 +261,7 @@ def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
     print(f"[parity] {scheme} last step from level {L - 2}: {m.name} L={L}", flush=True)
     outs, _ = api.refine(m, scheme, L)
     lag = {k: v.cpu().numpy() for k, v in outs[L].items()}
-    per, _ = api.refine(m, scheme, L, edges=True)
+    per, _ = api.refine(m, scheme, L, flags=_lib.FLAG_REBUILD_EACH_LEVEL)
     np.testing.assert_array_equal(lag["face_verts"], per[L]["face_verts"].cpu().numpy())
     np.testing.assert_array_equal(lag["positions"], per[L]["positions"].cpu().numpy())
     ref = oracle_mod.refine(m, scheme, L)
@@ -271,3 +272,6 @@ def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
         np.testing.assert_array_equal(every[k]["face_verts"].cpu().numpy(), ref[k].verts, err_msg=f"level {k}")
         assert normwise_err(every[k]["positions"].cpu().numpy(), ref[k].positions) <= POS_TOL
     np.testing.assert_array_equal(every[L]["positions"].cpu().numpy(), lag["positions"])
+    with_edges, _ = api.refine(m, scheme, L, edges=True)
+    np.testing.assert_array_equal(with_edges[L]["edge_verts"].cpu().numpy(), ref[L - 1].edges)
+    np.testing.assert_array_equal(with_edges[L]["positions"].cpu().numpy(), lag["positions"])
