@@ -231,9 +231,10 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   y.partials = c.take(4 * (scan_partials_ints(maxn) + 8));
   if (levels >= 2) {
     const bool rebuild = rebuilds_levels(scheme, flags);
-    // Loop's last step from level levels-2 never holds level levels-1's
-    // adjacency or face table in the workspace (only its positions)
-    const bool loop_lag = scheme == SUBDIV_LOOP && !rebuild && levels >= 3 && !L[levels - 1].creases;
+    // the last Loop or sqrt(3) step from level levels-2: level levels-1's
+    // adjacency and face table are never held in the workspace (only its
+    // positions)
+    const bool loop_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases;
     const int top = loop_lag ? levels - 1 : levels;  // levels 1 .. top-1 have adjacency slots and face tables
     long long mV = 0, mE = 0, mH = 0, mF = 0, mVp = 0;
     bool cr = false;
@@ -738,10 +739,9 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
   // levels-1): when that level is a refined one and the caller wants no edge
   // list of level levels-1
-  // (the last step from level levels-2 has no crease rules; Loop's writes
-  // the edge list of level levels-1 itself, sqrt(3)'s does not)
-  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases &&
-                       (scheme == SUBDIV_LOOP || !outs[levels].edge_verts);
+  // (the last step from level levels-2 has no crease rules; it writes the
+  // edge list of level levels-1 itself)
+  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases;
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -791,7 +791,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       // level k+1 from level m = k-1: `a` and `tprev` are level m's (the step
       // before carried nothing); Loop's edge bases of level m are in tbase
       const TriLag g{tprev, a, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E, fv1, P1,
-                     outs[k + 1].edge_verts};
+                     outs[k + 1].edge_verts, (int32_t)L[k].B};
       TriStep o{};  // the old vertices (level m's) walk their level-m rings
       o.t = tprev;
       o.P = P;
@@ -846,7 +846,10 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
         }
         if (carry) a = c.a1;
       } else {
-        if (carry) {
+        // (before the last step from level k with an edge list asked for, the
+        // face bases of level k give that list's ids)
+        if (before_lag && outs[levels].edge_verts) c.base = at<int32_t>(ws, y.tbase);
+        if (c.base) {
           SUBDIV_TIMED("sqrt3_count", k, tri_launch(SQRT3_COUNT, c, s));
           SUBDIV_TIMED("sqrt3_scan", k, launch_scan(c.base, c.base, t.F, at<int32_t>(ws, y.partials), nullptr, s));
         }

@@ -373,13 +373,15 @@ hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s);
 struct TriLag {
   Topo tm;               // level m (triangles)
   Adj am;                // level m: twin, eid, e2h (E = |e_m|)
-  const int32_t *base;   // Loop: [E_m + 1] first level-k edge id with higher end EP(e), per level-m edge
+  const int32_t *base;   // Loop: [E_m + 1] first level-k edge id with higher end EP(e), per level-m edge;
+                         // sqrt(3), with edges: [F_m + 1] first id (after the boundary ones) with higher end F_r
   const float *Pk;       // level-k positions [V_k]
   int32_t Vk;            // V_k = V_m + E_m (Loop), V_m + F_m (sqrt(3))
   int32_t Ek;            // Loop: E_k = base[E_m]
   int32_t *fv2;          // level k+1 face table (Loop [48 F_m], sqrt(3) [27 F_m])
   float *P2;             // level k+1 positions [V_{k+1}]
-  int32_t *edges;        // Loop, optional: (lo, hi) of level k's edges in id order [2 E_k]
+  int32_t *edges;        // optional: (lo, hi) of level k's edges in id order [2 E_k]
+  int32_t Bk;            // sqrt(3): boundary edges of level k (its first ids)
 };
 enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);

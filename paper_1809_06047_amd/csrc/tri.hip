@@ -1084,6 +1084,29 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3l_face(TriLag c) {
     const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
     wave_store<3>(lds, row, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vm + rw)), l, 3 * nw);
   }
+  if (c.edges && rid < F) {
+    // level k's edge list (the carried ids of the face kernel above): a kept
+    // boundary edge j of r keeps its id (the boundary edges of a refined level
+    // are its first ids); the edges with higher end F_r take Bk + base(r) +
+    // the rank of the lower end among r's corners, then Bk + base(r) + 3 +
+    // the rank of F_s among r's neighbours s < r
+    int2 *o = reinterpret_cast<int2 *>(c.edges);
+    const int br = c.Bk + c.base[r];
+    int nb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) nb[j] = tw[j] < 0 ? INT_MAX : tw[j] / 3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+      if (tw[j] < 0) {
+        const int e = c.am.eid[3 * r + j];
+        o[e] = make_int2(min(v[j], v[jn]), max(v[j], v[jn]));
+      }
+      o[br + (v[j] > v[jn]) + (v[j] > v[jp])] = make_int2(v[j], Fr);
+      if (nb[j] < r)
+        o[br + 3 + (nb[jn] < nb[j]) + (nb[jp] < nb[j])] = make_int2(Vm + nb[j], Fr);
+    }
+  }
 }
 
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s) {

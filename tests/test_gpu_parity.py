@@ -249,8 +249,7 @@ def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
     refined from) and level L-1's adjacency is never built. The final level
     equals the per-level path (the per-level build) bit for bit and the
     oracle within tolerance; asking for every level's face table as well
-    changes nothing; Loop's last step also writes level L-1's edge list
-    (sqrt(3) takes the per-level path when it is asked for)."""
+    changes nothing; the last step also writes level L-1's edge list."""
     rng = np.random.default_rng(21)
     m = {"icosphere": lambda: G.tri_cage(seed=18, level=2, hole_frac=0.0),
          "holes": lambda: G.tri_cage(seed=19, level=2, hole_frac=0.08),
