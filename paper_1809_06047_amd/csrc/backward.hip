@@ -211,21 +211,59 @@ __global__ void __launch_bounds__(kBlock) k_bw_vertex(BwdStep c) {
     return;
   }
   const int h0 = c.a.vhe[v];
-  int h = h0, n = 0;
+  // neighbour u of the last, boundary edge (incoming half-edge hp): v is in
+  // u's smooth rule (b_u), takes half of the edge point, and is one of u's two
+  // boundary neighbours
+  auto boundary_terms = [&](int hp) {
+    const int uu = c.t.fv[hp];
+    const float4 cu = coef[uu];
+    const f3 gu = ld3(c.g1, uu);
+    g = fma3(cu.y, gu, g);
+    g = fma3(0.5f, ld3(c.g1, V + F + c.a.eid[hp]), g);
+    g = fma3(cu.z, gu, g);
+  };
+  // the fan first (only the twin loads in sequence), then every term at once,
+  // added in the same order; longer fans walk one step at a time
+  constexpr int kFan = 8;
+  int hs[kFan], n = 0, h = h0, hb = -1;
+  bool go = true;
+#pragma unroll
+  for (int i = 0; i < kFan; ++i) {
+    hs[i] = h;  // past the end: repeats the last half-edge (loads stay in bounds)
+    if (go) {
+      n = i + 1;
+      const int hp = he_prev<ORDER>(c.t, h);
+      const int t = c.a.twin[hp];
+      if (t < 0) {
+        hb = hp;
+        go = false;
+      } else if (t == h0) {
+        go = false;
+      } else {
+        h = t;
+      }
+    }
+  }
+  if (!go) {
+    f3 tv[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) tv[i] = ld3(c.term, hs[i]);
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n) g = add3(g, tv[i]);
+    if (hb >= 0) boundary_terms(hb);
+    st3(c.g0, v, g);
+    return;
+  }
+  h = h0;
+  n = 0;
   while (true) {
     g = add3(g, ld3(c.term, h));
     ++n;
     const int hp = he_prev<ORDER>(c.t, h);
     const int t = c.a.twin[hp];
     if (t < 0) {
-      // neighbour u of the last, boundary edge: v is in u's smooth rule (b_u),
-      // takes half of the edge point, and is one of u's two boundary neighbours
-      const int uu = c.t.fv[hp];
-      const float4 cu = coef[uu];
-      const f3 gu = ld3(c.g1, uu);
-      g = fma3(cu.y, gu, g);
-      g = fma3(0.5f, ld3(c.g1, V + F + c.a.eid[hp]), g);
-      g = fma3(cu.z, gu, g);
+      boundary_terms(hp);
       break;
     }
     if (t == h0 || n >= SUBDIV_MAX_VALENCE) break;
