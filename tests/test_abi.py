@@ -102,3 +102,25 @@ def test_later_entry_points_reject_bad_arguments_without_device(lib):
                               None) == _lib.STATE
     assert lib.subdiv_backward(ctypes.byref(m), ctypes.byref(info), ws, ws, ws, 1, None) == _lib.STATE
     assert lib.subdiv_refine_positions(ctypes.byref(m), ctypes.byref(info), None, ws, 1, None) == _lib.INVALID_ARG
+
+
+def test_creases_by_scheme_without_device(lib):
+    """Creases: Catmull-Clark and Loop take them, sqrt(3) rejects them on the
+    host, and batches take them for Catmull-Clark only (their workspace bound
+    is 0 otherwise)."""
+    info = _lib.subdiv_plan_info()
+    m = _lib.subdiv_mesh()
+    m.num_vertices, m.num_faces, m.face_order = 3, 1, 3
+    m.face_verts = m.positions = 16  # never dereferenced: the crease check fails first
+    m.num_creases = 1
+    m.crease_verts = m.crease_sharpness = 16
+    assert lib.subdiv_plan(ctypes.byref(m), 2, 1, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
+    arr = (_lib.subdiv_mesh * 1)(m)
+    assert lib.subdiv_batch_workspace_bound(arr, 1, 1, 1, 0) == 0      # Loop batch with creases
+    assert lib.subdiv_batch_workspace_bound(arr, 1, 2, 1, 0) == 0      # sqrt(3) batch with creases
+    m.num_creases = 0
+    m.crease_verts = m.crease_sharpness = None
+    arr = (_lib.subdiv_mesh * 1)(m)
+    assert lib.subdiv_batch_workspace_bound(arr, 1, 1, 1, 0) > 0
+    # the bound of a creased Loop cage covers the crease tables of every level
+    assert lib.subdiv_workspace_bound(3, 1, 3, 1, 1, 3, 0) > lib.subdiv_workspace_bound(3, 1, 3, 0, 1, 3, 0)
