@@ -417,24 +417,26 @@ __global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
   if (e >= c.a.E) return;
   const int h = c.a.e2h[e];
   const int hn = he_next<3>(c.t, h), hp = he_prev<3>(c.t, h);
-  const f3 pab = add3(ld3(c.P, c.t.fv[h]), ld3(c.P, c.t.fv[hn]));
   const int t = c.a.twin[h];
-  f3 ep;
-  if (t < 0) ep = mul3(0.5f, pab);
-  else {
-    const f3 pcd = add3(ld3(c.P, c.t.fv[hp]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
-    ep = loop_edge_pt(pab, pcd);
-  }
-  if (t >= 0 && c.a.sig) {  // a crease edge: Loop's edge point blended with the midpoint
-    const double sg = c.a.sig[e];
-    if (sg >= 1.0) {
-      ep = mul3(0.5f, pab);
-    } else if (sg > 0.0) {
-      const float w = (float)sg;
-      ep = lin2(1.0f - w, ep, 0.5f * w, pab);
+  if (c.P1) {  // (without P1: only the counts, the points come from the level below)
+    const f3 pab = add3(ld3(c.P, c.t.fv[h]), ld3(c.P, c.t.fv[hn]));
+    f3 ep;
+    if (t < 0) ep = mul3(0.5f, pab);
+    else {
+      const f3 pcd = add3(ld3(c.P, c.t.fv[hp]), ld3(c.P, c.t.fv[he_prev<3>(c.t, t)]));
+      ep = loop_edge_pt(pab, pcd);
     }
+    if (t >= 0 && c.a.sig) {  // a crease edge: Loop's edge point blended with the midpoint
+      const double sg = c.a.sig[e];
+      if (sg >= 1.0) {
+        ep = mul3(0.5f, pab);
+      } else if (sg > 0.0) {
+        const float w = (float)sg;
+        ep = lin2(1.0f - w, ep, 0.5f * w, pab);
+      }
+    }
+    st3(c.P1, c.t.V + e, ep);
   }
-  st3(c.P1, c.t.V + e, ep);
   if (c.base) {  // children of level k+1 with higher end E_e
     const int n1 = c.a.eid[hn], n2 = c.a.eid[hp];
     int cnt = 2 + (n1 < e) + (n2 < e);
