@@ -193,12 +193,12 @@ AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool crea
 // over in closed form from the level it was refined from.
 bool rebuilds_levels(int, uint32_t flags) { return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0; }
 
-// Loop's last two steps both run from two levels below them: L >= 4 (so the
-// step before the last reads a refined level, L-3 >= 1) and no creases on
-// levels L-2 and L-1
-bool loop_lag2(int scheme, uint32_t flags, int levels, const Sizes *L) {
-  return scheme == SUBDIV_LOOP && !rebuilds_levels(scheme, flags) && levels >= 4 && !L[levels - 1].creases &&
-         !L[levels - 2].creases;
+// The last two Loop or sqrt(3) steps both run from two levels below them:
+// L >= 4 (so the step before the last reads a refined level, L-3 >= 1) and
+// no creases on levels L-2 and L-1
+bool tri_lag2(int scheme, uint32_t flags, int levels, const Sizes *L) {
+  return scheme != SUBDIV_CATMULL_CLARK && !rebuilds_levels(scheme, flags) && levels >= 4 &&
+         !L[levels - 1].creases && !L[levels - 2].creases;
 }
 
 Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long long C0) {
@@ -292,7 +292,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       mX = x > mX ? x : mX;
     }
     y.tbase = c.take(4 * (mX + 1));
-    if (loop_lag2(scheme, flags, levels, L)) y.tbase2 = c.take(4 * (L[levels - 2].E + 1));
+    if (tri_lag2(scheme, flags, levels, L))
+      y.tbase2 = c.take(4 * ((scheme == SUBDIV_LOOP ? L[levels - 2].E : L[levels - 2].F) + 1));
   }
   if (flags & SUBDIV_FLAG_KEEP_STATE) {
     long long gV = L[0].V, gH = L[0].H;
@@ -752,7 +753,7 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   // (the last step from level levels-2 has no crease rules; it writes the
   // edge list of level levels-1 itself)
   const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases;
-  const bool lag2 = tri_lag && loop_lag2(scheme, plan->flags, levels, L);
+  const bool lag2 = tri_lag && tri_lag2(scheme, plan->flags, levels, L);
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -800,13 +801,19 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
                                   s));
       a = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases);
     } else if (lag2 && k == levels - 2) {
-      // Loop, the step before the last, also from the level below (m = k-1,
-      // whose adjacency `aprev` and edge bases tbase step k-1 left in place):
-      // level k's edge bases (for the last step) into tbase2, counted on level
-      // k; level k+1's points from level m; its faces only for the caller
+      // the step before the last, also from the level below (m = k-1, whose
+      // adjacency `aprev` and edge or face bases tbase step k-1 left in
+      // place): level k's bases (for the last step) into tbase2, counted on
+      // level k (sqrt(3): only for the caller's edge list); level k+1's points
+      // from level m; its faces only for the caller
       TriStep cnt{t, a, P, nullptr, nullptr, Adj{}, at<int32_t>(ws, y.tbase2), (int32_t)L[k].B};
-      SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, cnt, s));
-      SUBDIV_TIMED("loop_scan", k, launch_scan(cnt.base, cnt.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
+      if (scheme == SUBDIV_LOOP) {
+        SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, cnt, s));
+        SUBDIV_TIMED("loop_scan", k, launch_scan(cnt.base, cnt.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
+      } else if (outs[levels].edge_verts) {
+        SUBDIV_TIMED("sqrt3_count", k, tri_launch(SQRT3_COUNT, cnt, s));
+        SUBDIV_TIMED("sqrt3_scan", k, launch_scan(cnt.base, cnt.base, t.F, at<int32_t>(ws, y.partials), nullptr, s));
+      }
       const TriLag g{tprev, aprev, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E,
                      outs[k + 1].face_verts, P1, outs[k + 1].edge_verts, (int32_t)L[k].B};
       TriStep o{};  // level m's vertices walk their level-m rings
@@ -816,9 +823,14 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
       o.Vg = (int32_t)L[k - 1].V;
       o.ap = aprev;
       o.Vq = (int32_t)L[k - 2].V;
-      SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
-      SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
-      if (g.fv2) SUBDIV_TIMED("loop_face", k, tri_lag_launch(LAG_LOOP_FACE, g, s));
+      if (scheme == SUBDIV_LOOP) {
+        SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
+        SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
+        if (g.fv2) SUBDIV_TIMED("loop_face", k, tri_lag_launch(LAG_LOOP_FACE, g, s));
+      } else {
+        SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, o, s));
+        SUBDIV_TIMED("sqrt3_face", k, tri_lag_launch(LAG_SQRT3_FACE, g, s));
+      }
     } else if (tri_lag && final) {
       // level k+1 from level m = k-1: `a` and `tprev` are level m's (the step
       // before carried nothing); Loop's edge bases of level m are in tbase

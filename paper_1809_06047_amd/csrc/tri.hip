@@ -1060,7 +1060,7 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3l_face(TriLag c) {
         row[9 * j + 3 * i + 2] = q;
       }
     }
-    wave_store<27>(lds, row, reinterpret_cast<uint32_t *>(c.fv2) + 27 * rw, l, 27 * nw);
+    if (c.fv2) wave_store<27>(lds, row, reinterpret_cast<uint32_t *>(c.fv2) + 27 * rw, l, 27 * nw);
   }
   {
     uint32_t fp[9];
