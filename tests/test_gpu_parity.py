@@ -242,8 +242,8 @@ def test_status_codes_match_oracle(oracle_mod):
 
 
 @pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
-@pytest.mark.parametrize("levels", [3, 4])
-@pytest.mark.parametrize("cage", ["icosphere", "holes", "fan", "bipyramid", "grid"])
+@pytest.mark.parametrize("cage,levels", [(c, L) for c in ("icosphere", "holes", "fan", "bipyramid", "grid")
+                                         for L in (3, 4)] + [("holes", 5), ("fan", 5)])
 def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
     """The last Loop or sqrt(3) step runs from level L-2 (the level L-1 was
     refined from) and level L-1's adjacency is never built. The final level
