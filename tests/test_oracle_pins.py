@@ -586,6 +586,80 @@ def test_semisharp_blend_is_linear_in_sigma(oracle_mod):
     np.testing.assert_allclose(half, 0.5 * (smooth + sharp), atol=1e-15)
 
 
+# Cube corners by sign pattern (meshgen.cube numbers (x>0, y>0, z>0) as bits)
+_B = 7          # (1, 1, 1)
+_A = 6          # (1, 1, -1), cube edge (A, B)
+_C = 5          # (1, -1, 1), cube edge (C, B)
+_D = 3          # (-1, 1, 1), cube edge (D, B)
+
+
+def _cube_creases(pairs, sigmas):
+    m = G.cube()
+    return G.Mesh(positions=m.positions, verts=m.verts, face_order=4,
+                  crease_verts=np.array([[min(p), max(p)] for p in pairs], np.int32),
+                  crease_sharp=np.array(sigmas, np.float32))
+
+
+def _crease_set(lvl, P_parent_pairs=None):
+    return {(int(a), int(b), float(s)) for (a, b), s in zip(lvl.crease_verts, lvl.crease_sharp)}
+
+
+def _vertex_at(P, x):
+    d = np.abs(P - np.asarray(x, np.float64)).sum(1)
+    i = int(np.argmin(d))
+    assert d[i] < 1e-12
+    return i
+
+
+def test_chaikin_uses_the_neighbour_crease_on_an_open_path(oracle_mod):
+    """Open crease path A - B - C along two cube edges with sigma(AB) = 3 and
+    sigma(BC) = 1 (Sec. 3.3, the two Chaikin equations, worked by hand). At B
+    (two creases) each child takes sigma_i from the other crease:
+    AB's half at B gets 1/4 (1 + 3*3) - 1 = 1.5 and BC's half gets
+    1/4 (3 + 3*1) - 1 = 0.5. At the single-crease ends the neighbour is the
+    crease itself: A's half gets 3 - 1 = 2 and C's half 1 - 1 = 0, which is
+    dropped. Both edges have sigma >= 1, so their edge points are midpoints.
+    One level further, with the level-1 values (A's half 2, B's halves 1.5
+    and 0.5) every end is again worked out by hand: {1, 0.875, 0.625, 0.25}
+    survive. A swapped argument order, the crease's own sigma at a two-crease
+    end, or a dropped clamp each breaks one of these numbers."""
+    lv = oracle_mod.refine(_cube_creases([(_A, _B), (_C, _B)], [3.0, 1.0]), "cc", 2)
+    P0, P1 = lv[0].positions, lv[1].positions
+    m_ab = _vertex_at(P1, (P0[_A] + P0[_B]) / 2)
+    m_bc = _vertex_at(P1, (P0[_C] + P0[_B]) / 2)
+    assert _crease_set(lv[1]) == {(_A, m_ab, 2.0), (_B, m_ab, 1.5), (_B, m_bc, 0.5)}
+    # level 2: (A, m_ab) 2 -> at A 2 - 1 = 1, at m_ab 1/4 (1.5 + 6) - 1 = 0.875;
+    # (B, m_ab) 1.5 -> at B 1/4 (0.5 + 4.5) - 1 = 0.25, at m_ab 1/4 (2 + 4.5) - 1 = 0.625;
+    # (B, m_bc) 0.5 -> at B 1/4 (1.5 + 1.5) - 1 < 0, at m_bc 0.5 - 1 < 0: both dropped
+    assert sorted(lv[2].crease_sharp.tolist()) == [0.25, 0.625, 0.875, 1.0]
+    ends = sorted(int(a) for a, _ in lv[2].crease_verts)
+    assert ends == sorted([_A, m_ab, _B, m_ab])
+
+
+def test_vertex_sharpness_is_the_mean_of_its_creases(oracle_mod):
+    """Vertex sharpness s = mean of the incident creases' sigma (Sec. 3.3,
+    the vertex-sharpness definition). The smooth corner point of the cube is
+    (5/9) p (the worked example above).
+    Two creases at B, sigma 0.25 and 0.75: s = 0.5, the crease rule
+    3/4 B + 1/8 (A + C) = (1, 0.75, 0.75), so B moves to
+    1/2 (5/9) (1,1,1) + 1/2 (1, 0.75, 0.75).
+    Three creases at B, sigma 0.125, 0.625, 0.75: s = 0.5 again (max 0.75,
+    min 0.125, no single sigma equals it), the corner rule keeps B, so B moves
+    to 1/2 (5/9) (1,1,1) + 1/2 (1,1,1) = (7/9) (1,1,1)."""
+    lv = oracle_mod.refine(_cube_creases([(_A, _B), (_C, _B)], [0.25, 0.75]), "cc", 1)
+    want = 0.5 * (5.0 / 9.0) * np.ones(3) + 0.5 * np.array([1.0, 0.75, 0.75])
+    np.testing.assert_allclose(lv[1].positions[_B], want, rtol=0, atol=1e-15)
+    # order of the creases in the list does not matter
+    lv = oracle_mod.refine(_cube_creases([(_C, _B), (_A, _B)], [0.75, 0.25]), "cc", 1)
+    np.testing.assert_allclose(lv[1].positions[_B], want, rtol=0, atol=1e-15)
+    for sig in ([0.125, 0.625, 0.75], [0.75, 0.125, 0.625], [0.625, 0.75, 0.125]):
+        lv = oracle_mod.refine(_cube_creases([(_A, _B), (_C, _B), (_D, _B)], sig), "cc", 1)
+        np.testing.assert_allclose(lv[1].positions[_B], (7.0 / 9.0) * np.ones(3), rtol=0, atol=1e-15)
+        # the three neighbours carry one crease each (k = 1): smooth corners
+        for v in (_A, _C, _D):
+            np.testing.assert_allclose(lv[1].positions[v], (5.0 / 9.0) * lv[0].positions[v], rtol=0, atol=1e-15)
+
+
 # ---------------------------------------------------------------- boundaries
 
 def _boundary_loop(m):
