@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-levels", type=int, default=5, help="levels of the oracle sample (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=1024,
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving trace (Poisson arrivals; 0 = skip the serving leg)")
     ap.add_argument("--serve-factors", default="0.5,0.8,1.0,1.2,1.5,2,3",
                     help="arrival rates as multiples of the per-mesh-launch saturation rate")
@@ -108,9 +108,17 @@ def cpu_baseline(mesh, levels):
     lv = oracle.refine(mesh, "cc", levels)
     dt = time.perf_counter() - t0
     faces = lv[-1].num_faces
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": faces / dt, "unit": "refined faces/s", "cores": 1, "kind": "oracle",
             "sample": f"same cage refined to level {levels} ({faces} faces) by the serial FP64 oracle, "
-                      f"{dt:.1f} s on one host core"}
+                      f"{dt:.1f} s on one host core",
+            "host_cpu": model, "host_logical_cpus": os.cpu_count(),
+            "host_cpus_usable": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 class TwoDeep:
@@ -520,8 +528,18 @@ def serving(args):
         pts.append({"factor": p["factor"], "qps": round(p["qps"], 1),
                     "batched": side(p["batched"], ("p50_ms", "p99_ms", "faces_per_s", "mean_batch", "max_queue")),
                     "per_mesh": side(p["per_mesh"], ("p50_ms", "p99_ms", "faces_per_s"))})
-    return {"requests": res["requests"], "per_mesh_saturation_qps": round(res["per_mesh_saturation_qps"], 1),
-            "budget_gib": res["budget_gib"], "slots": res["slots"], "max_batch": res["max_batch"], "points": pts}
+    cold = res.get("cold_cache")
+    if cold:
+        cold = {"factor": cold["factor"], "registered": cold["registered"],
+                "batched": side(cold["batched"], ("p50_ms", "p99_ms", "faces_per_s", "mean_batch"))}
+    return {"requests": res["requests"], "topologies": res["topologies"],
+            "per_mesh_saturation_qps": round(res["per_mesh_saturation_qps"], 1),
+            "budget_gib": res["budget_gib"], "slots": res["slots"], "max_batch": res["max_batch"],
+            "batched_server": "FIFO prefixes of the queue, any schemes and level counts; one subdiv_refine_batch "
+                              "per batch, no host round trip; topology cache warm (every cage topology of the "
+                              "trace planned once before the timed runs)",
+            "per_mesh_server": "one subdiv_plan (with its read-back) + subdiv_refine per request, FIFO, one stream",
+            "points": pts, "cold_cache": cold}
 
 
 if __name__ == "__main__":

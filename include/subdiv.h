@@ -171,9 +171,27 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
  * mesh and workspace (the workspace holds every level's topology; it must not
  * be reused in between). grad_out: [V_L*3] device, grad_in: [V_0*3] device,
  * both caller-owned; grad_in is overwritten. Enqueues work only.
- * Returns SUBDIV_STATE when the plan was not made for the adjoint. */
+ * Returns SUBDIV_STATE when the plan was not made for the adjoint, or when no
+ * subdiv_refine with this plan has been enqueued into `ws` since the last
+ * subdiv_plan, batch plan or subdiv_state_destroy that touched it (the
+ * library keeps a host-side record per workspace; it never reads state that
+ * was not written). */
 int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *grad_out, float *grad_in,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* The state of a refinement is the pair (plan, workspace): the plan holds
+ * the sizes, the caller's workspace the level-0 adjacency (after subdiv_plan
+ * or subdiv_refine) and, with SUBDIV_FLAG_KEEP_STATE, every level's topology
+ * and the adjoint's coefficients (after subdiv_refine). The library keeps a
+ * small host-side record of which plan each workspace holds; this call drops
+ * the record of `ws` when it belongs to `plan`, so that later calls that
+ * need the state (subdiv_backward, subdiv_refine_positions,
+ * subdiv_refine_vertex_data, subdiv_select, subdiv_extract) return
+ * SUBDIV_STATE and subdiv_refine rebuilds the cage adjacency. The device
+ * memory stays the caller's: free or reuse it once the work enqueued on it
+ * has completed. Host-only, no device work. Returns SUBDIV_STATE when `ws`
+ * holds no state of `plan`, SUBDIV_INVALID_ARG for null pointers. */
+int subdiv_state_destroy(const subdiv_plan_info *plan, const void *ws);
 
 /* ---- mesh reordering (Sec. 4.5) --------------------------------------------
  * Reverse Cuthill-McKee on the cage's vertex graph, for locality of the rows
@@ -249,7 +267,8 @@ int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const 
  * the result equals subdiv_refine's positions bit for bit. outs[k].positions
  * as in subdiv_refine (the final level is required; other fields are
  * ignored). Enqueues work only. Returns SUBDIV_STATE for a plan that does not
- * keep its state or a different workspace. */
+ * keep its state, or a workspace into which no subdiv_refine with this plan
+ * was enqueued (see subdiv_backward). */
 int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                             size_t ws_bytes, void *stream);
 
@@ -271,49 +290,60 @@ int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *pla
 int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const float *data, int dim,
                               float *out, void *ws, size_t ws_bytes, void *stream);
 
-/* ---- batches of uneven meshes (one scheme and level count per batch) ---
- * The meshes are packed into one disjoint union cage and refined together:
- * every stage runs as one launch over all meshes of the batch. Each mesh's
- * final level is then written to its own buffers in its own numbering and is
- * bit-identical to refining that mesh alone with the same plan flags (the
- * union's index rules keep every mesh's elements in their relative order).
- * A fault in any mesh fails the whole batch with that mesh's status code.
- * Loop and sqrt(3) batches need triangle meshes; creases: Catmull-Clark only. */
-typedef struct subdiv_batch_plan {
-  int32_t num_meshes;
-  int32_t scheme;
-  int32_t levels;
-  uint32_t flags;
-  subdiv_plan_info union_plan; /* plan of the packed union cage */
-  size_t workspace_bytes;      /* the workspace size the batch was planned in */
-  const void *priv_ws;         /* private: the planned workspace */
-  uint64_t priv_stamp;
-  int32_t priv_gather[4];      /* private: launch sizes of the final gather */
-} subdiv_batch_plan;
-
+/* ---- batches of uneven meshes -----------------------------------------
+ * A batch lists n meshes, each with its own scheme and level count. The
+ * meshes are grouped by (scheme, levels), in order of first appearance; the
+ * members of a group are packed into one disjoint union cage and refined
+ * together, every stage one launch over the whole group, and a group of one
+ * is refined as the mesh itself. Each mesh's final level is written to its
+ * own buffers in its own numbering and is bit-identical to refining that mesh
+ * alone (the union's index rules keep every mesh's elements in their
+ * relative order). Loop and sqrt(3) need triangle meshes; creases in batches:
+ * Catmull-Clark only.
+ *
+ * The refinement reads each mesh's counts (edges, boundary edges, largest
+ * sharpness) from a plan of that mesh - made by subdiv_plan, or for a whole
+ * batch at once by subdiv_plan_batch - so subdiv_refine_batch never waits for
+ * the device: a server that keeps the plans of the cages it has seen enqueues
+ * a whole batch without a host round trip. */
 #define SUBDIV_MAX_BATCH 65536
 
-/* Upper bound of the workspace a batch needs (host-only). `meshes` are read
- * for their sizes only (host structs with device pointers). */
-size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags);
+/* Workspace bytes a batch needs (host-only): the larger of what
+ * subdiv_plan_batch and subdiv_refine_batch use. With plans (one per mesh,
+ * as subdiv_refine_batch takes them) the refinement's part is exact;
+ * plans == NULL gives an upper bound from the sizes alone. `meshes` are read
+ * for their sizes only. Returns 0 for invalid arguments or plans that do not
+ * match their meshes. */
+size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n,
+                                    const subdiv_plan_info *plans, uint32_t flags);
 
-/* Packs the n meshes into the union cage inside `ws`, plans it (validation,
- * adjacency; waits for the stream to read back the union's counts and the
- * per-mesh edge and boundary counts), and fills plans[i] with the sizes of
- * every level of mesh i (size reports only: they cannot be passed to
- * subdiv_refine). A batch of one plans the mesh itself (no union). */
-int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags, void *ws,
-                      size_t ws_bytes, subdiv_batch_plan *bplan, subdiv_plan_info *plans, void *stream);
+/* Symbolic pass of a whole batch (Sec. 4.2, per group of the batch):
+ * validates every mesh, builds each group's union adjacency, reads back all
+ * counts and faults in one synchronisation of the stream, and fills
+ * plans[i] with the sizes of every level of mesh i for levels[i] levels.
+ * Each plans[i] is a plan of mesh i like subdiv_plan's (it can be passed to
+ * subdiv_refine with any workspace of plans[i].workspace_bytes, which then
+ * builds the cage adjacency itself) and the plan subdiv_refine_batch needs.
+ * A fault in any mesh fails the call with that fault's status code and
+ * zeroed plans. flags: 0 or SUBDIV_FLAG_REBUILD_EACH_LEVEL. */
+int subdiv_plan_batch(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n, uint32_t flags,
+                      void *ws, size_t ws_bytes, subdiv_plan_info *plans, void *stream);
 
-/* Refines a planned batch: outs[i] receives the final level of mesh i
- * (face_verts [H_L], positions [V_L*3], sized from plans[i]; edge_verts and
- * crease_sharpness are not written). The meshes must be the planned ones
- * (positions may change); `ws` must be the planned workspace. Enqueues work
- * only (the pointer tables go to the device through library-owned pinned
- * host memory). The union's final level is gathered into the outputs in
- * contiguous segments; a batch of one is refined straight into outs[0]. */
-int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_plan *bplan, subdiv_level_out *outs,
-                        void *ws, size_t ws_bytes, void *stream);
+/* Refines a batch: outs[i] receives the final level of mesh i (face_verts
+ * [H_L], positions [V_L*3], sized from plans[i].level[levels[i]] when
+ * plans[i].levels == levels[i], else from the level sizes of a plan with
+ * levels[i] levels; edge_verts and crease_sharpness are not written).
+ * plans[i] is a plan of mesh i (same face_verts pointer, scheme schemes[i],
+ * at least levels[i] levels, not SUBDIV_FLAG_KEEP_STATE): its cage counts
+ * size every level, so the call enqueues work only (the pointer and gather
+ * tables go to the device through library-owned pinned host memory, in
+ * stream order). Positions may differ from the planned ones. `ws` needs
+ * subdiv_batch_workspace_bound(meshes, schemes, levels, n, plans, flags)
+ * bytes and is overwritten. Returns SUBDIV_STATE when a plan does not match
+ * its mesh. */
+int subdiv_refine_batch(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n,
+                        const subdiv_plan_info *plans, subdiv_level_out *outs, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /* ---- optional stage timing ---------------------------------------------
  * When enabled (process-wide switch, default off), subdiv_plan and

@@ -61,12 +61,6 @@ class subdiv_extraction(ctypes.Structure):
                 ("crease_sharpness", c_vp), ("vertex_map", c_vp), ("face_map", c_vp)]
 
 
-class subdiv_batch_plan(ctypes.Structure):
-    _fields_ = [("num_meshes", c_i32), ("scheme", c_i32), ("levels", c_i32), ("flags", c_u32),
-                ("union_plan", subdiv_plan_info), ("workspace_bytes", c_sz), ("priv_ws", c_vp),
-                ("priv_stamp", c_u64), ("priv_gather", c_i32 * 4)]
-
-
 # every function the header declares, with its signature
 SIGNATURES = {
     "subdiv_workspace_bound": (c_sz, [c_i32, c_i32, c_i64, c_i32, ctypes.c_int, ctypes.c_int, c_u32]),
@@ -86,13 +80,17 @@ SIGNATURES = {
     "subdiv_extract": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                       ctypes.POINTER(subdiv_selection), ctypes.POINTER(subdiv_extraction), c_vp, c_sz,
                                       c_vp]),
-    "subdiv_batch_workspace_bound": (c_sz, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                             c_u32]),
-    "subdiv_plan_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int, c_u32,
-                                         c_vp, c_sz, ctypes.POINTER(subdiv_batch_plan),
+    "subdiv_batch_workspace_bound": (c_sz, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                             ctypes.POINTER(subdiv_plan_info), c_u32]),
+    "subdiv_plan_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int, c_u32, c_vp, c_sz,
                                          ctypes.POINTER(subdiv_plan_info), c_vp]),
-    "subdiv_refine_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.c_int, ctypes.POINTER(subdiv_batch_plan),
-                                           ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_refine_batch": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                           ctypes.POINTER(subdiv_plan_info), ctypes.POINTER(subdiv_level_out), c_vp,
+                                           c_sz, c_vp]),
+    "subdiv_state_destroy": (ctypes.c_int, [ctypes.POINTER(subdiv_plan_info), c_vp]),
     "subdiv_timing_enable": (None, [ctypes.c_int]),
     "subdiv_timing_select": (None, [ctypes.c_char_p, ctypes.c_int]),
     "subdiv_timing_read": (ctypes.c_int, [ctypes.POINTER(subdiv_stage_time), ctypes.c_int]),

@@ -201,6 +201,14 @@ class Refiner:
     def final(self):
         return self.outs[self.levels]
 
+    def release(self):
+        """Drop the library's record of the state this refiner's plan keeps in
+        its workspace (subdiv_state_destroy); later state calls on it fail
+        until the next plan and run. Returns True when a state was dropped."""
+        st = load().subdiv_state_destroy(ctypes.byref(self.plan_info), ctypes.c_void_p(self.ws.data_ptr()))
+        self._state_ready = False
+        return st == _lib.OK
+
     def backward(self, grad_out: torch.Tensor, grad_in: Optional[torch.Tensor] = None, stream=None):
         """grad_in = R^T grad_out for the last run (needs flags with
         FLAG_KEEP_STATE). Enqueues work only."""
@@ -390,75 +398,119 @@ class StreamingRefiner:
         return outs, ev
 
 
-class BatchRefiner:
-    """Plan + refine of a batch of uneven meshes (one scheme and level count):
-    one launch per stage for the whole batch, each mesh's final level in its
-    own tensors. Meshes are meshgen.Mesh or DeviceMesh."""
+def _per_mesh(x, n, conv=int):
+    if isinstance(x, (list, tuple, np.ndarray)):
+        if len(x) != n:
+            raise ValueError(f"expected {n} values, got {len(x)}")
+        return [conv(v) for v in x]
+    return [conv(x)] * n
 
-    def __init__(self, meshes, scheme, levels: int, flags: int = 0, device="cuda", ws: Optional[torch.Tensor] = None):
-        lib = load()
+
+def mesh_shape_struct(m) -> "_lib.subdiv_mesh":
+    """A subdiv_mesh carrying a host cage's sizes only (for the host-only
+    size queries; its pointers are placeholders that are never read)."""
+    s = _lib.subdiv_mesh()
+    s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
+    s.face_order = 0 if m.offsets is not None else m.face_order
+    s.face_offsets = 16 if m.offsets is not None else None
+    s.face_verts = s.positions = 16
+    s.num_creases = m.num_creases
+    if m.num_creases:
+        s.crease_verts = s.crease_sharpness = 16
+    return s
+
+
+class BatchRefiner:
+    """A batch of uneven meshes, each with its own scheme and level count
+    (`schemes` / `levels`: one value for every mesh, or one per mesh). The
+    library groups the meshes by (scheme, levels) and refines each group
+    with one launch per stage; every mesh's final level lands in its own
+    tensors. Meshes are meshgen.Mesh or DeviceMesh.
+
+    plan() runs subdiv_plan_batch: one read-back for the whole batch, one
+    plan per mesh. `plans` (one subdiv_plan_info per mesh, e.g. kept from
+    earlier plans of the same device cages) skips it. run() enqueues
+    subdiv_refine_batch, which never waits for the device."""
+
+    def __init__(self, meshes, schemes, levels, flags: int = 0, device="cuda", ws: Optional[torch.Tensor] = None,
+                 plans=None):
+        load()
         self.dmeshes = [m if isinstance(m, DeviceMesh) else DeviceMesh(m, device) for m in meshes]
         self.n = len(self.dmeshes)
-        self.scheme = _lib.SCHEMES.get(scheme, scheme)
-        self.levels = int(levels)
+        self.schemes = _per_mesh(schemes, self.n, lambda v: _lib.SCHEMES.get(v, v))
+        self.levels = _per_mesh(levels, self.n)
         self.flags = int(flags)
         self.device = self.dmeshes[0].device
         self.structs = (_lib.subdiv_mesh * self.n)(*[d.struct for d in self.dmeshes])
-        self.ws_bytes = int(lib.subdiv_batch_workspace_bound(self.structs, self.n, self.scheme, self.levels, self.flags))
-        if self.ws_bytes == 0:
-            raise _lib.SubdivError(_lib.INVALID_ARG, "subdiv_batch_workspace_bound")
-        if ws is not None and ws.numel() >= self.ws_bytes:
-            self.ws = ws
-        else:
-            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.bplan = _lib.subdiv_batch_plan()
+        self.c_schemes = (ctypes.c_int * self.n)(*self.schemes)
+        self.c_levels = (ctypes.c_int * self.n)(*self.levels)
         self.plans = (_lib.subdiv_plan_info * self.n)()
         self.outs: List[Dict[str, torch.Tensor]] = []
+        self._ws_arg = ws
+        self.ws = None
+        self.ws_bytes = 0
+        if plans is not None:
+            for i, p in enumerate(plans):
+                self.plans[i] = p
+            self._alloc()
 
     @staticmethod
-    def footprint(meshes, scheme, levels: int, flags: int = 0) -> int:
-        """Device bytes a batch needs: workspace bound (host-only)."""
+    def footprint(meshes, schemes, levels, flags: int = 0, plans=None) -> int:
+        """Workspace bytes of a batch of host cages (host-only): exact for the
+        refinement when `plans` are given, an upper bound otherwise."""
+        n = len(meshes)
+        structs = (_lib.subdiv_mesh * n)(*[mesh_shape_struct(m) for m in meshes])
+        sc = (ctypes.c_int * n)(*_per_mesh(schemes, n, lambda v: _lib.SCHEMES.get(v, v)))
+        lv = (ctypes.c_int * n)(*_per_mesh(levels, n))
+        pl = None
+        if plans is not None:
+            pl = (_lib.subdiv_plan_info * n)(*plans)
+        return int(load().subdiv_batch_workspace_bound(structs, sc, lv, n, pl, flags))
+
+    def _ensure_ws(self, with_plans: bool):
         lib = load()
-        structs = (_lib.subdiv_mesh * len(meshes))()
-        for i, m in enumerate(meshes):
-            s = structs[i]
-            s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
-            s.face_order = 0 if m.offsets is not None else m.face_order
-            s.face_offsets = 16 if m.offsets is not None else None  # sizes only: never dereferenced
-            s.face_verts = s.positions = 16
-            s.num_creases = m.num_creases
-            if m.num_creases:
-                s.crease_verts = s.crease_sharpness = 16
-        return int(lib.subdiv_batch_workspace_bound(structs, len(meshes), _lib.SCHEMES.get(scheme, scheme), levels,
-                                                    flags))
+        need = int(lib.subdiv_batch_workspace_bound(self.structs, self.c_schemes, self.c_levels, self.n,
+                                                    self.plans if with_plans else None, self.flags))
+        if need == 0:
+            raise _lib.SubdivError(_lib.INVALID_ARG, "subdiv_batch_workspace_bound")
+        if self.ws is None or self.ws_bytes < need:
+            if self._ws_arg is not None and self._ws_arg.numel() >= need:
+                self.ws = self._ws_arg
+            else:
+                self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self.ws_bytes = int(self.ws.numel())
 
     def plan(self, stream=None):
         lib = load()
+        self._ensure_ws(False)
         s = current_stream_handle(self.device) if stream is None else stream
-        st = lib.subdiv_plan_batch(self.structs, self.n, self.scheme, self.levels, self.flags,
-                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.byref(self.bplan),
-                                   self.plans, ctypes.c_void_p(s))
+        st = lib.subdiv_plan_batch(self.structs, self.c_schemes, self.c_levels, self.n, self.flags,
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.plans, ctypes.c_void_p(s))
         check(st, "subdiv_plan_batch")
-        L = self.levels
+        self._alloc()
+        return self.plans
+
+    def _alloc(self):
         arr = (_lib.subdiv_level_out * self.n)()
         self.outs = []
         for i in range(self.n):
-            li = self.plans[i].level[L]
+            li = self.plans[i].level[self.levels[i]]
             fv = torch.empty(li.num_halfedges, dtype=torch.int32, device=self.device)
             P = torch.empty((li.num_vertices, 3), dtype=torch.float32, device=self.device)
             arr[i].face_verts = fv.data_ptr()
             arr[i].positions = P.data_ptr()
             self.outs.append({"face_verts": fv, "positions": P})
         self._outs_struct = arr
-        return self.plans
 
     def output_faces(self) -> int:
-        return sum(int(self.plans[i].level[self.levels].num_faces) for i in range(self.n))
+        return sum(int(self.plans[i].level[self.levels[i]].num_faces) for i in range(self.n))
 
     def run(self, stream=None):
         lib = load()
+        self._ensure_ws(True)
         s = current_stream_handle(self.device) if stream is None else stream
-        st = lib.subdiv_refine_batch(self.structs, self.n, ctypes.byref(self.bplan), self._outs_struct,
-                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.c_void_p(s))
+        st = lib.subdiv_refine_batch(self.structs, self.c_schemes, self.c_levels, self.n, self.plans,
+                                     self._outs_struct, ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                     ctypes.c_void_p(s))
         check(st, "subdiv_refine_batch")
         return self.outs

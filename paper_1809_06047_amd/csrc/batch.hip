@@ -90,7 +90,7 @@ __global__ void k_concat_positions(const BatchMesh *m, int n, float *P) {
   st3(P, gid, ld3(b.P, gid - b.vofs));
 }
 
-// ---- per-mesh edge and boundary counts of the union cage --------------
+// ---- per-mesh counts of the union cage ---------------------------------
 // ebase = exclusive scan of lower-neighbour counts (edge base per vertex);
 // the edges of mesh i are ebase[vofs_i] .. ebase[vofs_{i+1}]
 __global__ void k_batch_edge_ranges(const BatchMesh *m, int n, const int32_t *ebase, int32_t *epre) {
@@ -100,10 +100,38 @@ __global__ void k_batch_edge_ranges(const BatchMesh *m, int n, const int32_t *eb
   epre[i] = ebase[v];
 }
 
+// boundary edges per mesh (the grid covers an upper bound of the union's
+// edges; the scan total epre[n] is the count)
 __global__ void k_batch_boundary_counts(const int32_t *epre, int n, const int32_t *bflag, int32_t *bcount) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= epre[n]) return;
   if (bflag[e]) atomicAdd(&bcount[seg_of(epre, n + 1, e)], 1);
+}
+
+// largest valence (incident faces, from the row pointer of M's row view) and
+// largest crease sharpness (float bits: sharpness is validated >= 0, so the
+// bits order like the values) per mesh
+__global__ void k_batch_maxima(const BatchMesh *m, int n, const int32_t *rowptr, const float *cs, long long VU,
+                               long long CU, int32_t *vmax, int32_t *smax) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < VU) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (m[mid].vofs <= gid) lo = mid;
+      else hi = mid;
+    }
+    atomicMax(&vmax[lo], rowptr[gid + 1] - rowptr[gid]);
+  }
+  if (gid < CU) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (m[mid].cofs <= gid) lo = mid;
+      else hi = mid;
+    }
+    atomicMax(&smax[lo], __float_as_int(cs[gid]));
+  }
 }
 
 // ---- gather the union's final level into each mesh's buffers ----------
@@ -148,13 +176,17 @@ hipError_t batch_concat_positions(const BatchMesh *m, int n, float *P, long long
   return hipGetLastError();
 }
 
-hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, long long E,
-                       int32_t *epre, int32_t *bcount, hipStream_t s) {
-  hipError_t err = launch_fill_i32(bcount, 0, n, s);
+hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, const int32_t *rowptr,
+                       const float *cs, long long VU, long long HU, long long CU, int32_t *epre, int32_t *bcount,
+                       int32_t *vmax, int32_t *smax, hipStream_t s) {
+  // bcount, vmax and smax are consecutive: one fill clears all three
+  hipError_t err = launch_fill_i32(bcount, 0, 3ll * n, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_batch_edge_ranges, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, m, n, ebase, epre);
-  hipLaunchKernelGGL(k_batch_boundary_counts, dim3(grid_for(E)), dim3(kBlock), 0, s, (const int32_t *)epre, n, bflag,
+  hipLaunchKernelGGL(k_batch_boundary_counts, dim3(grid_for(HU)), dim3(kBlock), 0, s, (const int32_t *)epre, n, bflag,
                      bcount);
+  const long long items = VU > CU ? VU : CU;
+  hipLaunchKernelGGL(k_batch_maxima, dim3(grid_for(items)), dim3(kBlock), 0, s, m, n, rowptr, cs, VU, CU, vmax, smax);
   return hipGetLastError();
 }
 

@@ -311,29 +311,69 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   return y;
 }
 
-// The vertex-rule coefficients depend on the topology and the creases only,
-// so they are fixed by the plan: the first backward pass with a plan's
-// workspace writes them into the kept state, and every later one with the
-// same plan (same stamp) reads them. Callers that keep the state only for
-// positions-only or vertex-data evaluation never pay for them.
-std::mutex g_coef_mu;
-std::unordered_map<const void *, uint64_t> g_coef_stamp;  // workspace -> plan whose coefficients it holds
+// What the library knows about each workspace it has been handed (host-side
+// records; the device memory itself is the caller's):
+//   plan  - stamp of the plan whose cage adjacency the level-0 region holds
+//           (written by subdiv_plan or by a refinement that rebuilt it);
+//   kept  - stamp of the SUBDIV_FLAG_KEEP_STATE plan whose every-level state
+//           a completed subdiv_refine enqueued into it (0: none);
+//   coef  - stamp of the plan whose adjoint vertex-rule coefficients it holds.
+// The coefficients depend on the topology and the creases only, so they are
+// fixed by the plan: the first backward pass with a plan's workspace writes
+// them into the kept state, and every later one with the same plan reads
+// them. Callers that keep the state only for positions-only or vertex-data
+// evaluation never pay for them. subdiv_state_destroy drops a record.
+struct WsRecord {
+  uint64_t plan = 0, kept = 0, coef = 0;
+};
+std::mutex g_ws_mu;
+std::unordered_map<const void *, WsRecord> g_ws;
 
-bool coefs_held(const void *ws, uint64_t stamp) {
-  std::lock_guard<std::mutex> lock(g_coef_mu);
-  const auto it = g_coef_stamp.find(ws);
-  return it != g_coef_stamp.end() && it->second == stamp;
+// one counter for every plan and batch plan, so that no two share a stamp
+uint64_t next_stamp() {
+  static std::atomic<uint64_t> stamp{1};
+  return stamp++;
 }
 
-void coefs_mark(const void *ws, uint64_t stamp) {
-  std::lock_guard<std::mutex> lock(g_coef_mu);
-  g_coef_stamp[ws] = stamp;
+WsRecord ws_record(const void *ws) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  const auto it = g_ws.find(ws);
+  return it == g_ws.end() ? WsRecord{} : it->second;
 }
 
-// a refinement that keeps the state writes it anew (the workspace may be new memory)
-void coefs_forget(const void *ws) {
-  std::lock_guard<std::mutex> lock(g_coef_mu);
-  g_coef_stamp.erase(ws);
+// a plan (re)wrote the level-0 region: nothing else it held is valid any more
+void ws_planned(const void *ws, uint64_t stamp) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  g_ws[ws] = WsRecord{stamp, 0, 0};
+}
+
+// a refinement wrote the level-0 region (reused or rebuilt) and, with the
+// state kept, every level's topology
+void ws_refined(const void *ws, uint64_t stamp, bool keep) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  g_ws[ws] = WsRecord{stamp, keep ? stamp : 0, 0};
+}
+
+void ws_coefs(const void *ws, uint64_t stamp) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  g_ws[ws].coef = stamp;
+}
+
+// a batch overwrote [ws, ws + bytes): every record inside is stale
+void ws_forget_range(const void *ws, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  const char *lo = static_cast<const char *>(ws), *hi = lo + bytes;
+  for (auto it = g_ws.begin(); it != g_ws.end();) {
+    const char *p = static_cast<const char *>(it->first);
+    if (p >= lo && p < hi)
+      it = g_ws.erase(it);
+    else
+      ++it;
+  }
+}
+
+bool state_kept(const subdiv_plan_info *plan, const void *ws) {
+  return plan->priv_stamp != 0 && ws_record(ws).kept == plan->priv_stamp;
 }
 
 template <class T>
@@ -550,6 +590,75 @@ int refine_cc_carried(const subdiv_mesh *mesh, const subdiv_level_out *outs, voi
   return SUBDIV_OK;
 }
 
+// The symbolic pass on a cage, enqueued only: validation of faces and
+// indices and the valence; then the adjacency, edge ids and creases, whose
+// kernels do nothing once a fault is recorded; for Loop and sqrt(3) refined
+// twice or more, the count of two-face components. Counts and faults are
+// left in the level-0 region's DeviceInfo for one read-back.
+int plan_enqueue(const subdiv_mesh *mesh, int scheme, int levels, void *ws, const Layout &y0, hipStream_t s) {
+  const long long H0 = cage_H(mesh);
+  const Topo t = cage_topo(mesh, H0, ws, y0);
+  DeviceInfo *dinfo = at<DeviceInfo>(ws, y0.info);
+  SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y0, s));
+  BuildScratch b = scratch0(ws, y0);
+  Adj a0 = adj_at(ws, y0.adj0, H0, mesh->num_creases > 0);
+  SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, a0, dinfo, s));
+  SUBDIV_TIMED("build", 0,
+               build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
+  if (scheme != SUBDIV_CATMULL_CLARK && levels >= 2) SUBDIV_TIMED("build", 0, count_pillows(t, a0, dinfo, s));
+  return SUBDIV_OK;
+}
+
+int plan_status(const DeviceInfo &h, int scheme, int levels) {
+  const int st = status_from_faults(h.faults);
+  if (st != SUBDIV_OK) return st;
+  // a two-face component refined by Loop or sqrt(3) is not manifold after one level
+  if (scheme != SUBDIV_CATMULL_CLARK && levels >= 2 && h.num_pillows > 0) return SUBDIV_NONMANIFOLD;
+  return SUBDIV_OK;
+}
+
+// A plan from the cage's counts: the closed-form sizes of every level, the
+// workspace refine needs, and a fresh stamp. `ws` is the workspace whose
+// level-0 region holds the cage's adjacency, or nullptr.
+int fill_plan(subdiv_plan_info *plan, const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags, long long E0,
+              long long B0, float max_sharp, int max_valence, const void *ws) {
+  std::memset(plan, 0, sizeof(*plan));
+  const long long H0 = cage_H(mesh);
+  Sizes L[SUBDIV_MAX_LEVELS + 1];
+  level_sizes(scheme, levels, mesh->num_vertices, mesh->num_faces, H0, E0, B0, mesh->face_offsets ? 0 : mesh->face_order,
+              max_sharp, mesh->num_creases, L);
+  if (!sizes_fit_int32(L, levels)) return SUBDIV_INVALID_ARG;
+  const Layout y = make_layout(scheme, levels, flags, L, mesh->num_creases);
+  plan->scheme = scheme;
+  plan->levels = levels;
+  plan->flags = flags;
+  plan->max_valence = max_valence;
+  plan->max_sharpness = max_sharp;
+  for (int k = 0; k <= levels; ++k) {
+    subdiv_level_info &li = plan->level[k];
+    li.num_vertices = L[k].V;
+    li.num_edges = L[k].E;
+    li.num_faces = L[k].F;
+    li.num_halfedges = L[k].H;
+    li.num_boundary_edges = L[k].B;
+    li.face_order = L[k].order;
+    long long cmax = 0;
+    if (L[k].creases) {
+      cmax = (long long)mesh->num_creases << (k < 30 ? k : 30);
+      if (cmax > L[k].E) cmax = L[k].E;
+    }
+    li.max_creases = (int32_t)cmax;
+  }
+  plan->workspace_bytes = y.total;
+  plan->priv_mesh_verts = mesh->face_verts;
+  plan->priv_ws = ws;
+  plan->priv_stamp = next_stamp();
+  return SUBDIV_OK;
+}
+
+int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
+                size_t ws_bytes, void *stream);
+
 }  // namespace
 
 // ---- the C ABI ---------------------------------------------------------
@@ -644,66 +753,37 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
   Sizes L0[SUBDIV_MAX_LEVELS + 1];
+  ws_planned(ws, 0);  // the level-0 region is rewritten from here on
   level_sizes(scheme, 0, mesh->num_vertices, mesh->num_faces, H0, H0, H0, 0, 0.f, mesh->num_creases, L0);
   const Layout y0 = make_layout(scheme, 0, flags, L0, mesh->num_creases);
   if (ws_bytes < y0.level0_end) return SUBDIV_WORKSPACE;
   SUBDIV_TRY(init_weight_tables());
-  Topo t = cage_topo(mesh, H0, ws, y0);
-  DeviceInfo *dinfo = at<DeviceInfo>(ws, y0.info);
+  if ((st = plan_enqueue(mesh, scheme, levels, ws, y0, s)) != SUBDIV_OK) return st;
   DeviceInfo hinfo{};
-  // validation of faces and indices, valence; then the adjacency, edge ids
-  // and creases, whose kernels do nothing once a fault is recorded: one
-  // read-back of the counts and faults for the whole build
-  SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y0, s));
-  BuildScratch b = scratch0(ws, y0);
-  Adj a0 = adj_at(ws, y0.adj0, H0, mesh->num_creases > 0);
-  SUBDIV_TIMED("build", 0, build_adjacency(t, scheme, b, a0, dinfo, s));
-  SUBDIV_TIMED("build", 0,
-               build_creases(t, b, a0, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
-  const bool pillow_check = scheme != SUBDIV_CATMULL_CLARK && levels >= 2;
-  if (pillow_check) SUBDIV_TIMED("build", 0, count_pillows(t, a0, dinfo, s));
-  SUBDIV_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  SUBDIV_TRY(hipMemcpyAsync(&hinfo, at<DeviceInfo>(ws, y0.info), sizeof(hinfo), hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
-  if ((st = status_from_faults(hinfo.faults)) != SUBDIV_OK) return st;
-  // a two-face component refined by Loop or sqrt(3) is not manifold after one level
-  if (pillow_check && hinfo.num_pillows > 0) return SUBDIV_NONMANIFOLD;
+  if ((st = plan_status(hinfo, scheme, levels)) != SUBDIV_OK) return st;
   float max_sharp;
   std::memcpy(&max_sharp, &hinfo.max_sharp_bits, 4);
-  Sizes L[SUBDIV_MAX_LEVELS + 1];
-  level_sizes(scheme, levels, mesh->num_vertices, mesh->num_faces, H0, hinfo.num_edges, hinfo.num_boundary,
-              t.order, max_sharp, mesh->num_creases, L);
-  if (!sizes_fit_int32(L, levels)) return SUBDIV_INVALID_ARG;
-  const Layout y = make_layout(scheme, levels, flags, L, mesh->num_creases);
-  plan->scheme = scheme;
-  plan->levels = levels;
-  plan->flags = flags;
-  plan->max_valence = hinfo.max_valence;
-  plan->max_sharpness = max_sharp;
-  for (int k = 0; k <= levels; ++k) {
-    subdiv_level_info &li = plan->level[k];
-    li.num_vertices = L[k].V;
-    li.num_edges = L[k].E;
-    li.num_faces = L[k].F;
-    li.num_halfedges = L[k].H;
-    li.num_boundary_edges = L[k].B;
-    li.face_order = L[k].order;
-    long long cmax = 0;
-    if (L[k].creases) {
-      cmax = (long long)mesh->num_creases << (k < 30 ? k : 30);
-      if (cmax > L[k].E) cmax = L[k].E;
-    }
-    li.max_creases = (int32_t)cmax;
-  }
-  plan->workspace_bytes = y.total;
-  plan->priv_mesh_verts = mesh->face_verts;
-  plan->priv_ws = ws;
-  static std::atomic<uint64_t> stamp{1};
-  plan->priv_stamp = stamp++;
+  if ((st = fill_plan(plan, mesh, scheme, levels, flags, hinfo.num_edges, hinfo.num_boundary, max_sharp,
+                      hinfo.max_valence, ws)) != SUBDIV_OK)
+    return st;
+  ws_planned(ws, plan->priv_stamp);
   return SUBDIV_OK;
 }
 
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream) {
+  const int st = refine_impl(mesh, plan, outs, ws, ws_bytes, stream);
+  if (st == SUBDIV_HIP) ws_planned(ws, 0);  // part of the work may be missing: the workspace holds nothing usable
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
+                size_t ws_bytes, void *stream) {
   if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
@@ -725,7 +805,12 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   DeviceInfo *dinfo = at<DeviceInfo>(ws, y.info);
   const bool cr0 = mesh->num_creases > 0;
   Adj a = adj_at(ws, y.adj0, L[0].E, cr0 && L[0].creases);
-  if (ws != plan->priv_ws) {  // the plan's level-0 adjacency is not in this workspace: build it again
+  const bool keep = (plan->flags & SUBDIV_FLAG_KEEP_STATE) != 0;
+  const bool reuse = ws_record(ws).plan == plan->priv_stamp;
+  // from here on the workspace holds this plan's level-0 adjacency and, with
+  // the state kept, every level's topology once the enqueued work has run
+  ws_refined(ws, plan->priv_stamp, keep);
+  if (!reuse) {  // the plan's level-0 adjacency is not in this workspace: build it again
     SUBDIV_TIMED("build", 0, build_level0_faces(mesh, scheme, t, ws, y, s));
     BuildScratch b = scratch0(ws, y);
     Adj full = adj_at(ws, y.adj0, H0, cr0);
@@ -740,7 +825,6 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   const float *P = mesh->positions;
   DeviceInfo *dinfo2 = at<DeviceInfo>(ws, y.info2);
   if (scheme == SUBDIV_CATMULL_CLARK && !rebuild) {
-    if (plan->flags & SUBDIV_FLAG_KEEP_STATE) coefs_forget(ws);
     return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, P, false, s);
   }
   // ---- generic build of every level (Loop, sqrt(3); Catmull-Clark on request)
@@ -914,13 +998,17 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
   }
   return SUBDIV_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs,
                             void *ws, size_t ws_bytes, void *stream) {
   if (!plan || !outs || !ws) return SUBDIV_INVALID_ARG;
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
-  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || !state_kept(plan, ws))
+    return SUBDIV_STATE;
   if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
   const int levels = plan->levels;
   if (!outs[levels].positions) return SUBDIV_INVALID_ARG;
@@ -942,7 +1030,8 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
   if (!plan || !data || !out || !ws || dim < 1) return SUBDIV_INVALID_ARG;
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
-  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || !state_kept(plan, ws))
+    return SUBDIV_STATE;
   if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -983,7 +1072,9 @@ int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const u
   if (!sel) return SUBDIV_INVALID_ARG;
   std::memset(sel, 0, sizeof(*sel));
   if (!plan || !ws || !mesh || rings < 1) return SUBDIV_INVALID_ARG;
-  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws) return SUBDIV_STATE;
+  if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws ||
+      ws_record(ws).plan != plan->priv_stamp)
+    return SUBDIV_STATE;
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
@@ -1016,7 +1107,7 @@ int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const 
                    const subdiv_extraction *out, void *ws, size_t ws_bytes, void *stream) {
   if (!plan || !sel || !out || !ws || !mesh) return SUBDIV_INVALID_ARG;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws ||
-      sel->priv_stamp != plan->priv_stamp || sel->priv_ws != ws)
+      ws_record(ws).plan != plan->priv_stamp || sel->priv_stamp != plan->priv_stamp || sel->priv_ws != ws)
     return SUBDIV_STATE;
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
@@ -1083,7 +1174,7 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
   int st = check_mesh_args(mesh, plan->scheme, plan->levels);
   if (st != SUBDIV_OK) return st;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts) return SUBDIV_STATE;
-  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || !state_kept(plan, ws)) return SUBDIV_STATE;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int levels = plan->levels;
@@ -1093,9 +1184,9 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
               plan->level[0].num_boundary_edges, plan->level[0].face_order, plan->max_sharpness, mesh->num_creases,
               L);
   const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
-  if (!coefs_held(ws, plan->priv_stamp)) {
+  if (ws_record(ws).coef != plan->priv_stamp) {
     if ((st = keep_bw_coefs(mesh, ws, y, L, levels, s)) != SUBDIV_OK) return st;
-    coefs_mark(ws, plan->priv_stamp);
+    ws_coefs(ws, plan->priv_stamp);
   }
   const float *g1 = grad_out;
   for (int k = levels - 1; k >= 0; --k) {
@@ -1110,85 +1201,136 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
   return SUBDIV_OK;
 }
 
+int subdiv_state_destroy(const subdiv_plan_info *plan, const void *ws) {
+  if (!plan || !ws) return SUBDIV_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  const auto it = g_ws.find(ws);
+  if (plan->priv_stamp == 0 || it == g_ws.end() ||
+      (it->second.plan != plan->priv_stamp && it->second.kept != plan->priv_stamp))
+    return SUBDIV_STATE;
+  g_ws.erase(it);
+  return SUBDIV_OK;
+}
+
 }  // extern "C"
 
 // ---- batches ------------------------------------------------------------
+// A batch lists meshes with a scheme and a level count each. Its meshes are
+// grouped by (scheme, levels), in order of first appearance; the members of
+// a group keep their batch order. A group of several meshes is packed into
+// one disjoint union cage and refined by the ordinary kernels, one launch per
+// stage for the whole group; a group of one is the mesh itself.
 namespace {
 
-struct BatchLayout {
-  size_t desc, tables, outtab, epre, bcount, ufv, uoff, uP, ucv, ucs, fvL, PL, uws;
-  size_t uws_bytes, total;
-  long long VU, FU, HU, CU, HL, VL;
-  bool general;
-  int order;
+struct Group {
+  int scheme = 0, levels = 0;
+  std::vector<int> idx;  // batch indices of the members
+  long long VU = 0, FU = 0, HU = 0, CU = 0;
+  int order = 0;
+  bool general = false;
+  Sizes L[SUBDIV_MAX_LEVELS + 1];  // sizes of the union's levels (exact when the members' counts are known)
+  size_t desc = 0, tables = 0, outtab = 0, stats = 0, ufv = 0, uoff = 0, uP = 0, ucv = 0, ucs = 0, fvL = 0, PL = 0;
+  size_t uws = 0, uws_bytes = 0;
+  bool single() const { return idx.size() == 1; }
 };
 
-// blocks of the union's final vertex ids: V_0, then per level F_k and/or E_k
-int gather_blocks(int scheme, int levels) {
-  return 1 + levels * (scheme == SUBDIV_CATMULL_CLARK ? 2 : 1);
+std::vector<Group> make_groups(const int *schemes, const int *levels, int n) {
+  std::vector<Group> g;
+  for (int i = 0; i < n; ++i) {
+    size_t k = 0;
+    for (; k < g.size(); ++k)
+      if (g[k].scheme == schemes[i] && g[k].levels == levels[i]) break;
+    if (k == g.size()) {
+      g.emplace_back();
+      g.back().scheme = schemes[i];
+      g.back().levels = levels[i];
+    }
+    g[k].idx.push_back(i);
+  }
+  return g;
 }
 
-bool batch_layout(const subdiv_mesh *m, int n, int scheme, int levels, uint32_t flags, BatchLayout &b) {
-  b = BatchLayout{};
-  long long VU = 0, FU = 0, HU = 0, CU = 0;
-  int order = m[0].face_offsets ? 0 : m[0].face_order;
-  for (int i = 0; i < n; ++i) {
-    VU += m[i].num_vertices;
-    FU += m[i].num_faces;
-    HU += cage_H(&m[i]);
-    CU += m[i].num_creases;
-    const int oi = m[i].face_offsets ? 0 : m[i].face_order;
-    if (oi != order) order = 0;
-  }
+// blocks of the union's final vertex ids: V_0, then per level F_k and/or E_k
+int gather_blocks(int scheme, int levels) { return 1 + levels * (scheme == SUBDIV_CATMULL_CLARK ? 2 : 1); }
+
+// Sizes and workspace regions of every group. for_plan: the symbolic pass
+// (the union cage, per-member statistics and the level-0 region); otherwise
+// the refinement (cages, gather tables, the union's final level and the
+// union's whole workspace). plans: the members' counts (edges, boundary
+// edges, largest sharpness), or nullptr for the upper bound E, B <= H.
+bool layout_groups(std::vector<Group> &gs, const subdiv_mesh *m, const subdiv_plan_info *plans, uint32_t flags,
+                   bool for_plan, size_t *total) {
   const long long lim = 0x7fffffffLL - 16;
-  if (VU > lim || FU > lim || HU > lim || CU > lim) return false;
-  Sizes L[SUBDIV_MAX_LEVELS + 1];
-  level_sizes(scheme, levels, VU, FU, HU, HU, HU, order, CU > 0 ? 1e30f : 0.f, CU, L);
-  if (!sizes_fit_int32(L, levels)) return false;
-  b.VU = VU;
-  b.FU = FU;
-  b.HU = HU;
-  b.CU = CU;
-  b.HL = L[levels].H;
-  b.VL = L[levels].V;
-  b.general = (order == 0);
-  b.order = order;
-  b.uws_bytes = subdiv_workspace_bound((int32_t)VU, (int32_t)FU, HU, (int32_t)CU, scheme, levels, flags);
-  if (b.uws_bytes == 0) return false;
   Carver c;
-  b.desc = c.take(sizeof(BatchMesh) * (size_t)n);
-  const size_t nseg = (size_t)gather_blocks(scheme, levels) * n;
-  b.tables = c.take(16 * nseg + 4 * (nseg + 1 + (size_t)gather_blocks(scheme, levels) + 1 + nseg + 2 * ((size_t)n + 1)));
-  b.outtab = c.take(sizeof(BatchOut) * (size_t)n);
-  b.epre = c.take(4 * (size_t)(n + 1));
-  b.bcount = c.take(4 * (size_t)n);
-  b.ufv = c.take(4 * HU);
-  b.uoff = b.general ? c.take(4 * (FU + 1)) : 0;
-  b.uP = c.take(12 * VU);
-  b.ucv = c.take(8 * (CU > 0 ? CU : 1));
-  b.ucs = c.take(4 * (CU > 0 ? CU : 1));
-  b.fvL = c.take(4 * b.HL);
-  b.PL = c.take(12 * b.VL);
-  b.uws = c.take(b.uws_bytes);
-  b.total = c.at + 256;
+  for (Group &g : gs) {
+    long long EU = 0, BU = 0;
+    float smax = 0.f;
+    g.VU = g.FU = g.HU = g.CU = 0;
+    g.order = m[g.idx[0]].face_offsets ? 0 : m[g.idx[0]].face_order;
+    for (const int i : g.idx) {
+      g.VU += m[i].num_vertices;
+      g.FU += m[i].num_faces;
+      g.HU += cage_H(&m[i]);
+      g.CU += m[i].num_creases;
+      const int oi = m[i].face_offsets ? 0 : m[i].face_order;
+      if (oi != g.order) g.order = 0;
+      if (plans) {
+        EU += plans[i].level[0].num_edges;
+        BU += plans[i].level[0].num_boundary_edges;
+        smax = plans[i].max_sharpness > smax ? plans[i].max_sharpness : smax;
+      }
+    }
+    if (g.VU > lim || g.FU > lim || g.HU > lim || g.CU > lim) return false;
+    if (!plans) {
+      EU = BU = g.HU;
+      smax = g.CU > 0 ? 1e30f : 0.f;
+    }
+    g.general = (g.order == 0);
+    const int lv = for_plan ? 0 : g.levels;
+    level_sizes(g.scheme, lv, g.VU, g.FU, g.HU, EU, BU, g.order, smax, g.CU, g.L);
+    if (!sizes_fit_int32(g.L, lv)) return false;
+    const Layout y = make_layout(g.scheme, lv, flags, g.L, g.CU);
+    g.uws_bytes = for_plan ? y.level0_end : y.total;
+    const size_t n = g.idx.size();
+    if (!g.single()) {
+      g.desc = c.take(sizeof(BatchMesh) * n);
+      if (for_plan) {
+        g.stats = c.take(4 * (4 * n + 1));  // edge prefix [n+1], boundary, valence and sharpness maxima [n] each
+      } else {
+        const size_t nblk = (size_t)gather_blocks(g.scheme, g.levels), nseg = nblk * n;
+        g.tables = c.take(16 * nseg + 4 * (nseg + 1 + nblk + 1 + nseg + 2 * (n + 1)));
+        g.outtab = c.take(sizeof(BatchOut) * n);
+        g.uP = c.take(12 * g.VU);
+        g.fvL = c.take(4 * g.L[g.levels].H);
+        g.PL = c.take(12 * g.L[g.levels].V);
+      }
+      g.ufv = c.take(4 * g.HU);
+      g.uoff = g.general ? c.take(4 * (g.FU + 1)) : 0;
+      g.ucv = c.take(8 * (g.CU > 0 ? g.CU : 1));
+      g.ucs = c.take(4 * (g.CU > 0 ? g.CU : 1));
+    }
+    g.uws = c.take(g.uws_bytes);
+  }
+  *total = c.at + 256;
   return true;
 }
 
-std::vector<BatchMesh> batch_descriptors(const subdiv_mesh *m, int n) {
-  std::vector<BatchMesh> d((size_t)n);
+std::vector<BatchMesh> batch_descriptors(const subdiv_mesh *m, const Group &g) {
+  std::vector<BatchMesh> d(g.idx.size());
   int vo = 0, fo = 0, ho = 0, co = 0;
-  for (int i = 0; i < n; ++i) {
-    BatchMesh &x = d[i];
-    x.fv = m[i].face_verts;
-    x.off = m[i].face_offsets;
-    x.order = m[i].face_offsets ? 0 : m[i].face_order;
-    x.P = m[i].positions;
-    x.cv = m[i].crease_verts;
-    x.cs = m[i].crease_sharpness;
-    x.V = m[i].num_vertices;
-    x.F = m[i].num_faces;
-    x.H = (int32_t)cage_H(&m[i]);
-    x.C = m[i].num_creases;
+  for (size_t k = 0; k < g.idx.size(); ++k) {
+    const subdiv_mesh &x0 = m[g.idx[k]];
+    BatchMesh &x = d[k];
+    x.fv = x0.face_verts;
+    x.off = x0.face_offsets;
+    x.order = x0.face_offsets ? 0 : x0.face_order;
+    x.P = x0.positions;
+    x.cv = x0.crease_verts;
+    x.cs = x0.crease_sharpness;
+    x.V = x0.num_vertices;
+    x.F = x0.num_faces;
+    x.H = (int32_t)cage_H(&x0);
+    x.C = x0.num_creases;
     x.vofs = vo;
     x.fofs = fo;
     x.hofs = ho;
@@ -1201,18 +1343,18 @@ std::vector<BatchMesh> batch_descriptors(const subdiv_mesh *m, int n) {
   return d;
 }
 
-subdiv_mesh union_mesh(const BatchLayout &b, void *ws, int n_creases) {
+subdiv_mesh union_mesh(const Group &g, void *ws) {
   subdiv_mesh u{};
-  u.num_vertices = (int32_t)b.VU;
-  u.num_faces = (int32_t)b.FU;
-  u.face_order = b.general ? 0 : b.order;
-  u.num_halfedges = (int32_t)b.HU;
-  u.face_offsets = b.general ? at<int32_t>(ws, b.uoff) : nullptr;
-  u.face_verts = at<int32_t>(ws, b.ufv);
-  u.positions = at<float>(ws, b.uP);
-  u.num_creases = n_creases;
-  u.crease_verts = n_creases ? at<int32_t>(ws, b.ucv) : nullptr;
-  u.crease_sharpness = n_creases ? at<float>(ws, b.ucs) : nullptr;
+  u.num_vertices = (int32_t)g.VU;
+  u.num_faces = (int32_t)g.FU;
+  u.face_order = g.general ? 0 : g.order;
+  u.num_halfedges = (int32_t)g.HU;
+  u.face_offsets = g.general ? at<int32_t>(ws, g.uoff) : nullptr;
+  u.face_verts = at<int32_t>(ws, g.ufv);
+  u.positions = g.uP ? at<float>(ws, g.uP) : nullptr;
+  u.num_creases = (int32_t)g.CU;
+  u.crease_verts = g.CU ? at<int32_t>(ws, g.ucv) : nullptr;
+  u.crease_sharpness = g.CU ? at<float>(ws, g.ucs) : nullptr;
   return u;
 }
 
@@ -1253,200 +1395,277 @@ hipError_t staged_upload(void *dst, const void *src, size_t bytes, hipStream_t s
   return hipSuccess;
 }
 
-int check_batch_args(const subdiv_mesh *m, int n, int scheme, int levels) {
-  if (!m || n < 1 || n > SUBDIV_MAX_BATCH) return SUBDIV_INVALID_ARG;
+int check_batch_args(const subdiv_mesh *m, const int *schemes, const int *levels, int n) {
+  if (!m || !schemes || !levels || n < 1 || n > SUBDIV_MAX_BATCH) return SUBDIV_INVALID_ARG;
   for (int i = 0; i < n; ++i) {
-    const int st = check_mesh_args(&m[i], scheme, levels);
+    const int st = check_mesh_args(&m[i], schemes[i], levels[i]);
     if (st != SUBDIV_OK) return st;
-    if (m[i].num_creases > 0 && scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;  // batches: CC creases
+    if (m[i].num_creases > 0 && schemes[i] != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;  // batches: CC creases
   }
   return SUBDIV_OK;
+}
+
+// a member's plan may serve this batch entry: same cage, scheme, and at least
+// as many levels validated
+bool member_plan_ok(const subdiv_plan_info &p, const subdiv_mesh &m, int scheme, int levels) {
+  return p.priv_stamp != 0 && p.priv_mesh_verts == m.face_verts && p.scheme == scheme && p.levels >= levels &&
+         !(p.flags & SUBDIV_FLAG_KEEP_STATE) && p.level[0].num_vertices == m.num_vertices &&
+         p.level[0].num_faces == m.num_faces && p.level[0].num_halfedges == cage_H(&m);
+}
+
+// The final gather of a group: block b of the union's level-L vertex ids
+// lists the members in order; member k numbers its vertices by its segments
+// of the blocks in block order. LS[k] are member k's level sizes.
+struct GatherPlan {
+  std::vector<int32_t> tab;
+  int face_chunks = 0, vertex_chunks = 0, nblk = 0;
+};
+
+bool gather_plan(const Group &g, const std::vector<Sizes> &LS, GatherPlan &gp) {
+  const int n = (int)g.idx.size(), levels = g.levels;
+  const bool has_f = g.scheme != SUBDIV_LOOP, has_e = g.scheme != SUBDIV_SQRT3;
+  const int per = (int)has_f + (int)has_e;
+  const int nblk = gather_blocks(g.scheme, levels), nseg = nblk * n;
+  auto bsize = [&](int blk, int k) -> long long {
+    const Sizes *Li = &LS[(size_t)k * (levels + 1)];
+    if (blk == 0) return Li[0].V;
+    const int lev = (blk - 1) / per, t = (blk - 1) % per;
+    return (has_f && t == 0) ? Li[lev].F : Li[lev].E;
+  };
+  std::vector<int32_t> seg(4 * (size_t)nseg), pch((size_t)nseg + 1, 0), ub((size_t)nblk + 1, 0), doff((size_t)nseg),
+      fpre((size_t)n + 1, 0), fch((size_t)n + 1, 0);
+  std::vector<long long> loc((size_t)n, 0);
+  for (int blk = 0; blk < nblk; ++blk) {
+    long long pre = 0;
+    for (int k = 0; k < n; ++k) {
+      const long long len = bsize(blk, k), x = blk * (long long)n + k;
+      seg[4 * x + 0] = (int32_t)(ub[blk] + pre);
+      seg[4 * x + 1] = k;
+      seg[4 * x + 2] = (int32_t)loc[k];
+      seg[4 * x + 3] = (int32_t)len;
+      doff[x] = (int32_t)(loc[k] - ub[blk] - pre);
+      pch[x + 1] = pch[x] + (int32_t)((len + kGather - 1) / kGather);
+      loc[k] += len;
+      pre += len;
+    }
+    ub[blk + 1] = (int32_t)(ub[blk] + pre);
+  }
+  for (int k = 0; k < n; ++k) {
+    const long long FLk = LS[(size_t)k * (levels + 1) + levels].F;
+    fpre[k + 1] = fpre[k] + (int32_t)FLk;
+    fch[k + 1] = fch[k] + (int32_t)((FLk + kGather - 1) / kGather);
+  }
+  if (ub[nblk] != g.L[levels].V || fpre[n] != g.L[levels].F) return false;
+  gp.tab.clear();
+  for (const auto *v : {&seg, &pch, &ub, &doff, &fpre, &fch}) gp.tab.insert(gp.tab.end(), v->begin(), v->end());
+  gp.face_chunks = fch[n];
+  gp.vertex_chunks = pch[nseg];
+  gp.nblk = nblk;
+  return true;
 }
 
 }  // namespace
 
 extern "C" {
 
-size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags) {
-  if (check_batch_args(meshes, n, scheme, levels) != SUBDIV_OK) return 0;
-  BatchLayout b;
-  if (!batch_layout(meshes, n, scheme, levels, flags, b)) return 0;
-  return b.total;
+size_t subdiv_batch_workspace_bound(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n,
+                                    const subdiv_plan_info *plans, uint32_t flags) {
+  if (check_batch_args(meshes, schemes, levels, n) != SUBDIV_OK) return 0;
+  if (flags & ~SUBDIV_FLAG_REBUILD_EACH_LEVEL) return 0;
+  if (plans)
+    for (int i = 0; i < n; ++i)
+      if (!member_plan_ok(plans[i], meshes[i], schemes[i], levels[i])) return 0;
+  std::vector<Group> gs = make_groups(schemes, levels, n);
+  size_t need_plan = 0, need_refine = 0;
+  if (!layout_groups(gs, meshes, nullptr, flags, true, &need_plan)) return 0;
+  if (!layout_groups(gs, meshes, plans, flags, false, &need_refine)) return 0;
+  return need_plan > need_refine ? need_plan : need_refine;
 }
 
-int subdiv_plan_batch(const subdiv_mesh *meshes, int n, int scheme, int levels, uint32_t flags, void *ws,
-                      size_t ws_bytes, subdiv_batch_plan *bplan, subdiv_plan_info *plans, void *stream) {
-  if (!bplan || !plans || !ws) return SUBDIV_INVALID_ARG;
-  std::memset(bplan, 0, sizeof(*bplan));
-  int st = check_batch_args(meshes, n, scheme, levels);
+int subdiv_plan_batch(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n, uint32_t flags,
+                      void *ws, size_t ws_bytes, subdiv_plan_info *plans, void *stream) {
+  if (!plans || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_batch_args(meshes, schemes, levels, n);
   if (st != SUBDIV_OK) return st;
-  if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;
-  BatchLayout b;
-  if (!batch_layout(meshes, n, scheme, levels, flags, b)) return SUBDIV_INVALID_ARG;
-  if (ws_bytes < b.total) return SUBDIV_WORKSPACE;
+  for (int i = 0; i < n; ++i) std::memset(&plans[i], 0, sizeof(plans[i]));
+  if (flags & ~SUBDIV_FLAG_REBUILD_EACH_LEVEL) return SUBDIV_INVALID_ARG;
+  std::vector<Group> gs = make_groups(schemes, levels, n);
+  size_t need = 0;
+  if (!layout_groups(gs, meshes, nullptr, flags, true, &need)) return SUBDIV_INVALID_ARG;
+  if (ws_bytes < need) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  static std::atomic<uint64_t> stamp{1};
-  if (n == 1) {  // a batch of one is the mesh itself: no union, no gather
-    st = subdiv_plan(&meshes[0], scheme, levels, flags, at<void>(ws, b.uws), b.uws_bytes, &bplan->union_plan, stream);
-    if (st != SUBDIV_OK) return st;
-    plans[0] = bplan->union_plan;
-    bplan->num_meshes = 1;
-    bplan->scheme = scheme;
-    bplan->levels = levels;
-    bplan->flags = flags;
-    bplan->workspace_bytes = b.total;
-    bplan->priv_ws = ws;
-    bplan->priv_stamp = stamp++;
-    return SUBDIV_OK;
+  ws_forget_range(ws, ws_bytes);
+  SUBDIV_TRY(init_weight_tables());
+  // every group's symbolic pass is enqueued before the one read-back
+  for (const Group &g : gs) {
+    void *uws = at<void>(ws, g.uws);
+    if (g.single()) {
+      const int i = g.idx[0];
+      Sizes L0[SUBDIV_MAX_LEVELS + 1];
+      level_sizes(g.scheme, 0, g.VU, g.FU, g.HU, g.HU, g.HU, 0, 0.f, g.CU, L0);
+      if ((st = plan_enqueue(&meshes[i], g.scheme, g.levels, uws, make_layout(g.scheme, 0, flags, L0, g.CU), s)) !=
+          SUBDIV_OK)
+        return st;
+      continue;
+    }
+    const std::vector<BatchMesh> desc = batch_descriptors(meshes, g);
+    const int ng = (int)g.idx.size();
+    SUBDIV_TRY(staged_upload(at<void>(ws, g.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
+    const BatchUnion u{at<int32_t>(ws, g.ufv), g.general ? at<int32_t>(ws, g.uoff) : nullptr, at<int32_t>(ws, g.ucv),
+                       at<float>(ws, g.ucs)};
+    long long items = g.HU;
+    items = (g.FU + 1 > items) ? g.FU + 1 : items;
+    items = (g.CU > items) ? g.CU : items;
+    SUBDIV_TRY(batch_concat_topology(at<BatchMesh>(ws, g.desc), ng, u, items, s));
+    const subdiv_mesh um = union_mesh(g, ws);
+    const Layout y0 = make_layout(g.scheme, 0, flags, g.L, g.CU);
+    if ((st = plan_enqueue(&um, g.scheme, g.levels, uws, y0, s)) != SUBDIV_OK) return st;
+    // per-member edge and boundary counts and maxima, from the union's build
+    int32_t *stats = at<int32_t>(ws, g.stats);
+    SUBDIV_TRY(batch_stats(at<BatchMesh>(ws, g.desc), ng, at<int32_t>(uws, y0.ebase), at<int32_t>(uws, y0.bflag),
+                           at<int32_t>(uws, y0.rowptr), g.CU ? at<float>(ws, g.ucs) : nullptr, g.VU, g.HU, g.CU, stats,
+                           stats + ng + 1, stats + 2 * ng + 1, stats + 3 * ng + 1, s));
   }
-  const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
-  SUBDIV_TRY(staged_upload(at<void>(ws, b.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
-  BatchUnion u{at<int32_t>(ws, b.ufv), b.general ? at<int32_t>(ws, b.uoff) : nullptr, at<int32_t>(ws, b.ucv),
-               at<float>(ws, b.ucs)};
-  long long items = b.HU;
-  items = (b.FU + 1 > items) ? b.FU + 1 : items;
-  items = (b.CU > items) ? b.CU : items;
-  SUBDIV_TRY(batch_concat_topology(at<BatchMesh>(ws, b.desc), n, u, items, s));
-  const subdiv_mesh um = union_mesh(b, ws, (int)b.CU);
-  void *uws = at<void>(ws, b.uws);
-  st = subdiv_plan(&um, scheme, levels, flags, uws, b.uws_bytes, &bplan->union_plan, stream);
-  if (st != SUBDIV_OK) return st;
-  // per-mesh edge and boundary counts of the cage, from the union's build
-  Sizes L0[SUBDIV_MAX_LEVELS + 1];
-  level_sizes(scheme, 0, b.VU, b.FU, b.HU, b.HU, b.HU, 0, 0.f, b.CU, L0);
-  const Layout y0 = make_layout(scheme, 0, flags, L0, b.CU);
-  SUBDIV_TRY(batch_stats(at<BatchMesh>(ws, b.desc), n, at<int32_t>(uws, y0.ebase), at<int32_t>(uws, y0.bflag),
-                         bplan->union_plan.level[0].num_edges, at<int32_t>(ws, b.epre), at<int32_t>(ws, b.bcount),
-                         s));
-  std::vector<int32_t> epre((size_t)n + 1), bcount((size_t)n);
-  SUBDIV_TRY(hipMemcpyAsync(epre.data(), at<int32_t>(ws, b.epre), 4 * epre.size(), hipMemcpyDeviceToHost, s));
-  SUBDIV_TRY(hipMemcpyAsync(bcount.data(), at<int32_t>(ws, b.bcount), 4 * bcount.size(), hipMemcpyDeviceToHost, s));
+  std::vector<DeviceInfo> hinfo(gs.size());
+  std::vector<std::vector<int32_t>> hstats(gs.size());
+  for (size_t k = 0; k < gs.size(); ++k) {
+    const Group &g = gs[k];
+    void *uws = at<void>(ws, g.uws);
+    Sizes L0[SUBDIV_MAX_LEVELS + 1];
+    level_sizes(g.scheme, 0, g.VU, g.FU, g.HU, g.HU, g.HU, 0, 0.f, g.CU, L0);
+    const Layout y0 = make_layout(g.scheme, 0, flags, L0, g.CU);
+    SUBDIV_TRY(hipMemcpyAsync(&hinfo[k], at<DeviceInfo>(uws, y0.info), sizeof(DeviceInfo), hipMemcpyDeviceToHost, s));
+    if (!g.single()) {
+      hstats[k].resize(4 * g.idx.size() + 1);
+      SUBDIV_TRY(hipMemcpyAsync(hstats[k].data(), at<int32_t>(ws, g.stats), 4 * hstats[k].size(),
+                                hipMemcpyDeviceToHost, s));
+    }
+  }
   SUBDIV_TRY(hipStreamSynchronize(s));
-  // per-mesh sizes (closed forms)
-  std::vector<Sizes> Lm((size_t)n * (levels + 1));
-  for (int i = 0; i < n; ++i) {
-    Sizes *Li = &Lm[(size_t)i * (levels + 1)];
-    const int oi = meshes[i].face_offsets ? 0 : meshes[i].face_order;
-    level_sizes(scheme, levels, meshes[i].num_vertices, meshes[i].num_faces, cage_H(&meshes[i]),
-                epre[i + 1] - epre[i], bcount[i], oi, bplan->union_plan.max_sharpness, meshes[i].num_creases, Li);
-    subdiv_plan_info &p = plans[i];
-    std::memset(&p, 0, sizeof(p));
-    p.scheme = scheme;
-    p.levels = levels;
-    p.flags = flags;
-    p.max_sharpness = bplan->union_plan.max_sharpness;
-    for (int k = 0; k <= levels; ++k) {
-      subdiv_level_info &li = p.level[k];
-      li.num_vertices = Li[k].V;
-      li.num_edges = Li[k].E;
-      li.num_faces = Li[k].F;
-      li.num_halfedges = Li[k].H;
-      li.num_boundary_edges = Li[k].B;
-      li.face_order = Li[k].order;
+  for (size_t k = 0; k < gs.size(); ++k)
+    if ((st = plan_status(hinfo[k], gs[k].scheme, gs[k].levels)) != SUBDIV_OK) return st;
+  for (size_t k = 0; k < gs.size(); ++k) {
+    const Group &g = gs[k];
+    const int ng = (int)g.idx.size();
+    for (int j = 0; j < ng; ++j) {
+      const int i = g.idx[j];
+      long long E0, B0;
+      int vmax;
+      float smax;
+      if (g.single()) {
+        E0 = hinfo[k].num_edges;
+        B0 = hinfo[k].num_boundary;
+        vmax = hinfo[k].max_valence;
+        std::memcpy(&smax, &hinfo[k].max_sharp_bits, 4);
+      } else {
+        const int32_t *h = hstats[k].data();
+        E0 = h[j + 1] - h[j];
+        B0 = h[ng + 1 + j];
+        vmax = h[2 * ng + 1 + j];
+        std::memcpy(&smax, &h[3 * ng + 1 + j], 4);
+      }
+      if (meshes[i].num_creases == 0) smax = 0.f;
+      if ((st = fill_plan(&plans[i], &meshes[i], g.scheme, g.levels, flags, E0, B0, smax, vmax, nullptr)) !=
+          SUBDIV_OK)
+        return st;
     }
   }
-  // the final gather's tables: block b of the union's level-L vertex ids
-  // lists the meshes in order; mesh i numbers its vertices by its segments
-  // of the blocks in block order
-  const bool has_f = scheme != SUBDIV_LOOP, has_e = scheme != SUBDIV_SQRT3;
-  const int nblk = gather_blocks(scheme, levels), nseg = nblk * n;
-  auto bsize = [&](int blk, int i) -> long long {
-    const Sizes *Li = &Lm[(size_t)i * (levels + 1)];
-    if (blk == 0) return Li[0].V;
-    const int k = (blk - 1) / ((int)has_f + (int)has_e), t = (blk - 1) % ((int)has_f + (int)has_e);
-    return (has_f && t == 0) ? Li[k].F : Li[k].E;
-  };
-  std::vector<int32_t> seg(4 * (size_t)nseg), pch((size_t)nseg + 1, 0), ub((size_t)nblk + 1, 0),
-      doff((size_t)nseg), fpre((size_t)n + 1, 0), fch((size_t)n + 1, 0);
-  std::vector<long long> loc((size_t)n, 0);
-  for (int blk = 0; blk < nblk; ++blk) {
-    long long pre = 0;
-    for (int i = 0; i < n; ++i) {
-      const long long len = bsize(blk, i), x = blk * (long long)n + i;
-      seg[4 * x + 0] = (int32_t)(ub[blk] + pre);
-      seg[4 * x + 1] = i;
-      seg[4 * x + 2] = (int32_t)loc[i];
-      seg[4 * x + 3] = (int32_t)len;
-      doff[x] = (int32_t)(loc[i] - ub[blk] - pre);
-      pch[x + 1] = pch[x] + (int32_t)((len + kGather - 1) / kGather);
-      loc[i] += len;
-      pre += len;
-    }
-    ub[blk + 1] = (int32_t)(ub[blk] + pre);
-  }
-  for (int i = 0; i < n; ++i) {
-    const long long FLi = Lm[(size_t)i * (levels + 1) + levels].F;
-    fpre[i + 1] = fpre[i] + (int32_t)FLi;
-    fch[i + 1] = fch[i] + (int32_t)((FLi + kGather - 1) / kGather);
-  }
-  if (ub[nblk] != bplan->union_plan.level[levels].num_vertices ||
-      fpre[n] != bplan->union_plan.level[levels].num_faces)
-    return SUBDIV_STATE;
-  std::vector<int32_t> tab;
-  tab.reserve(seg.size() + pch.size() + ub.size() + doff.size() + fpre.size() + fch.size());
-  for (const auto *v : {&seg, &pch, &ub, &doff, &fpre, &fch}) tab.insert(tab.end(), v->begin(), v->end());
-  SUBDIV_TRY(staged_upload(at<void>(ws, b.tables), tab.data(), 4 * tab.size(), s));
-  bplan->num_meshes = n;
-  bplan->scheme = scheme;
-  bplan->levels = levels;
-  bplan->flags = flags;
-  bplan->workspace_bytes = b.total;
-  bplan->priv_ws = ws;
-  bplan->priv_stamp = stamp++;
-  bplan->priv_gather[0] = fch[n];
-  bplan->priv_gather[1] = pch[nseg];
-  bplan->priv_gather[2] = nblk;
+  ws_forget_range(ws, ws_bytes);
   return SUBDIV_OK;
 }
 
-int subdiv_refine_batch(const subdiv_mesh *meshes, int n, const subdiv_batch_plan *bplan, subdiv_level_out *outs,
-                        void *ws, size_t ws_bytes, void *stream) {
-  if (!bplan || !outs || !ws) return SUBDIV_INVALID_ARG;
-  int st = check_batch_args(meshes, n, bplan->scheme, bplan->levels);
+int subdiv_refine_batch(const subdiv_mesh *meshes, const int *schemes, const int *levels, int n,
+                        const subdiv_plan_info *plans, subdiv_level_out *outs, void *ws, size_t ws_bytes,
+                        void *stream) {
+  if (!plans || !outs || !ws) return SUBDIV_INVALID_ARG;
+  int st = check_batch_args(meshes, schemes, levels, n);
   if (st != SUBDIV_OK) return st;
-  if (bplan->priv_stamp == 0 || n != bplan->num_meshes || ws != bplan->priv_ws) return SUBDIV_STATE;
-  if (ws_bytes < bplan->workspace_bytes) return SUBDIV_WORKSPACE;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
+    if (!member_plan_ok(plans[i], meshes[i], schemes[i], levels[i])) return SUBDIV_STATE;
     if (!outs[i].face_verts || !outs[i].positions || reinterpret_cast<uintptr_t>(outs[i].face_verts) % 16 != 0)
       return SUBDIV_INVALID_ARG;
-  BatchLayout b;
-  if (!batch_layout(meshes, n, bplan->scheme, bplan->levels, bplan->flags, b)) return SUBDIV_INVALID_ARG;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (n == 1) {  // the mesh itself, straight into its outputs
-    subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
-    uo[bplan->levels].face_verts = outs[0].face_verts;
-    uo[bplan->levels].positions = outs[0].positions;
-    return subdiv_refine(&meshes[0], &bplan->union_plan, uo, at<void>(ws, b.uws), b.uws_bytes, stream);
   }
-  // pointer tables: the meshes (positions may have moved) and the outputs
-  const std::vector<BatchMesh> desc = batch_descriptors(meshes, n);
-  std::vector<BatchOut> ot((size_t)n);
-  for (int i = 0; i < n; ++i) ot[i] = BatchOut{outs[i].face_verts, outs[i].positions};
-  SUBDIV_TRY(staged_upload(at<void>(ws, b.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
-  SUBDIV_TRY(staged_upload(at<void>(ws, b.outtab), ot.data(), sizeof(BatchOut) * ot.size(), s));
-  SUBDIV_TRY(batch_concat_positions(at<BatchMesh>(ws, b.desc), n, at<float>(ws, b.uP), b.VU, s));
-  const subdiv_mesh um = union_mesh(b, ws, (int)b.CU);
-  const int L = bplan->levels;
-  subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
-  uo[L].face_verts = at<int32_t>(ws, b.fvL);
-  uo[L].positions = at<float>(ws, b.PL);
-  st = subdiv_refine(&um, &bplan->union_plan, uo, at<void>(ws, b.uws), b.uws_bytes, stream);
-  if (st != SUBDIV_OK) return st;
-  BatchTables t{};
-  t.n = n;
-  t.order = bplan->scheme == SUBDIV_CATMULL_CLARK ? 4 : 3;
-  t.nblk = bplan->priv_gather[2];
-  t.nseg = t.nblk * n;
-  const int32_t *tb = at<int32_t>(ws, b.tables);
-  t.seg = reinterpret_cast<const int4 *>(tb);
-  t.pch = tb + 4ll * t.nseg;
-  t.ub = t.pch + t.nseg + 1;
-  t.doff = t.ub + t.nblk + 1;
-  t.fpre = t.doff + t.nseg;
-  t.fch = t.fpre + n + 1;
-  SUBDIV_TIMED("batch_extract", L,
-               batch_extract(t, at<int32_t>(ws, b.fvL), at<float>(ws, b.PL), at<BatchOut>(ws, b.outtab),
-                             bplan->priv_gather[0], bplan->priv_gather[1], s));
+  const uint32_t flags = plans[0].flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL;
+  std::vector<Group> gs = make_groups(schemes, levels, n);
+  size_t need = 0;
+  if (!layout_groups(gs, meshes, plans, flags, false, &need)) return SUBDIV_INVALID_ARG;
+  if (ws_bytes < need) return SUBDIV_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ws_forget_range(ws, ws_bytes);
+  SUBDIV_TRY(init_weight_tables());
+  for (const Group &g : gs) {
+    const int L = g.levels, ng = (int)g.idx.size();
+    void *uws = at<void>(ws, g.uws);
+    // every member's sizes for its level count (its plan may cover more levels)
+    std::vector<Sizes> LS((size_t)ng * (L + 1));
+    for (int j = 0; j < ng; ++j) {
+      const subdiv_plan_info &p = plans[g.idx[j]];
+      const subdiv_mesh &mj = meshes[g.idx[j]];
+      level_sizes(g.scheme, L, mj.num_vertices, mj.num_faces, cage_H(&mj), p.level[0].num_edges,
+                  p.level[0].num_boundary_edges, mj.face_offsets ? 0 : mj.face_order, p.max_sharpness, mj.num_creases,
+                  &LS[(size_t)j * (L + 1)]);
+    }
+    if (g.single()) {
+      // the mesh itself, straight into its outputs, with its plan for this level count
+      const int i = g.idx[0];
+      subdiv_plan_info p;
+      if ((st = fill_plan(&p, &meshes[i], g.scheme, L, flags, plans[i].level[0].num_edges,
+                          plans[i].level[0].num_boundary_edges, plans[i].max_sharpness, plans[i].max_valence,
+                          nullptr)) != SUBDIV_OK)
+        return st;
+      subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
+      uo[L].face_verts = outs[i].face_verts;
+      uo[L].positions = outs[i].positions;
+      if ((st = refine_impl(&meshes[i], &p, uo, uws, g.uws_bytes, s)) != SUBDIV_OK) return st;
+      continue;
+    }
+    const std::vector<BatchMesh> desc = batch_descriptors(meshes, g);
+    std::vector<BatchOut> ot((size_t)ng);
+    for (int j = 0; j < ng; ++j) ot[j] = BatchOut{outs[g.idx[j]].face_verts, outs[g.idx[j]].positions};
+    GatherPlan gp;
+    if (!gather_plan(g, LS, gp)) return SUBDIV_STATE;
+    SUBDIV_TRY(staged_upload(at<void>(ws, g.desc), desc.data(), sizeof(BatchMesh) * desc.size(), s));
+    SUBDIV_TRY(staged_upload(at<void>(ws, g.outtab), ot.data(), sizeof(BatchOut) * ot.size(), s));
+    SUBDIV_TRY(staged_upload(at<void>(ws, g.tables), gp.tab.data(), 4 * gp.tab.size(), s));
+    const BatchUnion u{at<int32_t>(ws, g.ufv), g.general ? at<int32_t>(ws, g.uoff) : nullptr, at<int32_t>(ws, g.ucv),
+                       at<float>(ws, g.ucs)};
+    long long items = g.HU;
+    items = (g.FU + 1 > items) ? g.FU + 1 : items;
+    items = (g.CU > items) ? g.CU : items;
+    SUBDIV_TRY(batch_concat_topology(at<BatchMesh>(ws, g.desc), ng, u, items, s));
+    SUBDIV_TRY(batch_concat_positions(at<BatchMesh>(ws, g.desc), ng, at<float>(ws, g.uP), g.VU, s));
+    // the union's plan from its members' counts (a disjoint union of valid
+    // cages is valid); refine_impl builds its cage adjacency in uws
+    const subdiv_mesh um = union_mesh(g, ws);
+    float smax = 0.f;
+    int vmax = 0;
+    for (const int i : g.idx) {
+      smax = plans[i].max_sharpness > smax ? plans[i].max_sharpness : smax;
+      vmax = plans[i].max_valence > vmax ? plans[i].max_valence : vmax;
+    }
+    subdiv_plan_info up;
+    if ((st = fill_plan(&up, &um, g.scheme, L, flags, g.L[0].E, g.L[0].B, smax, vmax, nullptr)) != SUBDIV_OK)
+      return st;
+    subdiv_level_out uo[SUBDIV_MAX_LEVELS + 1] = {};
+    uo[L].face_verts = at<int32_t>(ws, g.fvL);
+    uo[L].positions = at<float>(ws, g.PL);
+    if ((st = refine_impl(&um, &up, uo, uws, g.uws_bytes, s)) != SUBDIV_OK) return st;
+    BatchTables t{};
+    t.n = ng;
+    t.order = g.scheme == SUBDIV_CATMULL_CLARK ? 4 : 3;
+    t.nblk = gp.nblk;
+    t.nseg = t.nblk * ng;
+    const int32_t *tb = at<int32_t>(ws, g.tables);
+    t.seg = reinterpret_cast<const int4 *>(tb);
+    t.pch = tb + 4ll * t.nseg;
+    t.ub = t.pch + t.nseg + 1;
+    t.doff = t.ub + t.nblk + 1;
+    t.fpre = t.doff + t.nseg;
+    t.fch = t.fpre + ng + 1;
+    SUBDIV_TIMED("batch_extract", L,
+                 batch_extract(t, at<int32_t>(ws, g.fvL), at<float>(ws, g.PL), at<BatchOut>(ws, g.outtab),
+                               gp.face_chunks, gp.vertex_chunks, s));
+  }
   return SUBDIV_OK;
 }
 

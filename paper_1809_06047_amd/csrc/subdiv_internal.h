@@ -334,8 +334,11 @@ struct BatchOut {
 };
 hipError_t batch_concat_topology(const BatchMesh *m, int n, const BatchUnion &u, long long items, hipStream_t s);
 hipError_t batch_concat_positions(const BatchMesh *m, int n, float *P, long long V, hipStream_t s);
-hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, long long E,
-                       int32_t *epre, int32_t *bcount, hipStream_t s);
+// per-mesh edge prefix [n+1], boundary edges, largest valence and largest
+// crease sharpness (float bits) [n] each; bcount, vmax, smax consecutive
+hipError_t batch_stats(const BatchMesh *m, int n, const int32_t *ebase, const int32_t *bflag, const int32_t *rowptr,
+                       const float *cs, long long VU, long long HU, long long CU, int32_t *epre, int32_t *bcount,
+                       int32_t *vmax, int32_t *smax, hipStream_t s);
 hipError_t batch_extract(const BatchTables &t, const int32_t *fvL, const float *PL, const BatchOut *out,
                          int face_chunks, int vertex_chunks, hipStream_t s);
 

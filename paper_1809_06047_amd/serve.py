@@ -4,24 +4,26 @@ A request is a cage (a meshgen.Mesh), a scheme and a level count; its result
 is the final level's face table and positions, left resident on the device.
 
 Scheduler (`Server`, host logic only):
-  * arrivals join a first-in first-out queue;
-  * whenever an execution slot is free, the oldest queued request picks the
-    group (scheme, levels); the longest run of that group's queued requests,
-    in arrival order and at most `max_batch` long, whose device footprint
-    fits the part of the HBM budget not held by batches in flight, is
-    admitted as one batch;
-  * a batch is one subdiv_plan_batch + subdiv_refine_batch on the slot's
-    stream: every stage is one launch over all of its meshes, and every
-    mesh's output is bitwise the one it gets when refined alone;
+  * arrivals join a first-in first-out queue (the executor prepares them:
+    on the GPU, a cage topology seen for the first time is uploaded and
+    planned once, and every request takes its level sizes from that plan);
+  * whenever an execution slot is free, the longest prefix of the queue, at
+    most `max_batch` requests and `max_batch_faces` output faces, whose
+    device footprint fits the part of the HBM budget not held by batches in
+    flight, is admitted as one batch -- requests of every scheme and level
+    count together, strictly in arrival order;
+  * a batch is one subdiv_refine_batch on the executor's stream: the library
+    groups it by (scheme, levels), every group runs one launch per stage,
+    and every mesh's output is bitwise the one it gets when refined alone;
   * its requests complete when the batch's completion event has fired;
   * a request whose footprint alone exceeds the whole budget is rejected; a
     launch that runs out of device memory puts its requests back and retries
     with half the batch once memory has been released.
 Latency = completion - arrival, on the host clock.
 
-Footprint of a batch = the library's workspace bound for the union of its
-cages + the device copy of the cages + every request's final-level face
-table and positions (exact level sizes from the cage's edge count).
+Footprint of a batch = the library's exact workspace size for it (from the
+members' plans) + the device copy of its positions + every request's
+final-level face table and positions (level sizes from the plans).
 
 Baseline (`serve_per_mesh`): the same trace served first-in first-out with
 one plan + refine per request on one stream.
@@ -29,6 +31,7 @@ one plan + refine per request on one stream.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import time
@@ -65,62 +68,6 @@ class Request:
         return self.done - self.arrival
 
 
-_EDGE_CACHE: Dict[int, tuple] = {}
-
-
-def edge_count(mesh) -> int:
-    """Undirected edges of a cage (cached per face table object: the
-    serving cages of one frequency share their topology arrays)."""
-    key = id(mesh.verts)
-    hit = _EDGE_CACHE.get(key)
-    if hit is not None and hit[0] is mesh.verts:
-        return hit[1]
-    v = np.asarray(mesh.verts, np.int64)
-    if mesh.offsets is None:
-        f = v.reshape(-1, int(mesh.face_order))
-        nxt = np.roll(f, -1, axis=1).reshape(-1)
-    else:
-        off = np.asarray(mesh.offsets, np.int64)
-        cnt = np.diff(off)
-        face = np.repeat(np.arange(cnt.size), cnt)
-        slot = np.arange(v.size) - off[face]
-        nxt = v[off[face] + (slot + 1) % cnt[face]]
-    lo, hi = np.minimum(v, nxt), np.maximum(v, nxt)
-    E = int(np.unique(hi * (int(v.max()) + 1) + lo).size)
-    _EDGE_CACHE[key] = (mesh.verts, E)
-    return E
-
-
-def final_sizes(V: int, F: int, H: int, E: int, scheme: str, levels: int):
-    """(V, F, H, E) of the refined level `levels` from the cage's counts.
-    Catmull-Clark: one vertex per vertex, face and edge; one quad per
-    half-edge; every edge splits in two and every half-edge adds one edge
-    inside its face. Loop: one vertex per vertex and edge; four triangles per
-    triangle; 2E + 3F edges. sqrt(3): one vertex per vertex and face; three
-    triangles per triangle; every edge stays (flipped or on the boundary) and
-    every face adds three."""
-    for _ in range(levels):
-        if scheme == "cc":
-            V, F, H, E = V + F + E, H, 4 * H, 2 * E + H
-        elif scheme == "loop":
-            V, F, E = V + E, 4 * F, 2 * E + 3 * F
-            H = 3 * F
-        elif scheme == "sqrt3":
-            V, F, E = V + F, 3 * F, E + 3 * F
-            H = 3 * F
-        else:
-            raise ValueError(scheme)
-    return V, F, H, E
-
-
-def request_bytes(mesh, scheme: str, levels: int) -> tuple:
-    """(io bytes, final faces): cage arrays in, final face table + positions out."""
-    V, F, H, C = mesh.num_vertices, mesh.num_faces, mesh.num_halfedges, mesh.num_creases
-    VL, FL, HL, _ = final_sizes(V, F, H, edge_count(mesh), scheme, levels)
-    cage = 4 * H + 12 * V + 12 * C + (4 * (F + 1) if mesh.offsets is not None else 0)
-    return cage + 4 * HL + 12 * VL, FL
-
-
 # ---------------------------------------------------------------------------
 # the scheduler
 # ---------------------------------------------------------------------------
@@ -139,12 +86,13 @@ class _Inflight:
 
 class Server:
     """Continuous batching over an executor with the interface
-    prepare(req), footprint_fn(reqs, scheme, levels) -> f(k) (bytes of the
-    batch reqs[:k], non-decreasing in k, INF when it cannot be planned),
-    launch(reqs, scheme, levels, slot) -> handle (may raise ExecutorOOM),
-    done(handle) -> bool, results(handle) -> list of per-request outputs
-    (called only when results are kept), retire(handle) (the batch's memory
-    may be released once the outputs taken from it are dropped)."""
+    prepare(reqs) (sets r.footprint and r.final_faces of newly arrived
+    requests), footprint_fn(reqs) -> f(k) (bytes of the batch reqs[:k],
+    non-decreasing in k, INF when it cannot be planned), launch(reqs, slot)
+    -> handle (may raise ExecutorOOM), done(handle) -> bool,
+    results(handle) -> list of per-request outputs (called only when
+    results are kept), retire(handle) (the batch's memory may be released
+    once the outputs taken from it are dropped)."""
 
     def __init__(self, executor, hbm_budget: int, slots: int = 1, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
@@ -163,17 +111,21 @@ class Server:
         self.on_complete: Optional[Callable[[Request], None]] = None
         self.stats: Dict = {}
 
-    # the longest admissible run of the head request's group
+    # the longest admissible prefix of the queue
     def _form(self, queue: deque, avail: int):
-        head = queue[0]
-        key = (head.scheme, head.levels)
-        cands = [r for r in queue if (r.scheme, r.levels) == key][: self._cap]
-        faces = np.cumsum([r.final_faces for r in cands])
-        cands = cands[: max(1, int(np.searchsorted(faces, self.max_batch_faces, side="right")))]
-        f = self.ex.footprint_fn(cands, head.scheme, head.levels)
+        cands = []
+        faces = 0
+        for r in queue:
+            if len(cands) == self._cap or (cands and faces + r.final_faces > self.max_batch_faces):
+                break
+            cands.append(r)
+            faces += r.final_faces
+        f = self.ex.footprint_fn(cands)
         if f(1) > avail:
             return None, f(1)
         lo, hi = 1, len(cands)  # f(lo) <= avail
+        if f(hi) <= avail:
+            return cands, f(hi)
         while lo < hi:
             mid = (lo + hi + 1) // 2
             if f(mid) <= avail:
@@ -196,12 +148,13 @@ class Server:
         t0 = self.clock()
         while i < n or queue or any(b is not None for b in inflight):
             now = self.clock() - t0
-            while i < n and reqs[i].arrival <= now:
-                r = reqs[i]
-                r.footprint, r.final_faces = request_bytes(r.mesh, r.scheme, r.levels)
-                self.ex.prepare(r)
-                queue.append(r)
-                i += 1
+            j = i
+            while j < n and reqs[j].arrival <= now:
+                j += 1
+            if j > i:
+                self.ex.prepare(reqs[i:j])
+                queue.extend(reqs[i:j])
+                i = j
             st["max_queue"] = max(st["max_queue"], len(queue))
             progressed = False
             # retire finished batches
@@ -236,7 +189,7 @@ class Server:
                         continue
                     break  # wait for memory
                 try:
-                    h = self.ex.launch(batch, batch[0].scheme, batch[0].levels, free[0])
+                    h = self.ex.launch(batch, free[0])
                 except ExecutorOOM:
                     st["oom_retries"] += 1
                     if any(b is not None for b in inflight):
@@ -250,8 +203,8 @@ class Server:
                         st["rejected"] += 1
                     progressed = True
                     continue
-                ids = {id(r) for r in batch}
-                queue = deque(r for r in queue if id(r) not in ids)
+                for _ in range(len(batch)):  # the batch is a prefix of the queue
+                    queue.popleft()
                 for r in batch:
                     r.batch = nbatch
                 inflight[free[0]] = _Inflight(batch, h, int(fp), nbatch)
@@ -302,140 +255,141 @@ def reserve(device, nbytes: int, stream=None):
         del x
 
 
-def _packed(mesh) -> tuple:
-    """One int32 array holding a cage's face table, column pointer, crease
-    pairs, positions and sharpness (float bits), every part starting on a
-    16-byte boundary; returns (array, part offsets in ints)."""
-    parts = [np.ascontiguousarray(mesh.verts, np.int32).reshape(-1)]
-    parts.append(None if mesh.offsets is None else np.ascontiguousarray(mesh.offsets, np.int32).reshape(-1))
-    parts.append(np.ascontiguousarray(mesh.crease_verts, np.int32).reshape(-1) if mesh.num_creases else None)
-    parts.append(np.ascontiguousarray(mesh.positions, np.float32).reshape(-1).view(np.int32))
-    parts.append(np.ascontiguousarray(mesh.crease_sharp, np.float32).reshape(-1).view(np.int32)
-                 if mesh.num_creases else None)
-    offs, chunks, at = [], [], 0
-    for x in parts:
-        if x is None:
-            offs.append(-1)
-            continue
-        offs.append(at)
-        pad = (-x.size) % 4
-        chunks.append(x)
-        if pad:
-            chunks.append(np.zeros(pad, np.int32))
-        at += x.size + pad
-    return np.concatenate(chunks), offs
+class _Cage:
+    """A cage topology the executor has seen: its device arrays (face table,
+    column pointer, creases; the positions of the request that brought it)
+    and the library's plan of it for `levels` levels, whose counts size every
+    level of every later request with this topology."""
+
+    def __init__(self, dmesh, plan, levels: int):
+        self.dmesh = dmesh
+        self.plan = plan
+        self.levels = levels
 
 
 class GpuBatchExecutor:
-    """Runs each batch through the library's batch entry points (all streams
-    at the default priority): one upload of the packed cages, one workspace,
-    one allocation per output kind.
+    """Runs each batch as one subdiv_refine_batch on one stream (default
+    priority); batches in flight queue behind each other on it, so the host
+    forms and enqueues the next batch while the previous one runs.
 
-    one_refine_stream=False: every slot plans and refines on its own stream.
-    one_refine_stream=True: plans go to a plan stream and every refinement to
-    one refine stream, so with two slots the next batch is uploaded and
-    planned while the previous one refines, and its refinement queues behind
-    it instead of running beside it. A batch's cage upload and workspace are
-    allocated for the plan stream and its outputs for the refine stream; all
-    of them are released only after the batch has retired."""
+    Cages are keyed by their host face-table object and scheme. A topology
+    seen for the first time is uploaded and planned once (subdiv_plan_batch
+    over every new cage of an arrival burst: one read-back for all of them,
+    on a stream of its own); the plans then give every later request its
+    level sizes and let subdiv_refine_batch run without any host round
+    trip. A batch uploads only its positions (one pinned copy) and allocates
+    one workspace and one output block per kind, released after it retires."""
 
-    def __init__(self, device="cuda", slots: int = 1, reserve_bytes: int = 0, one_refine_stream: bool = False):
+    def __init__(self, device="cuda", reserve_bytes: int = 0, plan_levels: int = 4):
         import torch
-        from . import _lib
-        self.torch = torch
-        self._lib = _lib
+        from . import _lib, api
+        self.torch, self._lib, self.api = torch, _lib, api
         self.lib = _lib.load()
         self.device = torch.device(device)
-        self.one_refine_stream = one_refine_stream
-        if one_refine_stream:
-            self.plan_stream = torch.cuda.Stream(self.device)
-            self.refine_stream = torch.cuda.Stream(self.device)
-            for s in (self.plan_stream, self.refine_stream):
-                reserve(self.device, reserve_bytes, s)
-        else:
-            self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
-            for s in self.streams:
-                reserve(self.device, reserve_bytes, s)
+        self.stream = torch.cuda.Stream(self.device)
+        self.reg_stream = torch.cuda.Stream(self.device)
+        self.plan_levels = int(plan_levels)
+        self.cages: Dict[tuple, _Cage] = {}
+        self._keep_alive: Dict[tuple, object] = {}
+        self.registered = 0
+        reserve(self.device, reserve_bytes, self.stream)
 
-    def prepare(self, r: Request):
-        m = r.mesh
-        r.meta["packed"] = _packed(m)
-        s = self._lib.subdiv_mesh()
-        s.num_vertices, s.num_faces, s.num_halfedges = m.num_vertices, m.num_faces, m.num_halfedges
-        s.face_order = 0 if m.offsets is not None else m.face_order
-        s.face_offsets = 16 if m.offsets is not None else None  # sizes only: never dereferenced
-        s.face_verts = s.positions = 16
-        s.num_creases = m.num_creases
-        if m.num_creases:
-            s.crease_verts = s.crease_sharpness = 16
-        r.meta["shape"] = s
+    @staticmethod
+    def _key(r):
+        return (id(r.mesh.verts), r.scheme)
 
-    def footprint_fn(self, reqs, scheme, levels):
-        structs = (self._lib.subdiv_mesh * len(reqs))(*[r.meta["shape"] for r in reqs])
+    def _register(self, reqs):
+        torch, L, api = self.torch, self._lib, self.api
+        new, seen = [], set()
+        for r in reqs:
+            k = self._key(r)
+            c = self.cages.get(k)
+            if (c is None or c.levels < r.levels) and k not in seen:
+                seen.add(k)
+                new.append(r)
+        if not new:
+            return
+        levels = [max(self.plan_levels, r.levels) for r in new]
+        with torch.cuda.stream(self.reg_stream):
+            dms = [api.DeviceMesh(r.mesh, self.device) for r in new]
+            b = api.BatchRefiner(dms, [r.scheme for r in new], levels)
+            b.plan(stream=self.reg_stream.cuda_stream)
+        for r, dm, lv, k in zip(new, dms, levels, range(len(new))):
+            p = L.subdiv_plan_info()
+            ctypes_copy(p, b.plans[k])
+            self.cages[self._key(r)] = _Cage(dm, p, lv)
+            self._keep_alive[self._key(r)] = r.mesh.verts  # the key's id stays this array's
+        self.registered += len(new)
+
+    def prepare(self, reqs):
+        self._register(reqs)
+        for r in reqs:
+            c = self.cages[self._key(r)]
+            li = c.plan.level[r.levels]
+            r.meta["cage"] = c
+            r.final_faces = int(li.num_faces)
+            # positions in, final face table and positions out
+            r.footprint = 12 * r.mesh.num_vertices + 4 * int(li.num_halfedges) + 12 * int(li.num_vertices)
+
+    def _arrays(self, reqs):
+        L = self._lib
+        n = len(reqs)
+        structs = (L.subdiv_mesh * n)(*[r.meta["cage"].dmesh.struct for r in reqs])
+        sc = (ctypes.c_int * n)(*[L.SCHEMES[r.scheme] for r in reqs])
+        lv = (ctypes.c_int * n)(*[r.levels for r in reqs])
+        plans = (L.subdiv_plan_info * n)(*[r.meta["cage"].plan for r in reqs])
+        return structs, sc, lv, plans
+
+    def footprint_fn(self, reqs):
+        structs, sc, lv, plans = self._arrays(reqs)
         io = np.cumsum([r.footprint for r in reqs])
-        sid = self._lib.SCHEMES[scheme]
         lib = self.lib
 
         def f(k: int):
-            ws = int(lib.subdiv_batch_workspace_bound(structs, k, sid, levels, 0))
+            ws = int(lib.subdiv_batch_workspace_bound(structs, sc, lv, k, plans, 0))
             return INF if ws == 0 else ws + int(io[k - 1])
         return f
 
-    def launch(self, reqs, scheme, levels, slot):
-        import ctypes
+    def launch(self, reqs, slot):
         torch, L, lib = self.torch, self._lib, self.lib
-        if self.one_refine_stream:
-            s, rs = self.plan_stream, self.refine_stream
-        else:
-            s = rs = self.streams[slot]
         n = len(reqs)
-        sid = L.SCHEMES[scheme]
+        structs, sc, lv, plans = self._arrays(reqs)
         try:
-            with torch.cuda.stream(s):
-                host = np.concatenate([r.meta["packed"][0] for r in reqs])
-                dev = torch.from_numpy(host).to(self.device)
-                base = dev.data_ptr()
-                structs = (L.subdiv_mesh * n)()
-                at = 0
+            with torch.cuda.stream(self.stream):
+                nv = [r.mesh.num_vertices for r in reqs]
+                vofs = np.concatenate([[0], np.cumsum(nv)])
+                host = torch.empty(3 * int(vofs[-1]), dtype=torch.float32, pin_memory=True)
+                hn = host.numpy()
                 for k, r in enumerate(reqs):
-                    arr, offs = r.meta["packed"]
-                    structs[k] = r.meta["shape"]
-                    st = structs[k]  # a view into the array
-                    st.face_verts = base + 4 * (at + offs[0])
-                    st.face_offsets = None if offs[1] < 0 else base + 4 * (at + offs[1])
-                    st.crease_verts = None if offs[2] < 0 else base + 4 * (at + offs[2])
-                    st.positions = base + 4 * (at + offs[3])
-                    st.crease_sharpness = None if offs[4] < 0 else base + 4 * (at + offs[4])
-                    at += arr.size
-                ws_bytes = int(lib.subdiv_batch_workspace_bound(structs, n, sid, levels, 0))
+                    hn[3 * int(vofs[k]):3 * int(vofs[k + 1])] = np.asarray(r.mesh.positions, np.float32).reshape(-1)
+                dev = torch.empty(hn.size, dtype=torch.float32, device=self.device)
+                dev.copy_(host, non_blocking=True)
+                base = dev.data_ptr()
+                for k in range(n):
+                    structs[k].positions = base + 12 * int(vofs[k])
+                ws_bytes = int(lib.subdiv_batch_workspace_bound(structs, sc, lv, n, plans, 0))
                 if ws_bytes == 0:
                     raise L.SubdivError(L.INVALID_ARG, "subdiv_batch_workspace_bound")
                 ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
-                bplan = L.subdiv_batch_plan()
-                plans = (L.subdiv_plan_info * n)()
-                L.check(lib.subdiv_plan_batch(structs, n, sid, levels, 0, ctypes.c_void_p(ws.data_ptr()), ws_bytes,
-                                              ctypes.byref(bplan), plans, ctypes.c_void_p(s.cuda_stream)),
-                        "subdiv_plan_batch")
-            # (the plan read back on s: its work is done before the refinement below starts)
-            with torch.cuda.stream(rs):
                 # outputs: one int32 and one float32 allocation, every face table 16-byte aligned
-                hs = [int(plans[k].level[levels].num_halfedges) for k in range(n)]
-                vs = [int(plans[k].level[levels].num_vertices) for k in range(n)]
+                hs = [int(plans[k].level[reqs[k].levels].num_halfedges) for k in range(n)]
+                vs = [int(plans[k].level[reqs[k].levels].num_vertices) for k in range(n)]
                 hofs = np.concatenate([[0], np.cumsum([(h + 3) // 4 * 4 for h in hs])])
-                vofs = np.concatenate([[0], np.cumsum(vs)])
+                pofs = np.concatenate([[0], np.cumsum(vs)])
                 fv = torch.empty(int(hofs[-1]), dtype=torch.int32, device=self.device)
-                P = torch.empty((int(vofs[-1]), 3), dtype=torch.float32, device=self.device)
+                P = torch.empty((int(pofs[-1]), 3), dtype=torch.float32, device=self.device)
                 outs = (L.subdiv_level_out * n)()
                 for k in range(n):
                     outs[k].face_verts = fv.data_ptr() + 4 * int(hofs[k])
-                    outs[k].positions = P.data_ptr() + 12 * int(vofs[k])
-                L.check(lib.subdiv_refine_batch(structs, n, ctypes.byref(bplan), outs, ctypes.c_void_p(ws.data_ptr()),
-                                                ws_bytes, ctypes.c_void_p(rs.cuda_stream)), "subdiv_refine_batch")
+                    outs[k].positions = P.data_ptr() + 12 * int(pofs[k])
+                L.check(lib.subdiv_refine_batch(structs, sc, lv, n, plans, outs, ctypes.c_void_p(ws.data_ptr()),
+                                                ws_bytes, ctypes.c_void_p(self.stream.cuda_stream)),
+                        "subdiv_refine_batch")
                 ev = torch.cuda.Event()
-                ev.record(rs)
+                ev.record(self.stream)
         except torch.cuda.OutOfMemoryError as e:
             raise ExecutorOOM(str(e)) from e
-        return dict(ev=ev, keep=(dev, ws, fv, P), hofs=hofs, hs=hs, vofs=vofs)
+        return dict(ev=ev, keep=(dev, ws, fv, P, host), hofs=hofs, hs=hs, pofs=pofs)
 
     def done(self, h) -> bool:
         return h["ev"].query()
@@ -443,10 +397,15 @@ class GpuBatchExecutor:
     def results(self, h):
         fv, P = h["keep"][2], h["keep"][3]
         return [{"face_verts": fv[int(h["hofs"][k]):int(h["hofs"][k]) + h["hs"][k]],
-                 "positions": P[int(h["vofs"][k]):int(h["vofs"][k + 1])]} for k in range(len(h["hs"]))]
+                 "positions": P[int(h["pofs"][k]):int(h["pofs"][k + 1])]} for k in range(len(h["hs"]))]
 
     def retire(self, h):
         h.clear()
+
+
+def ctypes_copy(dst, src):
+    """Byte copy of one ctypes structure into another of the same type."""
+    ctypes.memmove(ctypes.addressof(dst), ctypes.addressof(src), ctypes.sizeof(dst))
 
 
 def serve_per_mesh(requests: List[Request], device="cuda", clock=time.perf_counter, sleep=time.sleep,
@@ -461,8 +420,8 @@ def serve_per_mesh(requests: List[Request], device="cuda", clock=time.perf_count
         while clock() - t0 < r.arrival:  # same idle policy as the server: sleep, then spin
             gap = r.arrival - (clock() - t0)
             sleep(min(gap - 200e-6, 1e-3) if gap > 200e-6 else 0.0)
-        r.footprint, r.final_faces = request_bytes(r.mesh, r.scheme, r.levels)
-        outs, _ = refine(r.mesh, r.scheme, r.levels, device=device)
+        outs, rf = refine(r.mesh, r.scheme, r.levels, device=device)
+        r.final_faces = int(rf.plan_info.level[r.levels].num_faces)
         r.done = clock() - t0
         r.result = outs[r.levels] if keep_results else None
     torch.cuda.synchronize(device)
@@ -494,55 +453,76 @@ def _retime(reqs: List[Request], base_times: np.ndarray, qps: float) -> List[Req
 
 def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), seed: int = 4, budget_gib: float = 64.0,
           slots: int = 2, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
-          log=print, one_refine_stream: bool = True) -> Dict:
+          log=print, cold_factor: Optional[float] = 1.0) -> Dict:
     """Measure the per-mesh-launch saturation rate, then serve the trace at
-    each factor x that rate with the batched server and the baseline. By
-    default two batches are in flight: the next one is uploaded and planned
-    while the previous one refines, and refinements run one after the other
-    on one stream."""
+    each factor x that rate with the batched server and the baseline.
+
+    The batched server's topology cache is warm for the timed points: a
+    warm-up serves one request of every (scheme, levels) group, the head of
+    the trace, and one request of every cage topology the trace holds, so
+    every later request is refined from its topology's kept plan. At
+    `cold_factor` (if not None) the trace is served once more by a server
+    whose cache starts empty: there the first request of each topology pays
+    its registration plan (one read-back) inside its latency."""
     import torch
     trace = make_trace(n_requests, seed=seed, qps=1.0)
     base_t = np.array([r.arrival for r in trace])
     # both servers start from an allocator that already holds the memory a
-    # large request needs (one segment per stream they use)
-    reserve_bytes = int(min(budget_gib, 8.0) * 2**30) // max(1, slots)
+    # large request needs
+    reserve_bytes = int(min(budget_gib, 8.0) * 2**30)
     reserve(device, reserve_bytes)
-    ex = GpuBatchExecutor(device, slots, reserve_bytes, one_refine_stream=one_refine_stream)
-    # warm-up of both paths: one request of every (scheme, levels) group and
-    # the head of the trace, all arriving at once
-    seen, warm = set(), []
+    budget = int(budget_gib * 2**30)
+    ex = GpuBatchExecutor(device, reserve_bytes)
+    # warm-up of both paths: one request of every (scheme, levels) group, the
+    # head of the trace, and (batched server) every topology, all at t = 0
+    seen, warm, topo = set(), [], set()
     for r in trace:
         if (r.scheme, r.levels) not in seen:
             seen.add((r.scheme, r.levels))
             warm.append(r)
     warm += trace[:min(64, n_requests)]
-    Server(ex, int(budget_gib * 2**30), slots, max_batch).run(_retime(warm, np.zeros(len(warm)), 1.0))
-    serve_per_mesh(_retime(warm, np.zeros(len(warm)), 1.0), device)
+    for r in trace:
+        if (id(r.mesh.verts), r.scheme) not in topo:
+            topo.add((id(r.mesh.verts), r.scheme))
+            warm.append(r)
+    Server(ex, budget, slots, max_batch).run(_retime(warm, np.zeros(len(warm)), 1.0))
+    serve_per_mesh(_retime(warm[:64], np.zeros(min(64, len(warm))), 1.0), device)
     # saturation of the baseline: everything arrives at t = 0
     ns = min(n_requests, sat_requests or n_requests)
     sat_reqs = _retime(trace[:ns], np.zeros(ns), 1.0)
     sat = serve_per_mesh(sat_reqs, device)
     sat_qps = ns / sat["makespan"]
-    log(f"[serve] per-mesh saturation {sat_qps:.1f} req/s over {ns} requests")
-    points = []
-    for fac in factors:
-        qps = fac * sat_qps
+    log(f"[serve] per-mesh saturation {sat_qps:.1f} req/s over {ns} requests; {len(topo)} cage topologies")
+
+    def batched(qps, executor):
         rb = _retime(trace, base_t, qps)
-        srv = Server(ex, int(budget_gib * 2**30), slots, max_batch)
+        srv = Server(executor, budget, slots, max_batch)
         torch.cuda.reset_peak_memory_stats(device)
         st = srv.run(rb)
         b = summarize(rb, st["makespan"])
         b.update(batches=st["batches"], mean_batch=float(np.mean(st["batch_sizes"])) if st["batch_sizes"] else 0.0,
                  max_queue=st["max_queue"], peak_admitted_gib=st["peak_admitted_bytes"] / 2**30,
                  peak_allocated_gib=torch.cuda.max_memory_allocated(device) / 2**30)
+        return b
+
+    points = []
+    for fac in factors:
+        qps = fac * sat_qps
+        b = batched(qps, ex)
         rp = _retime(trace, base_t, qps)
         sp = serve_per_mesh(rp, device)
         p = summarize(rp, sp["makespan"])
         points.append(dict(factor=fac, qps=qps, batched=b, per_mesh=p))
-        log(f"[serve] x{fac}: {qps:.0f} req/s batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms "
-            f"(mean batch {b['mean_batch']:.1f}) | per-mesh p50 {p['p50_ms']:.2f} p99 {p['p99_ms']:.2f} ms")
+        log(f"[serve] x{fac}: {qps:.0f} req/s batched p50 {b['p50_ms']:.3f} p99 {b['p99_ms']:.3f} ms "
+            f"(mean batch {b['mean_batch']:.1f}) | per-mesh p50 {p['p50_ms']:.3f} p99 {p['p99_ms']:.3f} ms")
+    cold = None
+    if cold_factor is not None:
+        cex = GpuBatchExecutor(device, 0)
+        cold = dict(factor=cold_factor, batched=batched(cold_factor * sat_qps, cex), registered=cex.registered)
+        log(f"[serve] x{cold_factor} cold cache: p50 {cold['batched']['p50_ms']:.3f} "
+            f"p99 {cold['batched']['p99_ms']:.3f} ms ({cex.registered} topologies registered in the trace)")
     return dict(requests=n_requests, seed=seed, budget_gib=budget_gib, slots=slots, max_batch=max_batch,
-                per_mesh_saturation_qps=sat_qps, points=points)
+                topologies=len(topo), per_mesh_saturation_qps=sat_qps, points=points, cold_cache=cold)
 
 
 def main(argv=None):
@@ -551,8 +531,7 @@ def main(argv=None):
     ap.add_argument("--factors", default="0.5,0.8,1.0,1.2,1.5,2,3")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=64.0)
-    ap.add_argument("--slots", type=int, default=1,
-                    help="batches in flight at once (one: a second concurrent batch only slows the first)")
+    ap.add_argument("--slots", type=int, default=2, help="batches in flight at once (queued on one stream)")
     ap.add_argument("--max-batch", type=int, default=256)
     a = ap.parse_args(argv)
     res = sweep(a.requests, tuple(float(x) for x in a.factors.split(",")), a.seed, a.budget_gib, a.slots,

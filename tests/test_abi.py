@@ -116,11 +116,88 @@ def test_creases_by_scheme_without_device(lib):
     m.crease_verts = m.crease_sharpness = 16
     assert lib.subdiv_plan(ctypes.byref(m), 2, 1, 0, None, 0, ctypes.byref(info), None) == _lib.INVALID_ARG
     arr = (_lib.subdiv_mesh * 1)(m)
-    assert lib.subdiv_batch_workspace_bound(arr, 1, 1, 1, 0) == 0      # Loop batch with creases
-    assert lib.subdiv_batch_workspace_bound(arr, 1, 2, 1, 0) == 0      # sqrt(3) batch with creases
+    one = (ctypes.c_int * 1)(1)
+    loop, sqrt3 = (ctypes.c_int * 1)(1), (ctypes.c_int * 1)(2)
+    assert lib.subdiv_batch_workspace_bound(arr, loop, one, 1, None, 0) == 0     # Loop batch with creases
+    assert lib.subdiv_batch_workspace_bound(arr, sqrt3, one, 1, None, 0) == 0    # sqrt(3) batch with creases
     m.num_creases = 0
     m.crease_verts = m.crease_sharpness = None
     arr = (_lib.subdiv_mesh * 1)(m)
-    assert lib.subdiv_batch_workspace_bound(arr, 1, 1, 1, 0) > 0
+    assert lib.subdiv_batch_workspace_bound(arr, loop, one, 1, None, 0) > 0
     # the bound of a creased Loop cage covers the crease tables of every level
     assert lib.subdiv_workspace_bound(3, 1, 3, 1, 1, 3, 0) > lib.subdiv_workspace_bound(3, 1, 3, 0, 1, 3, 0)
+
+
+def test_state_calls_need_a_refinement_in_that_workspace(lib):
+    """A plan that keeps its state, but with no subdiv_refine enqueued into
+    the workspace (the order plan, then backward / positions / vertex data):
+    the library's host-side record of the workspace has no kept state, so
+    every call that reads it returns SUBDIV_STATE before any device work
+    (the never-written level tables would otherwise be read as indices).
+    subdiv_state_destroy knows no state there either."""
+    info = _lib.subdiv_plan_info()
+    info.levels, info.scheme, info.flags = 2, 0, 2   # Catmull-Clark, SUBDIV_FLAG_KEEP_STATE
+    info.priv_stamp = 1 << 60                        # looks planned; no such plan ever ran
+    m = _lib.subdiv_mesh()
+    m.num_vertices, m.num_faces, m.face_order = 4, 1, 4
+    m.face_verts = m.positions = 16                  # never dereferenced
+    info.priv_mesh_verts = 16
+    ws = ctypes.c_void_p(1 << 20)
+    info.priv_ws = ws.value
+    outs = (_lib.subdiv_level_out * 3)()
+    outs[2].positions = 16
+    assert lib.subdiv_backward(ctypes.byref(m), ctypes.byref(info), ws, ws, ws, 1 << 30, None) == _lib.STATE
+    assert lib.subdiv_refine_positions(ctypes.byref(m), ctypes.byref(info), outs, ws, 1 << 30, None) == _lib.STATE
+    assert lib.subdiv_refine_vertex_data(ctypes.byref(m), ctypes.byref(info), ws, 3, ws, ws, 1 << 30, None) == \
+        _lib.STATE
+    sel = _lib.subdiv_selection()
+    assert lib.subdiv_select(ctypes.byref(m), ctypes.byref(info), None, 1, ws, 1 << 30, ctypes.byref(sel),
+                             None) == _lib.STATE
+    assert lib.subdiv_state_destroy(ctypes.byref(info), ws) == _lib.STATE
+    assert lib.subdiv_state_destroy(None, ws) == _lib.INVALID_ARG
+    assert lib.subdiv_state_destroy(ctypes.byref(info), None) == _lib.INVALID_ARG
+
+
+def test_batch_arguments_without_device(lib):
+    """Per-mesh schemes and level counts: the host-only bound grows with
+    either, rejects bad entries, and a mismatched member plan (never made,
+    another cage) is refused before any device work."""
+    tri = _lib.subdiv_mesh()
+    tri.num_vertices, tri.num_faces, tri.face_order = 4, 4, 3
+    tri.face_verts = tri.positions = 16
+    quad = _lib.subdiv_mesh()
+    quad.num_vertices, quad.num_faces, quad.face_order = 8, 6, 4
+    quad.face_verts = quad.positions = 32
+    arr = (_lib.subdiv_mesh * 3)(tri, quad, tri)
+    sc = (ctypes.c_int * 3)(1, 0, 2)
+    lv = (ctypes.c_int * 3)(2, 3, 1)
+    b = lib.subdiv_batch_workspace_bound(arr, sc, lv, 3, None, 0)
+    assert b > 0
+    lv2 = (ctypes.c_int * 3)(2, 4, 1)
+    assert lib.subdiv_batch_workspace_bound(arr, sc, lv2, 3, None, 0) > b
+    bad = (ctypes.c_int * 3)(1, 0, 3)
+    assert lib.subdiv_batch_workspace_bound(arr, bad, lv, 3, None, 0) == 0      # scheme out of range
+    assert lib.subdiv_batch_workspace_bound(arr, sc, (ctypes.c_int * 3)(2, 0, 1), 3, None, 0) == 0   # 0 levels
+    assert lib.subdiv_batch_workspace_bound(arr, sc, lv, 3, None, 4) == 0       # KEEP_STATE is not for batches
+    plans = (_lib.subdiv_plan_info * 3)()
+    assert lib.subdiv_batch_workspace_bound(arr, sc, lv, 3, plans, 0) == 0      # never planned
+    outs = (_lib.subdiv_level_out * 3)()
+    for o in outs:
+        o.face_verts = o.positions = 64
+    assert lib.subdiv_refine_batch(arr, sc, lv, 3, plans, outs, ctypes.c_void_p(1 << 20), 1 << 30, None) == \
+        _lib.STATE
+    for i, (m, s, l) in enumerate([(tri, 1, 2), (quad, 0, 3), (tri, 2, 1)]):
+        p = plans[i]
+        p.priv_stamp, p.priv_mesh_verts, p.scheme, p.levels = 1 << 61, m.face_verts, s, l
+        p.level[0].num_vertices, p.level[0].num_faces = m.num_vertices, m.num_faces
+        p.level[0].num_halfedges = m.num_faces * m.face_order
+    plans[1].levels = 2                                                          # fewer levels than asked for
+    assert lib.subdiv_refine_batch(arr, sc, lv, 3, plans, outs, ctypes.c_void_p(1 << 20), 1 << 30, None) == \
+        _lib.STATE
+    plans[1].levels = 3
+    plans[2].priv_mesh_verts = 48                                                # another cage
+    assert lib.subdiv_refine_batch(arr, sc, lv, 3, plans, outs, ctypes.c_void_p(1 << 20), 1 << 30, None) == \
+        _lib.STATE
+    plans[2].priv_mesh_verts = 16
+    assert lib.subdiv_refine_batch(arr, sc, lv, 3, plans, outs, ctypes.c_void_p(1 << 20), 16, None) == \
+        _lib.WORKSPACE

@@ -155,3 +155,32 @@ def test_backward_coefficients_once_per_plan():
     np.testing.assert_array_equal(e, f)
     # every row of R sums to one, so a gradient of ones sums to the refined vertex count
     assert abs(float(e.sum()) - 3 * r2.level_info(3)["V"]) <= 1e-3 * 3 * r2.level_info(3)["V"]
+
+
+def test_state_calls_follow_the_workspace_record():
+    """The order plan -> backward (no refinement yet) is refused with
+    SUBDIV_STATE before any device work; after a run the state calls work;
+    after subdiv_state_destroy (Refiner.release) they are refused again, and
+    a new run brings the state back with the same gradient bits."""
+    m = G.cc_cage(seed=2, level=2)
+    r = api.Refiner(m, "cc", 2, flags=_lib.FLAG_KEEP_STATE)
+    r.plan()
+    V2 = r.plan_info.level[2].num_vertices
+    g = torch.linspace(-1, 1, V2 * 3, device="cuda").reshape(V2, 3)
+    for call in (lambda: r.backward(g), r.run_positions,
+                 lambda: r.run_vertex_data(torch.ones((m.num_vertices, 2), device="cuda"))):
+        with pytest.raises(_lib.SubdivError) as e:
+            call()
+        assert e.value.status == _lib.STATE
+    r.run()
+    g1 = r.backward(g).clone()
+    torch.cuda.synchronize()
+    assert r.release()
+    with pytest.raises(_lib.SubdivError) as e:
+        r.backward(g)
+    assert e.value.status == _lib.STATE
+    assert not r.release()
+    r.run()
+    g2 = r.backward(g)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)

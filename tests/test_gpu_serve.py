@@ -8,6 +8,7 @@ import torch
 from paper_1809_06047_amd import api
 from paper_1809_06047_amd import meshgen as G
 from paper_1809_06047_amd import serve as S
+from tests.parity_util import POS_TOL, normwise_err
 
 pytestmark = pytest.mark.gpu
 
@@ -19,21 +20,22 @@ def _trace(n, seed, tmax=3000.0):
         sc = "cc" if k % 2 == 0 else "loop"
         T = float(np.exp(rng.uniform(np.log(100.0), np.log(tmax))))
         reqs.append(S.Request(rid=k, arrival=float(k) * 1e-4, mesh=G.serving_cage(T, sc, rng), scheme=sc,
-                              levels=int(rng.integers(1, 4))))
+                              levels=int(rng.integers(1, 5))))
     return reqs
 
 
-@pytest.mark.parametrize("one_refine_stream", [False, True])
-def test_batched_server_outputs_equal_solo_refinement(one_refine_stream):
-    """Two batches in flight, each on its own stream or (two deep) planned on
-    a plan stream while the previous one refines on the shared refine stream."""
+def test_batched_server_outputs_equal_solo_refinement(oracle_mod):
+    """Batches mix schemes and level counts (levels 1-4, so Loop at level 4
+    runs its last two steps from the level below them); every request's
+    result equals, bit for bit, a solo plan + refine of its cage, and every
+    third one the oracle within the positions tolerance."""
     reqs = _trace(48, 21)
-    print(f"[serve] 48 requests, one refine stream {one_refine_stream}, "
-          f"faces {[r.mesh.num_faces for r in reqs[:6]]}...", flush=True)
-    srv = S.Server(S.GpuBatchExecutor("cuda", 2, one_refine_stream=one_refine_stream), 8 * 2**30, slots=2,
-                   max_batch=16, keep_results=True)
+    print(f"[serve] 48 requests, faces {[r.mesh.num_faces for r in reqs[:6]]}...", flush=True)
+    ex = S.GpuBatchExecutor("cuda")
+    srv = S.Server(ex, 8 * 2**30, slots=2, max_batch=16, keep_results=True)
     st = srv.run(reqs)
     assert st["rejected"] == 0 and st["batches"] < len(reqs)
+    assert ex.registered <= len(reqs)
     torch.cuda.synchronize()
     for r in reqs:
         outs, _ = api.refine(r.mesh, r.scheme, r.levels)
@@ -41,12 +43,16 @@ def test_batched_server_outputs_equal_solo_refinement(one_refine_stream):
         assert torch.equal(r.result["face_verts"], solo["face_verts"]), r.rid
         assert torch.equal(r.result["positions"], solo["positions"]), r.rid
         assert r.final_faces == solo["face_verts"].numel() // (4 if r.scheme == "cc" else 3)
+        if r.rid % 3 == 0:
+            ref = oracle_mod.refine(r.mesh, r.scheme, r.levels)[r.levels]
+            np.testing.assert_array_equal(r.result["face_verts"].cpu().numpy(), ref.verts)
+            assert normwise_err(r.result["positions"].cpu().numpy(), ref.positions) <= POS_TOL, r.rid
 
 
 def test_per_mesh_baseline_matches_batched():
     reqs = _trace(12, 22)
     base = [S.Request(rid=r.rid, arrival=r.arrival, mesh=r.mesh, scheme=r.scheme, levels=r.levels) for r in reqs]
-    S.Server(S.GpuBatchExecutor("cuda", 1), 4 * 2**30, slots=1, keep_results=True).run(reqs)
+    S.Server(S.GpuBatchExecutor("cuda"), 4 * 2**30, slots=1, keep_results=True).run(reqs)
     S.serve_per_mesh(base, keep_results=True)
     for a, b in zip(reqs, base):
         assert torch.equal(a.result["positions"], b.result["positions"]), a.rid
@@ -55,6 +61,7 @@ def test_per_mesh_baseline_matches_batched():
 
 def test_sweep_runs_end_to_end():
     res = S.sweep(n_requests=32, factors=(1.0,), budget_gib=8.0, sat_requests=16, log=lambda s: print(s, flush=True))
+    assert res["cold_cache"]["batched"]["served"] == 32
     (p,) = res["points"]
     assert res["per_mesh_saturation_qps"] > 0
     for side in ("batched", "per_mesh"):
