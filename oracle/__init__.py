@@ -25,7 +25,11 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CATMULL_CLARK, LOOP, SQRT3 = 0, 1, 2
-SCHEMES = {"cc": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3}
+# sqrt(3) with Kobbelt's two-step boundary cycle: the sqrt(3) step (fixed
+# boundary) from even levels, the trisection step (code 3) from odd ones
+SQRT3_KOBBELT = 3
+TRISECT_STEP = 3
+SCHEMES = {"cc": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3, "sqrt3k": SQRT3_KOBBELT}
 
 
 def build(force: bool = True) -> str:
@@ -153,11 +157,14 @@ def step(lvl: Level, scheme: int, want_R: bool = False) -> Level:
 
 def refine(mesh, scheme, levels: int, want_R: bool = False) -> List[Level]:
     """Levels 0..levels of the refinement of a float32 cage (level 0 = the
-    cage in FP64). scheme: 0/1/2 or 'cc'/'loop'/'sqrt3'."""
+    cage in FP64). scheme: 0/1/2/3 or 'cc'/'loop'/'sqrt3'/'sqrt3k' (sqrt(3)
+    with Kobbelt's boundary cycle: levels 1, 3, ... by the sqrt(3) step,
+    levels 2, 4, ... by the trisection step)."""
     s = SCHEMES.get(scheme, scheme)
     out = [level_from_mesh(mesh) if not isinstance(mesh, Level) else mesh]
-    for _ in range(levels):
-        out.append(step(out[-1], s, want_R))
+    for k in range(levels):
+        sk = s if s != SQRT3_KOBBELT else (SQRT3 if k % 2 == 0 else TRISECT_STEP)
+        out.append(step(out[-1], sk, want_R))
     return out
 
 

@@ -27,6 +27,12 @@
 //   Loop ........................... App. B, eq:loop_smooth and beta, the
 //                                    1-to-4 split
 //   single-SpMV matrix R_k ......... Sec. 3.6 (P_{i+1} = R_i P_i)
+//   sqrt(3) boundary ............... App. A leaves the boundary to Kobbelt's
+//                                    sqrt(3) paper: a two-step cycle whose
+//                                    second step trisects the boundary
+//                                    (scheme code 3 below, the "trisection
+//                                    step"; the first step of the cycle is
+//                                    the sqrt(3) step with fixed boundary)
 //
 // Readings where the paper is silent (each listed in the design notes):
 //   * 0-based ids; -1 = "no face".
@@ -49,6 +55,21 @@
 //     in FP64 with the fixed order 0.25*(si + 3.0*sj) - 1.0 (no contraction,
 //     this file is compiled with -ffp-contract=off); a child is kept iff > 0.
 //   * Invalid inputs are rejected (status codes below) instead of refined.
+//   * sqrt(3) trisection step (the second step of Kobbelt's boundary cycle;
+//     the paper defers the boundary rule to that work, so every detail here
+//     is a reading): every face has at most one boundary edge (true after a
+//     first step, whose boundary faces are (v_j, v_j+1, face point)). A
+//     boundary face r with boundary edge j = (u, w) gets no face point;
+//     instead its edge is trisected by p (near u, index |v| + r) and q (near
+//     w, index |v| + |f| + rank of r among the boundary faces). Its children
+//     are 3r+j = (p, q, v_j+2), 3r+j+1 = (v_j+1, X, q), 3r+j+2 = (v_j+2, X, p);
+//     p and q stand in for the missing face point wherever a neighbour's
+//     flipped edge would reach it (q across edge j+1, p across edge j+2).
+//     Boundary points follow the ternary subdivision of a uniform cubic
+//     B-spline curve (mask [1 4 10 16 19 16 10 4 1] / 27): p = (u- + 16 u +
+//     10 w) / 27, q = (10 u + 16 w + w+) / 27, old boundary vertex
+//     (4 a + 19 v + 4 b) / 27 over its boundary neighbours; interior
+//     vertices and face points as in the sqrt(3) step.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -58,7 +79,7 @@
 
 namespace {
 
-enum Scheme { CATMULL_CLARK = 0, LOOP = 1, SQRT3 = 2 };
+enum Scheme { CATMULL_CLARK = 0, LOOP = 1, SQRT3 = 2, SQRT3_TRISECT = 3 };
 
 // Fault flags; the reported status is the first set flag in this order.
 enum Fault {
@@ -325,6 +346,38 @@ struct Result {
   std::vector<double> r_val;
 };
 
+// Boundary faces of a trisection step: slot of the face's boundary edge (or
+// -1) and the face's rank among the boundary faces (face order). Faults when
+// a face has more than one boundary edge.
+struct BoundaryFaces {
+  std::vector<int> slot, rank;
+  int count = 0;
+  unsigned faults = 0;
+};
+BoundaryFaces boundary_faces(const Level& L, const Adjacency& A) {
+  BoundaryFaces b;
+  b.slot.assign(L.nf(), -1);
+  b.rank.assign(L.nf(), -1);
+  for (int r = 0; r < L.nf(); ++r) {
+    int n = 0;
+    for (int h = L.off[r]; h < L.off[r + 1]; ++h) {
+      const int e = A.he_eid[h];
+      if (A.e_he1[e] < 0) {
+        b.slot[r] = h - L.off[r];
+        ++n;
+      }
+    }
+    if (n > 1) b.faults |= F_INVALID_ARG;
+    if (n == 1) b.rank[r] = b.count++;
+  }
+  return b;
+}
+
+// the boundary neighbour of boundary vertex v other than w
+int other_boundary_nbr(const Adjacency& A, int v, int w) {
+  return A.bnd.at(v, 0) == w ? A.bnd.at(v, 1) : A.bnd.at(v, 0);
+}
+
 template <class T>
 struct Evaluator {
   // Vertex data of the refined level, from vertex data of this level.
@@ -478,6 +531,40 @@ struct Evaluator {
         acc(smooth, 0.125, P[opposite(A.e_he1[e])]);
         crease_edge(sig[e], smooth, P[a], P[b], ep);
       }
+    } else if (scheme == SQRT3_TRISECT) {
+      const BoundaryFaces bf = boundary_faces(L, A);
+      const std::vector<T> f = face_points(P);
+      out.resize((size_t)V + F + bf.count);
+      for (int v = 0; v < V; ++v) {
+        T& S = out[v];
+        if (A.bnd.size(v) > 0) {  // ternary cubic B-spline rule on the boundary polygon
+          acc(S, 4.0 / 27.0, P[A.bnd.at(v, 0)]);
+          acc(S, 19.0 / 27.0, P[v]);
+          acc(S, 4.0 / 27.0, P[A.bnd.at(v, 1)]);
+          continue;
+        }
+        const double n = (double)A.nbrs.size(v);
+        const double alpha = (4.0 - 2.0 * std::cos(2.0 * M_PI / n)) / 9.0;
+        acc(S, 1.0 - alpha, P[v]);
+        for (const int* w = A.nbrs.begin(v); w != A.nbrs.end(v); ++w) acc(S, alpha / n, P[*w]);
+      }
+      for (int r = 0; r < F; ++r) {
+        if (bf.slot[r] < 0) {
+          out[(size_t)V + r] = f[r];
+          continue;
+        }
+        const int j = bf.slot[r];
+        const int u = L.fv[L.off[r] + j], w = L.fv[L.off[r] + (j + 1) % 3];
+        const int um = other_boundary_nbr(A, u, w), wp = other_boundary_nbr(A, w, u);
+        T& p = out[(size_t)V + r];
+        acc(p, 1.0 / 27.0, P[um]);
+        acc(p, 16.0 / 27.0, P[u]);
+        acc(p, 10.0 / 27.0, P[w]);
+        T& q = out[(size_t)V + F + bf.rank[r]];
+        acc(q, 10.0 / 27.0, P[u]);
+        acc(q, 16.0 / 27.0, P[w]);
+        acc(q, 1.0 / 27.0, P[wp]);
+      }
     } else {  // SQRT3
       const std::vector<T> f = face_points(P);
       out.resize((size_t)V + F);
@@ -570,6 +657,49 @@ void refine_topology(int scheme, const Level& L, const Adjacency& A, const std::
       t[2] = e[2];
     }
     inherit_creases(V, V, A, sig, R);
+  } else if (scheme == SQRT3_TRISECT) {
+    const BoundaryFaces bf = boundary_faces(L, A);
+    O.nv = V + F + bf.count;
+    O.off.resize((size_t)3 * F + 1);
+    O.fv.resize((size_t)9 * F);
+    for (int i = 0; i <= 3 * F; ++i) O.off[i] = 3 * i;
+    // the point of face s that its neighbour across s's edge i links to: the
+    // face point, or on a boundary face q (edge j+1) or p (edge j+2)
+    auto link = [&](int s, int i) {
+      const int js = bf.slot[s];
+      if (js < 0) return V + s;
+      return i == (js + 1) % 3 ? V + F + bf.rank[s] : V + s;
+    };
+    for (int r = 0; r < F; ++r) {
+      const int b = L.off[r];
+      int X[3];  // across edge i: the neighbour's linked point (boundary edge: unused)
+      for (int i = 0; i < 3; ++i) {
+        const int e = A.he_eid[b + i];
+        const int other = A.e_he0[e] == b + i ? A.e_he1[e] : A.e_he0[e];
+        X[i] = other >= 0 ? link(A.he_face[other], other - L.off[A.he_face[other]]) : -1;
+      }
+      const int j = bf.slot[r];
+      for (int i = 0; i < 3; ++i) {
+        int* t = &O.fv[(size_t)3 * (b + i)];
+        if (j < 0) {
+          t[0] = L.fv[b + i];
+          t[1] = X[i];
+          t[2] = V + r;
+        } else if (i == j) {  // (p, q, v_j+2)
+          t[0] = V + r;
+          t[1] = V + F + bf.rank[r];
+          t[2] = L.fv[b + (j + 2) % 3];
+        } else if (i == (j + 1) % 3) {  // (v_j+1, X, q)
+          t[0] = L.fv[b + i];
+          t[1] = X[i];
+          t[2] = V + F + bf.rank[r];
+        } else {  // (v_j+2, X, p)
+          t[0] = L.fv[b + i];
+          t[1] = X[i];
+          t[2] = V + r;
+        }
+      }
+    }
   } else {
     O.nv = V + F;
     O.off.resize((size_t)3 * F + 1);
@@ -602,7 +732,7 @@ void* oracle_step(int scheme, int nv, int nf, const int* off, const int* fv, con
   Result* R = new Result();
   R->scheme = scheme;
   unsigned faults = 0;
-  if (scheme < 0 || scheme > 2 || nv < 0 || nf < 0 || nc < 0) faults |= F_INVALID_ARG;
+  if (scheme < 0 || scheme > 3 || nv < 0 || nf < 0 || nc < 0) faults |= F_INVALID_ARG;
   Level L;
   L.nv = nv;
   if (!faults) {
@@ -616,7 +746,8 @@ void* oracle_step(int scheme, int nv, int nf, const int* off, const int* fv, con
     if (scheme != CATMULL_CLARK) {
       for (int f = 0; f < nf; ++f)
         if (L.off[f + 1] - L.off[f] != 3) faults |= F_SCHEME_MESH;
-      if (nc > 0 && scheme == SQRT3) faults |= F_INVALID_ARG;  // creases: Catmull-Clark and Loop
+      if (nc > 0 && (scheme == SQRT3 || scheme == SQRT3_TRISECT))
+        faults |= F_INVALID_ARG;  // creases: Catmull-Clark and Loop
     }
   }
   Adjacency A;
@@ -625,6 +756,7 @@ void* oracle_step(int scheme, int nv, int nf, const int* off, const int* fv, con
     A = analyse(L);
     faults |= A.faults;
   }
+  if (!faults && scheme == SQRT3_TRISECT) faults |= boundary_faces(L, A).faults;
   if (!faults) {
     std::vector<Crease> cr;
     for (int i = 0; i < nc; ++i) {
