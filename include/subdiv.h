@@ -162,6 +162,29 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* ---- refinement in the library's own workspace -------------------------
+ * For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * subdiv_refine with the workspace taken from a device array the library
+ * holds for the life of the process, SUBDIV_STATIC_WORKSPACE_BYTES on every
+ * GPU it runs on (each device has its own copy; its address is looked up
+ * once per device, on the first call with that device current). The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * The caller still passes the mesh, a plan from subdiv_plan (made with any
+ * workspace; the cage adjacency is built again in the library's workspace
+ * unless the previous call on this device refined the same plan) and the
+ * outputs, as for subdiv_refine. Every call on a GPU shares that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Returns SUBDIV_WORKSPACE when plan->workspace_bytes exceeds the array
+ * (subdiv_last_error() then names both sizes), SUBDIV_INVALID_ARG for a plan
+ * made with SUBDIV_FLAG_KEEP_STATE (its state would live in memory the
+ * caller cannot pass to subdiv_backward), and otherwise what subdiv_refine
+ * returns. Enqueues work only. */
+#define SUBDIV_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int subdiv_refine_static(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs,
+                         void *stream);
+
 /* Adjoint of the refinement (reverse mode; Catmull-Clark). Refinement is
  * linear in the vertex data, P_L = R P_0 with R = R_{L-1} ... R_0 fixed by
  * the topology and creases (Sec. 3.6, eq:singleSpMV), so
@@ -374,7 +397,8 @@ int subdiv_timing_read(subdiv_stage_time *out, int max_out);
  * again. Process-wide, like subdiv_timing_enable. */
 void subdiv_timing_select(const char *stage, int level);
 
-/* HIP error text of the last SUBDIV_HIP status on this thread ("" if none). */
+/* HIP error text of the last SUBDIV_HIP status on this thread, or the sizes
+ * behind the last SUBDIV_WORKSPACE of subdiv_refine_static ("" if none). */
 const char *subdiv_last_error(void);
 
 /* Human-readable name of a status code. */

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsubdiv.so")
 CATMULL_CLARK, LOOP, SQRT3 = 0, 1, 2
 SCHEMES = {"cc": CATMULL_CLARK, "catmull-clark": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3}
 
+STATIC_WORKSPACE_BYTES = 64 << 20  # SUBDIV_STATIC_WORKSPACE_BYTES
 OK, INVALID_ARG, SCHEME_MESH, NONMANIFOLD, DEGENERATE, BAD_CREASE, WORKSPACE, HIP, STATE = 0, -1, -2, -3, -4, -5, \
     -6, -7, -8
 MAX_LEVELS = 10
@@ -68,6 +69,8 @@ SIGNATURES = {
                                    ctypes.POINTER(subdiv_plan_info), c_vp]),
     "subdiv_refine": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                      ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
+    "subdiv_refine_static": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
+                                            ctypes.POINTER(subdiv_level_out), c_vp]),
     "subdiv_refine_positions": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                                ctypes.POINTER(subdiv_level_out), c_vp, c_sz, c_vp]),
     "subdiv_refine_vertex_data": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
@@ -122,7 +125,7 @@ class SubdivError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         lib = load()
         msg = lib.subdiv_strerror(status).decode()
-        if status == HIP:
+        if status in (HIP, WORKSPACE) and lib.subdiv_last_error():
             msg += ": " + lib.subdiv_last_error().decode()
         super().__init__(f"{where}: status {status} ({msg})")
         self.status = status

@@ -160,6 +160,17 @@ class Refiner:
         check(st, "subdiv_refine")
         return self.outs
 
+    def run_static(self, stream=None):
+        """The refinement in the library's own device workspace
+        (subdiv_refine_static): same outputs as run(), nothing allocated by the
+        call; the plan may come from any workspace."""
+        lib = load()
+        s = current_stream_handle(self.dmesh.device) if stream is None else stream
+        st = lib.subdiv_refine_static(ctypes.byref(self.dmesh.struct), ctypes.byref(self.plan_info),
+                                      self._outs_struct, ctypes.c_void_p(s))
+        check(st, "subdiv_refine_static")
+        return self.outs
+
     def run_positions(self, stream=None):
         """Static topology: refine the cage's current positions again with the
         kept state of the last run (plan with FLAG_KEEP_STATE, Catmull-Clark);

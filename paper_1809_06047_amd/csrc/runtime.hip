@@ -781,6 +781,60 @@ int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_
 
 }  // extern "C"
 
+// ---- the library's own workspace, for callers that cannot allocate -------
+// A file-scope device array: each GPU the library runs on holds its own copy
+// from the load of the code object until the process ends. Host code never
+// passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): the first call on a device, with that
+// device current, asks HIP for the array's address there and keeps it.
+namespace {
+__device__ __align__(256) unsigned char scratch[SUBDIV_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_workspace(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return SUBDIV_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!ptr) return SUBDIV_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SUBDIV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int subdiv_refine_static(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs,
+                         void *stream) {
+  if (!plan || !outs) return SUBDIV_INVALID_ARG;
+  // the kept state would live where the caller cannot name it
+  if (plan->flags & SUBDIV_FLAG_KEEP_STATE) return SUBDIV_INVALID_ARG;
+  if (plan->priv_stamp == 0) return SUBDIV_STATE;
+  if (plan->workspace_bytes > SUBDIV_STATIC_WORKSPACE_BYTES) {
+    g_last_error = "plan needs " + std::to_string(plan->workspace_bytes) + " workspace bytes; the static workspace holds " +
+                   std::to_string((size_t)SUBDIV_STATIC_WORKSPACE_BYTES);
+    return SUBDIV_WORKSPACE;
+  }
+  void *ws = nullptr;
+  int st = static_workspace(&ws);
+  if (st != SUBDIV_OK) return st;
+  st = refine_impl(mesh, plan, outs, ws, SUBDIV_STATIC_WORKSPACE_BYTES, stream);
+  if (st == SUBDIV_HIP) ws_planned(ws, 0);
+  return st;
+}
+
+}  // extern "C"
+
 namespace {
 int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                 size_t ws_bytes, void *stream) {
