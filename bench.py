@@ -39,7 +39,8 @@ HBM_PEAK_GBS = 8000.0
 #   cc_edge_group per parent edge   : write 4 edge points 48 + read and write the edge-point
 #                                     vertex 12 + 12                                         = 72 B
 # Per parent quad (V ~ F, E ~ 2F): 392 + 24 + 144 = 560 B = 35 B per refined face.
-BYTES_PER_UNIT = {"cc_group": ("F", 392), "cc_old_vertex": ("V", 24), "cc_edge_group": ("E", 72)}
+BYTES_PER_UNIT = {"cc_group": lambda m: 392 * m["F"], "cc_old_vertex": lambda m: 24 * m["V"],
+                  "cc_edge_group": lambda m: 72 * m["E"]}
 
 # HBM bytes per launch of the dominant kernel from the committed rocprofv3
 # counter passes (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
@@ -175,10 +176,16 @@ def main():
         r.plan()
         r.run()
     torch.cuda.synchronize()
-    all_stages = _lib.timing_read()
+    krecs = _lib.timing_read_kernels()
     _lib.timing_enable(False)
+    all_stages = {}
+    for stage, level, _, _, _, n, ms in krecs:
+        n0, t0 = all_stages.get((stage, level), (0, 0.0))
+        all_stages[(stage, level)] = (n0 + n, t0 + ms)
     cand = {k: v for k, v in all_stages.items() if k[0] in BYTES_PER_UNIT}
     dname, dlevel = max(cand.items(), key=lambda kv: kv[1][1])[0]
+    dkern = [(kern, items, block) for stage, level, kern, items, block, _, _ in krecs
+             if (stage, level) == (dname, dlevel)]
     device_ms = sum(v[1] for v in all_stages.values()) / calib
 
     # the same steps one after the other on one stream (reported beside the
@@ -213,12 +220,17 @@ def main():
     value = faces_out / (ms_per_step / 1000.0)
 
     launches, total_ms = stages[(dname, dlevel)]
-    unit_key, per_unit = BYTES_PER_UNIT[dname]
-    units = info[dlevel - 1][unit_key]  # one thread per element of the parent level
+    nbytes = BYTES_PER_UNIT[dname](info[dlevel - 1])  # one thread per element of the parent level
     avg_ms = total_ms / launches
-    achieved = per_unit * units / (avg_ms / 1000.0) / 1e9
+    achieved = nbytes / (avg_ms / 1000.0) / 1e9
     alone_ms = all_stages[(dname, dlevel)][1] / all_stages[(dname, dlevel)][0]
-    alone_gbs = per_unit * units / (alone_ms / 1000.0) / 1e9
+    alone_gbs = nbytes / (alone_ms / 1000.0) / 1e9
+    # the whole last step (every stage of level L-1 -> L) against the step's
+    # compulsory bytes: read M_{L-1} and P_{L-1}, write M_L and P_L
+    k_info = info[L - 1]
+    step_bytes = 16 * k_info["F"] + 12 * k_info["V"] + 16 * info[L]["F"] + 12 * info[L]["V"]
+    step_ms = sum(v[1] for kk, v in all_stages.items() if kk[1] == L - 1) / calib
+    step_gbs = step_bytes / (step_ms / 1000.0) / 1e9
 
     out = {
         "metric": METRIC,
@@ -252,13 +264,20 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dname, dlevel),
             "avg_launch_ms": round(avg_ms, 5),
-            "algorithmic_bytes_per_launch": per_unit * units,
+            "algorithmic_bytes_per_launch": nbytes,
             # the timed steps run two deep, so the other slot's small levels and
             # plan share the GPU with this kernel; the same kernel in the
             # calibration steps, one step at a time on one stream:
             "alone": {"avg_launch_ms": round(alone_ms, 5), "achieved": round(alone_gbs, 1),
                       "frac": round(alone_gbs / HBM_PEAK_GBS, 4)},
         },
+        "tuning": {"table": os.path.relpath(_lib.tuning_source(), ROOT) if os.path.isabs(_lib.tuning_source())
+                   else _lib.tuning_source(),
+                   "dominant_kernel": [{"kernel": k, "items": n, "block": b} for k, n, b in dkern]},
+        "last_step": {"levels": f"{L - 1} -> {L}", "device_ms": round(step_ms, 5), "compulsory_bytes": step_bytes,
+                      "achieved_GBs": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                      "note": "every stage of the last step (calibration steps, one at a time) against reading "
+                              "M and P of level L-1 once and writing M and P of level L once"},
         "device_ms_per_step": round(device_ms, 4),
         "stages_ms_per_step": {f"{k[0]}@{k[1]}": round(v[1] / calib, 4) for k, v in sorted(all_stages.items())},
         "stages_note": "stage times from untimed calibration steps with an event pair around every stage; "

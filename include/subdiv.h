@@ -76,9 +76,11 @@ enum {
 #define SUBDIV_FLAG_REBUILD_EACH_LEVEL 1u /* rebuild E/F from M at every level (generic M M^T path)
                                              instead of carrying them over in closed form */
 #define SUBDIV_FLAG_KEEP_STATE 2u         /* keep every level's topology in the workspace for
-                                             subdiv_backward (whose first call after a
-                                             subdiv_refine also writes the adjoint's per-vertex
-                                             rule coefficients there) */
+                                             subdiv_refine_positions, subdiv_refine_vertex_data
+                                             (every scheme) and subdiv_backward (Catmull-Clark;
+                                             its first call after a subdiv_refine also writes the
+                                             adjoint's per-vertex rule coefficients there); not
+                                             with SUBDIV_FLAG_REBUILD_EACH_LEVEL */
 
 /* ---- inputs ----------------------------------------------------------- */
 typedef struct subdiv_mesh {
@@ -194,7 +196,8 @@ int subdiv_refine_static(const subdiv_mesh *mesh, const subdiv_plan_info *plan, 
  * mesh and workspace (the workspace holds every level's topology; it must not
  * be reused in between). grad_out: [V_L*3] device, grad_in: [V_0*3] device,
  * both caller-owned; grad_in is overwritten. Enqueues work only.
- * Returns SUBDIV_STATE when the plan was not made for the adjoint, or when no
+ * Returns SUBDIV_STATE when the plan was not made for the adjoint (no
+ * SUBDIV_FLAG_KEEP_STATE, or a Loop or sqrt(3) plan), or when no
  * subdiv_refine with this plan has been enqueued into `ws` since the last
  * subdiv_plan, batch plan or subdiv_state_destroy that touched it (the
  * library keeps a host-side record per workspace; it never reads state that
@@ -281,8 +284,8 @@ int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const 
                    const subdiv_extraction *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Static topology (Sec. 3.6: P_L = R_{L-1} ... R_0 P_0 with every R_k fixed
- * by topology and creases). Re-evaluates the positions of a Catmull-Clark
- * refinement planned with SUBDIV_FLAG_KEEP_STATE, after one completed
+ * by topology and creases). Re-evaluates the positions of a refinement (any
+ * scheme) planned with SUBDIV_FLAG_KEEP_STATE, after one completed
  * subdiv_refine with the same plan, cage topology and workspace, for the
  * cage positions now in mesh->positions. The operators are applied
  * matrix-free by the same stencil kernels as subdiv_refine, reading the kept
@@ -300,9 +303,9 @@ int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *pla
  * same R_{L-1} ... R_0, fixed by topology and creases). Refines data
  * ([V_0*dim] device floats, row-major: vertex v's channels at v*dim) into
  * out ([V_L*dim] device floats, caller-owned, overwritten), dim >= 1. The
- * state requirements are those of subdiv_refine_positions (a Catmull-Clark
- * plan with SUBDIV_FLAG_KEEP_STATE, one completed subdiv_refine with the same
- * plan, cage topology and workspace). Channels go three at a time through
+ * state requirements are those of subdiv_refine_positions (a plan of any
+ * scheme with SUBDIV_FLAG_KEEP_STATE, one completed subdiv_refine with the
+ * same plan, cage topology and workspace). Channels go three at a time through
  * the kernels of subdiv_refine_positions: channels 3c..3c+2 of out equal, bit
  * for bit, the positions it writes for those three channels as cage
  * positions (channels past dim read as zero). Between calls the workspace
@@ -397,8 +400,57 @@ int subdiv_timing_read(subdiv_stage_time *out, int max_out);
  * again. Process-wide, like subdiv_timing_enable. */
 void subdiv_timing_select(const char *stage, int level);
 
-/* HIP error text of the last SUBDIV_HIP status on this thread, or the sizes
- * behind the last SUBDIV_WORKSPACE of subdiv_refine_static ("" if none). */
+/* The same records with the tuned kernel of each stage: per (stage, level,
+ * kernel, element count, workgroup size), the kernel being the last tuned
+ * launch inside the stage (kernel "" when the stage has none). Clears the
+ * records like subdiv_timing_read; returns the entries written or a
+ * negative status. */
+typedef struct subdiv_kernel_time {
+  char stage[24];
+  char kernel[24];
+  int32_t level;
+  int32_t block;
+  int64_t items;
+  int32_t launches;
+  int32_t reserved0;
+  double total_ms;
+} subdiv_kernel_time;
+int subdiv_timing_read_kernels(subdiv_kernel_time *out, int max_out);
+
+/* ---- launch shapes ------------------------------------------------------
+ * The per-element kernels of the refinement steps and of the adjoint run
+ * with a workgroup size (64, 128, 256 or 512 lanes) taken per kernel and size
+ * bucket from a tuning table; the outputs do not depend on it (every lane owns
+ * its element; lanes cooperate only within a wave). The table is a JSON file
+ * written by the tuner (python -m paper_1809_06047_amd.tune):
+ *   {"kernels": {"<kernel>": [[max_items, block], ...], ...}, ...}
+ * where a launch over n elements takes the first entry with n <= max_items
+ * (max_items < 0: any n; past the last entry: the last). The library reads it
+ * once, at its first launch, from the path in the environment variable
+ * SUBDIV_TUNING if set (empty: none), else from tuning_gfx950.json beside
+ * libsubdiv.so if present; kernels without entries use 256. Process-wide. */
+/* Replace the table with the file at `path` (NULL or "": no table, 256
+ * everywhere). On a malformed file the table is unchanged and the call returns
+ * SUBDIV_INVALID_ARG (subdiv_last_error() says why). */
+int subdiv_tuning_load(const char *path);
+/* Set one entry: kernel "<name>" or "*" (every kernel); max_items < 0 makes
+ * `block` the kernel's only entry, else the entry with that bound is added or
+ * replaced. SUBDIV_INVALID_ARG for an unknown kernel or a block other than
+ * 64, 128, 256, 512. */
+int subdiv_tuning_set(const char *kernel, int64_t max_items, int block);
+/* The workgroup size a launch of `kernel` over `items` elements takes, or a
+ * negative status for an unknown kernel. */
+int subdiv_tuning_block(const char *kernel, int64_t items);
+/* Where the table came from: its path, "built-in", or "set by
+ * subdiv_tuning_set". Valid until the next tuning call. */
+const char *subdiv_tuning_source(void);
+/* Name of tunable kernel `index` (0, 1, ... until SUBDIV_INVALID_ARG) into
+ * out[max_out]. */
+int subdiv_tuning_kernel_name(int index, char *out, int max_out);
+
+/* HIP error text of the last SUBDIV_HIP status on this thread, the sizes
+ * behind the last SUBDIV_WORKSPACE of subdiv_refine_static, or why the last
+ * subdiv_tuning_load failed ("" if none). */
 const char *subdiv_last_error(void);
 
 /* Human-readable name of a status code. */

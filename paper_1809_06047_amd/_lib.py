@@ -62,6 +62,11 @@ class subdiv_extraction(ctypes.Structure):
                 ("crease_sharpness", c_vp), ("vertex_map", c_vp), ("face_map", c_vp)]
 
 
+class subdiv_kernel_time(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_char * 24), ("kernel", ctypes.c_char * 24), ("level", c_i32), ("block", c_i32),
+                ("items", c_i64), ("launches", c_i32), ("reserved0", c_i32), ("total_ms", ctypes.c_double)]
+
+
 # every function the header declares, with its signature
 SIGNATURES = {
     "subdiv_workspace_bound": (c_sz, [c_i32, c_i32, c_i64, c_i32, ctypes.c_int, ctypes.c_int, c_u32]),
@@ -97,6 +102,12 @@ SIGNATURES = {
     "subdiv_timing_enable": (None, [ctypes.c_int]),
     "subdiv_timing_select": (None, [ctypes.c_char_p, ctypes.c_int]),
     "subdiv_timing_read": (ctypes.c_int, [ctypes.POINTER(subdiv_stage_time), ctypes.c_int]),
+    "subdiv_timing_read_kernels": (ctypes.c_int, [ctypes.POINTER(subdiv_kernel_time), ctypes.c_int]),
+    "subdiv_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "subdiv_tuning_set": (ctypes.c_int, [ctypes.c_char_p, c_i64, ctypes.c_int]),
+    "subdiv_tuning_block": (ctypes.c_int, [ctypes.c_char_p, c_i64]),
+    "subdiv_tuning_source": (ctypes.c_char_p, []),
+    "subdiv_tuning_kernel_name": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_int]),
     "subdiv_last_error": (ctypes.c_char_p, []),
     "subdiv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "subdiv_version": (ctypes.c_int, []),
@@ -125,7 +136,7 @@ class SubdivError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         lib = load()
         msg = lib.subdiv_strerror(status).decode()
-        if status in (HIP, WORKSPACE) and lib.subdiv_last_error():
+        if status in (HIP, WORKSPACE, INVALID_ARG) and lib.subdiv_last_error():
             msg += ": " + lib.subdiv_last_error().decode()
         super().__init__(f"{where}: status {status} ({msg})")
         self.status = status
@@ -147,6 +158,45 @@ def timing_read(max_out: int = 512):
     if n < 0:
         raise SubdivError(n, "subdiv_timing_read")
     return {(buf[i].name.decode(), buf[i].level): (buf[i].launches, buf[i].total_ms) for i in range(n)}
+
+
+def timing_read_kernels(max_out: int = 1024):
+    """[(stage, level, kernel, items, block, launches, total_ms)] recorded since the last read."""
+    buf = (subdiv_kernel_time * max_out)()
+    n = load().subdiv_timing_read_kernels(buf, max_out)
+    if n < 0:
+        raise SubdivError(n, "subdiv_timing_read_kernels")
+    return [(buf[i].stage.decode(), buf[i].level, buf[i].kernel.decode(), buf[i].items, buf[i].block,
+             buf[i].launches, buf[i].total_ms) for i in range(n)]
+
+
+def tuning_kernels():
+    """Names of the tunable kernels."""
+    out, i = [], 0
+    buf = ctypes.create_string_buffer(32)
+    while load().subdiv_tuning_kernel_name(i, buf, 32) == OK:
+        out.append(buf.value.decode())
+        i += 1
+    return out
+
+
+def tuning_load(path=None):
+    check(load().subdiv_tuning_load(path.encode() if path else None), "subdiv_tuning_load")
+
+
+def tuning_set(kernel: str, block: int, max_items: int = -1):
+    check(load().subdiv_tuning_set(kernel.encode(), int(max_items), int(block)), "subdiv_tuning_set")
+
+
+def tuning_block(kernel: str, items: int) -> int:
+    b = load().subdiv_tuning_block(kernel.encode(), int(items))
+    if b < 0:
+        raise SubdivError(b, "subdiv_tuning_block")
+    return b
+
+
+def tuning_source() -> str:
+    return load().subdiv_tuning_source().decode()
 
 
 def check(status: int, where: str):

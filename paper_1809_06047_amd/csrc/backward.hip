@@ -48,8 +48,8 @@ __device__ __forceinline__ BwdCoef smooth_or_blend(int n, int k, double ssum) {
 // boundary edge, and its only possible creases are the two halves of e, the
 // level-k edges base(e) and base(e) + 1 (base(e) = 4 e - boundary edges
 // before e). Only the older vertices walk their ring.
-template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_bw_coef(BwdStep c) {
+template <int BLK, int ORDER>
+__global__ void __launch_bounds__(BLK) k_bw_coef(BwdStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   float4 *out = reinterpret_cast<float4 *>(c.coef);
@@ -114,8 +114,8 @@ __device__ __forceinline__ void edge_coef(const BwdStep &c, int h, float &m, flo
 //   term(h) = b_w gV_w + m_e gE_e + gf_q (+ d_w gV_w when u is c1/c2 of w),
 // so the vertex kernel adds one 12-byte term per ring step instead of
 // gathering six arrays at every step.
-template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_bw_face(BwdStep c) {
+template <int BLK, int ORDER>
+__global__ void __launch_bounds__(BLK) k_bw_face(BwdStep c) {
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int V = c.t.V, F = c.t.F;
   const float4 *coef = reinterpret_cast<const float4 *>(c.coef);
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) k_bw_face(BwdStep c) {
   if constexpr (ORDER > 0) {
     // uniform faces: the corners and edges are loaded once, and the terms of
     // the wave's faces (contiguous) leave through LDS as whole lines
-    __shared__ uint32_t stage[kBlock / 64][64 * (3 * ORDER | 1)];
+    __shared__ uint32_t stage[BLK / 64][64 * (3 * ORDER | 1)];
     const bool valid = rid < F;
     const int r = valid ? rid : F - 1;
     const int l = threadIdx.x & 63;
@@ -194,8 +194,8 @@ __global__ void __launch_bounds__(kBlock) k_bw_face(BwdStep c) {
 // adjoint of the whole level at every vertex: its own vertex rule plus the
 // terms of its outgoing half-edges, and on a boundary the incoming boundary
 // edge (u -> v), whose half-edge belongs to u
-template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_bw_vertex(BwdStep c) {
+template <int BLK, int ORDER>
+__global__ void __launch_bounds__(BLK) k_bw_vertex(BwdStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   const int V = c.t.V, F = c.t.F;
@@ -273,12 +273,11 @@ __global__ void __launch_bounds__(kBlock) k_bw_vertex(BwdStep c) {
 }
 
 hipError_t bw_launch(int which, const BwdStep &c, hipStream_t s) {
-  const unsigned gv = grid_for(c.t.V), gf = grid_for(c.t.F);
-#define SUBDIV_BW(ORD)                                                                  \
-  do {                                                                                  \
-    if (which == BW_COEF) hipLaunchKernelGGL(k_bw_coef<ORD>, dim3(gv), dim3(kBlock), 0, s, c);   \
-    else if (which == BW_FACE) hipLaunchKernelGGL(k_bw_face<ORD>, dim3(gf), dim3(kBlock), 0, s, c); \
-    else hipLaunchKernelGGL(k_bw_vertex<ORD>, dim3(gv), dim3(kBlock), 0, s, c);                 \
+#define SUBDIV_BW(ORD)                                                           \
+  do {                                                                           \
+    if (which == BW_COEF) SUBDIV_LAUNCH_TUNED_T(TK_BW_COEF, c.t.V, s, k_bw_coef, ORD, c);  \
+    else if (which == BW_FACE) SUBDIV_LAUNCH_TUNED_T(TK_BW_FACE, c.t.F, s, k_bw_face, ORD, c); \
+    else SUBDIV_LAUNCH_TUNED_T(TK_BW_VERTEX, c.t.V, s, k_bw_vertex, ORD, c);               \
   } while (0)
   if (c.t.order == 4) SUBDIV_BW(4);
   else if (c.t.order == 3) SUBDIV_BW(3);

@@ -45,8 +45,8 @@ __device__ __forceinline__ int face_of(const LagStep &c, int h) {
 }
 
 // ------------------------------------------------------------- group kernel
-template <int OM>
-__global__ void __launch_bounds__(kBlock) k_lag_group(LagStep c) {
+template <int BLK, int OM>
+__global__ void __launch_bounds__(BLK) k_lag_group(LagStep c) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= c.tm.F) return;
   const Topo &tm = c.tm;
@@ -108,8 +108,8 @@ __global__ void __launch_bounds__(kBlock) k_lag_group(LagStep c) {
 }
 
 // ------------------------------------------------------------ vertex kernel
-template <int OM>
-__global__ void __launch_bounds__(kBlock) k_lag_vertex(LagStep c) {
+template <int BLK, int OM>
+__global__ void __launch_bounds__(BLK) k_lag_vertex(LagStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.tm.V) return;
   const Topo &tm = c.tm;
@@ -180,8 +180,8 @@ __global__ void __launch_bounds__(kBlock) k_lag_vertex(LagStep c) {
 }
 
 // -------------------------------------------------------------- edge kernel
-template <int OM>
-__global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
+template <int BLK, int OM>
+__global__ void __launch_bounds__(BLK) k_lag_edge(LagStep c) {
   const int eid = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = eid < c.am.E;
   const int e = valid ? eid : c.am.E - 1;  // every lane takes part in the staged store
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
     // the children's edge points, VFk + base .. base + nchild - 1, are one
     // contiguous run over the wave (base(e + 1) = base(e) + nchild(e)): they
     // leave through LDS as runs of 64 consecutive dwords
-    __shared__ uint32_t stage[kBlock / 64][64 * 12];
+    __shared__ uint32_t stage[BLK / 64][64 * 12];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     uint32_t *lds = stage[w];
     const int base0 = __shfl(base, 0, 64);
@@ -333,11 +333,11 @@ __global__ void __launch_bounds__(kBlock) k_lag_edge(LagStep c) {
 template <int OM>
 static void lag_launch_t(int which, const LagStep &c, hipStream_t s) {
   if (which == LAG_GROUP)
-    hipLaunchKernelGGL(k_lag_group<OM>, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED_T(TK_LAG_GROUP, c.tm.F, s, k_lag_group, OM, c);
   else if (which == LAG_VERTEX)
-    hipLaunchKernelGGL(k_lag_vertex<OM>, dim3(grid_for(c.tm.V)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED_T(TK_LAG_VERTEX, c.tm.V, s, k_lag_vertex, OM, c);
   else
-    hipLaunchKernelGGL(k_lag_edge<OM>, dim3(grid_for(c.am.E)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED_T(TK_LAG_EDGE, c.am.E, s, k_lag_edge, OM, c);
 }
 
 hipError_t lag_launch(int which, const LagStep &c, hipStream_t s) {
@@ -378,7 +378,8 @@ __device__ __forceinline__ f3 shfl_xor3(f3 v, int mask, int width) {
   return f3{__shfl_xor(v.x, mask, width), __shfl_xor(v.y, mask, width), __shfl_xor(v.z, mask, width)};
 }
 
-__global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_lag2_group(Lag2Step c) {
   const LagStep &L = c.s;
   const int pid = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = pid < L.tm.F;  // F_m is a multiple of 4: quads of lanes are complete
@@ -418,7 +419,7 @@ __global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
   // per-face outputs are contiguous over the wave (face p owns [16 p, 16 p + 16)
   // of every level-k row array and 12 floats of face points): they leave
   // through the wave's LDS slice as whole lines
-  __shared__ int4 stage[kBlock / 64][32 * 17];
+  __shared__ int4 stage[BLK / 64][32 * 17];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const long long pw = (long long)blockIdx.x * blockDim.x + (w << 6);  // first face of the wave
   const int nw = (int)min(64ll, (long long)L.tm.F - pw);               // faces of the wave
@@ -528,7 +529,8 @@ __global__ void __launch_bounds__(kBlock) k_lag2_group(Lag2Step c) {
 }
 
 // edge points of level g (EP_g vertices): two half rings, crease valency
-__global__ void __launch_bounds__(kBlock) k_lag2_combine(Lag2Step c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_lag2_combine(Lag2Step c) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= c.Eg) return;
   const LagStep &L = c.s;
@@ -574,7 +576,8 @@ __global__ void __launch_bounds__(kBlock) k_lag2_combine(Lag2Step c) {
 __device__ __forceinline__ int quad_next(int h) { return (h & ~3) | ((h + 1) & 3); }
 __device__ __forceinline__ int quad_prev(int h) { return (h & ~3) | ((h + 3) & 3); }
 
-__global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_lag2_older(Lag2Step c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.Vg) return;
   const LagStep &L = c.s;
@@ -711,11 +714,11 @@ __global__ void __launch_bounds__(kBlock) k_lag2_older(Lag2Step c) {
 
 hipError_t lag2_launch(int which, const Lag2Step &c, hipStream_t s) {
   if (which == LAG2_GROUP)
-    hipLaunchKernelGGL(k_lag2_group, dim3(grid_for(c.s.tm.F)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_LAG2_GROUP, c.s.tm.F, s, k_lag2_group, c);
   else if (which == LAG2_COMBINE)
-    hipLaunchKernelGGL(k_lag2_combine, dim3(grid_for(c.Eg)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_LAG2_COMBINE, c.Eg, s, k_lag2_combine, c);
   else
-    hipLaunchKernelGGL(k_lag2_older, dim3(grid_for(c.Vg)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_LAG2_OLDER, c.Vg, s, k_lag2_older, c);
   return hipGetLastError();
 }
 

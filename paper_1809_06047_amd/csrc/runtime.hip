@@ -32,6 +32,9 @@ struct TimingRec {
   const char *name;
   int level;
   hipEvent_t a, b;
+  int key;          // tuned kernel of the stage (its last tuned launch), or -1
+  long long items;  // its element count
+  int block;        // and workgroup size
 };
 std::mutex g_tmu;
 std::atomic<bool> g_timing{false};
@@ -61,6 +64,7 @@ hipEvent_t timing_begin(const char *name, int level, hipStream_t s) {
     g_pool.push_back(e);
     return nullptr;
   }
+  tune_note_reset();
   return e;
 }
 
@@ -80,7 +84,9 @@ void timing_end(hipEvent_t a, const char *name, int level, hipStream_t s) {
     g_pool.push_back(b);
     return;
   }
-  g_recs.push_back(TimingRec{name, level, a, b});
+  TimingRec r{name, level, a, b, -1, 0, 0};
+  tune_note_take(&r.key, &r.items, &r.block);
+  g_recs.push_back(r);
 }
 
 #define SUBDIV_TIMED(name, level, expr)          \
@@ -196,9 +202,15 @@ bool rebuilds_levels(int, uint32_t flags) { return (flags & SUBDIV_FLAG_REBUILD_
 // The last two Loop or sqrt(3) steps both run from two levels below them:
 // L >= 4 (so the step before the last reads a refined level, L-3 >= 1) and
 // no creases on levels L-2 and L-1
+// The last Loop or sqrt(3) step from level L-2 (level L-1's adjacency never
+// built): not when every level's state is kept
+bool tri_lag(int scheme, uint32_t flags, int levels, const Sizes *L) {
+  return scheme != SUBDIV_CATMULL_CLARK && !rebuilds_levels(scheme, flags) && !(flags & SUBDIV_FLAG_KEEP_STATE) &&
+         levels >= 3 && !L[levels - 1].creases;
+}
+// and the step before it from level L-3 too
 bool tri_lag2(int scheme, uint32_t flags, int levels, const Sizes *L) {
-  return scheme != SUBDIV_CATMULL_CLARK && !rebuilds_levels(scheme, flags) && levels >= 4 &&
-         !L[levels - 1].creases && !L[levels - 2].creases;
+  return tri_lag(scheme, flags, levels, L) && levels >= 4 && !L[levels - 2].creases;
 }
 
 Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long long C0) {
@@ -243,7 +255,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     // the last Loop or sqrt(3) step from level levels-2: level levels-1's
     // adjacency and face table are never held in the workspace (only its
     // positions)
-    const bool loop_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases;
+    const bool keep = (flags & SUBDIV_FLAG_KEEP_STATE) != 0;
+    const bool loop_lag = tri_lag(scheme, flags, levels, L);
     const int top = loop_lag ? levels - 1 : levels;  // levels 1 .. top-1 have adjacency slots and face tables
     long long mV = 0, mE = 0, mH = 0, mF = 0, mVp = 0;
     bool cr = false;
@@ -257,7 +270,7 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     for (int k = 1; k < levels; ++k) mVp = L[k].V > mVp ? L[k].V : mVp;
     const bool cc_carry = scheme == SUBDIV_CATMULL_CLARK && !rebuild;
     // rotating adjacency slots; with the state kept every level has its own region instead
-    const int nslots = cc_carry ? ((flags & SUBDIV_FLAG_KEEP_STATE) ? 0 : 3) : 2;
+    const int nslots = keep ? 0 : (cc_carry ? 3 : 2);
     for (int s = 0; s < nslots; ++s) y.slot[s] = carve_adj(c, mV, mE, mH, cr, true);
     if (cc_carry && levels >= 4) {
       y.hs = c.take(24 * mE);
@@ -276,7 +289,7 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
       y.bsigcnt = c.take(4 * mH);
     }
     for (int s = 0; s < 2; ++s) {
-      y.mfv[s] = c.take(4 * (mH > 0 ? mH : 1));
+      if (!keep) y.mfv[s] = c.take(4 * (mH > 0 ? mH : 1));  // (kept levels hold their own face tables)
       y.mP[s] = c.take(12 * mVp);
     }
   }
@@ -305,7 +318,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     y.bg[0] = c.take(12 * gV);
     y.bg[1] = c.take(12 * gV);
     y.bterm = c.take(12 * gH);
-    for (int k = 0; k < levels; ++k) y.kcoef[k] = c.take(16 * L[k].V);
+    if (scheme == SUBDIV_CATMULL_CLARK)  // the adjoint covers Catmull-Clark
+      for (int k = 0; k < levels; ++k) y.kcoef[k] = c.take(16 * L[k].V);
   }
   y.total = c.at + 256;
   return y;
@@ -590,6 +604,39 @@ int refine_cc_carried(const subdiv_mesh *mesh, const subdiv_level_out *outs, voi
   return SUBDIV_OK;
 }
 
+// Loop and sqrt(3) positions from the kept state (static topology, Sec. 3.6):
+// every level's face table and adjacency (and Loop's sharpness) are in the
+// levels' own regions, so each step runs the point kernels of the per-level
+// path with every topology output switched off: the same kernels on the same
+// operands as the refinement that kept the state, so the same bits.
+int refine_tri_kept(int scheme, const subdiv_level_out *outs, void *ws, const Layout &y, const Sizes *L, int levels,
+                    Topo t, Adj a, const float *P, hipStream_t s) {
+  Adj aprev{};
+  for (int k = 0; k < levels; ++k) {
+    const bool final = (k == levels - 1);
+    float *P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
+    if (final) P1 = outs[k + 1].positions;
+    TriStep c{t, a, P, nullptr, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev,
+              k >= 2 ? (int32_t)L[k - 2].V : 0};
+    if (scheme == SUBDIV_LOOP) {
+      SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));
+      SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, c, s));
+      if (L[k].creases && a.sig && a.vcr) SUBDIV_TIMED("loop_crease", k, loop_crease_launch(c, nullptr, s));
+    } else {
+      SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, c, s));
+      SUBDIV_TIMED("sqrt3_face", k, tri_launch(SQRT3_FACE, c, s));
+    }
+    if (!final) {
+      aprev = a;
+      a = adj_at(ws, y.keep[k + 1], L[k + 1].E, L[k + 1].creases != 0);
+      t = Topo{(int32_t)L[k + 1].V, (int32_t)L[k + 1].F, (int32_t)L[k + 1].H, 3, nullptr, nullptr,
+               at<int32_t>(ws, y.keep[k + 1].fv)};
+    }
+    P = P1;
+  }
+  return SUBDIV_OK;
+}
+
 // The symbolic pass on a cage, enqueued only: validation of faces and
 // indices and the valence; then the adjacency, edge ids and creases, whose
 // kernels do nothing once a fault is recorded; for Loop and sqrt(3) refined
@@ -661,6 +708,10 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
 
 }  // namespace
 
+namespace subdiv {
+void subdiv_set_error(const char *msg) { g_last_error = msg ? msg : ""; }
+}  // namespace subdiv
+
 // ---- the C ABI ---------------------------------------------------------
 extern "C" {
 
@@ -712,6 +763,43 @@ int subdiv_timing_read(subdiv_stage_time *out, int max_out) {
   return n;
 }
 
+int subdiv_timing_read_kernels(subdiv_kernel_time *out, int max_out) {
+  if (!out || max_out < 0) return SUBDIV_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tmu);
+  int n = 0;
+  hipError_t first = hipSuccess;
+  for (const TimingRec &r : g_recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && first == hipSuccess) first = e;
+    const char *kname = r.key >= 0 ? tune_key_name(r.key) : "";
+    int i = 0;
+    for (; i < n; ++i)
+      if (out[i].level == r.level && out[i].items == r.items && out[i].block == r.block &&
+          std::strncmp(out[i].stage, r.name, sizeof(out[i].stage)) == 0 &&
+          std::strncmp(out[i].kernel, kname, sizeof(out[i].kernel)) == 0)
+        break;
+    if (i == n) {
+      if (n == max_out) continue;
+      std::memset(&out[n], 0, sizeof(out[n]));
+      std::strncpy(out[n].stage, r.name, sizeof(out[n].stage) - 1);
+      std::strncpy(out[n].kernel, kname, sizeof(out[n].kernel) - 1);
+      out[n].level = r.level;
+      out[n].items = r.items;
+      out[n].block = r.block;
+      ++n;
+    }
+    out[i].launches += 1;
+    out[i].total_ms += ms;
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  if (first != hipSuccess) return hip_fail(first);
+  return n;
+}
+
 const char *subdiv_last_error(void) { return g_last_error.c_str(); }
 
 const char *subdiv_strerror(int st) {
@@ -745,10 +833,8 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   int st = check_mesh_args(mesh, scheme, levels);
   if (st != SUBDIV_OK) return st;
   if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL | SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_INVALID_ARG;
-  // the adjoint covers Catmull-Clark with the carried-over adjacency
-  if ((flags & SUBDIV_FLAG_KEEP_STATE) &&
-      (scheme != SUBDIV_CATMULL_CLARK || (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL)))
-    return SUBDIV_INVALID_ARG;
+  // the kept state is that of the carried-over adjacency
+  if ((flags & SUBDIV_FLAG_KEEP_STATE) && (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;
   if (!ws) return SUBDIV_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
@@ -890,11 +976,15 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
   // list of level levels-1
   // (the last step from level levels-2 has no crease rules; it writes the
   // edge list of level levels-1 itself)
-  const bool tri_lag = scheme != SUBDIV_CATMULL_CLARK && !rebuild && levels >= 3 && !L[levels - 1].creases;
-  const bool lag2 = tri_lag && tri_lag2(scheme, plan->flags, levels, L);
+  const bool tri_lag = ::tri_lag(scheme, plan->flags, levels, L);
+  const bool lag2 = tri_lag2(scheme, plan->flags, levels, L);
+  // level k's adjacency (and face table): a rotating slot, or with the state
+  // kept the level's own region
+  auto tri_slot = [&](int k) -> const AdjOffsets & { return keep ? y.keep[k] : y.slot[k & 1]; };
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
+    if (keep && scheme != SUBDIV_CATMULL_CLARK && !final) fv1 = at<int32_t>(ws, y.keep[k + 1].fv);
     float *P1 = outs[k + 1].positions ? outs[k + 1].positions : at<float>(ws, y.mP[(k + 1) & 1]);
     if (final) {
       fv1 = outs[k + 1].face_verts;
@@ -1006,9 +1096,9 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       const bool lcr = scheme == SUBDIV_LOOP && L[k].creases && a.sig && a.vcr;
       double *sig1 = nullptr;
       if (lcr && L[k + 1].creases)
-        sig1 = final ? outs[k + 1].crease_sharpness : adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, true).sig;
+        sig1 = final ? outs[k + 1].crease_sharpness : adj_at(ws, tri_slot(k + 1), L[k + 1].E, true).sig;
       if (carry) {
-        c.a1 = adj_at(ws, y.slot[(k + 1) & 1], L[k + 1].E, L[k + 1].creases != 0);
+        c.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, L[k + 1].creases != 0);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
       }
       if (carry || (before_lag && scheme == SUBDIV_LOOP) || sig1) c.base = at<int32_t>(ws, y.tbase);
@@ -1043,6 +1133,8 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
         if (carry) a = c.a1;
       }
     }
+    if (keep && scheme != SUBDIV_CATMULL_CLARK && !final && outs[k + 1].face_verts)
+      SUBDIV_TRY(hipMemcpyAsync(outs[k + 1].face_verts, fv1, 4 * L[k + 1].H, hipMemcpyDeviceToDevice, s));
     // level k+1 becomes the input of the next step
     tprev = t;
     aprev2 = aprev;
@@ -1063,7 +1155,7 @@ int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *pla
   if (st != SUBDIV_OK) return st;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || !state_kept(plan, ws))
     return SUBDIV_STATE;
-  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_STATE;
   const int levels = plan->levels;
   if (!outs[levels].positions) return SUBDIV_INVALID_ARG;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
@@ -1076,6 +1168,7 @@ int subdiv_refine_positions(const subdiv_mesh *mesh, const subdiv_plan_info *pla
   const Layout y = make_layout(plan->scheme, levels, plan->flags, L, mesh->num_creases);
   const Topo t = cage_topo(mesh, H0, ws, y);
   const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0 && L[0].creases);
+  if (plan->scheme != SUBDIV_CATMULL_CLARK) return refine_tri_kept(plan->scheme, outs, ws, y, L, levels, t, a, mesh->positions, s);
   return refine_cc_carried(mesh, outs, ws, y, L, levels, plan->flags, t, a, mesh->positions, true, s);
 }
 
@@ -1086,7 +1179,7 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
   if (st != SUBDIV_OK) return st;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || !state_kept(plan, ws))
     return SUBDIV_STATE;
-  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;
+  if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_STATE;
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int levels = plan->levels;
@@ -1112,8 +1205,10 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
     for (int g = 0; g < 2 && c0 + 3 * g < dim; ++g) {
       SUBDIV_TRY(launch_pack3(data, dim, c0 + 3 * g, L[0].V, slice0, s));
       outs[levels].positions = sliceL[g];
-      if ((st = refine_cc_carried(&m, outs, ws, y, L, levels, plan->flags, t, a, slice0, true, s)) != SUBDIV_OK)
-        return st;
+      st = plan->scheme == SUBDIV_CATMULL_CLARK
+               ? refine_cc_carried(&m, outs, ws, y, L, levels, plan->flags, t, a, slice0, true, s)
+               : refine_tri_kept(plan->scheme, outs, ws, y, L, levels, t, a, slice0, s);
+      if (st != SUBDIV_OK) return st;
     }
     const int ncols = dim - c0 < 6 ? dim - c0 : 6;
     SUBDIV_TRY(launch_unpack6(sliceL[0], sliceL[1], dim, c0, ncols, L[levels].V, out, s));
@@ -1229,6 +1324,7 @@ int subdiv_backward(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const
   if (st != SUBDIV_OK) return st;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts) return SUBDIV_STATE;
   if (!(plan->flags & SUBDIV_FLAG_KEEP_STATE) || !state_kept(plan, ws)) return SUBDIV_STATE;
+  if (plan->scheme != SUBDIV_CATMULL_CLARK) return SUBDIV_STATE;  // the adjoint covers Catmull-Clark
   if (ws_bytes < plan->workspace_bytes) return SUBDIV_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int levels = plan->levels;

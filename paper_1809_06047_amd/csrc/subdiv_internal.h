@@ -164,6 +164,65 @@ inline unsigned grid_for(long long n, int block = kBlock) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// ---- launch shapes from the tuning table ------------------------------
+// The per-element kernels of the refinement steps are instantiated for
+// several workgroup sizes; the tuning table (written by the tuner, loaded by
+// the library at its first launch) picks one per kernel and size bucket.
+// Every kernel's results are independent of the workgroup size: each lane
+// owns its element, and the only cooperation is within a wave (LDS staging of
+// stores, shuffles), never across the workgroup.
+enum TuneKey {
+  TK_LAG_GROUP, TK_LAG_VERTEX, TK_LAG_EDGE, TK_LAG2_GROUP, TK_LAG2_COMBINE, TK_LAG2_OLDER,
+  TK_LOOP_EDGE, TK_LOOP_VERTEX, TK_LOOP_FACE, TK_SQRT3_COUNT, TK_SQRT3_FACE, TK_SQRT3_VERTEX,
+  TK_LOOPL_FACE, TK_LOOPL_EDGE, TK_SQRT3L_FACE, TK_BW_COEF, TK_BW_FACE, TK_BW_VERTEX,
+  TK_COUNT
+};
+const char *tune_key_name(int key);
+// workgroup size for `items` elements of kernel `key` (64, 128, 256 or 512);
+// with timing on, the launch is noted for the stage record
+int tuned_block(int key, long long items);
+// the last tuned launch of this thread since the reset (for the stage timing)
+void tune_note_reset();
+bool tune_note_take(int *key, long long *items, int *block);
+// text for subdiv_last_error() of this thread
+void subdiv_set_error(const char *msg);
+
+// Launch KERNEL<B> (a kernel template over the workgroup size B; the _T form
+// passes one more template argument, KERNEL<B, TARG>) with the table's B for
+// `items` elements, one lane per element.
+#define SUBDIV_LAUNCH_TUNED_T(key, items, stream, KERNEL, TARG, ...)                                          \
+  do {                                                                                                        \
+    const long long _n = (items);                                                                             \
+    switch (tuned_block((key), _n)) {                                                                         \
+      case 64:                                                                                                \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL<64, TARG>), dim3(grid_for(_n, 64)), dim3(64), 0, stream,     \
+                           __VA_ARGS__);                                                                      \
+        break;                                                                                                \
+      case 128:                                                                                               \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL<128, TARG>), dim3(grid_for(_n, 128)), dim3(128), 0, stream,  \
+                           __VA_ARGS__);                                                                      \
+        break;                                                                                                \
+      case 512:                                                                                               \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL<512, TARG>), dim3(grid_for(_n, 512)), dim3(512), 0, stream,  \
+                           __VA_ARGS__);                                                                      \
+        break;                                                                                                \
+      default:                                                                                                \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL<256, TARG>), dim3(grid_for(_n, 256)), dim3(256), 0, stream,  \
+                           __VA_ARGS__);                                                                      \
+        break;                                                                                                \
+    }                                                                                                         \
+  } while (0)
+#define SUBDIV_LAUNCH_TUNED(key, items, stream, KERNEL, ...)                                                        \
+  do {                                                                                                              \
+    const long long _n = (items);                                                                                   \
+    switch (tuned_block((key), _n)) {                                                                               \
+      case 64: hipLaunchKernelGGL(KERNEL<64>, dim3(grid_for(_n, 64)), dim3(64), 0, stream, __VA_ARGS__); break;     \
+      case 128: hipLaunchKernelGGL(KERNEL<128>, dim3(grid_for(_n, 128)), dim3(128), 0, stream, __VA_ARGS__); break; \
+      case 512: hipLaunchKernelGGL(KERNEL<512>, dim3(grid_for(_n, 512)), dim3(512), 0, stream, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<256>, dim3(grid_for(_n, 256)), dim3(256), 0, stream, __VA_ARGS__); break;  \
+    }                                                                                                               \
+  } while (0)
+
 // ---- launchers (each returns hipGetLastError() of its launches) --------
 hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s);

@@ -412,7 +412,8 @@ __device__ __forceinline__ int lt_new(int x, int bound, int o1, int o2) {
   return (x < bound && x != o1 && x != o2) ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_loop_edge(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_loop_edge(TriStep c) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= c.a.E) return;
   const int h = c.a.e2h[e];
@@ -470,7 +471,8 @@ __device__ __forceinline__ f3 loop_ep_point(const TriStep &c, int u) {
   return loop_v6_pt(p, add3(add3(pa, pb), add3(add3(n1, n2), add3(x, y))));
 }
 
-__global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_loop_vertex(TriStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   if (c.Vg > 0 && v >= c.Vg) {  // an edge point of the previous level: no ring walk
@@ -502,10 +504,11 @@ __global__ void __launch_bounds__(kBlock) k_loop_vertex(TriStep c) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_loop_face(TriStep c) {
   // the 12-int rows of every face (children, and when carried their twins
   // and edge ids) are contiguous over the wave: they leave through LDS
-  __shared__ uint32_t stage[kBlock / 64][64 * 13];
+  __shared__ uint32_t stage[BLK / 64][64 * 13];
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = rid < c.t.F;
   const int r = valid ? rid : c.t.F - 1;
@@ -591,7 +594,8 @@ __global__ void __launch_bounds__(kBlock) k_loop_face(TriStep c) {
 // scan of 3 + |{neighbours s < r}| over the faces:
 //   (v, F_r) -> B + base(r) + rank of v among r's corners,
 //   (F_x, F_m), x < m -> B + base(m) + 3 + |{neighbours s of m, s < x}|.
-__global__ void __launch_bounds__(kBlock) k_sqrt3_count(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_sqrt3_count(TriStep c) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= c.t.F) return;
   int cnt = 3;
@@ -605,10 +609,11 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_count(TriStep c) {
 
 __device__ __forceinline__ int rank3(int x, int a, int b) { return (x > a) + (x > b); }
 
-__global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_sqrt3_face(TriStep c) {
   // the 9-int rows of every face (children, and when carried their twins and
   // edge ids) are contiguous over the wave: they leave through LDS
-  __shared__ uint32_t stage[kBlock / 64][64 * 9];
+  __shared__ uint32_t stage[BLK / 64][64 * 9];
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = rid < c.t.F;
   const int r = valid ? rid : c.t.F - 1;
@@ -696,7 +701,8 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3_face(TriStep c) {
   if (valid) c.a1.vhe[V + r] = vhe_fp;
 }
 
-__global__ void __launch_bounds__(kBlock) k_sqrt3_vertex(TriStep c) {
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   if (c.Vg > 0 && v >= c.Vg) {
@@ -851,8 +857,9 @@ hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s) {
 // takes the same points. Sums keep the operand grouping of the per-level
 // kernels above (two-term sums commute) and the stencils are the same
 // uncontracted ones, so both give the same bits.
-__global__ void __launch_bounds__(kBlock) k_loopl_face(TriLag c) {
-  __shared__ int4 stage[kBlock / 64][32 * 13];
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_loopl_face(TriLag c) {
+  __shared__ int4 stage[BLK / 64][32 * 13];
   const int F = c.tm.F;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = rid < F ? rid : F - 1;  // every lane takes part in the staged store
@@ -922,8 +929,9 @@ __global__ void __launch_bounds__(kBlock) k_loopl_face(TriLag c) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_loopl_edge(TriLag c) {
-  __shared__ uint32_t stage[kBlock / 64][64 * 18];
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
+  __shared__ uint32_t stage[BLK / 64][64 * 18];
   const int E = c.am.E;
   const int eid = blockIdx.x * blockDim.x + threadIdx.x;
   const int e = eid < E ? eid : E - 1;  // every lane takes part in the staged stores
@@ -1017,8 +1025,9 @@ __global__ void __launch_bounds__(kBlock) k_loopl_edge(TriLag c) {
 // face point of q)), the face points of r's three children and the vertex
 // point of F_r (r's corners and the face points across its interior edges).
 // The sums are those of the per-level kernels, in the same order.
-__global__ void __launch_bounds__(kBlock) k_sqrt3l_face(TriLag c) {
-  __shared__ uint32_t stage[kBlock / 64][64 * 27];
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_sqrt3l_face(TriLag c) {
+  __shared__ uint32_t stage[BLK / 64][64 * 27];
   const int F = c.tm.F;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = rid < F ? rid : F - 1;  // every lane takes part in the staged stores
@@ -1113,33 +1122,33 @@ __global__ void __launch_bounds__(kBlock) k_sqrt3l_face(TriLag c) {
 
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s) {
   if (which == LAG_LOOP_FACE)
-    hipLaunchKernelGGL(k_loopl_face, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_LOOPL_FACE, c.tm.F, s, k_loopl_face, c);
   else if (which == LAG_LOOP_EDGE)
-    hipLaunchKernelGGL(k_loopl_edge, dim3(grid_for(c.am.E)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_LOOPL_EDGE, c.am.E, s, k_loopl_edge, c);
   else
-    hipLaunchKernelGGL(k_sqrt3l_face, dim3(grid_for(c.tm.F)), dim3(kBlock), 0, s, c);
+    SUBDIV_LAUNCH_TUNED(TK_SQRT3L_FACE, c.tm.F, s, k_sqrt3l_face, c);
   return hipGetLastError();
 }
 
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s) {
   switch (which) {
     case LOOP_EDGE:
-      hipLaunchKernelGGL(k_loop_edge, dim3(grid_for(c.a.E)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_LOOP_EDGE, c.a.E, s, k_loop_edge, c);
       break;
     case LOOP_VERTEX:
-      hipLaunchKernelGGL(k_loop_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_LOOP_VERTEX, c.t.V, s, k_loop_vertex, c);
       break;
     case LOOP_FACE:
-      hipLaunchKernelGGL(k_loop_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_LOOP_FACE, c.t.F, s, k_loop_face, c);
       break;
     case SQRT3_FACE:
-      hipLaunchKernelGGL(k_sqrt3_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_SQRT3_FACE, c.t.F, s, k_sqrt3_face, c);
       break;
     case SQRT3_COUNT:
-      hipLaunchKernelGGL(k_sqrt3_count, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_SQRT3_COUNT, c.t.F, s, k_sqrt3_count, c);
       break;
     default:
-      hipLaunchKernelGGL(k_sqrt3_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+      SUBDIV_LAUNCH_TUNED(TK_SQRT3_VERTEX, c.t.V, s, k_sqrt3_vertex, c);
       break;
   }
   return hipGetLastError();

@@ -201,3 +201,43 @@ def test_batch_arguments_without_device(lib):
     plans[2].priv_mesh_verts = 16
     assert lib.subdiv_refine_batch(arr, sc, lv, 3, plans, outs, ctypes.c_void_p(1 << 20), 16, None) == \
         _lib.WORKSPACE
+
+
+def test_tuning_table_host_calls(lib, tmp_path):
+    """The launch-shape table: load, lookup by size bucket, single entries,
+    malformed files rejected with the table unchanged (host-only calls)."""
+    names = _lib.tuning_kernels()
+    assert "lag2_group" in names and "loopl_face" in names and "bw_vertex" in names
+    t = tmp_path / "t.json"
+    t.write_text('{"device": "gfx950", "note": {"x": [1, 2.5, "y"]}, '
+                 '"kernels": {"lag2_group": [[1000, 64], [100000, 128], [-1, 512]], "lag_edge": [[-1, 128]]}}')
+    _lib.tuning_load(str(t))
+    assert _lib.tuning_source() == str(t)
+    assert _lib.tuning_block("lag2_group", 10) == 64
+    assert _lib.tuning_block("lag2_group", 1000) == 64
+    assert _lib.tuning_block("lag2_group", 1001) == 128
+    assert _lib.tuning_block("lag2_group", 10 ** 9) == 512
+    assert _lib.tuning_block("lag_edge", 5) == 128
+    assert _lib.tuning_block("loop_face", 5) == 256  # no entry: the default
+    bad = tmp_path / "bad.json"
+    for text in ('{"kernels": {"lag2_group": [[10, 96]]}}',          # not a supported block
+                 '{"kernels": {"nope": [[10, 64]]}}',                 # unknown kernel
+                 '{"kernels": {"lag_edge": [[100, 64], [10, 128]]}}',  # unordered buckets
+                 '{"kernels": {"lag_edge": [[100, 64]]'):             # truncated
+        bad.write_text(text)
+        with pytest.raises(_lib.SubdivError) as e:
+            _lib.tuning_load(str(bad))
+        assert e.value.status == _lib.INVALID_ARG
+        assert _lib.tuning_block("lag2_group", 10) == 64  # unchanged
+    _lib.tuning_set("loop_face", 128)
+    _lib.tuning_set("loop_face", 512, max_items=100)
+    assert _lib.tuning_block("loop_face", 50) == 512 and _lib.tuning_block("loop_face", 5000) == 128
+    with pytest.raises(_lib.SubdivError):
+        _lib.tuning_set("loop_face", 100)
+    _lib.tuning_set("*", 64)
+    assert all(_lib.tuning_block(n, 12345) == 64 for n in names)
+    _lib.tuning_load(None)
+    assert _lib.tuning_source() == "built-in"
+    assert all(_lib.tuning_block(n, 12345) == 256 for n in names)
+    default = os.path.join(ROOT, "paper_1809_06047_amd", "tuning_gfx950.json")
+    _lib.tuning_load(default if os.path.exists(default) else None)
