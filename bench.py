@@ -291,7 +291,7 @@ def main():
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
         out["triangle_schemes"] = {sc: scheme_leg(G.tri_cage(), sc, args.tri_levels, max(3, args.steps // 4))
-                                   for sc in ("loop", "sqrt3")}
+                                   for sc in ("loop", "sqrt3", "sqrt3k")}
     if args.serve_requests > 0:
         out["serving"] = serving(args)
     if args.cpu_levels > 0:

@@ -27,6 +27,7 @@
  *   Catmull-Clark  [vertex points | face points | edge points]  (|v|+r, |v|+|f|+e)
  *   Loop           [vertex points | edge points]
  *   sqrt(3)        [vertex points | face points]                (App. A, |v|+i)
+ *   trisection     [vertex points | face points or p | q]       (SUBDIV_SQRT3_KOBBELT, even levels)
  * Edge ids enumerate the strict upper triangle of E in CSC order, i.e. the
  * edges {lo < hi} sorted ascending by (hi, lo).
  * Child faces: Catmull-Clark child j of face r is at col_ptr[r] + j and is
@@ -49,7 +50,14 @@ extern "C" {
 enum {
   SUBDIV_CATMULL_CLARK = 0, /* Sec. 3 */
   SUBDIV_LOOP = 1,          /* App. B, triangle meshes */
-  SUBDIV_SQRT3 = 2          /* App. A, triangle meshes */
+  SUBDIV_SQRT3 = 2,         /* App. A, triangle meshes; boundary vertices fixed, boundary edges kept */
+  SUBDIV_SQRT3_KOBBELT = 3  /* App. A with the boundary rule it defers to Kobbelt's sqrt(3) paper: a two-step
+                               cycle, levels 1, 3, ... by the sqrt(3) step with the boundary fixed, levels 2,
+                               4, ... by a trisection step that splits every boundary edge in three (a boundary
+                               face r gets two edge points instead of its face point: p at |v| + r, q at
+                               |v| + |f| + its rank among the boundary faces) with the ternary cubic B-spline
+                               rule on the boundary. Triangle meshes, no creases; every level is built by the
+                               generic mapped product; not in batches, no kept state */
 };
 
 enum {
@@ -384,7 +392,8 @@ int subdiv_refine_batch(const subdiv_mesh *meshes, const int *schemes, const int
  * refined from its parent level's adjacency, one thread per parent face /
  * vertex / edge), "loop_edge", "loop_scan", "loop_vertex", "loop_face",
  * "sqrt3_count", "sqrt3_scan", "sqrt3_face", "sqrt3_vertex" (the scans give
- * the next level's edge ids), "bw_coef", "bw_face", "bw_vertex" (adjoint),
+ * the next level's edge ids), "sqrt3_trisect" (SUBDIV_SQRT3_KOBBELT's
+ * trisection step), "bw_coef", "bw_face", "bw_vertex" (adjoint),
  * "batch_extract", "edge_export"; level = the level refined. */
 typedef struct subdiv_stage_time {
   char name[24];

@@ -11,8 +11,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsubdiv.so")
 
-CATMULL_CLARK, LOOP, SQRT3 = 0, 1, 2
-SCHEMES = {"cc": CATMULL_CLARK, "catmull-clark": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3}
+CATMULL_CLARK, LOOP, SQRT3, SQRT3_KOBBELT = 0, 1, 2, 3
+SCHEMES = {"cc": CATMULL_CLARK, "catmull-clark": CATMULL_CLARK, "loop": LOOP, "sqrt3": SQRT3,
+           "sqrt3k": SQRT3_KOBBELT}
 
 STATIC_WORKSPACE_BYTES = 64 << 20  # SUBDIV_STATIC_WORKSPACE_BYTES
 OK, INVALID_ARG, SCHEME_MESH, NONMANIFOLD, DEGENERATE, BAD_CREASE, WORKSPACE, HIP, STATE = 0, -1, -2, -3, -4, -5, \

@@ -115,7 +115,8 @@ struct Sizes {
 // Closed-form counts of the refined levels (index rules of Sec. 3.2, App. A, App. B).
 void level_sizes(int scheme, int levels, long long V0, long long F0, long long H0, long long E0, long long B0,
                  int order0, float max_sharp, long long C0, Sizes *L) {
-  L[0] = Sizes{V0, E0, F0, H0, B0, order0, (scheme != SUBDIV_SQRT3 && C0 > 0 && max_sharp > 0.f) ? 1 : 0};
+  const bool sqrt3 = scheme == SUBDIV_SQRT3 || scheme == SUBDIV_SQRT3_KOBBELT;
+  L[0] = Sizes{V0, E0, F0, H0, B0, order0, (!sqrt3 && C0 > 0 && max_sharp > 0.f) ? 1 : 0};
   for (int k = 0; k < levels; ++k) {
     const Sizes &a = L[k];
     Sizes b{};
@@ -123,6 +124,8 @@ void level_sizes(int scheme, int levels, long long V0, long long F0, long long H
       b = Sizes{a.V + a.F + a.E, 2 * a.E + a.H, a.H, 4 * a.H, 2 * a.B, 4, 0};
     } else if (scheme == SUBDIV_LOOP) {
       b = Sizes{a.V + a.E, 2 * a.E + 3 * a.F, 4 * a.F, 12 * a.F, 2 * a.B, 3, 0};
+    } else if (scheme == SUBDIV_SQRT3_KOBBELT && k % 2 == 1) {  // trisection step: two points per boundary edge
+      b = Sizes{a.V + a.F + a.B, a.E + 3 * a.F + a.B, 3 * a.F, 9 * a.F, 3 * a.B, 3, 0};
     } else {
       b = Sizes{a.V + a.F, a.E + 3 * a.F, 3 * a.F, 9 * a.F, a.B, 3, 0};
     }
@@ -171,6 +174,7 @@ struct Layout {
   size_t hs, term0;    // half rings / corner-0 terms of the corner-class kernels
   size_t tbase;        // edge bases of the next level (triangle schemes with carried adjacency)
   size_t tbase2;       // Loop, second step from below: the edge bases of level L-2 beside level L-3's
+  size_t tslot, trank, tnb;  // sqrt(3) trisection steps: boundary slot and rank per face, boundary neighbours
   size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
@@ -197,7 +201,10 @@ AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool crea
 // Levels >= 1 are built from scratch by the generic mapped product when the
 // caller asks for it; otherwise every scheme carries each level's adjacency
 // over in closed form from the level it was refined from.
-bool rebuilds_levels(int, uint32_t flags) { return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0; }
+// sqrt(3) with Kobbelt's boundary cycle always takes the generic build.
+bool rebuilds_levels(int scheme, uint32_t flags) {
+  return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0 || scheme == SUBDIV_SQRT3_KOBBELT;
+}
 
 // The last two Loop or sqrt(3) steps both run from two levels below them:
 // L >= 4 (so the step before the last reads a refined level, L-3 >= 1) and
@@ -307,6 +314,16 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     y.tbase = c.take(4 * (mX + 1));
     if (tri_lag2(scheme, flags, levels, L))
       y.tbase2 = c.take(4 * ((scheme == SUBDIV_LOOP ? L[levels - 2].E : L[levels - 2].F) + 1));
+  }
+  if (scheme == SUBDIV_SQRT3_KOBBELT && levels >= 2) {  // trisection steps from the odd levels
+    long long tV = 1, tF = 1;
+    for (int k = 1; k < levels; k += 2) {
+      tV = L[k].V > tV ? L[k].V : tV;
+      tF = L[k].F > tF ? L[k].F : tF;
+    }
+    y.tslot = c.take(4 * tF);
+    y.trank = c.take(4 * (tF + 1));
+    y.tnb = c.take(8 * tV);
   }
   if (flags & SUBDIV_FLAG_KEEP_STATE) {
     long long gV = L[0].V, gH = L[0].H;
@@ -469,13 +486,14 @@ Topo cage_topo(const subdiv_mesh *m, long long H, void *ws, const Layout &y) {
 int check_mesh_args(const subdiv_mesh *m, int scheme, int levels) {
   if (!m || !m->face_verts || !m->positions) return SUBDIV_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(m->face_verts) % 16 != 0) return SUBDIV_INVALID_ARG;  // read as int4 rows
-  if (scheme < 0 || scheme > 2 || levels < 1 || levels > SUBDIV_MAX_LEVELS) return SUBDIV_INVALID_ARG;
+  if (scheme < 0 || scheme > SUBDIV_SQRT3_KOBBELT || levels < 1 || levels > SUBDIV_MAX_LEVELS) return SUBDIV_INVALID_ARG;
   if (m->num_vertices < 1 || m->num_faces < 1) return SUBDIV_INVALID_ARG;
   if (!m->face_offsets && m->face_order != 3 && m->face_order != 4) return SUBDIV_INVALID_ARG;
   if (m->face_offsets && m->num_halfedges < 3) return SUBDIV_INVALID_ARG;
   if (m->num_creases < 0 || (m->num_creases > 0 && (!m->crease_verts || !m->crease_sharpness)))
     return SUBDIV_INVALID_ARG;
-  if (m->num_creases > 0 && scheme == SUBDIV_SQRT3) return SUBDIV_INVALID_ARG;  // creases: CC and Loop
+  if (m->num_creases > 0 && (scheme == SUBDIV_SQRT3 || scheme == SUBDIV_SQRT3_KOBBELT))
+    return SUBDIV_INVALID_ARG;  // creases: CC and Loop
   return SUBDIV_OK;
 }
 
@@ -818,7 +836,9 @@ const char *subdiv_strerror(int st) {
 }
 
 size_t subdiv_workspace_bound(int32_t V, int32_t F, int64_t H, int32_t C, int scheme, int levels, uint32_t flags) {
-  if (V < 1 || F < 1 || H < 3 || levels < 1 || levels > SUBDIV_MAX_LEVELS || scheme < 0 || scheme > 2) return 0;
+  if (V < 1 || F < 1 || H < 3 || levels < 1 || levels > SUBDIV_MAX_LEVELS || scheme < 0 ||
+      scheme > SUBDIV_SQRT3_KOBBELT)
+    return 0;
   Sizes L[SUBDIV_MAX_LEVELS + 1];
   // E0 <= H0 and B0 <= H0 bound every later level from above
   level_sizes(scheme, levels, V, F, H, H, H, 0, C > 0 ? 1e30f : 0.f, C, L);
@@ -834,7 +854,7 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   if (st != SUBDIV_OK) return st;
   if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL | SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_INVALID_ARG;
   // the kept state is that of the carried-over adjacency
-  if ((flags & SUBDIV_FLAG_KEEP_STATE) && (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL)) return SUBDIV_INVALID_ARG;
+  if ((flags & SUBDIV_FLAG_KEEP_STATE) && rebuilds_levels(scheme, flags)) return SUBDIV_INVALID_ARG;
   if (!ws) return SUBDIV_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
@@ -1084,9 +1104,21 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
         SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, o, s));
         SUBDIV_TIMED("sqrt3_face", k, tri_lag_launch(LAG_SQRT3_FACE, g, s));
       }
+    } else if (scheme == SUBDIV_SQRT3_KOBBELT && k % 2 == 1) {
+      // the trisection step of the boundary cycle (level k came from a sqrt(3) step)
+      const TrisectStep ts{t, a, P, fv1, P1, at<int32_t>(ws, y.tslot), at<int32_t>(ws, y.trank),
+                           at<int32_t>(ws, y.tnb)};
+      SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_MARK, ts, s));
+      SUBDIV_TIMED("sqrt3_trisect", k, launch_scan(ts.brank, ts.brank, t.F, at<int32_t>(ws, y.partials), nullptr, s));
+      SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_VERTEX, ts, s));
+      SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_FACE, ts, s));
     } else {
-      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, k >= 1 ? (int32_t)L[k - 1].V : 0, aprev,
-                k >= 2 ? (int32_t)L[k - 2].V : 0};
+      // (sqrt(3) with the boundary cycle: a level after a trisection step has
+      // boundary points among its new vertices, so the vertex step walks every
+      // ring on the level itself)
+      const bool walk_own = scheme == SUBDIV_SQRT3_KOBBELT;
+      TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, (k >= 1 && !walk_own) ? (int32_t)L[k - 1].V : 0,
+                aprev, k >= 2 ? (int32_t)L[k - 2].V : 0};
       // before the last step from level k: Loop still needs level k's edge
       // bases; nothing is carried, and level k+1's face table is only written
       // for the caller
@@ -1551,6 +1583,7 @@ int check_batch_args(const subdiv_mesh *m, const int *schemes, const int *levels
     const int st = check_mesh_args(&m[i], schemes[i], levels[i]);
     if (st != SUBDIV_OK) return st;
     if (m[i].num_creases > 0 && schemes[i] != SUBDIV_CATMULL_CLARK) return SUBDIV_INVALID_ARG;  // batches: CC creases
+    if (schemes[i] == SUBDIV_SQRT3_KOBBELT) return SUBDIV_INVALID_ARG;  // not in batches
   }
   return SUBDIV_OK;
 }

@@ -428,6 +428,21 @@ hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
 // inherited sharpness of level k+1's edges into sig1 (cleared by the caller)
 hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s);
 
+// Trisection step of sqrt(3) with Kobbelt's boundary cycle (see tri.hip):
+// level k (whose faces have at most one boundary edge each) to level k+1.
+struct TrisectStep {
+  Topo t;
+  Adj a;            // level k: twin, vhe (the boundary half-edge of a boundary vertex)
+  const float *P;
+  int32_t *fv1;     // [9 F] children
+  float *P1;        // [(V + F + B) * 3]
+  int32_t *bslot;   // [F] slot of the face's boundary edge, or -1
+  int32_t *brank;   // [F + 1] boundary flags, scanned into the ranks among the boundary faces
+  int32_t *bnb;     // [2 V] previous and next boundary neighbour of a boundary vertex
+};
+enum { TRISECT_MARK = 0, TRISECT_FACE = 1, TRISECT_VERTEX = 2 };
+hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s);
+
 // Last Loop or sqrt(3) step k -> k+1 computed from level m = k-1 (which
 // level k was refined from): its faces, edges and adjacency are a quarter
 // (a third) the size of level k's, and level k's are closed-form functions of

@@ -834,6 +834,123 @@ hipError_t loop_crease_launch(const TriStep &c, double *sig1, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------- sqrt(3) with Kobbelt's boundary cycle
+// App. A leaves the sqrt(3) boundary to Kobbelt's sqrt(3) work, whose boundary
+// rule runs over two steps: the first is the sqrt(3) step with the boundary
+// fixed (the kernels above); the second, the trisection step here, splits
+// every boundary edge in three. Reading (the oracle's): a face has at most one
+// boundary edge (every face after a sqrt(3) step does); a boundary face r with
+// boundary edge j = (u, w) gets no face point but two points on that edge, p
+// near u at |v| + r (the face point's index) and q near w at |v| + |f| + (rank
+// of r among the boundary faces), which stand in for the face point wherever
+// a neighbour's flipped edge reaches r: q across r's edge j+1, p across edge
+// j+2. Its children are 3r+j = (p, q, v_j+2), 3r+j+1 = (v_j+1, X_j+1, q) and
+// 3r+j+2 = (v_j+2, X_j+2, p); interior faces split as in the sqrt(3) step.
+// Boundary points follow the ternary refinement of a uniform cubic B-spline
+// curve on the boundary polygon (mask [1 4 10 16 19 16 10 4 1] / 27):
+// p = (u- + 16 u + 10 w) / 27, q = (10 u + 16 w + w+) / 27, a boundary vertex
+// (4 a + 19 v + 4 b) / 27 over its boundary neighbours a, b. Interior vertices
+// and face points are those of the sqrt(3) step.
+
+// per face: the slot of its boundary edge (or -1) and a boundary flag (scanned
+// into the ranks afterwards); per boundary edge u -> w: w is u's next and u is
+// w's previous boundary neighbour
+__global__ void __launch_bounds__(kBlock) k_trisect_mark(TrisectStep c) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= c.t.F) return;
+  int slot = -1;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (c.a.twin[3 * r + j] < 0) slot = j;
+  c.bslot[r] = slot;
+  c.brank[r] = slot >= 0;
+  if (slot >= 0) {
+    const int u = c.t.fv[3 * r + slot], w = c.t.fv[3 * r + (slot + 1) % 3];
+    c.bnb[2 * u + 1] = w;
+    c.bnb[2 * w] = u;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_trisect_vertex(TrisectStep c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c.t.V) return;
+  const f3 p = ld3(c.P, v);
+  f3 S;
+  if (c.a.twin[c.a.vhe[v]] < 0) {  // the canonical half-edge of a boundary vertex is its boundary one
+    const f3 nb = add3(ld3(c.P, c.bnb[2 * v]), ld3(c.P, c.bnb[2 * v + 1]));
+    S = lin2(19.0f / 27.0f, p, 4.0f / 27.0f, nb);
+  } else {
+    const Ring R = ring3(c.t, c.a, c.P, v);
+    S = sqrt3_pt(p, R.sum, R.faces);
+  }
+  st3(c.P1, v, S);
+}
+
+__global__ void __launch_bounds__(kBlock) k_trisect_face(TrisectStep c) {
+  __shared__ uint32_t stage[kBlock / 64][64 * 9];
+  const int rid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = rid < c.t.F;
+  const int r = valid ? rid : c.t.F - 1;
+  const int l = threadIdx.x & 63;
+  uint32_t *lds = stage[threadIdx.x >> 6];
+  const long long rw = (long long)rid - l;  // first face of the wave
+  const int cnt = (int)min(64ll, (long long)c.t.F - rw) * 9;
+  const int V = c.t.V, F = c.t.F;
+  int v[3], X[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    v[i] = c.t.fv[3 * r + i];
+    const int t = c.a.twin[3 * r + i];
+    X[i] = -1;
+    if (t >= 0) {  // the neighbour's point toward r: its face point, or its q across its edge after the boundary one
+      const int s = t / 3, js = c.bslot[s];
+      X[i] = (js >= 0 && t % 3 == (js + 1) % 3) ? V + F + c.brank[s] : V + s;
+    }
+  }
+  const int j = c.bslot[r];
+  const int P_ = V + r, Q = j >= 0 ? V + F + c.brank[r] : -1;
+  if (valid) {
+    if (j < 0) {
+      const f3 sum = add3(add3(ld3(c.P, v[0]), ld3(c.P, v[1])), ld3(c.P, v[2]));
+      st3(c.P1, V + r, mul3(1.0f / 3.0f, sum));
+    } else {
+      const int u = v[j], w = v[(j + 1) % 3];
+      const f3 pu = ld3(c.P, u), pw = ld3(c.P, w);
+      const f3 pum = ld3(c.P, c.bnb[2 * u]), pwp = ld3(c.P, c.bnb[2 * w + 1]);
+      st3(c.P1, P_, add3(lin2(1.0f / 27.0f, pum, 16.0f / 27.0f, pu), mul3(10.0f / 27.0f, pw)));
+      st3(c.P1, Q, add3(lin2(10.0f / 27.0f, pu, 16.0f / 27.0f, pw), mul3(1.0f / 27.0f, pwp)));
+    }
+  }
+  uint32_t row[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    int a0 = v[i], a1 = X[i], a2 = V + r;  // interior: (v_i, X_i, F_r)
+    if (j >= 0) {
+      if (i == j) {
+        a0 = P_, a1 = Q, a2 = v[(i + 2) % 3];
+      } else if (i == (j + 1) % 3) {
+        a2 = Q;
+      } else {
+        a2 = P_;
+      }
+    }
+    row[3 * i + 0] = a0;
+    row[3 * i + 1] = a1;
+    row[3 * i + 2] = a2;
+  }
+  wave_store<9>(lds, row, reinterpret_cast<uint32_t *>(c.fv1) + 9 * rw, l, cnt);
+}
+
+hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s) {
+  if (which == TRISECT_MARK)
+    hipLaunchKernelGGL(k_trisect_mark, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+  else if (which == TRISECT_FACE)
+    hipLaunchKernelGGL(k_trisect_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_trisect_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- Loop, last step
 // Level k+1 computed from level m = k-1, the level that level k was refined
 // from. With E_j = |v_m| + e_j for the edges e_j of a level-m face

@@ -241,3 +241,11 @@ def test_tuning_table_host_calls(lib, tmp_path):
     assert all(_lib.tuning_block(n, 12345) == 256 for n in names)
     default = os.path.join(ROOT, "paper_1809_06047_amd", "tuning_gfx950.json")
     _lib.tuning_load(default if os.path.exists(default) else None)
+
+
+def test_kobbelt_scheme_host_checks(lib):
+    """sqrt(3) with the boundary cycle (scheme 3): sizes bounded like the other
+    schemes; batches and kept state refused without touching the device."""
+    assert lib.subdiv_workspace_bound(162, 304, 912, 0, 3, 4, 0) > 0
+    assert lib.subdiv_workspace_bound(162, 304, 912, 0, 4, 4, 0) == 0
+    assert lib.subdiv_workspace_bound(162, 304, 912, 0, 3, 4, 0) >= lib.subdiv_workspace_bound(162, 304, 912, 0, 2, 4, 0)
