@@ -352,7 +352,9 @@ def scheme_leg(mesh, scheme, levels, steps):
     last = levels - 1  # the last step: level L-1 -> L
     roof = {}
     for (name, lvl), (n, tot) in stages.items():
-        if lvl != last or name not in TRI_BYTES:
+        # (the byte counts are those of the last step from two levels down,
+        # which sqrt(3) with the boundary cycle does not take)
+        if lvl != last or name not in TRI_BYTES or scheme == "sqrt3k":
             continue
         nbytes = TRI_BYTES[name](r.level_info(last), r.level_info(last - 1))
         avg = tot / n
