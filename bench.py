@@ -287,6 +287,7 @@ def main():
         out["static_topology"] = static_leg(mesh, args.levels, max(5, args.steps // 2))
         out["selective"] = selective_leg(mesh, 4, 2, 2, max(3, args.steps // 4))
         out["reorder"] = reorder_leg(mesh, args.levels, max(5, args.steps // 2))
+        out["adaptive"] = adaptive_leg(args.seed, args.levels, 1, max(3, args.steps // 4))
     if args.adjoint_levels > 0 and not args.no_side_legs:
         out["adjoint"] = adjoint_leg(mesh, args.adjoint_levels, max(3, args.steps // 4))
     if args.tri_levels > 0:
@@ -479,6 +480,41 @@ def selective_leg(mesh, base_level, rings, extra_levels, steps):
             "ms_whole_plan_refine": round(ms_whole, 4),
             "region_faces_out": part.level_info(extra_levels)["F"],
             "whole_faces_out": whole.level_info(extra_levels)["F"]}
+
+
+def adaptive_leg(seed, levels, rings, steps):
+    """Feature-adaptive refinement (Sec. 3.4 level after level) of the 10k
+    cage's topology without creases: on every level the region `rings` rings
+    around the cage's extraordinary vertices (pinches closed) is extracted and
+    refined one level; against the uniform refinement of the same cage. Every
+    adaptive level synchronises on its plans and its selection."""
+    import torch
+    from paper_1809_06047_amd import api
+    from paper_1809_06047_amd import meshgen as G
+    mesh = G.cc_cage(seed=seed, crease_frac=0.0)
+    dm = api.DeviceMesh(mesh, "cuda")
+    res = api.adaptive_refine(dm, levels, rings)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.adaptive_refine(dm, levels, rings)
+    torch.cuda.synchronize()
+    ms_adaptive = (time.perf_counter() - t0) * 1000.0 / steps
+    r = api.Refiner(dm, "cc", levels)
+    r.plan()
+    r.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.plan()
+        r.run()
+    torch.cuda.synchronize()
+    ms_uniform = (time.perf_counter() - t0) * 1000.0 / steps
+    return {"workload": f"Catmull-Clark levels 0->{levels} of the 10k cage without creases, {rings} ring(s) around "
+                        "the extraordinary vertices (valence != 4) on every level",
+            "region_faces_per_level": [g["mesh"].F for g in res],
+            "uniform_faces_per_level": [r.level_info(k + 1)["F"] for k in range(levels)],
+            "ms_adaptive": round(ms_adaptive, 4), "ms_uniform_plan_refine": round(ms_uniform, 4)}
 
 
 def adjoint_leg(mesh, levels, steps):

@@ -262,6 +262,7 @@ typedef struct subdiv_selection {
   int32_t num_creases;    /* C' */
   int32_t face_order;     /* the cage's uniform order (3 or 4), or 0: the extraction has a column pointer */
   int32_t rings;
+  uint32_t flags;         /* the selection's flags (subdiv_select_ex) */
   uint64_t priv_stamp;    /* private: the plan it was made with */
   const void *priv_ws;
 } subdiv_selection;
@@ -275,6 +276,9 @@ typedef struct subdiv_extraction {
   float *crease_sharpness;   /* [C'] */
   int32_t *vertex_map;       /* [V'] cage id of every extracted vertex, or NULL */
   int32_t *face_map;         /* [F'] cage id of every extracted face, or NULL */
+  uint8_t *seed_flags;       /* [V'] x_0 of every extracted vertex (1: it was a seed), or NULL: the
+                                seeds carried into the extraction, for feature-adaptive refinement
+                                that selects and extracts again on every refined level */
 } subdiv_extraction;
 
 /* Selection: seed is a [V] device byte mask (non-zero = selected) or NULL for
@@ -284,6 +288,19 @@ typedef struct subdiv_extraction {
  * stream). Returns SUBDIV_STATE without the cage's plan in this workspace. */
 int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings, void *ws,
                   size_t ws_bytes, subdiv_selection *sel, void *stream);
+
+/* The selection with options. SUBDIV_SELECT_CLOSE_PINCHES: after the rings,
+ * every selected vertex whose selected faces form more than one fan around
+ * it (two selected regions touching at one vertex, which would make the
+ * extraction non-manifold there) gets its whole star selected, and the pass
+ * repeats until no such vertex is left (every pass reads the previous pass's
+ * selection only, so the result does not depend on thread order); a
+ * selection still pinched after 16 passes returns SUBDIV_NONMANIFOLD. This is
+ * the selection of feature-adaptive refinement, which extracts again on every
+ * refined level. flags 0 is subdiv_select. */
+#define SUBDIV_SELECT_CLOSE_PINCHES 1u
+int subdiv_select_ex(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings,
+                     uint32_t flags, void *ws, size_t ws_bytes, subdiv_selection *sel, void *stream);
 
 /* Extraction into the caller's buffers; enqueues work only. An empty
  * selection writes nothing. Returns SUBDIV_STATE when sel was not made with
@@ -465,7 +482,8 @@ const char *subdiv_last_error(void);
 /* Human-readable name of a status code. */
 const char *subdiv_strerror(int status);
 
-/* Library version, 1000*major + minor. */
+/* Library version, 1000*major + minor (1001: seed_flags in subdiv_extraction,
+ * SUBDIV_SQRT3_KOBBELT, the tuning table, subdiv_refine_static). */
 int subdiv_version(void);
 
 #ifdef __cplusplus

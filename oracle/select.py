@@ -49,8 +49,58 @@ def mesh_matrix(mesh) -> sp.csc_matrix:
     return sp.csc_matrix((np.ones(rows.size), (rows, cols)), shape=(mesh.num_vertices, len(faces)))
 
 
-def select(mesh, rings: int = 1, seed: Optional[np.ndarray] = None):
-    """(x_rings, q_rings-1) as boolean vectors over the cage's vertices and faces."""
+def _pinched(faces, star, q, v) -> bool:
+    """The selected faces around v form more than one fan: taking two selected
+    faces of v as joined when they share an edge at v, they fall into more
+    than one component."""
+    sel = [f for f in star[v] if q[f]]
+    if len(sel) < 2:
+        return False
+    edges_at_v = {}
+    for f in sel:
+        c = faces[f]
+        i = c.index(v)
+        for w in (c[(i + 1) % len(c)], c[i - 1]):
+            edges_at_v.setdefault(w, []).append(f)
+    parent = {f: f for f in sel}
+
+    def root(f):
+        while parent[f] != f:
+            f = parent[f]
+        return f
+    for fs in edges_at_v.values():
+        for g in fs[1:]:
+            parent[root(g)] = root(fs[0])
+    return len({root(f) for f in sel}) > 1
+
+
+def close_pinches(mesh, x, q, max_passes: int = 16):
+    """Pinch closing (a reading: the paper's extraction does not meet the case
+    of two selected regions touching at one vertex, whose extraction would not
+    be manifold there): every selected vertex whose selected faces form more
+    than one fan gets its whole star selected, q <- q + faces of those stars
+    and x <- M q, pass after pass, each pass reading the previous one's
+    selection, until no such vertex is left."""
+    faces = mesh.face_list()
+    star = [[] for _ in range(mesh.num_vertices)]
+    for f, c in enumerate(faces):
+        for v in c:
+            star[v].append(f)
+    M = mesh_matrix(mesh)
+    for _ in range(max_passes):
+        pinch = [v for v in np.flatnonzero(x) if _pinched(faces, star, q, int(v))]
+        if not pinch:
+            return x, q
+        q = q.copy()
+        for v in pinch:
+            q[star[v]] = True
+        x = (M @ q.astype(np.float64)) > 0
+    raise ValueError("selection still pinched after every pass")
+
+
+def select(mesh, rings: int = 1, seed: Optional[np.ndarray] = None, close: bool = False):
+    """(x_rings, q_rings-1) as boolean vectors over the cage's vertices and
+    faces (with `close`, pinches closed afterwards)."""
     if rings < 1:
         raise ValueError("rings >= 1")
     M = mesh_matrix(mesh)
@@ -64,12 +114,16 @@ def select(mesh, rings: int = 1, seed: Optional[np.ndarray] = None):
         q = (M.T @ x) > 0                      # q_i = M^T x_i
         x = (M @ q.astype(np.float64)) > 0     # x_{i+1} = M q_i
         x = x.astype(np.float64)
+    if close:
+        return close_pinches(mesh, x > 0, q)
     return x > 0, q
 
 
-def extract(mesh, rings: int = 1, seed: Optional[np.ndarray] = None) -> Extracted:
-    """M' = X M X-ring and P' = X P for the selection of `select`."""
-    xs, qs = select(mesh, rings, seed)
+def extract(mesh, rings: int = 1, seed: Optional[np.ndarray] = None, dtype=np.float32,
+            close: bool = False) -> Extracted:
+    """M' = X M X-ring and P' = X P for the selection of `select` (positions
+    copied in `dtype`; with `close`, pinches closed)."""
+    xs, qs = select(mesh, rings, seed, close)
     vsel = np.flatnonzero(xs).astype(np.int32)
     fsel = np.flatnonzero(qs).astype(np.int32)
     newid = np.full(mesh.num_vertices, -1, np.int64)
@@ -80,7 +134,7 @@ def extract(mesh, rings: int = 1, seed: Optional[np.ndarray] = None) -> Extracte
     sizes = np.array([len(f) for f in kept], np.int64)
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     verts = np.array([v for f in kept for v in f], np.int32)
-    P = np.asarray(mesh.positions, np.float32)[vsel]
+    P = np.asarray(mesh.positions, dtype)[vsel]
     # creases on edges of the extracted faces
     edges = set()
     for f in kept:
@@ -99,3 +153,55 @@ def extract(mesh, rings: int = 1, seed: Optional[np.ndarray] = None) -> Extracte
     crease_sharp = np.array([cs[i] for i in order], np.float32)
     return Extracted(offsets=offsets, verts=verts, positions=P, crease_verts=crease_verts,
                      crease_sharp=crease_sharp, vertex_map=vsel, face_map=fsel)
+
+
+class _Region:
+    """A level's mesh for the selection: faces, FP64 positions, no creases."""
+
+    def __init__(self, offsets, verts, positions):
+        self.offsets = np.asarray(offsets, np.int64)
+        self.verts = np.asarray(verts, np.int64)
+        self.positions = np.asarray(positions, np.float64)
+        self.num_vertices = self.positions.shape[0]
+        self.crease_verts = None
+        self.crease_sharp = None
+
+    def face_list(self):
+        o = self.offsets
+        return [self.verts[o[i]:o[i + 1]].tolist() for i in range(len(o) - 1)]
+
+
+@dataclasses.dataclass
+class AdaptiveLevel:
+    region: Extracted          # the extraction of level k (maps into level k's mesh), FP64 positions
+    refined: object            # the region refined one Catmull-Clark level (an oracle Level)
+    seed: np.ndarray           # (V_{k+1},) seed flags of the refined region's vertices
+
+
+def adaptive(mesh, levels: int, rings: int = 1, seed: Optional[np.ndarray] = None):
+    """Feature-adaptive refinement, Sec. 3.4 applied level after level: select
+    and extract the region `rings` rings around the seeds, refine only the
+    region one Catmull-Clark level (the oracle's step, FP64 throughout), and
+    carry the seeds - the cage's extraordinary vertices unless given - to the
+    refined region, where the extracted vertices keep their ids and the new
+    points are not seeds. Every selection closes its pinches (see
+    close_pinches). Stops early when a selection is empty."""
+    from . import CATMULL_CLARK, Level, level_from_mesh, step
+    lv0 = level_from_mesh(mesh)
+    cur = _Region(lv0.offsets, lv0.verts, lv0.positions)
+    if seed is None:
+        M = mesh_matrix(cur)
+        seed = (np.asarray(M @ np.ones(M.shape[1])).ravel() != 4).astype(np.uint8)
+    out = []
+    for _ in range(int(levels)):
+        e = extract(cur, rings, seed, dtype=np.float64, close=True)
+        if e.vertex_map.size == 0:
+            break
+        lv = step(Level(offsets=e.offsets, verts=e.verts, positions=e.positions,
+                        crease_verts=np.zeros((0, 2), np.int32), crease_sharp=np.zeros(0)), CATMULL_CLARK)
+        nseed = np.zeros(lv.num_vertices, np.uint8)
+        nseed[:e.vertex_map.size] = np.asarray(seed)[e.vertex_map]
+        out.append(AdaptiveLevel(region=e, refined=lv, seed=nseed))
+        cur = _Region(lv.offsets, lv.verts, lv.positions)
+        seed = nseed
+    return out

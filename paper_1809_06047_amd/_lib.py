@@ -21,6 +21,7 @@ OK, INVALID_ARG, SCHEME_MESH, NONMANIFOLD, DEGENERATE, BAD_CREASE, WORKSPACE, HI
 MAX_LEVELS = 10
 MAX_VALENCE = 1024
 FLAG_REBUILD_EACH_LEVEL = 1
+SELECT_CLOSE_PINCHES = 1
 FLAG_KEEP_STATE = 2
 
 c_i32, c_i64, c_u32, c_u64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, \
@@ -55,12 +56,12 @@ class subdiv_stage_time(ctypes.Structure):
 
 class subdiv_selection(ctypes.Structure):
     _fields_ = [("num_vertices", c_i32), ("num_faces", c_i32), ("num_halfedges", c_i32), ("num_creases", c_i32),
-                ("face_order", c_i32), ("rings", c_i32), ("priv_stamp", c_u64), ("priv_ws", c_vp)]
+                ("face_order", c_i32), ("rings", c_i32), ("flags", c_u32), ("priv_stamp", c_u64), ("priv_ws", c_vp)]
 
 
 class subdiv_extraction(ctypes.Structure):
     _fields_ = [("face_offsets", c_vp), ("face_verts", c_vp), ("positions", c_vp), ("crease_verts", c_vp),
-                ("crease_sharpness", c_vp), ("vertex_map", c_vp), ("face_map", c_vp)]
+                ("crease_sharpness", c_vp), ("vertex_map", c_vp), ("face_map", c_vp), ("seed_flags", c_vp)]
 
 
 class subdiv_kernel_time(ctypes.Structure):
@@ -86,6 +87,8 @@ SIGNATURES = {
     "subdiv_rcm_order": (ctypes.c_int, [c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "subdiv_select": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp, ctypes.c_int,
                                      c_vp, c_sz, ctypes.POINTER(subdiv_selection), c_vp]),
+    "subdiv_select_ex": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info), c_vp,
+                                        ctypes.c_int, c_u32, c_vp, c_sz, ctypes.POINTER(subdiv_selection), c_vp]),
     "subdiv_extract": (ctypes.c_int, [ctypes.POINTER(subdiv_mesh), ctypes.POINTER(subdiv_plan_info),
                                       ctypes.POINTER(subdiv_selection), ctypes.POINTER(subdiv_extraction), c_vp, c_sz,
                                       c_vp]),

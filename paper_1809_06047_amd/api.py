@@ -277,7 +277,8 @@ def refine(mesh, scheme, levels: int, flags: int = 0, keep: str = "final", edges
     return outs, r
 
 
-def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int = 1, stream=None) -> Dict:
+def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int = 1, stream=None,
+                   close_pinches: bool = False) -> Dict:
     """Selective subdivision (Sec. 3.4): the region around the seed vertices
     of `r`'s cage (planned with r.plan()), `rings` face rings deep, as a cage
     of its own. seed: [V] uint8/bool device mask, or None for the
@@ -294,9 +295,9 @@ def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int
         seed = seed.to(torch.uint8).contiguous()
         seed_ptr = ctypes.c_void_p(seed.data_ptr())
     sel = _lib.subdiv_selection()
-    check(lib.subdiv_select(ctypes.byref(d.struct), ctypes.byref(r.plan_info), seed_ptr, int(rings),
-                            ctypes.c_void_p(r.ws.data_ptr()), r.ws_bytes, ctypes.byref(sel), ctypes.c_void_p(s)),
-          "subdiv_select")
+    check(lib.subdiv_select_ex(ctypes.byref(d.struct), ctypes.byref(r.plan_info), seed_ptr, int(rings),
+                               _lib.SELECT_CLOSE_PINCHES if close_pinches else 0, ctypes.c_void_p(r.ws.data_ptr()),
+                               r.ws_bytes, ctypes.byref(sel), ctypes.c_void_p(s)), "subdiv_select_ex")
     V1, F1, H1, C1, order = sel.num_vertices, sel.num_faces, sel.num_halfedges, sel.num_creases, sel.face_order
     dev = d.device
     out = {"positions": torch.empty((V1, 3), dtype=torch.float32, device=dev),
@@ -306,9 +307,10 @@ def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int
            "crease_verts": torch.empty((C1, 2), dtype=torch.int32, device=dev) if C1 else None,
            "crease_sharpness": torch.empty(C1, dtype=torch.float32, device=dev) if C1 else None,
            "vertex_map": torch.empty(V1, dtype=torch.int32, device=dev),
-           "face_map": torch.empty(F1, dtype=torch.int32, device=dev)}
+           "face_map": torch.empty(F1, dtype=torch.int32, device=dev),
+           "seed_flags": torch.empty(V1, dtype=torch.uint8, device=dev)}
     e = _lib.subdiv_extraction()
-    for k in ("positions", "face_verts", "face_offsets", "crease_verts", "vertex_map", "face_map"):
+    for k in ("positions", "face_verts", "face_offsets", "crease_verts", "vertex_map", "face_map", "seed_flags"):
         if out[k] is not None and out[k].numel():
             setattr(e, k, out[k].data_ptr())
     if out["crease_sharpness"] is not None:
@@ -318,6 +320,51 @@ def extract_region(r: "Refiner", seed: Optional[torch.Tensor] = None, rings: int
     out["mesh"] = None if V1 == 0 else DeviceMesh.from_tensors(
         out["face_verts"], out["face_offsets"], out["positions"], out["crease_verts"], out["crease_sharpness"],
         order if order else 0, name=f"{d.name}-region")
+    return out
+
+
+def adaptive_refine(mesh, levels: int, rings: int = 1, seed: Optional[torch.Tensor] = None, device="cuda",
+                    stream=None) -> List[Dict]:
+    """Feature-adaptive Catmull-Clark refinement (Sec. 3.4, level after
+    level): on every level the region `rings` face rings around the seeds is
+    selected and extracted (subdiv_select, subdiv_extract), and only that
+    region is refined one level (subdiv_plan, subdiv_refine); the seeds - the
+    cage's extraordinary vertices (valence != 4) unless `seed` is given - keep
+    their ids through the refinement and are carried into every extraction
+    (the extraction's seed flags), while the extraction's own boundary never
+    seeds; pinches (regions touching at one vertex) are closed
+    (SUBDIV_SELECT_CLOSE_PINCHES). Returns, per level k = 0 .. levels-1
+    (fewer when a selection comes out empty), the extraction of level k
+    ("region": DeviceMesh, with vertex_map / face_map into level k's mesh)
+    and the refined region of level k + 1 ("mesh": DeviceMesh, whose first
+    region-vertex-count vertices are the region's vertices). Cages with creases are refused (the
+    refined region's sharpness would have to become a crease list again).
+    Each level synchronises on the plans and the selection (sizes)."""
+    dm = mesh if isinstance(mesh, DeviceMesh) else DeviceMesh(mesh, device)
+    if dm.C:
+        raise ValueError("adaptive_refine takes cages without creases")
+    out = []
+    cur = Refiner(dm, "cc", 1)
+    cur.plan(stream)
+    for k in range(int(levels)):
+        reg = extract_region(cur, seed, rings, stream, close_pinches=True)
+        if reg["mesh"] is None:
+            break
+        rr = Refiner(reg["mesh"], "cc", 1)
+        rr.plan(stream)
+        fin = rr.run(stream)[1]
+        V1 = rr.level_info(1)["V"]
+        nxt = DeviceMesh.from_tensors(fin["face_verts"], None, fin["positions"], None, None, 4,
+                                      name=f"{dm.name}-adaptive{k + 1}")
+        out.append({"level": k, "region": reg["mesh"], "vertex_map": reg["vertex_map"], "face_map": reg["face_map"],
+                    "mesh": nxt})
+        # the region's vertices keep their ids in its refinement; the new
+        # points never seed
+        seed = torch.zeros(V1, dtype=torch.uint8, device=dm.device)
+        seed[:reg["mesh"].V].copy_(reg["seed_flags"])
+        if k + 1 < levels:
+            cur = Refiner(nxt, "cc", 1)
+            cur.plan(stream)
     return out
 
 

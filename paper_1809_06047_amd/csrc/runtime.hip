@@ -167,7 +167,8 @@ struct Layout {
   size_t nval, rowptr, cursor, inc, cand, cntlo, ebase, bflag, sigcnt, partials0;
   size_t hface0;
   AdjOffsets adj0;
-  size_t sel_x[2], sel_q, sel_vnew, sel_fnew, sel_onew, sel_flag, sel_cnew, sel_totals;  // selective extraction
+  size_t sel_x[2], sel_q, sel_vnew, sel_fnew, sel_onew, sel_flag, sel_cnew, sel_totals, sel_x0;  // selective extraction
+  size_t sel_qadd, sel_changed;
   size_t level0_end;
   // per-level regions
   AdjOffsets slot[3];  // adjacency of levels k-2, k-1, k rotate through these (index level % 3)
@@ -249,6 +250,9 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   y.sel_flag = c.take(4 * ((F0 > H0 ? F0 : H0) + 1));
   y.sel_cnew = c.take(4 * (H0 + 1));
   y.sel_totals = c.take(16);
+  y.sel_x0 = c.take(V0);
+  y.sel_qadd = c.take(4 * F0);
+  y.sel_changed = c.take(4 * kPinchPasses);
   y.level0_end = c.at;
   // everything below may depend on the level count and on E0
   long long maxn = 1;
@@ -453,6 +457,9 @@ SelectScratch select_scratch(void *ws, const Layout &y) {
   w.cnew = at<int32_t>(ws, y.sel_cnew);
   w.partials = at<int32_t>(ws, y.partials0);
   w.totals = at<int32_t>(ws, y.sel_totals);
+  w.seed0 = at<uint8_t>(ws, y.sel_x0);
+  w.qadd = at<int32_t>(ws, y.sel_qadd);
+  w.changed = at<int32_t>(ws, y.sel_changed);
   return w;
 }
 
@@ -733,7 +740,7 @@ void subdiv_set_error(const char *msg) { g_last_error = msg ? msg : ""; }
 // ---- the C ABI ---------------------------------------------------------
 extern "C" {
 
-int subdiv_version(void) { return 1000; }
+int subdiv_version(void) { return 1001; }
 
 void subdiv_timing_enable(int on) { g_timing.store(on != 0); }
 
@@ -1250,9 +1257,14 @@ int subdiv_refine_vertex_data(const subdiv_mesh *mesh, const subdiv_plan_info *p
 
 int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings, void *ws,
                   size_t ws_bytes, subdiv_selection *sel, void *stream) {
+  return subdiv_select_ex(mesh, plan, seed, rings, 0u, ws, ws_bytes, sel, stream);
+}
+
+int subdiv_select_ex(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const uint8_t *seed, int rings,
+                     uint32_t flags, void *ws, size_t ws_bytes, subdiv_selection *sel, void *stream) {
   if (!sel) return SUBDIV_INVALID_ARG;
   std::memset(sel, 0, sizeof(*sel));
-  if (!plan || !ws || !mesh || rings < 1) return SUBDIV_INVALID_ARG;
+  if (!plan || !ws || !mesh || rings < 1 || (flags & ~SUBDIV_SELECT_CLOSE_PINCHES)) return SUBDIV_INVALID_ARG;
   if (plan->priv_stamp == 0 || mesh->face_verts != plan->priv_mesh_verts || ws != plan->priv_ws ||
       ws_record(ws).plan != plan->priv_stamp)
     return SUBDIV_STATE;
@@ -1269,16 +1281,20 @@ int subdiv_select(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const u
   const Topo t = cage_topo(mesh, H0, ws, y);
   const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0);
   const SelectScratch w = select_scratch(ws, y);
-  SUBDIV_TRY(select_region(t, a, w, seed, at<int32_t>(ws, y.nval), rings, s));
-  int32_t tot[4];
+  const bool close = (flags & SUBDIV_SELECT_CLOSE_PINCHES) != 0;
+  SUBDIV_TRY(select_region(t, a, w, seed, at<int32_t>(ws, y.nval), rings, close, s));
+  int32_t tot[4], last = 0;
   SUBDIV_TRY(hipMemcpyAsync(tot, w.totals, sizeof(tot), hipMemcpyDeviceToHost, s));
+  if (close) SUBDIV_TRY(hipMemcpyAsync(&last, w.changed + kPinchPasses - 1, 4, hipMemcpyDeviceToHost, s));
   SUBDIV_TRY(hipStreamSynchronize(s));
+  if (last) return SUBDIV_NONMANIFOLD;  // still pinched after every pass
   sel->num_vertices = tot[0];
   sel->num_faces = tot[1];
   sel->num_halfedges = t.order > 0 ? tot[1] * t.order : tot[2];
   sel->num_creases = tot[3];
   sel->face_order = t.order;
   sel->rings = rings;
+  sel->flags = flags;
   sel->priv_stamp = plan->priv_stamp;
   sel->priv_ws = ws;
   return SUBDIV_OK;
@@ -1306,8 +1322,8 @@ int subdiv_extract(const subdiv_mesh *mesh, const subdiv_plan_info *plan, const 
   const Layout y = make_layout(plan->scheme, plan->levels, plan->flags, L, mesh->num_creases);
   const Topo t = cage_topo(mesh, H0, ws, y);
   const Adj a = adj_at(ws, y.adj0, L[0].E, mesh->num_creases > 0);
-  ExtractOut o{out->face_verts, out->face_offsets, out->face_map, out->vertex_map, out->crease_verts,
-               out->positions, out->crease_sharpness, sel->num_faces, sel->num_creases};
+  ExtractOut o{out->seed_flags, out->face_verts, out->face_offsets, out->face_map, out->vertex_map,
+               out->crease_verts, out->positions, out->crease_sharpness, sel->num_faces, sel->num_creases};
   SUBDIV_TRY(extract_region(t, a, select_scratch(ws, y), sel->rings, mesh->positions, o, s));
   return SUBDIV_OK;
 }

@@ -18,10 +18,12 @@
 
 namespace subdiv {
 
-__global__ void k_sel_seed(int V, const uint8_t *seed, const int32_t *valence, int32_t *x) {
+__global__ void k_sel_seed(int V, const uint8_t *seed, const int32_t *valence, int32_t *x, uint8_t *x0) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  x[v] = seed ? (seed[v] != 0) : (valence[v] != 4);
+  const int s = seed ? (seed[v] != 0) : (valence[v] != 4);
+  x[v] = s;
+  x0[v] = (uint8_t)s;  // kept for the extraction's seed flags (x[] is overwritten by later rings)
 }
 
 template <int ORDER>
@@ -37,6 +39,59 @@ template <int ORDER>
 __global__ void k_sel_mark(Topo t, const int32_t *q, int32_t *x) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= t.F || !q[f]) return;
+  for (int h = face_begin<ORDER>(t, f); h < face_end<ORDER>(t, f); ++h) x[t.fv[h]] = 1;
+}
+
+// Pinch closing (a reading; the paper's extraction matrices do not meet the
+// case): two selected regions that touch at one vertex would give the
+// extraction a vertex with two fans, which is no manifold. Per pass, every
+// selected vertex whose selected faces around it form more than one run in
+// rotation order marks its whole star (into qadd: the pass reads q alone, so
+// the result does not depend on lane order); the merge then adds those faces
+// to q and their corners to x. A pass whose predecessor changed nothing does
+// nothing.
+template <int ORDER>
+__global__ void k_pinch_find(Topo t, Adj a, const int32_t *q, const int32_t *x, int32_t *qadd, int32_t *changed,
+                             int pass) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= t.V || !x[v] || (pass > 0 && changed[pass - 1] == 0)) return;
+  const int h0 = a.vhe[v];
+  int runs = 0, first = -1, prev = -1, n = 0;
+  int h = h0;
+  while (true) {
+    const int sel = q[he_face<ORDER>(t, h)] != 0;
+    if (n == 0) first = sel;
+    else runs += (sel && !prev);
+    prev = sel;
+    ++n;
+    const int tw = a.twin[he_prev<ORDER>(t, h)];
+    if (tw < 0) {  // the fan ends at the boundary: the first run starts at the first face
+      runs += first;
+      break;
+    }
+    if (tw == h0 || n >= SUBDIV_MAX_VALENCE) {  // closed: the first face follows the last
+      runs += (first && !prev);
+      if (runs == 0 && first) runs = 1;  // the whole star
+      break;
+    }
+    h = tw;
+  }
+  if (runs < 2) return;
+  h = h0;
+  for (int i = 0; i < n; ++i) {
+    qadd[he_face<ORDER>(t, h)] = 1;
+    const int tw = a.twin[he_prev<ORDER>(t, h)];
+    if (tw < 0) break;
+    h = tw;
+  }
+  changed[pass] = 1;
+}
+
+template <int ORDER>
+__global__ void k_pinch_merge(Topo t, int32_t *q, int32_t *x, const int32_t *qadd, const int32_t *changed, int pass) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= t.F || changed[pass] == 0 || !qadd[f]) return;
+  q[f] = 1;
   for (int h = face_begin<ORDER>(t, f); h < face_end<ORDER>(t, f); ++h) x[t.fv[h]] = 1;
 }
 
@@ -63,12 +118,13 @@ __global__ void k_sel_creases(Topo t, Adj a, const int32_t *q, int32_t *flag) {
 }
 
 __global__ void k_ext_vertices(int V, const int32_t *x, const int32_t *vnew, const float *P, float *P1,
-                               int32_t *vmap) {
+                               int32_t *vmap, const uint8_t *x0, uint8_t *seed1) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V || !x[v]) return;
   const int n = vnew[v];
   st3(P1, n, ld3(P, v));
   if (vmap) vmap[n] = v;
+  if (seed1) seed1[n] = x0[v];
 }
 
 template <int ORDER>
@@ -100,11 +156,11 @@ __global__ void k_ext_creases(Topo t, Adj a, const int32_t *flag, const int32_t 
 
 template <int ORDER>
 static hipError_t select_t(const Topo &t, const Adj &a, const SelectScratch &w, const uint8_t *seed,
-                           const int32_t *valence, int rings, hipStream_t s) {
+                           const int32_t *valence, int rings, bool close_pinches, hipStream_t s) {
   hipError_t err;
   const unsigned gv = grid_for(t.V), gf = grid_for(t.F), gh = grid_for(t.H);
   int32_t *x = w.x[0], *xn = w.x[1];
-  hipLaunchKernelGGL(k_sel_seed, dim3(gv), dim3(kBlock), 0, s, t.V, seed, valence, x);
+  hipLaunchKernelGGL(k_sel_seed, dim3(gv), dim3(kBlock), 0, s, t.V, seed, valence, x, w.seed0);
   for (int i = 0; i < rings; ++i) {
     hipLaunchKernelGGL(k_sel_faces<ORDER>, dim3(gf), dim3(kBlock), 0, s, t, x, w.q);
     if ((err = launch_fill_i32(xn, 0, t.V, s)) != hipSuccess) return err;
@@ -114,6 +170,14 @@ static hipError_t select_t(const Topo &t, const Adj &a, const SelectScratch &w, 
     xn = tmp;
   }
   // the final vertex flags always sit in x[rings & 1]
+  if (close_pinches) {
+    if ((err = launch_fill_i32(w.qadd, 0, t.F, s)) != hipSuccess) return err;
+    if ((err = launch_fill_i32(w.changed, 0, kPinchPasses, s)) != hipSuccess) return err;
+    for (int p = 0; p < kPinchPasses; ++p) {
+      hipLaunchKernelGGL(k_pinch_find<ORDER>, dim3(gv), dim3(kBlock), 0, s, t, a, w.q, x, w.qadd, w.changed, p);
+      hipLaunchKernelGGL(k_pinch_merge<ORDER>, dim3(gf), dim3(kBlock), 0, s, t, w.q, x, w.qadd, w.changed, p);
+    }
+  }
   if ((err = launch_scan(x, w.vnew, t.V, w.partials, w.totals + 0, s)) != hipSuccess) return err;
   if ((err = launch_scan(w.q, w.fnew, t.F, w.partials, w.totals + 1, s)) != hipSuccess) return err;
   if (ORDER == 0) {
@@ -130,17 +194,18 @@ static hipError_t select_t(const Topo &t, const Adj &a, const SelectScratch &w, 
 }
 
 hipError_t select_region(const Topo &t, const Adj &a, const SelectScratch &w, const uint8_t *seed,
-                         const int32_t *valence, int rings, hipStream_t s) {
-  if (t.order == 4) return select_t<4>(t, a, w, seed, valence, rings, s);
-  if (t.order == 3) return select_t<3>(t, a, w, seed, valence, rings, s);
-  return select_t<0>(t, a, w, seed, valence, rings, s);
+                         const int32_t *valence, int rings, bool close_pinches, hipStream_t s) {
+  if (t.order == 4) return select_t<4>(t, a, w, seed, valence, rings, close_pinches, s);
+  if (t.order == 3) return select_t<3>(t, a, w, seed, valence, rings, close_pinches, s);
+  return select_t<0>(t, a, w, seed, valence, rings, close_pinches, s);
 }
 
 template <int ORDER>
 static hipError_t extract_t(const Topo &t, const Adj &a, const SelectScratch &w, int rings, const float *P,
                             const ExtractOut &o, hipStream_t s) {
   const int32_t *x = w.x[rings & 1];
-  hipLaunchKernelGGL(k_ext_vertices, dim3(grid_for(t.V)), dim3(kBlock), 0, s, t.V, x, w.vnew, P, o.P, o.vmap);
+  hipLaunchKernelGGL(k_ext_vertices, dim3(grid_for(t.V)), dim3(kBlock), 0, s, t.V, x, w.vnew, P, o.P, o.vmap,
+                     (const uint8_t *)w.seed0, o.seed);
   hipLaunchKernelGGL(k_ext_faces<ORDER>, dim3(grid_for(t.F)), dim3(kBlock), 0, s, t, w.q, w.fnew, w.onew, w.vnew,
                      o.fv, o.off, o.fmap, o.F);
   if (a.sig && o.C > 0) {

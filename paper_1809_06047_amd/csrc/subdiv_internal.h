@@ -343,15 +343,24 @@ struct SelectScratch {
   int32_t *cnew;               // [H+1] crease ids
   int32_t *partials;           // scan partials (max(V, H) items)
   int32_t *totals;             // [4] V', F', H' (general cages), C'
+  uint8_t *seed0;              // [V] the seed flags x_0
+  int32_t *qadd;               // [F] faces added by the pinch passes
+  int32_t *changed;            // [kPinchPasses] 1 when that pass added faces
 };
+// passes of the pinch closing of a selection (SUBDIV_SELECT_CLOSE_PINCHES)
+constexpr int kPinchPasses = 16;
 struct ExtractOut {
+  uint8_t *seed;               // [V'] x_0 of every extracted vertex, or nullptr
   int32_t *fv, *off, *fmap, *vmap, *cv;
   float *P, *cs;
   int32_t F, C;
 };
 // flags and scans; totals are left on the device for one read-back
+// close_pinches: after the rings, every selected vertex whose selected faces
+// form more than one fan gets its whole star selected, pass after pass, until
+// no such vertex is left (at most kPinchPasses passes; changed[] tells)
 hipError_t select_region(const Topo &t, const Adj &a, const SelectScratch &w, const uint8_t *seed,
-                         const int32_t *valence, int rings, hipStream_t s);
+                         const int32_t *valence, int rings, bool close_pinches, hipStream_t s);
 hipError_t extract_region(const Topo &t, const Adj &a, const SelectScratch &w, int rings, const float *P,
                           const ExtractOut &o, hipStream_t s);
 

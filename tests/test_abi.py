@@ -44,7 +44,7 @@ def test_struct_layouts_match_header():
 
 
 def test_host_entry_points(lib):
-    assert lib.subdiv_version() == 1000
+    assert lib.subdiv_version() == 1001
     assert lib.subdiv_strerror(-3) == b"non-manifold or inconsistently oriented mesh"
     assert lib.subdiv_last_error() == b""
     # workspace bound: grows with levels, zero on invalid input or int32 overflow

@@ -99,3 +99,83 @@ def test_refining_the_extraction_matches_the_uniform_refinement_near_the_seed():
 def test_rings_must_be_positive():
     with pytest.raises(ValueError):
         S.extract(_grid(), rings=0)
+
+
+def _smooth_cage(seed=24, level=2):
+    return G.cc_cage(seed=seed, level=level, crease_frac=0.0)
+
+
+def test_adaptive_with_wide_rings_is_uniform_refinement():
+    """Rings wide enough to reach every face: every level's extraction is the
+    whole level, so the adaptive chain is the uniform refinement, bit for bit
+    in FP64."""
+    m = _smooth_cage(level=1)
+    ad = S.adaptive(m, 3, rings=50)
+    uni = refine(m, "cc", 3)
+    assert len(ad) == 3
+    for k, a in enumerate(ad):
+        assert a.region.vertex_map.tolist() == list(range(uni[k].num_vertices))
+        np.testing.assert_array_equal(a.refined.verts, uni[k + 1].verts)
+        np.testing.assert_array_equal(a.refined.positions, uni[k + 1].positions)
+
+
+def _seed_chain(ad, seeds):
+    """Ids of the cage's seed vertices on every refined region (old vertices
+    keep their ids; the extraction renumbers by rank)."""
+    ids, out = np.asarray(seeds), []
+    for a in ad:
+        vm = a.region.vertex_map
+        pos = np.searchsorted(vm, ids)
+        assert np.all(vm[pos] == ids), "a seed left the region"
+        ids = pos
+        out.append(ids.copy())
+    return out
+
+
+@pytest.mark.parametrize("rings", [1, 2])
+def test_adaptive_keeps_the_seeds_exact(rings):
+    """A seed's vertex point needs only its star, whose faces and corners the
+    extraction keeps at every level; refined again and again, the seeds end
+    where the uniform refinement puts them (same FP64 stencils). The region
+    stays a fraction of the uniform level."""
+    m = _smooth_cage()
+    L = 3
+    ad = S.adaptive(m, L, rings=rings)
+    uni = refine(m, "cc", L)
+    M = S.mesh_matrix(m)
+    seeds = np.flatnonzero(np.asarray(M @ np.ones(M.shape[1])).ravel() != 4)
+    assert seeds.size > 0
+    for k, ids in enumerate(_seed_chain(ad, seeds)):
+        np.testing.assert_allclose(ad[k].refined.positions[ids], uni[k + 1].positions[seeds], rtol=0, atol=1e-12)
+        assert ad[k].refined.num_faces <= uni[k + 1].num_faces
+    assert ad[-1].refined.num_faces < (0.5 if rings == 1 else 1.0) * uni[L].num_faces
+
+
+def test_adaptive_seed_flags_follow_the_old_vertices():
+    m = _smooth_cage()
+    ad = S.adaptive(m, 2, rings=1)
+    for a in ad:
+        nv = a.region.vertex_map.size
+        assert not a.seed[nv:].any()  # new points never seed
+    M = S.mesh_matrix(m)
+    n0 = int((np.asarray(M @ np.ones(M.shape[1])).ravel() != 4).sum())
+    assert int(ad[0].seed.sum()) == n0 and int(ad[1].seed.sum()) == n0
+
+
+def test_pinch_closing_joins_regions_touching_at_a_vertex():
+    """Two seeds on a grid diagonal two apart: their one-ring regions meet
+    at one vertex only, which the plain extraction leaves with two fans; the
+    closed selection adds that vertex's whole star, and the two regions
+    become one manifold patch."""
+    m = _grid()
+    seed = np.zeros(m.num_vertices, np.uint8)
+    seed[_vid(1, 1)] = 1
+    seed[_vid(3, 3)] = 1
+    x, q = S.select(m, 1, seed)
+    assert q.sum() == 8  # two 2 x 2 blocks of quads sharing the vertex (2, 2)
+    xc, qc = S.select(m, 1, seed, close=True)
+    assert qc.sum() == 10 and qc[1 * 4 + 2] and qc[2 * 4 + 1]  # the two faces around (2, 2) between the blocks
+    assert xc.sum() == x.sum() + 2
+    faces = m.face_list()
+    star = [[f for f, c in enumerate(faces) if v in c] for v in range(m.num_vertices)]
+    assert not any(S._pinched(faces, star, qc, v) for v in np.flatnonzero(xc))
