@@ -584,7 +584,8 @@ def serving(args):
     for p in res["points"]:
         pts.append({"factor": p["factor"], "qps": round(p["qps"], 1),
                     "batched": side(p["batched"], ("p50_ms", "p99_ms", "faces_per_s", "mean_batch", "max_queue")),
-                    "per_mesh": side(p["per_mesh"], ("p50_ms", "p99_ms", "faces_per_s"))})
+                    "per_mesh": side(p["per_mesh"], ("p50_ms", "p99_ms", "faces_per_s")),
+                    "per_mesh_cached_plans": side(p["per_mesh_cached"], ("p50_ms", "p99_ms", "faces_per_s"))})
     cold = res.get("cold_cache")
     if cold:
         cold = {"factor": cold["factor"], "registered": cold["registered"],
@@ -596,6 +597,8 @@ def serving(args):
                               "per batch, no host round trip; topology cache warm (every cage topology of the "
                               "trace planned once before the timed runs)",
             "per_mesh_server": "one subdiv_plan (with its read-back) + subdiv_refine per request, FIFO, one stream",
+            "per_mesh_cached_plans_server": "one request at a time through the batched server's executor and topology "
+                                            "cache (kept plan, one positions upload, the mesh refined alone), FIFO",
             "points": pts, "cold_cache": cold}
 
 

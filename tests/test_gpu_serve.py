@@ -64,5 +64,5 @@ def test_sweep_runs_end_to_end():
     assert res["cold_cache"]["batched"]["served"] == 32
     (p,) = res["points"]
     assert res["per_mesh_saturation_qps"] > 0
-    for side in ("batched", "per_mesh"):
+    for side in ("batched", "per_mesh", "per_mesh_cached"):
         assert p[side]["served"] == 32 and p[side]["p99_ms"] >= p[side]["p50_ms"] > 0
