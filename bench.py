@@ -129,12 +129,17 @@ class TwoDeep:
     validates, builds and refines its cage in full."""
 
     def __init__(self, dmesh, levels, scheme="cc"):
+        import torch
         from paper_1809_06047_amd import api
         self.dmesh = dmesh
         self.sr = api.StreamingRefiner(scheme, levels)
         for _ in range(2):  # both slots' refiners exist from the start
             self.sr.step(dmesh)
         self.rs = [self.sr.refiner(0), self.sr.refiner(1)]
+        # the slots' refinements run on non-blocking streams: they must be done
+        # before a caller plans or refines with these refiners on another
+        # stream (a plan rewrites the workspace a refinement still reads)
+        torch.cuda.synchronize()
 
     def step(self):
         self.sr.step(self.dmesh)

@@ -434,6 +434,10 @@ class StreamingRefiner:
         self.i = 0
 
     def refiner(self, slot: int) -> Optional[Refiner]:
+        """The slot's refiner. Its last refinement may still run on the slot's
+        stream (non-blocking): wait for it (the event step() returned, or a
+        device synchronisation) before planning or refining with it on another
+        stream, since a plan rewrites the workspace that refinement reads."""
         return self.slots[slot]
 
     def step(self, dmesh: "DeviceMesh"):
