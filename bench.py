@@ -596,14 +596,18 @@ def serving(args):
         cold = {"factor": cold["factor"], "registered": cold["registered"],
                 "batched": side(cold["batched"], ("p50_ms", "p99_ms", "faces_per_s", "mean_batch"))}
     return {"requests": res["requests"], "topologies": res["topologies"],
+            "single_request_graphs": {"captured": res["graphs"], "max_final_faces": res["graph_max_faces"],
+                                      "replays": res["graph_launches"]},
             "per_mesh_saturation_qps": round(res["per_mesh_saturation_qps"], 1),
             "budget_gib": res["budget_gib"], "slots": res["slots"], "max_batch": res["max_batch"],
             "batched_server": "FIFO prefixes of the queue, any schemes and level counts; one subdiv_refine_batch "
                               "per batch, no host round trip; topology cache warm (every cage topology of the "
-                              "trace planned once before the timed runs)",
+                              "trace planned once before the timed runs); a batch of one whose final level is "
+                              "small replays its (topology, levels) HIP graph",
             "per_mesh_server": "one subdiv_plan (with its read-back) + subdiv_refine per request, FIFO, one stream",
             "per_mesh_cached_plans_server": "one request at a time through the batched server's executor and topology "
-                                            "cache (kept plan, one positions upload, the mesh refined alone), FIFO",
+                                            "cache (kept plan, one positions upload, the mesh refined alone, the "
+                                            "same graphs), FIFO",
             "points": pts, "cold_cache": cold}
 
 

@@ -280,7 +280,7 @@ class GpuBatchExecutor:
     trip. A batch uploads only its positions (one pinned copy) and allocates
     one workspace and one output block per kind, released after it retires."""
 
-    def __init__(self, device="cuda", reserve_bytes: int = 0, plan_levels: int = 4):
+    def __init__(self, device="cuda", reserve_bytes: int = 0, plan_levels: int = 4, graph_max_faces: int = 0):
         import torch
         from . import _lib, api
         self.torch, self._lib, self.api = torch, _lib, api
@@ -292,6 +292,11 @@ class GpuBatchExecutor:
         self.cages: Dict[tuple, _Cage] = {}
         self._keep_alive: Dict[tuple, object] = {}
         self.registered = 0
+        # single-request refinements captured as HIP graphs (see precapture)
+        self.graph_max_faces = int(graph_max_faces)
+        self.graphs: Dict[tuple, dict] = {}
+        self.graph_stream = torch.cuda.Stream(self.device)
+        self.graph_launches = 0
         reserve(self.device, reserve_bytes, self.stream)
 
     @staticmethod
@@ -350,9 +355,80 @@ class GpuBatchExecutor:
             return INF if ws == 0 else ws + int(io[k - 1])
         return f
 
+    # ---- single requests replayed from HIP graphs --------------------------
+    # At low load almost every batch holds one request, and its time goes to
+    # launching some thirty small kernels from the host. A request whose
+    # (cage topology, level count) was captured runs as one graph launch: its
+    # positions go into the graph's static input, the graph replays the
+    # library's refinement of that mesh alone (the kernels only: a batch of
+    # one enqueues no copies and no memsets), and the result is the graph's
+    # static output, which stays the request's until it retires (a second
+    # request with the same key meanwhile runs eagerly).
+
+    def _graph_key(self, r):
+        return (self._key(r), r.levels)
+
+    def precapture(self, reqs):
+        """Capture one graph per (topology, level count) among `reqs` whose
+        final level has at most graph_max_faces faces."""
+        torch, L, lib = self.torch, self._lib, self.lib
+        self.prepare(reqs)
+        for r in reqs:
+            key = self._graph_key(r)
+            if key in self.graphs:
+                continue
+            c = self.cages[self._key(r)]
+            li = c.plan.level[r.levels]
+            if int(li.num_faces) > self.graph_max_faces:
+                continue
+            structs, sc, lv, plans = self._arrays([r])
+            V = r.mesh.num_vertices
+            P_in = torch.empty((V, 3), dtype=torch.float32, device=self.device)
+            P_in.copy_(torch.from_numpy(np.ascontiguousarray(r.mesh.positions, np.float32)))
+            structs[0].positions = P_in.data_ptr()
+            ws_bytes = int(lib.subdiv_batch_workspace_bound(structs, sc, lv, 1, plans, 0))
+            ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+            fv = torch.empty(int(li.num_halfedges), dtype=torch.int32, device=self.device)
+            P = torch.empty((int(li.num_vertices), 3), dtype=torch.float32, device=self.device)
+            outs = (L.subdiv_level_out * 1)()
+            outs[0].face_verts = fv.data_ptr()
+            outs[0].positions = P.data_ptr()
+            gs = self.graph_stream
+
+            def call():
+                L.check(lib.subdiv_refine_batch(structs, sc, lv, 1, plans, outs, ctypes.c_void_p(ws.data_ptr()),
+                                                ws_bytes, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                        "subdiv_refine_batch")
+            torch.cuda.synchronize(self.device)
+            with torch.cuda.stream(gs):
+                call()  # eager once: the same enqueues the capture records
+            gs.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=gs):
+                call()
+            self.graphs[key] = dict(g=g, P_in=P_in, ws=ws, fv=fv, P=P, args=(structs, sc, lv, plans, outs),
+                                    busy=False, H=int(li.num_halfedges))
+
+    def _launch_graph(self, r, e):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            host = torch.from_numpy(np.ascontiguousarray(r.mesh.positions, np.float32)).pin_memory()
+            e["P_in"].copy_(host, non_blocking=True)
+            e["g"].replay()
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        e["busy"] = True
+        self.graph_launches += 1
+        return dict(ev=ev, keep=(host,), graph=e, hofs=np.array([0, e["H"]]), hs=[e["H"]],
+                    pofs=np.array([0, e["P"].shape[0]]))
+
     def launch(self, reqs, slot):
         torch, L, lib = self.torch, self._lib, self.lib
         n = len(reqs)
+        if n == 1:
+            e = self.graphs.get(self._graph_key(reqs[0]))
+            if e is not None and not e["busy"]:
+                return self._launch_graph(reqs[0], e)
         structs, sc, lv, plans = self._arrays(reqs)
         try:
             with torch.cuda.stream(self.stream):
@@ -395,11 +471,16 @@ class GpuBatchExecutor:
         return h["ev"].query()
 
     def results(self, h):
+        if "graph" in h:  # the graph's static outputs are reused by its next replay
+            e = h["graph"]
+            return [{"face_verts": e["fv"].clone(), "positions": e["P"].clone()}]
         fv, P = h["keep"][2], h["keep"][3]
         return [{"face_verts": fv[int(h["hofs"][k]):int(h["hofs"][k]) + h["hs"][k]],
                  "positions": P[int(h["pofs"][k]):int(h["pofs"][k + 1])]} for k in range(len(h["hs"]))]
 
     def retire(self, h):
+        if "graph" in h:
+            h["graph"]["busy"] = False
         h.clear()
 
 
@@ -473,7 +554,7 @@ def _retime(reqs: List[Request], base_times: np.ndarray, qps: float) -> List[Req
 
 def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), seed: int = 4, budget_gib: float = 64.0,
           slots: int = 2, max_batch: int = 256, device="cuda", sat_requests: Optional[int] = None,
-          log=print, cold_factor: Optional[float] = 1.0) -> Dict:
+          log=print, cold_factor: Optional[float] = 1.0, graph_max_faces: int = 1 << 18) -> Dict:
     """Measure the per-mesh-launch saturation rate, then serve the trace at
     each factor x that rate with the batched server and the baseline.
 
@@ -492,7 +573,7 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), s
     reserve_bytes = int(min(budget_gib, 8.0) * 2**30)
     reserve(device, reserve_bytes)
     budget = int(budget_gib * 2**30)
-    ex = GpuBatchExecutor(device, reserve_bytes)
+    ex = GpuBatchExecutor(device, reserve_bytes, graph_max_faces=graph_max_faces)
     # warm-up of both paths: one request of every (scheme, levels) group, the
     # head of the trace, and (batched server) every topology, all at t = 0
     seen, warm, topo = set(), [], set()
@@ -506,6 +587,11 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), s
             topo.add((id(r.mesh.verts), r.scheme))
             warm.append(r)
     Server(ex, budget, slots, max_batch).run(_retime(warm, np.zeros(len(warm)), 1.0))
+    # every (topology, level count) of the trace with a small final level gets
+    # its single-request graph before the timed runs
+    t0 = time.perf_counter()
+    ex.precapture(trace)
+    log(f"[serve] {len(ex.graphs)} single-request graphs captured in {time.perf_counter() - t0:.2f} s")
     serve_per_mesh(_retime(warm[:64], np.zeros(min(64, len(warm))), 1.0), device)
     # saturation of the baseline: everything arrives at t = 0
     ns = min(n_requests, sat_requests or n_requests)
@@ -546,7 +632,8 @@ def sweep(n_requests: int = 4096, factors=(0.5, 0.8, 1.0, 1.2, 1.5, 2.0, 3.0), s
         log(f"[serve] x{cold_factor} cold cache: p50 {cold['batched']['p50_ms']:.3f} "
             f"p99 {cold['batched']['p99_ms']:.3f} ms ({cex.registered} topologies registered in the trace)")
     return dict(requests=n_requests, seed=seed, budget_gib=budget_gib, slots=slots, max_batch=max_batch,
-                topologies=len(topo), per_mesh_saturation_qps=sat_qps, points=points, cold_cache=cold)
+                topologies=len(topo), per_mesh_saturation_qps=sat_qps, points=points, cold_cache=cold,
+                graphs=len(ex.graphs), graph_max_faces=graph_max_faces, graph_launches=ex.graph_launches)
 
 
 def main(argv=None):
@@ -557,9 +644,11 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=2, help="batches in flight at once (queued on one stream)")
     ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--graph-max-faces", type=int, default=1 << 18,
+                    help="single requests with at most this many final faces replay a captured graph (0: none)")
     a = ap.parse_args(argv)
     res = sweep(a.requests, tuple(float(x) for x in a.factors.split(",")), a.seed, a.budget_gib, a.slots,
-                a.max_batch)
+                a.max_batch, graph_max_faces=a.graph_max_faces)
     print(json.dumps(res))
 
 

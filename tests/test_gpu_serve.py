@@ -1,6 +1,8 @@
 """Serving on the GPU: the continuous-batching server returns, for every
 request, bitwise the final level that a solo plan + refine of its cage gives,
 and the QPS sweep runs end to end on a short trace."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -66,3 +68,37 @@ def test_sweep_runs_end_to_end():
     assert res["per_mesh_saturation_qps"] > 0
     for side in ("batched", "per_mesh", "per_mesh_cached"):
         assert p[side]["served"] == 32 and p[side]["p99_ms"] >= p[side]["p50_ms"] > 0
+
+
+def test_graph_replays_equal_eager_refinement():
+    """Single requests replayed from their (topology, level count) HIP graph:
+    every replay, with new positions each time and eager work and
+    synchronisations between the replays, equals the eager plan + refine of
+    the same cage bit for bit; a key whose graph is busy runs eagerly."""
+    reqs = _trace(10, 23, tmax=1500.0)
+    ex = S.GpuBatchExecutor("cuda", graph_max_faces=1 << 20)
+    ex.precapture(reqs)
+    assert len(ex.graphs) == len({ex._graph_key(r) for r in reqs})
+    rng = np.random.default_rng(24)
+    for rep in range(3):
+        for r in reqs:
+            m = dataclasses.replace(r.mesh, positions=(r.mesh.positions + rng.normal(
+                0, 0.01, r.mesh.positions.shape)).astype(np.float32))
+            q = S.Request(rid=r.rid, arrival=0.0, mesh=m, scheme=r.scheme, levels=r.levels)
+            ex.prepare([q])
+            h = ex.launch([q], 0)
+            assert "graph" in h
+            h2 = ex.launch([q], 0)  # the same key while the first holds the graph: eager
+            assert "graph" not in h2
+            h["ev"].synchronize()
+            h2["ev"].synchronize()
+            got, got2 = ex.results(h)[0], ex.results(h2)[0]
+            ex.retire(h)
+            ex.retire(h2)
+            torch.randn(1 << 16, device="cuda").sum().item()  # eager work between the replays
+            outs, _ = api.refine(m, r.scheme, r.levels)
+            want = outs[r.levels]
+            for res in (got, got2):
+                assert torch.equal(res["face_verts"], want["face_verts"]), (rep, r.rid)
+                assert torch.equal(res["positions"], want["positions"]), (rep, r.rid)
+    assert ex.graph_launches == 3 * len(reqs)
