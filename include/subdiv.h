@@ -56,8 +56,9 @@ enum {
                                4, ... by a trisection step that splits every boundary edge in three (a boundary
                                face r gets two edge points instead of its face point: p at |v| + r, q at
                                |v| + |f| + its rank among the boundary faces) with the ternary cubic B-spline
-                               rule on the boundary. Triangle meshes, no creases; every level is built by the
-                               generic mapped product; not in batches, no kept state */
+                               rule on the boundary. Triangle meshes, no creases; both steps carry the next
+                               level's adjacency over in closed form (the generic mapped product on request, as
+                               for the other schemes); not in batches, no kept state */
 };
 
 enum {
@@ -85,7 +86,8 @@ enum {
                                              instead of carrying them over in closed form */
 #define SUBDIV_FLAG_KEEP_STATE 2u         /* keep every level's topology in the workspace for
                                              subdiv_refine_positions, subdiv_refine_vertex_data
-                                             (every scheme) and subdiv_backward (Catmull-Clark;
+                                             (every scheme but SUBDIV_SQRT3_KOBBELT) and
+                                             subdiv_backward (Catmull-Clark;
                                              its first call after a subdiv_refine also writes the
                                              adjoint's per-vertex rule coefficients there); not
                                              with SUBDIV_FLAG_REBUILD_EACH_LEVEL */

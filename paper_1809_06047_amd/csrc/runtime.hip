@@ -176,6 +176,7 @@ struct Layout {
   size_t tbase;        // edge bases of the next level (triangle schemes with carried adjacency)
   size_t tbase2;       // Loop, second step from below: the edge bases of level L-2 beside level L-3's
   size_t tslot, trank, tnb;  // sqrt(3) trisection steps: boundary slot and rank per face, boundary neighbours
+  size_t tbase3, tmask;      // and, for the carried adjacency, run bases and per-face point kinds
   size_t partials;     // scan partials of every level after the cage
   size_t bnval, browptr, bcursor, binc, bcand, bcntlo, bebase, bbflag, bsigcnt;  // rebuild scratch
   size_t mfv[2], mP[2];
@@ -202,9 +203,9 @@ AdjOffsets carve_adj(Carver &c, long long V, long long E, long long H, bool crea
 // Levels >= 1 are built from scratch by the generic mapped product when the
 // caller asks for it; otherwise every scheme carries each level's adjacency
 // over in closed form from the level it was refined from.
-// sqrt(3) with Kobbelt's boundary cycle always takes the generic build.
 bool rebuilds_levels(int scheme, uint32_t flags) {
-  return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0 || scheme == SUBDIV_SQRT3_KOBBELT;
+  (void)scheme;
+  return (flags & SUBDIV_FLAG_REBUILD_EACH_LEVEL) != 0;
 }
 
 // The last two Loop or sqrt(3) steps both run from two levels below them:
@@ -212,9 +213,10 @@ bool rebuilds_levels(int scheme, uint32_t flags) {
 // no creases on levels L-2 and L-1
 // The last Loop or sqrt(3) step from level L-2 (level L-1's adjacency never
 // built): not when every level's state is kept
+// (sqrt(3) with the boundary cycle steps level by level)
 bool tri_lag(int scheme, uint32_t flags, int levels, const Sizes *L) {
-  return scheme != SUBDIV_CATMULL_CLARK && !rebuilds_levels(scheme, flags) && !(flags & SUBDIV_FLAG_KEEP_STATE) &&
-         levels >= 3 && !L[levels - 1].creases;
+  return (scheme == SUBDIV_LOOP || scheme == SUBDIV_SQRT3) && !rebuilds_levels(scheme, flags) &&
+         !(flags & SUBDIV_FLAG_KEEP_STATE) && levels >= 3 && !L[levels - 1].creases;
 }
 // and the step before it from level L-3 too
 bool tri_lag2(int scheme, uint32_t flags, int levels, const Sizes *L) {
@@ -259,6 +261,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
   for (int k = 1; k <= levels; ++k) {
     maxn = L[k].V > maxn ? L[k].V : maxn;
     maxn = L[k].E > maxn ? L[k].E : maxn;
+    // a trisection step scans two counts per face
+    if (scheme == SUBDIV_SQRT3_KOBBELT && k % 2 == 1 && k < levels) maxn = 2 * L[k].F > maxn ? 2 * L[k].F : maxn;
   }
   y.partials = c.take(4 * (scan_partials_ints(maxn) + 8));
   if (levels >= 2) {
@@ -328,6 +332,8 @@ Layout make_layout(int scheme, int levels, uint32_t flags, const Sizes *L, long 
     y.tslot = c.take(4 * tF);
     y.trank = c.take(4 * (tF + 1));
     y.tnb = c.take(8 * tV);
+    y.tbase3 = c.take(4 * (2 * tF + 1));  // carried adjacency: edge counts of the p / face-point and q runs
+    y.tmask = c.take(tF);
   }
   if (flags & SUBDIV_FLAG_KEEP_STATE) {
     long long gV = L[0].V, gH = L[0].H;
@@ -861,7 +867,8 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
   if (st != SUBDIV_OK) return st;
   if (flags & ~(SUBDIV_FLAG_REBUILD_EACH_LEVEL | SUBDIV_FLAG_KEEP_STATE)) return SUBDIV_INVALID_ARG;
   // the kept state is that of the carried-over adjacency
-  if ((flags & SUBDIV_FLAG_KEEP_STATE) && rebuilds_levels(scheme, flags)) return SUBDIV_INVALID_ARG;
+  if ((flags & SUBDIV_FLAG_KEEP_STATE) && (rebuilds_levels(scheme, flags) || scheme == SUBDIV_SQRT3_KOBBELT))
+    return SUBDIV_INVALID_ARG;
   if (!ws) return SUBDIV_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long H0 = cage_H(mesh);
@@ -1008,6 +1015,17 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
   // level k's adjacency (and face table): a rotating slot, or with the state
   // kept the level's own region
   auto tri_slot = [&](int k) -> const AdjOffsets & { return keep ? y.keep[k] : y.slot[k & 1]; };
+  // sqrt(3) old-vertex steps whose neighbours are the face points of level l >= 1:
+  // the cage's vertices and face points read their rings from the cage
+  auto cage_rings = [&](TriStep &o, int l) {
+    if (l < 1) return;
+    o.a0 = adj_at(ws, y.adj0, L[0].E, false);
+    o.V0 = (int32_t)L[0].V;
+    o.F0 = (int32_t)L[0].F;
+    int p3 = 1;
+    for (int i = 1; i < l; ++i) p3 *= 3;
+    o.pow3 = p3;
+  };
   for (int k = 0; k < levels; ++k) {
     const bool final = (k == levels - 1);
     int32_t *fv1 = outs[k + 1].face_verts ? outs[k + 1].face_verts : at<int32_t>(ws, y.mfv[(k + 1) & 1]);
@@ -1078,6 +1096,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       o.Vg = (int32_t)L[k - 1].V;
       o.ap = aprev;
       o.Vq = (int32_t)L[k - 2].V;
+      if (scheme == SUBDIV_SQRT3) cage_rings(o, k - 1);
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
         SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
@@ -1103,6 +1122,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       // the older vertices walk there
       o.app = aprev2;
       o.Vr = k >= 3 ? (int32_t)L[k - 3].V : 0;
+      if (scheme == SUBDIV_SQRT3) cage_rings(o, k - 1);
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
         SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
@@ -1113,12 +1133,26 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       }
     } else if (scheme == SUBDIV_SQRT3_KOBBELT && k % 2 == 1) {
       // the trisection step of the boundary cycle (level k came from a sqrt(3) step)
-      const TrisectStep ts{t, a, P, fv1, P1, at<int32_t>(ws, y.tslot), at<int32_t>(ws, y.trank),
-                           at<int32_t>(ws, y.tnb)};
+      TrisectStep ts{t, a, P, fv1, P1, at<int32_t>(ws, y.tslot), at<int32_t>(ws, y.trank),
+                     at<int32_t>(ws, y.tnb)};
+      const bool carry = !rebuild && !final;  // level k+1's adjacency in closed form
+      if (carry) {
+        ts.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, false);
+        ts.base = at<int32_t>(ws, y.tbase3);
+        ts.pmask = at<uint8_t>(ws, y.tmask);
+        ts.nbnd = (int32_t)L[k].B;
+      }
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_MARK, ts, s));
       SUBDIV_TIMED("sqrt3_trisect", k, launch_scan(ts.brank, ts.brank, t.F, at<int32_t>(ws, y.partials), nullptr, s));
+      if (carry) {
+        SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_COUNT, ts, s));
+        SUBDIV_TIMED("sqrt3_trisect", k,
+                     launch_scan(ts.base, ts.base, 2ll * t.F, at<int32_t>(ws, y.partials), nullptr, s));
+      }
+      // (the vertex step writes the old vertices' starts that the face step may lower)
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_VERTEX, ts, s));
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_FACE, ts, s));
+      if (carry) a = ts.a1;
     } else {
       // (sqrt(3) with the boundary cycle: a level after a trisection step has
       // boundary points among its new vertices, so the vertex step walks every

@@ -429,6 +429,11 @@ struct TriStep {
   int32_t Vq;    // levels >= 2: vertices of level k-2 (the old vertices v >= Vq are its edge / face points)
   Adj app;       // when set (twin != nullptr): adjacency of level k-2, where the rings of v < Vq are walked
   int32_t Vr;    // with app: vertices of level k-3 (0 when level k-2 is the cage)
+  // sqrt(3), when set (a0.twin != nullptr): the cage's adjacency, from which the
+  // rings of the cage vertices and of the cage's face points are read instead
+  Adj a0;
+  int32_t V0, F0;  // the cage's vertices and faces
+  int32_t pow3;    // 3^(l-1), l >= 1 the level whose face points are the neighbours (Vg = V_l)
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
@@ -448,8 +453,13 @@ struct TrisectStep {
   int32_t *bslot;   // [F] slot of the face's boundary edge, or -1
   int32_t *brank;   // [F + 1] boundary flags, scanned into the ranks among the boundary faces
   int32_t *bnb;     // [2 V] previous and next boundary neighbour of a boundary vertex
+  // carried adjacency of level k+1 (a1.twin null: none)
+  Adj a1;           // twin, eid [9 F], vhe [V + F + B], e2h, bscan (boundary edges only) [E']
+  int32_t *base;    // [2 F + 1] edge counts per higher end (points p / face points, then q), scanned
+  uint8_t *pmask;   // [F] bit i: the point across edge i toward this face is a face point or p
+  int32_t nbnd;     // B = boundary faces of level k
 };
-enum { TRISECT_MARK = 0, TRISECT_FACE = 1, TRISECT_VERTEX = 2 };
+enum { TRISECT_MARK = 0, TRISECT_FACE = 1, TRISECT_VERTEX = 2, TRISECT_COUNT = 3 };
 hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s);
 
 // Last Loop or sqrt(3) step k -> k+1 computed from level m = k-1 (which

@@ -339,15 +339,95 @@ __device__ __forceinline__ Ring ring_prev2_loop(const TriStep &c, int v) {
   return R;
 }
 
+// sqrt(3) needs no lookup on level k-1 at all: the image of an interior
+// half-edge h of level k-2 is the first slot 3h of the child at h, whose twin
+// is slot 2 of the child at v of the face s across h (h's twin t = 3s + i,
+// that child 3s + (i+1) mod 3), so the face point across the image is
+// Vg + 3 (t / 3) + (t mod 3 + 1) mod 3, from the twin on level k-2 alone.
+__device__ __forceinline__ int sqrt3_across_image(int t) { return 3 * (t / 3) + (t % 3 + 1) % 3; }
+
+// The rings of the cage's vertices and of its face points from the cage's
+// adjacency (twice as many ints as cage faces: it stays in L2) rather than a
+// walk on level l: repeating the map above, a half-edge of level b with twin
+// t = 3s + i has on level l > b the image across from the face
+// 3^(l-b-1) (3s + (i+1) mod 3). A cage vertex (b = 0) walks its cage fan. The
+// face point of cage face r (b = 1, l >= 2) has the six-half-edge ring of the
+// closed form above, starting at the least of them; the twins of its
+// half-edges on level 1 follow from r's three cage twins (t2 of the edge
+// before, 9r + 3j + 1). Same neighbours in the same order as the walks.
+__device__ __forceinline__ bool ring_cage_sqrt3(const TriStep &c, int v, Ring &R) {
+  const int32_t *tw0 = c.a0.twin;
+  if (v < c.V0) {
+    const int m0 = c.pow3;
+    const int h0 = c.a0.vhe[v];
+    int hs[kFan], hb;
+    const int n = fan3(tw0, h0, hs, hb);
+    if (n > 0) {
+      R.faces = n;
+      if (hb >= 0) {  // on the boundary: the vertex stays where it is
+        R.ub = 0;
+        return true;
+      }
+      int ts[kFan];
+      f3 pt[kFan];
+#pragma unroll
+      for (int i = 0; i < kFan; ++i) ts[i] = tw0[hs[i]];
+#pragma unroll
+      for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + m0 * sqrt3_across_image(ts[i]));
+#pragma unroll
+      for (int i = 0; i < kFan; ++i)
+        if (i < n) R.sum = add3(R.sum, pt[i]);
+      return true;
+    }
+    int h = h0;
+    while (true) {
+      const int ts = tw0[h];
+      if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + m0 * sqrt3_across_image(ts)));
+      ++R.faces;
+      const int tw = tw0[h % 3 == 0 ? h + 2 : h - 1];
+      if (tw < 0) {
+        R.ub = 0;
+        break;
+      }
+      if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+      h = tw;
+    }
+    return true;
+  }
+  if (c.pow3 >= 3 && v < c.V0 + c.F0) {
+    const int r = v - c.V0;
+    const int t[3] = {tw0[3 * r], tw0[3 * r + 1], tw0[3 * r + 2]};
+    if (t[0] < 0 || t[1] < 0 || t[2] < 0) return false;  // next to the boundary: walked
+    int p0 = 0, best = 9 * r + 2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int t1 = 9 * (t[j] / 3) + 3 * (t[j] % 3) + 1;  // F_r -> F_s on level 1
+      if (t1 < best) {
+        best = t1;
+        p0 = 2 * j + 1;
+      }
+    }
+    const int m1 = c.pow3 / 3;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int y = p0 + u < 6 ? p0 + u : p0 + u - 6, j = y >> 1, tp = t[(j + 2) % 3];
+      const int T = (y & 1) ? 9 * r + 3 * j + 1 : 9 * (tp / 3) + 3 * (tp % 3);
+      R.sum = add3(R.sum, ld3(c.P, c.Vg + m1 * sqrt3_across_image(T)));
+    }
+    R.faces = 6;
+    return true;
+  }
+  return false;
+}
+
 __device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
   const Adj &x = c.app;
-  const int32_t *twin1 = c.ap.twin;
   const int h0 = x.vhe[v];
   Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
   if (c.Vr > 0 && v >= c.Vr) {
     const int r = v - c.Vr;
     const int *tr = x.twin + 9ll * r;
-    const int t1[3] = {tr[1], tr[4], tr[7]};
+    const int t1[3] = {tr[1], tr[4], tr[7]}, t2[3] = {tr[2], tr[5], tr[8]};
     if (t1[0] % 3 == 1 && t1[1] % 3 == 1 && t1[2] % 3 == 1) {
       int p0 = 0;
 #pragma unroll
@@ -356,10 +436,11 @@ __device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int y = p0 + t < 6 ? p0 + t : p0 + t - 6, j = y >> 1;
-        // the ring's half-edges alternate F_r -> v_j (slot 2 of r's child j)
-        // and F_r -> F_s (the twin of its slot 1); all interior
-        const int he = (y & 1) ? t1[j] : 9 * r + 3 * j + 2;
-        R.sum = add3(R.sum, ld3(c.P, c.Vg + twin1[3 * he] / 3));
+        // the ring's half-edges alternate F_r -> v_j (slot 2 of r's child j,
+        // twin t2[j]) and F_r -> F_s (t1[j], the twin of r's child j's slot
+        // 1); all interior
+        const int tw = (y & 1) ? 9 * r + 3 * j + 1 : t2[j];
+        R.sum = add3(R.sum, ld3(c.P, c.Vg + sqrt3_across_image(tw)));
       }
       R.faces = 6;
       return R;
@@ -368,23 +449,27 @@ __device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
   int hs[kFan], hb;
   const int n = fan3(x.twin, h0, hs, hb);
   if (n > 0) {
+    if (hb >= 0) {  // on the boundary: the vertex stays where it is
+      R.faces = n;
+      R.ub = 0;
+      return R;
+    }
     int ts[kFan];
     f3 pt[kFan];
 #pragma unroll
-    for (int i = 0; i < kFan; ++i) ts[i] = twin1[3 * hs[i]];
+    for (int i = 0; i < kFan; ++i) ts[i] = x.twin[hs[i]];  // (the row the fan step just read)
 #pragma unroll
-    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + (ts[i] >= 0 ? ts[i] / 3 : 0));
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + sqrt3_across_image(ts[i]));
 #pragma unroll
     for (int i = 0; i < kFan; ++i)
-      if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
+      if (i < n) R.sum = add3(R.sum, pt[i]);
     R.faces = n;
-    if (hb >= 0) R.ub = 0;
     return R;
   }
   int h = h0;
   while (true) {
-    const int ts = twin1[3 * h];
-    if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + ts / 3));
+    const int ts = x.twin[h];
+    if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + sqrt3_across_image(ts)));
     ++R.faces;
     const int tw = x.twin[he_prev<3>(c.t, h)];
     if (tw < 0) {
@@ -727,9 +812,11 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
     return;
   }
   const f3 p = ld3(c.P, v);
-  const Ring R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
-                 : (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v)
-                                            : ring_prev_sqrt3(c, v);
+  Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
+  if (!c.a0.twin || !ring_cage_sqrt3(c, v, R))
+    R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
+        : (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v)
+                                   : ring_prev_sqrt3(c, v);
   f3 S;
   if (R.ub >= 0) {
     S = p;
@@ -875,8 +962,10 @@ __global__ void __launch_bounds__(kBlock) k_trisect_vertex(TrisectStep c) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.t.V) return;
   const f3 p = ld3(c.P, v);
+  const int h0 = c.a.vhe[v];
+  const bool bnd = c.a.twin[h0] < 0;  // the canonical half-edge of a boundary vertex is its boundary one
   f3 S;
-  if (c.a.twin[c.a.vhe[v]] < 0) {  // the canonical half-edge of a boundary vertex is its boundary one
+  if (bnd) {
     const f3 nb = add3(ld3(c.P, c.bnb[2 * v]), ld3(c.P, c.bnb[2 * v + 1]));
     S = lin2(19.0f / 27.0f, p, 4.0f / 27.0f, nb);
   } else {
@@ -884,6 +973,187 @@ __global__ void __launch_bounds__(kBlock) k_trisect_vertex(TrisectStep c) {
     S = sqrt3_pt(p, R.sum, R.faces);
   }
   st3(c.P1, v, S);
+  if (c.a1.twin) {
+    // start half-edge on level k+1 (see the carried adjacency below): a
+    // boundary vertex u leaves along u -> p of the face r whose boundary edge
+    // starts at u, which lies in the child at u of the face across r's edge
+    // after next; an interior vertex keeps the first slot of the child at its
+    // level-k start (the face kernel then lowers it where v is the apex of a
+    // boundary face)
+    if (bnd) {
+      const int t = c.a.twin[3 * (h0 / 3) + (h0 % 3 + 2) % 3];
+      c.a1.vhe[v] = 9 * (t / 3) + 3 * (t % 3);
+    } else {
+      c.a1.vhe[v] = 3 * h0;
+    }
+  }
+}
+
+// Edge counts of level k+1 per higher end: the points V + r (face point, or p
+// of a boundary face) come first in id order, then the q points V + F + rank;
+// the counts of both runs are scanned together, so base[r] and base[F + rank
+// ... ] follow. pmask records which of the face's edges see a V + s point of
+// the face across (rather than its q).
+__global__ void __launch_bounds__(kBlock) k_trisect_count(TrisectStep c) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= c.t.F) return;
+  const int F = c.t.F, j = c.bslot[r];
+  int s[3];
+  bool isp[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int t = c.a.twin[3 * r + i];
+    s[i] = t < 0 ? -1 : t / 3;
+    const int js = t < 0 ? -1 : c.bslot[s[i]];
+    isp[i] = t >= 0 && !(js >= 0 && t % 3 == (js + 1) % 3);
+  }
+  int cp, cq = 0;
+  if (j < 0) {
+    cp = 3 + (isp[0] && s[0] < r) + (isp[1] && s[1] < r) + (isp[2] && s[2] < r);
+  } else {
+    const int jn = (j + 1) % 3, jp = (j + 2) % 3;
+    cp = 2 + (isp[jp] && s[jp] < r);
+    cq = 3 + (isp[jn] || s[jn] < r);
+  }
+  c.base[r] = cp;
+  c.base[F + r] = cq;
+  c.pmask[r] = (uint8_t)(isp[0] | (isp[1] << 1) | (isp[2] << 2));
+}
+
+// Carried adjacency of level k+1 (h' = 9 r + 3 i + slot; slot s runs from
+// corner s to corner s+1 of child 3r+i). Write (s_i, i'_i) for the face across
+// edge i of r and the slot of the shared edge in it, so that s's corner i' is
+// r's v_{i+1} and its corner i'+1 is r's v_i; X_i is s's point toward r.
+// Twins:
+//   slot 1 of a child at an interior edge i (X_i -> V + r or -> q): slot 1 of
+//     s's child i';
+//   v_i -> X_i (slot 0): X_i -> v_i is slot 2 of s's child i'+1 when s has no
+//     boundary edge, slot 1 of s's child j_s (q -> its apex) when X_i is s's
+//     q, and none when X_i is s's p (then v_i -> p is a boundary segment);
+//   V + r -> v_i of an interior face: slot 0 of the child at v_i of the face
+//     across edge i-1 (s's child i'');
+//   boundary face (j; u, w, z the corners j, j+1, j+2): p -> q and q -> w are
+//     boundary segments, q -> z pairs with slot 0 of the child i' of the face
+//     across edge j+1, and z -> p (child j) with p -> z (child j+2).
+// Edge ids ((hi, lo) order): no edge joins two old vertices, so the runs of
+// the points V + r come first (lower neighbours: r's corners, or z and u, then
+// the points V + s < V + r of the faces across), then the runs of the q
+// points (lower neighbours z and w, then p and a V + s point across edge j+1,
+// then an earlier q across it). Boundary edges keep their ranks: u - p of the
+// boundary faces in face order, then per boundary face q - w and p - q.
+__device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool valid, const int (&v)[3],
+                                              const int (&X)[3], uint32_t *lds, long long rw, int l, int cnt) {
+  const int V = c.t.V, F = c.t.F, j = c.bslot[r];
+  const int32_t *baseP = c.base, *baseQ = c.base + F;
+  int s[3], ip[3], js[3];
+  bool isp[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int t = c.a.twin[3 * r + i];
+    s[i] = t < 0 ? r : t / 3;  // (a boundary edge's entries are never used)
+    ip[i] = t < 0 ? 0 : t % 3;
+    js[i] = t < 0 ? -1 : c.bslot[s[i]];
+    isp[i] = X[i] >= 0 && X[i] < V + F;
+  }
+  const int bP = baseP[r];
+  // edge (v_i, X_i), edge i interior
+  auto id_vX = [&](int i, int vi, int vn) {
+    if (!isp[i]) return baseQ[s[i]] + (vi > vn);
+    if (js[i] >= 0) return baseP[s[i]] + (vi > vn);
+    const int w = c.t.fv[3 * s[i] + (ip[i] + 2) % 3];
+    return baseP[s[i]] + rank3(vi, vn, w);
+  };
+  // edge (X_i, V + r), edge i interior; r's own lower V + s neighbours: those
+  // across its three edges (no boundary edge), or across edge j+2 alone
+  auto id_XP = [&](int i, bool own_bnd) {
+    const int x = s[i];
+    if (!isp[i]) return baseQ[x] + 2 + (r > x);
+    if (x < r) {
+      if (own_bnd) return bP + 2;
+      return bP + 3 + (isp[0] && s[0] < x) + (isp[1] && s[1] < x) + (isp[2] && s[2] < x);
+    }
+    if (js[i] >= 0) return baseP[x] + 2;  // the only lower V + s neighbour of x's p is V + r
+    int k = 0;
+    const uint8_t pm = c.pmask[x];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) k += ((pm >> m) & 1) && c.a.twin[3 * x + m] / 3 < r;
+    return baseP[x] + 3 + k;
+  };
+  // v_i -> X_i: its twin in the face across (see above)
+  auto flip = [&](int i) {
+    return js[i] < 0 ? 9 * s[i] + 3 * ((ip[i] + 1) % 3) + 2 : ip[i] == (js[i] + 1) % 3 ? 9 * s[i] + 3 * js[i] + 1 : -1;
+  };
+  uint32_t tw1[9], ei1[9];
+  if (j < 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int in = (i + 1) % 3, im = (i + 2) % 3;
+      tw1[3 * i + 0] = flip(i);
+      tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
+      tw1[3 * i + 2] = 9 * s[im] + 3 * ip[im];
+      ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
+      ei1[3 * i + 1] = id_XP(i, false);
+      ei1[3 * i + 2] = bP + rank3(v[i], v[in], v[im]);
+    }
+    if (valid) {
+      int m0 = 9 * r + 2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) m0 = min(m0, (int)tw1[3 * i + 1]);
+      c.a1.vhe[V + r] = m0;
+    }
+  } else {
+    const int bQ = baseQ[r];
+    int idPQ = 0, idwQ = 0, iduP = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int in = (i + 1) % 3, im = (i + 2) % 3;
+      if (i == j) {  // (p, q, z): p -> q, q -> z, z -> p; u = v_i, w = v_in, z = v_im
+        idPQ = bQ + 2 + (isp[in] && s[in] < r);
+        iduP = bP + (v[i] > v[im]);
+        tw1[3 * i + 0] = -1;
+        tw1[3 * i + 1] = 9 * s[in] + 3 * ip[in];
+        tw1[3 * i + 2] = 9 * r + 3 * im + 2;
+        ei1[3 * i + 0] = idPQ;
+        ei1[3 * i + 1] = bQ + (v[im] > v[in]);
+        ei1[3 * i + 2] = bP + (v[im] > v[i]);
+      } else if (i == (j + 1) % 3) {  // (w, X, q): w = v_i, z = v_in
+        idwQ = bQ + (v[i] > v[in]);
+        tw1[3 * i + 0] = flip(i);
+        tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
+        tw1[3 * i + 2] = -1;
+        ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
+        ei1[3 * i + 1] = isp[i] ? bQ + 2 + (s[i] > r) : (s[i] < r ? bQ + 3 : baseQ[s[i]] + 3);
+        ei1[3 * i + 2] = idwQ;
+      } else {  // (z, X, p): z = v_i, u = v_in
+        tw1[3 * i + 0] = flip(i);
+        tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
+        tw1[3 * i + 2] = 9 * r + 3 * in + 2;
+        ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
+        ei1[3 * i + 1] = id_XP(i, true);
+        ei1[3 * i + 2] = bP + (v[i] > v[in]);
+      }
+    }
+    if (valid) {
+      const int rk = c.brank[r], B = c.nbnd, jn = (j + 1) % 3;
+      c.a1.bscan[iduP] = rk;  // u - p
+      c.a1.bscan[idwQ] = B + 2 * rk;  // q - w
+      c.a1.bscan[idPQ] = B + 2 * rk + 1;
+      c.a1.vhe[V + r] = 9 * r + 3 * j;
+      c.a1.vhe[V + F + rk] = 9 * r + 3 * jn + 2;
+      const int z = c.t.fv[3 * r + (j + 2) % 3];
+      if (c.a.twin[c.a.vhe[z]] >= 0) atomicMin(&c.a1.vhe[z], 9 * r + 3 * j + 2);  // the apex z -> p
+    }
+  }
+  if (valid) {
+    // every edge once, by its lower half-edge (the only one on the boundary)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int h = 9 * r + i, t = (int)tw1[i];
+      if (t < 0 || h < t) c.a1.e2h[ei1[i]] = h;
+    }
+  }
+  wave_store<9>(lds, tw1, reinterpret_cast<uint32_t *>(c.a1.twin) + 9 * rw, l, cnt);
+  wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
 }
 
 __global__ void __launch_bounds__(kBlock) k_trisect_face(TrisectStep c) {
@@ -939,6 +1209,8 @@ __global__ void __launch_bounds__(kBlock) k_trisect_face(TrisectStep c) {
     row[3 * i + 2] = a2;
   }
   wave_store<9>(lds, row, reinterpret_cast<uint32_t *>(c.fv1) + 9 * rw, l, cnt);
+  if (!c.a1.twin) return;
+  trisect_carry(c, r, valid, v, X, lds, rw, l, cnt);
 }
 
 hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s) {
@@ -946,6 +1218,8 @@ hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s) {
     hipLaunchKernelGGL(k_trisect_mark, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
   else if (which == TRISECT_FACE)
     hipLaunchKernelGGL(k_trisect_face, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
+  else if (which == TRISECT_COUNT)
+    hipLaunchKernelGGL(k_trisect_count, dim3(grid_for(c.t.F)), dim3(kBlock), 0, s, c);
   else
     hipLaunchKernelGGL(k_trisect_vertex, dim3(grid_for(c.t.V)), dim3(kBlock), 0, s, c);
   return hipGetLastError();

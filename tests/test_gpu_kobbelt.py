@@ -58,3 +58,20 @@ def test_kobbelt_rejections():
     assert e.value.status == _lib.INVALID_ARG
     with pytest.raises(Exception):
         api.BatchRefiner([m, m], ["sqrt3k", "sqrt3k"], [2, 2]).plan()
+
+
+@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 5), ("triangle", 4)])
+def test_kobbelt_carried_adjacency_equals_rebuild(cage, levels):
+    """Both steps of the cycle carry the next level's adjacency over in closed
+    form; the generic per-level build (SUBDIV_FLAG_REBUILD_EACH_LEVEL) gives
+    the same face tables, edge lists and, since the ring walks start at the
+    same half-edges, the same position bits at every level."""
+    m = CAGES[cage]()
+    print(f"[kobbelt] {m.name} L={levels}: carried vs rebuilt", flush=True)
+    a, _ = api.refine(m, "sqrt3k", levels, keep="all", edges=True)
+    b, _ = api.refine(m, "sqrt3k", levels, flags=_lib.FLAG_REBUILD_EACH_LEVEL, keep="all", edges=True)
+    torch.cuda.synchronize()
+    for k in range(1, levels + 1):
+        for key in ("face_verts", "edge_verts", "positions"):
+            np.testing.assert_array_equal(a[k][key].cpu().numpy(), b[k][key].cpu().numpy(),
+                                          err_msg=f"level {k} {key}")
