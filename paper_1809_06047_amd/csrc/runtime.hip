@@ -1142,6 +1142,8 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
         ts.pmask = at<uint8_t>(ws, y.tmask);
         ts.nbnd = (int32_t)L[k].B;
       }
+      ts.fpV = (int32_t)L[k - 1].V;  // (k is odd: level k was refined from level k-1)
+      ts.fpF = (int32_t)L[k - 1].F;
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_MARK, ts, s));
       SUBDIV_TIMED("sqrt3_trisect", k, launch_scan(ts.brank, ts.brank, t.F, at<int32_t>(ws, y.partials), nullptr, s));
       if (carry) {
@@ -1155,11 +1157,16 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       if (carry) a = ts.a1;
     } else {
       // (sqrt(3) with the boundary cycle: a level after a trisection step has
-      // boundary points among its new vertices, so the vertex step walks every
-      // ring on the level itself)
+      // boundary points among its new vertices, so the vertex step walks the
+      // rings on the level itself; the points born from faces away from the
+      // boundary read theirs from their child rows)
       const bool walk_own = scheme == SUBDIV_SQRT3_KOBBELT;
       TriStep c{t, a, P, fv1, P1, Adj{}, nullptr, (int32_t)L[k].B, (k >= 1 && !walk_own) ? (int32_t)L[k - 1].V : 0,
                 aprev, k >= 2 ? (int32_t)L[k - 2].V : 0};
+      if (walk_own && k >= 1) {  // the points born from level k-1's faces
+        c.fpV = (int32_t)L[k - 1].V;
+        c.fpF = (int32_t)L[k - 1].F;
+      }
       // before the last step from level k: Loop still needs level k's edge
       // bases; nothing is carried, and level k+1's face table is only written
       // for the caller

@@ -434,6 +434,9 @@ struct TriStep {
   Adj a0;
   int32_t V0, F0;  // the cage's vertices and faces
   int32_t pow3;    // 3^(l-1), l >= 1 the level whose face points are the neighbours (Vg = V_l)
+  // rings walked on level k itself (Vg = 0) of a refined level: the points
+  // fpV .. fpV + fpF - 1 born from the faces of level k-1 (fpF = 0: none)
+  int32_t fpV, fpF;
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
@@ -458,6 +461,7 @@ struct TrisectStep {
   int32_t *base;    // [2 F + 1] edge counts per higher end (points p / face points, then q), scanned
   uint8_t *pmask;   // [F] bit i: the point across edge i toward this face is a face point or p
   int32_t nbnd;     // B = boundary faces of level k
+  int32_t fpV, fpF; // level k's face points of the faces of level k-1 (fpF = 0 on the cage)
 };
 enum { TRISECT_MARK = 0, TRISECT_FACE = 1, TRISECT_VERTEX = 2, TRISECT_COUNT = 3 };
 hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s);

@@ -134,6 +134,33 @@ __device__ __forceinline__ Ring ring3(const Topo &t, const Adj &a, const float *
   return R;
 }
 
+// The point born from face r of the level below (a face point, or p of the
+// trisection step) whose three child rows read (v_i, X_i, point), every X_i a
+// new point: its ring on its own level is v_0, X_0, v_1, X_1, v_2, X_2 around
+// from the start (the least of the half-edges point -> v_i = 9r + 3i + 2 and
+// point -> X_i = twin of slot 1 of child i), the order of the walk. Faces next
+// to the boundary (an X_i that is a corner, or other rows) are walked.
+__device__ __forceinline__ bool ring_rows_fp(const Topo &t, const Adj &a, const float *P, int v, int r, Ring &R) {
+  const int32_t *rw = t.fv + 9ll * r;
+  int x[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) x[i] = rw[i];
+  if (x[2] != v || x[5] != v || x[8] != v || x[1] < v - r || x[4] < v - r || x[7] < v - r) return false;
+  const int h0 = a.vhe[v];
+  const int32_t *tr = a.twin + 9ll * r;
+  int p0 = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (tr[3 * i + 1] == h0) p0 = 2 * i + 1;
+  f3 pt[6];
+#pragma unroll
+  for (int y = 0; y < 6; ++y) pt[y] = ld3(P, x[3 * (y >> 1) + (y & 1)]);
+#pragma unroll
+  for (int u = 0; u < 6; ++u) R.sum = add3(R.sum, pt[p0 + u < 6 ? p0 + u : p0 + u - 6]);
+  R.faces = 6;
+  return true;
+}
+
 // The old vertices v < Vg of a refined level k keep their rings from level
 // k-1: their level-k half-edges are the first slots of the children at their
 // level-(k-1) half-edges, in the same rotation order, and the neighbour along
@@ -813,10 +840,13 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
   }
   const f3 p = ld3(c.P, v);
   Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
-  if (!c.a0.twin || !ring_cage_sqrt3(c, v, R))
-    R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
-        : (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v)
-                                   : ring_prev_sqrt3(c, v);
+  if (c.a0.twin && ring_cage_sqrt3(c, v, R)) {
+  } else if (c.Vg == 0) {
+    if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R)))
+      R = ring3(c.t, c.a, c.P, v);
+  } else {
+    R = (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v) : ring_prev_sqrt3(c, v);
+  }
   f3 S;
   if (R.ub >= 0) {
     S = p;
@@ -969,7 +999,9 @@ __global__ void __launch_bounds__(kBlock) k_trisect_vertex(TrisectStep c) {
     const f3 nb = add3(ld3(c.P, c.bnb[2 * v]), ld3(c.P, c.bnb[2 * v + 1]));
     S = lin2(19.0f / 27.0f, p, 4.0f / 27.0f, nb);
   } else {
-    const Ring R = ring3(c.t, c.a, c.P, v);
+    Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
+    if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R)))
+      R = ring3(c.t, c.a, c.P, v);
     S = sqrt3_pt(p, R.sum, R.faces);
   }
   st3(c.P1, v, S);
