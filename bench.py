@@ -81,6 +81,7 @@ def parse():
                     help="levels of the adjoint leg on the same cage (0 = skip)")
     ap.add_argument("--tri-levels", type=int, default=5,
                     help="levels of the Loop and sqrt(3) legs on the holed triangle cage (0 = skip)")
+    ap.add_argument("--depth", type=int, default=2, help="steps in flight in the timed loop (refine streams)")
     ap.add_argument("--no-side-legs", action="store_true",
                     help="skip the static-topology, selective, reorder and adjoint legs (for kernel profiles: "
                          "the Catmull-Clark kernels then come from full refinements of the headline workload only)")
@@ -128,14 +129,14 @@ class TwoDeep:
     refines, and refines on its slot's stream beside step i-1; every step
     validates, builds and refines its cage in full."""
 
-    def __init__(self, dmesh, levels, scheme="cc"):
+    def __init__(self, dmesh, levels, scheme="cc", depth=2):
         import torch
         from paper_1809_06047_amd import api
         self.dmesh = dmesh
-        self.sr = api.StreamingRefiner(scheme, levels)
-        for _ in range(2):  # both slots' refiners exist from the start
+        self.sr = api.StreamingRefiner(scheme, levels, depth=depth)
+        for _ in range(depth):  # every slot's refiner exists from the start
             self.sr.step(dmesh)
-        self.rs = [self.sr.refiner(0), self.sr.refiner(1)]
+        self.rs = [self.sr.refiner(j) for j in range(depth)]
         # the slots' refinements run on non-blocking streams: they must be done
         # before a caller plans or refines with these refiners on another
         # stream (a plan rewrites the workspace a refinement still reads)
@@ -160,7 +161,7 @@ def main():
 
     mesh = G.cc_cage(seed=args.seed)
     dmesh = api.DeviceMesh(mesh, "cuda")
-    pipe = TwoDeep(dmesh, args.levels)
+    pipe = TwoDeep(dmesh, args.levels, depth=args.depth)
     r = pipe.rs[0]
     r.plan()
     torch.cuda.synchronize()
@@ -206,7 +207,7 @@ def main():
     # timed region: steps two deep (TwoDeep); events around the dominant kernel
     # only, so that the event pairs of the other stages do not sit between the
     # kernels of the step
-    for _ in range(2):  # both refiners' outputs allocated for stream R again
+    for _ in range(args.depth):  # every refiner's outputs allocated for its slot's stream again
         pipe.step()
     _lib.timing_select(dname, dlevel)
     _lib.timing_enable(True)

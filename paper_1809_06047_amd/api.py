@@ -410,13 +410,13 @@ def plan_status(mesh, scheme, levels: int = 1, device="cuda") -> int:
 
 
 class StreamingRefiner:
-    """Cages with changing topology, refined one after the other, two deep:
-    the plan of cage i (into its own workspace, on a plan stream) overlaps
-    the refinement of cage i-1, so the GPU does not idle while the host waits
-    for a plan's read-back. Each of the two slots (workspace, outputs) has
-    its own refine stream, so cage i's refinement also runs beside cage
-    i-1's: the launch-bound small levels of one fill the gaps of the other's
-    HBM-bound last level. Every cage is still validated, built and refined
+    """Cages with changing topology, refined one after the other, `depth`
+    deep (default two): the plan of cage i (into its own workspace, on a plan
+    stream) overlaps the refinement of cage i-1, so the GPU does not idle
+    while the host waits for a plan's read-back. Each slot (workspace,
+    outputs) has its own refine stream, so cage i's refinement also runs
+    beside the ones before it: the launch-bound small levels of one fill the
+    gaps of another's HBM-bound last level. Every cage is still validated, built and refined
     in full. step() returns the cage's output dicts (as Refiner.run) and an
     event recorded after its refinement; the tensors are ready once the
     event has completed. A slot's refiner is reused while the cage is the
@@ -424,13 +424,16 @@ class StreamingRefiner:
     workspace, and its refinements run in order on its stream. All streams
     have the default priority."""
 
-    def __init__(self, scheme, levels: int, flags: int = 0, keep: str = "final", device="cuda"):
+    def __init__(self, scheme, levels: int, flags: int = 0, keep: str = "final", device="cuda", depth: int = 2):
         self.scheme, self.levels, self.flags, self.keep = scheme, int(levels), int(flags), keep
+        if int(depth) < 1:
+            raise ValueError("depth must be at least 1")
+        self.depth = int(depth)
         dev = torch.device(device)
         self.plan_stream = torch.cuda.Stream(dev)
-        self.refine_streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
-        self.slots: List[Optional[Refiner]] = [None, None]
-        self.done: List[Optional[torch.cuda.Event]] = [None, None]
+        self.refine_streams = [torch.cuda.Stream(dev) for _ in range(self.depth)]
+        self.slots: List[Optional[Refiner]] = [None] * self.depth
+        self.done: List[Optional[torch.cuda.Event]] = [None] * self.depth
         self.i = 0
 
     def refiner(self, slot: int) -> Optional[Refiner]:
@@ -441,7 +444,7 @@ class StreamingRefiner:
         return self.slots[slot]
 
     def step(self, dmesh: "DeviceMesh"):
-        j = self.i & 1
+        j = self.i % self.depth
         r = self.slots[j]
         rs = self.refine_streams[j]
         if self.done[j] is not None:
