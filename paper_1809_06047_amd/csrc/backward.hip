@@ -211,6 +211,28 @@ __global__ void __launch_bounds__(BLK) k_bw_vertex(BwdStep c) {
     return;
   }
   const int h0 = c.a.vhe[v];
+  if (ORDER == 4 && c.Vp > 0 && v >= c.Vp + c.Fp) {
+    // edge point of parent edge e' (interior): its four half-edges in closed
+    // form, in the walk's order from the canonical start: with a the half-edge
+    // of e' whose child carries the start, the twin of child a's slot 0 is
+    // slot 3 of child bn = next(b) across, b the other half-edge of e', and
+    // the ring is 4a+1, 4bn+3, 4b+1, 4an+3 (an = next(a)), from its first or
+    // its last entry
+    const int a0 = (h0 & 3) == 1 ? (h0 >> 2) : (((h0 >> 2) & ~3) | (((h0 >> 2) + 3) & 3));
+    const int tw = c.a.twin[4 * a0];
+    if (tw >= 0) {
+      const int bn = tw >> 2, b0 = (bn & ~3) | ((bn + 3) & 3), an = (a0 & ~3) | ((a0 + 1) & 3);
+      const int cyc[4] = {4 * a0 + 1, 4 * bn + 3, 4 * b0 + 1, 4 * an + 3};
+      const bool at0 = (h0 & 3) == 1;
+      f3 tv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tv[j] = ld3(c.term, at0 ? cyc[j] : cyc[(j + 3) & 3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) g = add3(g, tv[j]);
+      st3(c.g0, v, g);
+      return;
+    }
+  }
   // neighbour u of the last, boundary edge (incoming half-edge hp): v is in
   // u's smooth rule (b_u), takes half of the edge point, and is one of u's two
   // boundary neighbours

@@ -1,8 +1,8 @@
-"""Cages with changing topology streamed two deep (api.StreamingRefiner: the
-plan of one cage overlaps the refinement of the previous one, and the two
-slots' refinements run side by side on their own streams, each with its own
-workspace): every step's output equals refining that cage alone, bit for
-bit."""
+"""Cages with changing topology streamed two (or three) deep
+(api.StreamingRefiner: the plan of one cage overlaps the refinement of the
+previous one, and the slots' refinements run side by side on their own
+streams, each with its own workspace): every step's output equals refining
+that cage alone, bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -13,8 +13,8 @@ from paper_1809_06047_amd import meshgen as G
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("scheme", ["cc", "loop"])
-def test_streamed_cages_equal_solo_refinement(scheme):
+@pytest.mark.parametrize("scheme,depth", [("cc", 2), ("loop", 2), ("cc", 3)])
+def test_streamed_cages_equal_solo_refinement(scheme, depth):
     if scheme == "cc":
         cages = [G.cc_cage(seed=31, level=2), G.cc_cage(seed=32, level=1), G.grid_patch(5, 4)]
     else:
@@ -22,8 +22,8 @@ def test_streamed_cages_equal_solo_refinement(scheme):
                  G.grid_patch(4, 3, tri=True)]
     L = 3
     dms = [api.DeviceMesh(m, "cuda") for m in cages]
-    sr = api.StreamingRefiner(scheme, L)
-    order = [0, 1, 2, 2, 0, 1, 1, 0]  # changing and repeated cages, both slots
+    sr = api.StreamingRefiner(scheme, L, depth=depth)
+    order = [0, 1, 2, 2, 0, 1, 1, 0]  # changing and repeated cages, every slot
     got = []
     for k in order:
         outs, ev = sr.step(dms[k])
