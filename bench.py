@@ -149,8 +149,9 @@ class TwoDeep:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the refinement of one cage "
-              "is a single-GPU workload; see the design notes for how it would shard)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported: the refinement of one cage "
+              "is a single-GPU workload (several GPUs would each refine a block of the cage's faces with a ghost "
+              "ring, or serve their own requests)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

@@ -1144,6 +1144,9 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       }
       ts.fpV = (int32_t)L[k - 1].V;  // (k is odd: level k was refined from level k-1)
       ts.fpF = (int32_t)L[k - 1].F;
+      // level k-1's adjacency stays in place until this step's face kernel
+      // (the per-level build walks level k instead, the form this is checked against)
+      if (!rebuild) ts.ap = aprev;
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_MARK, ts, s));
       SUBDIV_TIMED("sqrt3_trisect", k, launch_scan(ts.brank, ts.brank, t.F, at<int32_t>(ws, y.partials), nullptr, s));
       if (carry) {
@@ -1166,6 +1169,14 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       if (walk_own && k >= 1) {  // the points born from level k-1's faces
         c.fpV = (int32_t)L[k - 1].V;
         c.fpF = (int32_t)L[k - 1].F;
+        // a level made by the trisection step (the step before was one): its
+        // old vertices' rings from level k-1's fans and boundary slots, which
+        // stay in place until this step's face kernel (the per-level build
+        // walks them on level k, the form the closed one is checked against)
+        if (k % 2 == 0 && !rebuild) {
+          c.pbslot = at<int32_t>(ws, y.tslot);
+          c.pbrank = at<int32_t>(ws, y.trank);
+        }
       }
       // before the last step from level k: Loop still needs level k's edge
       // bases; nothing is carried, and level k+1's face table is only written

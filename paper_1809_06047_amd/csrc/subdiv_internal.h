@@ -437,6 +437,10 @@ struct TriStep {
   // rings walked on level k itself (Vg = 0) of a refined level: the points
   // fpV .. fpV + fpF - 1 born from the faces of level k-1 (fpF = 0: none)
   int32_t fpV, fpF;
+  // level k made by a trisection step (sqrt(3) with the boundary cycle): the
+  // boundary slot and rank of each level-(k-1) face (with ap = level k-1's
+  // adjacency), from which the old vertices' rings follow; nullptr otherwise
+  const int32_t *pbslot, *pbrank;
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
@@ -462,6 +466,8 @@ struct TrisectStep {
   uint8_t *pmask;   // [F] bit i: the point across edge i toward this face is a face point or p
   int32_t nbnd;     // B = boundary faces of level k
   int32_t fpV, fpF; // level k's face points of the faces of level k-1 (fpF = 0 on the cage)
+  Adj ap;           // optional (twin != nullptr): level k-1's adjacency, where the old vertices'
+                    // rings are walked (level k came from it by a sqrt(3) step)
 };
 enum { TRISECT_MARK = 0, TRISECT_FACE = 1, TRISECT_VERTEX = 2, TRISECT_COUNT = 3 };
 hipError_t trisect_launch(int which, const TrisectStep &c, hipStream_t s);

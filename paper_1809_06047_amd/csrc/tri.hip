@@ -161,6 +161,76 @@ __device__ __forceinline__ bool ring_rows_fp(const Topo &t, const Adj &a, const 
   return true;
 }
 
+// An interior old vertex v of a level k made by a trisection step has one
+// neighbour per level-(k-1) face s_i around it, in the order of its fan
+// there (g_i the half-edge leaving v in s_i): the point of the face s_{i-1}
+// before s_i toward s_i (its q when s_i lies across the edge after its
+// boundary edge, else its face point or p), followed by p_i itself when v is
+// the apex of the boundary face s_i (opposite its boundary edge j). Those
+// entries come from the half-edges 3 g_i and 9 s_i + 3 j + 2 of level k, and
+// the walk starts at the least of them. So the ring is read from level k-1's
+// fan, a third of level k's rows. Boundary vertices are fixed.
+__device__ __forceinline__ bool ring_trisected_old(const TriStep &c, int v, Ring &R) {
+  const Adj &x = c.ap;
+  const int g0 = x.vhe[v];
+  int gs[kFan], hb;
+  const int n = fan3(x.twin, g0, gs, hb);
+  if (n < 0) return false;  // a longer fan: walked on level k
+  if (hb >= 0) {  // on the boundary: the vertex stays where it is
+    R.faces = n;
+    R.ub = 0;
+    return true;
+  }
+  const int Vp = c.fpV, Fp = c.fpF;
+  int glast = gs[0];
+#pragma unroll
+  for (int i = 0; i < kFan; ++i)
+    if (i < n) glast = gs[i];
+  int sl[kFan];
+#pragma unroll
+  for (int i = 0; i < kFan; ++i) sl[i] = c.pbslot[gs[i] / 3];
+  int nb[2 * kFan], key[2 * kFan];
+  bool ok[2 * kFan];
+#pragma unroll
+  for (int i = 0; i < kFan; ++i) {
+    const int gp = i == 0 ? glast : gs[i - 1], sp = gp / 3;
+    const int jp = i == 0 ? c.pbslot[sp] : sl[i - 1];
+    const bool q = jp >= 0 && (gp % 3 + 2) % 3 == (jp + 1) % 3;  // s_i lies across sp's edge after its boundary edge
+    nb[2 * i] = q ? Vp + Fp + c.pbrank[sp] : Vp + sp;
+    key[2 * i] = 3 * gs[i];
+    ok[2 * i] = i < n;
+    const int si = gs[i] / 3, j = sl[i];
+    ok[2 * i + 1] = i < n && j >= 0 && gs[i] % 3 == (j + 2) % 3;
+    nb[2 * i + 1] = Vp + si;
+    key[2 * i + 1] = 9 * si + 3 * j + 2;
+  }
+  int st = 0, best = key[0];
+#pragma unroll
+  for (int e = 1; e < 2 * kFan; ++e)
+    if (ok[e] && key[e] < best) {
+      best = key[e];
+      st = e;
+    }
+  f3 pt[2 * kFan];
+#pragma unroll
+  for (int e = 0; e < 2 * kFan; ++e) pt[e] = ld3(c.P, ok[e] ? nb[e] : v);
+  int m = 0;
+#pragma unroll
+  for (int e = 0; e < 2 * kFan; ++e)
+    if (ok[e] && e >= st) {
+      R.sum = add3(R.sum, pt[e]);
+      ++m;
+    }
+#pragma unroll
+  for (int e = 0; e < 2 * kFan; ++e)
+    if (ok[e] && e < st) {
+      R.sum = add3(R.sum, pt[e]);
+      ++m;
+    }
+  R.faces = m;
+  return true;
+}
+
 // The old vertices v < Vg of a refined level k keep their rings from level
 // k-1: their level-k half-edges are the first slots of the children at their
 // level-(k-1) half-edges, in the same rotation order, and the neighbour along
@@ -240,6 +310,42 @@ __device__ __forceinline__ Ring ring_prev_loop(const TriStep &c, int v) {
   return R;
 }
 
+// The walk itself: the ring of an old vertex of a level refined by a sqrt(3)
+// step from the level with adjacency a, walked there from the vertex's start
+// h0: the neighbour across each half-edge is the face point Vg + (the face
+// of its twin).
+__device__ __forceinline__ void walk_below_sqrt3(const Adj &a, const float *P, int Vg, int h0, Ring &R) {
+  int hs[kFan], hb;
+  const int n = fan3(a.twin, h0, hs, hb);
+  if (n > 0) {
+    int ts[kFan];
+    f3 pt[kFan];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) ts[i] = a.twin[hs[i]];
+#pragma unroll
+    for (int i = 0; i < kFan; ++i) pt[i] = ld3(P, Vg + (ts[i] >= 0 ? ts[i] / 3 : 0));
+#pragma unroll
+    for (int i = 0; i < kFan; ++i)
+      if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
+    R.faces = n;
+    if (hb >= 0) R.ub = 0;  // on the boundary: the vertex stays where it is
+    return;
+  }
+  int h = h0;
+  while (true) {
+    const int ts = a.twin[h];
+    if (ts >= 0) R.sum = add3(R.sum, ld3(P, Vg + ts / 3));
+    ++R.faces;
+    const int tw = a.twin[h % 3 == 0 ? h + 2 : h - 1];
+    if (tw < 0) {
+      R.ub = 0;  // on the boundary: the vertex stays where it is
+      break;
+    }
+    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    h = tw;
+  }
+}
+
 __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
   const Adj &a = c.ap;
   const int h0 = a.vhe[v];
@@ -265,35 +371,7 @@ __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
       return R;
     }
   }
-  int hs[kFan], hb;
-  const int n = fan3(a.twin, h0, hs, hb);
-  if (n > 0) {
-    int ts[kFan];
-    f3 pt[kFan];
-#pragma unroll
-    for (int i = 0; i < kFan; ++i) ts[i] = a.twin[hs[i]];
-#pragma unroll
-    for (int i = 0; i < kFan; ++i) pt[i] = ld3(c.P, c.Vg + (ts[i] >= 0 ? ts[i] / 3 : 0));
-#pragma unroll
-    for (int i = 0; i < kFan; ++i)
-      if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
-    R.faces = n;
-    if (hb >= 0) R.ub = 0;  // on the boundary: the vertex stays where it is
-    return R;
-  }
-  int h = h0;
-  while (true) {
-    const int ts = a.twin[h];
-    if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + ts / 3));
-    ++R.faces;
-    const int tw = a.twin[he_prev<3>(c.t, h)];
-    if (tw < 0) {
-      R.ub = 0;  // on the boundary: the vertex stays where it is
-      break;
-    }
-    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
-    h = tw;
-  }
+  walk_below_sqrt3(a, c.P, c.Vg, h0, R);
   return R;
 }
 
@@ -842,8 +920,10 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
   Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
   if (c.a0.twin && ring_cage_sqrt3(c, v, R)) {
   } else if (c.Vg == 0) {
-    if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R)))
+    if (c.pbslot && v < c.fpV && ring_trisected_old(c, v, R)) {
+    } else if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R))) {
       R = ring3(c.t, c.a, c.P, v);
+    }
   } else {
     R = (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v) : ring_prev_sqrt3(c, v);
   }
@@ -1000,8 +1080,11 @@ __global__ void __launch_bounds__(kBlock) k_trisect_vertex(TrisectStep c) {
     S = lin2(19.0f / 27.0f, p, 4.0f / 27.0f, nb);
   } else {
     Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
-    if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R)))
+    if (c.ap.twin && v < c.fpV) {
+      walk_below_sqrt3(c.ap, c.P, c.fpV, c.ap.vhe[v], R);  // level k came from a sqrt(3) step
+    } else if (!(v >= c.fpV && v < c.fpV + c.fpF && ring_rows_fp(c.t, c.a, c.P, v, v - c.fpV, R))) {
       R = ring3(c.t, c.a, c.P, v);
+    }
     S = sqrt3_pt(p, R.sum, R.faces);
   }
   st3(c.P1, v, S);
