@@ -406,20 +406,23 @@ class GpuBatchExecutor:
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=gs):
                 call()
+            # a pinned staging buffer and a completion event of the graph's own:
+            # a replay reuses them only after the previous one has retired
+            host = torch.empty((V, 3), dtype=torch.float32, pin_memory=True)
             self.graphs[key] = dict(g=g, P_in=P_in, ws=ws, fv=fv, P=P, args=(structs, sc, lv, plans, outs),
-                                    busy=False, H=int(li.num_halfedges))
+                                    busy=False, H=int(li.num_halfedges), host=host, host_np=host.numpy(),
+                                    ev=torch.cuda.Event())
 
     def _launch_graph(self, r, e):
         torch = self.torch
+        e["host_np"][...] = r.mesh.positions  # (the graph is not busy: its last copy has completed)
         with torch.cuda.stream(self.stream):
-            host = torch.from_numpy(np.ascontiguousarray(r.mesh.positions, np.float32)).pin_memory()
-            e["P_in"].copy_(host, non_blocking=True)
+            e["P_in"].copy_(e["host"], non_blocking=True)
             e["g"].replay()
-            ev = torch.cuda.Event()
-            ev.record(self.stream)
+            e["ev"].record(self.stream)
         e["busy"] = True
         self.graph_launches += 1
-        return dict(ev=ev, keep=(host,), graph=e, hofs=np.array([0, e["H"]]), hs=[e["H"]],
+        return dict(ev=e["ev"], keep=(), graph=e, hofs=np.array([0, e["H"]]), hs=[e["H"]],
                     pofs=np.array([0, e["P"].shape[0]]))
 
     def launch(self, reqs, slot):
@@ -473,7 +476,13 @@ class GpuBatchExecutor:
     def results(self, h):
         if "graph" in h:  # the graph's static outputs are reused by its next replay
             e = h["graph"]
-            return [{"face_verts": e["fv"].clone(), "positions": e["P"].clone()}]
+            torch = self.torch
+            # copied on the replay stream, so the next replay comes after the copy;
+            # the caller's stream waits for it
+            with torch.cuda.stream(self.stream):
+                out = {"face_verts": e["fv"].clone(), "positions": e["P"].clone()}
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+            return [out]
         fv, P = h["keep"][2], h["keep"][3]
         return [{"face_verts": fv[int(h["hofs"][k]):int(h["hofs"][k]) + h["hs"][k]],
                  "positions": P[int(h["pofs"][k]):int(h["pofs"][k + 1])]} for k in range(len(h["hs"]))]

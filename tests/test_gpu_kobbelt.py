@@ -10,6 +10,7 @@ import torch
 from paper_1809_06047_amd import _lib, api
 from paper_1809_06047_amd import meshgen as G
 from tests.parity_util import POS_TOL, normwise_err
+from tests.test_gpu_parity import _bipyramid
 
 pytestmark = pytest.mark.gpu
 
@@ -19,10 +20,14 @@ CAGES = {
     "triangle": lambda: G.Mesh(positions=np.array([[0, 0, 0], [1, 0, 0], [0.2, 1, 0.5]], np.float32),
                                verts=np.array([0, 1, 2], np.int32), face_order=3, name="triangle"),
     "closed": lambda: G.tri_cage(seed=72, level=2, hole_frac=0.0),
+    # an interior apex of valence 12 inside a boundary ring: the fans longer
+    # than the kernels' unrolled eight are walked
+    "fan12": lambda: _bipyramid(12, closed=False),
 }
 
 
-@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 5), ("triangle", 5), ("closed", 4), ("holes", 2)])
+@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 5), ("triangle", 5), ("closed", 4), ("holes", 2),
+                                         ("fan12", 5)])
 def test_kobbelt_matches_oracle(oracle_mod, cage, levels):
     m = CAGES[cage]()
     print(f"[kobbelt] {m.name} L={levels}", flush=True)
@@ -60,7 +65,7 @@ def test_kobbelt_rejections():
         api.BatchRefiner([m, m], ["sqrt3k", "sqrt3k"], [2, 2]).plan()
 
 
-@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 5), ("triangle", 4)])
+@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 5), ("triangle", 4), ("fan12", 5)])
 def test_kobbelt_carried_adjacency_equals_rebuild(cage, levels):
     """Both steps of the cycle carry the next level's adjacency over in closed
     form; the generic per-level build (SUBDIV_FLAG_REBUILD_EACH_LEVEL) gives
