@@ -1080,15 +1080,15 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       // level k (sqrt(3): only for the caller's edge list); level k+1's points
       // from level m; its faces only for the caller
       TriStep cnt{t, a, P, nullptr, nullptr, Adj{}, at<int32_t>(ws, y.tbase2), (int32_t)L[k].B};
-      if (scheme == SUBDIV_LOOP) {
-        SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, cnt, s));
-        SUBDIV_TIMED("loop_scan", k, launch_scan(cnt.base, cnt.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
-      } else if (outs[levels].edge_verts) {
+      if (scheme != SUBDIV_LOOP && outs[levels].edge_verts) {
         SUBDIV_TIMED("sqrt3_count", k, tri_launch(SQRT3_COUNT, cnt, s));
         SUBDIV_TIMED("sqrt3_scan", k, launch_scan(cnt.base, cnt.base, t.F, at<int32_t>(ws, y.partials), nullptr, s));
       }
-      const TriLag g{tprev, aprev, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E,
-                     outs[k + 1].face_verts, P1, outs[k + 1].edge_verts, (int32_t)L[k].B};
+      TriLag g{tprev, aprev, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E,
+               outs[k + 1].face_verts, P1, outs[k + 1].edge_verts, (int32_t)L[k].B};
+      // Loop: level k's edge counts come out of the edge kernel's runs (in
+      // closed form from level m) and are scanned after it
+      if (scheme == SUBDIV_LOOP) g.cnt1 = cnt.base;
       TriStep o{};  // level m's vertices walk their level-m rings
       o.t = tprev;
       o.P = P;
@@ -1100,6 +1100,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));
         SUBDIV_TIMED("loop_edge", k, tri_lag_launch(LAG_LOOP_EDGE, g, s));
+        SUBDIV_TIMED("loop_scan", k, launch_scan(cnt.base, cnt.base, a.E, at<int32_t>(ws, y.partials), nullptr, s));
         if (g.fv2) SUBDIV_TIMED("loop_face", k, tri_lag_launch(LAG_LOOP_FACE, g, s));
       } else {
         SUBDIV_TIMED("sqrt3_vertex", k, tri_launch(SQRT3_VERTEX, o, s));

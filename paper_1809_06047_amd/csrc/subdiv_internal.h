@@ -488,6 +488,8 @@ struct TriLag {
   float *P2;             // level k+1 positions [V_{k+1}]
   int32_t *edges;        // optional: (lo, hi) of level k's edges in id order [2 E_k]
   int32_t Bk;            // sqrt(3): boundary edges of level k (its first ids)
+  int32_t *cnt1;         // Loop, optional: [E_k] per level-k edge 2 + |N(e) below e| (scanned
+                         // afterwards into level k's own edge bases)
 };
 enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);

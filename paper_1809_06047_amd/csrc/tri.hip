@@ -1460,6 +1460,7 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
     lds[off + 3 * slot + 2] = __float_as_uint(p.z);
   };
   const int lo_slot = a < b ? 0 : 1;  // (a, E_e) is base + 0 when a is the lower old end
+  int sa_ = INT_MAX, sb_ = INT_MAX;  // s's edges at a and b (none on the boundary)
   f3 S;
   int n;
   if (t < 0) {
@@ -1473,6 +1474,8 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
   } else {
     const int s = t / 3, i = t - 3 * s;  // t = s's half-edge b -> a
     const int sa = c.am.eid[3 * s + (i == 2 ? 0 : i + 1)], sb = c.am.eid[3 * s + (i == 0 ? 2 : i - 1)];
+    sa_ = sa;
+    sb_ = sb;
     const f3 psa = ld3(c.Pk, Vm + sa), psb = ld3(c.Pk, Vm + sb);
     S = loop_v6_pt(pE, add3(add3(pa, pb), add3(add3(pra, prb), add3(psa, psb))));
     put(lo_slot, loop_edge_pt(add3(pa, pE), add3(pra, psa)));
@@ -1511,6 +1514,35 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
     run_store(lds, dst, count, l);
   }
   __builtin_amdgcn_wave_barrier();
+  if (c.cnt1) {
+    // level k's own edge counts, 2 + |N below|, over the same run of ids. An
+    // end edge (a, E_e) lies in the corner children at a: its other edges
+    // there, (E_ra, a) and (a, E_sa), sit in the runs of ra and sa, so they
+    // come first exactly when ra < e (sa < e); (E_e, E_ra) and (E_sa, E_e)
+    // come after it. An edge (E_x, E_e), x < e, lies in the corner child at
+    // the end c shared with x and in the centre child of their face, whose
+    // third edge is y: (c, E_e) and (c, E_x) always come first, (E_y, E_e)
+    // when y < x, (E_x, E_y) when y < e.
+    const int ka = 2 + (ra < e) + (t >= 0 && sa_ < e), kb = 2 + (rb < e) + (t >= 0 && sb_ < e);
+    lds[base - base0 + lo_slot] = ka;
+    lds[base - base0 + 1 - lo_slot] = kb;
+    auto mid = [&](int x, int y, int slot) { lds[base - base0 + slot] = 4 + (y < x) + (y < e); };
+    if (t < 0) {
+      if (ra < e) mid(ra, rb, 2 + (rb < ra));
+      if (rb < e) mid(rb, ra, 2 + (ra < rb));
+    } else {
+      auto rank = [&](int x) { return (ra < x) + (rb < x) + (sa_ < x) + (sb_ < x); };
+      if (ra < e) mid(ra, rb, 2 + rank(ra));
+      if (rb < e) mid(rb, ra, 2 + rank(rb));
+      if (sa_ < e) mid(sa_, sb_, 2 + rank(sa_));
+      if (sb_ < e) mid(sb_, sa_, 2 + rank(sb_));
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int end = min(__shfl(base + n, min(63, E - 1 - (eid - l)), 64), c.Ek);
+    const int count = (eid - l < E) ? end - base0 : 0;
+    run_store(lds, reinterpret_cast<uint32_t *>(c.cnt1) + base0, count, l);
+    __builtin_amdgcn_wave_barrier();
+  }
   {
     const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
     const int count = 3 * (int)min(64ll, (long long)E - (eid - l));
