@@ -314,15 +314,17 @@ def main():
 #   edge kernel reads the edge's half-edge (4 B), reads and writes the vertex
 #   point of its edge point (24 B) and writes the edge points of level k's
 #   edges (12 B each); the vertex kernel reads and writes the positions of
-#   level m's vertices (24 B);
+#   level m's vertices (24 B), of level m-1's only when the step before also
+#   ran from two levels down (L >= 4: it wrote the final points of level m's
+#   edge points);
 #   sqrt(3) (computed from level m): the face kernel reads a level-m face's
 #   vertex and twin rows (24 B), writes its 9 grandchildren (108 B) and the
 #   face points of its 3 children (36 B), and reads and writes the vertex
 #   point of its face point (24 B); the vertex kernel reads and writes the
 #   positions of level m's vertices.
-TRI_BYTES = {"loop_face": lambda k, m: 216 * m["F"], "loop_edge": lambda k, m: 12 * k["E"] + 28 * m["E"],
-             "loop_vertex": lambda k, m: 24 * m["V"],
-             "sqrt3_face": lambda k, m: 192 * m["F"], "sqrt3_vertex": lambda k, m: 24 * m["V"]}
+TRI_BYTES = {"loop_face": lambda k, m, g: 216 * m["F"], "loop_edge": lambda k, m, g: 12 * k["E"] + 28 * m["E"],
+             "loop_vertex": lambda k, m, g: 24 * (g or m)["V"],
+             "sqrt3_face": lambda k, m, g: 192 * m["F"], "sqrt3_vertex": lambda k, m, g: 24 * m["V"]}
 
 
 def scheme_leg(mesh, scheme, levels, steps):
@@ -364,7 +366,8 @@ def scheme_leg(mesh, scheme, levels, steps):
         # which sqrt(3) with the boundary cycle does not take)
         if lvl != last or name not in TRI_BYTES or scheme == "sqrt3k":
             continue
-        nbytes = TRI_BYTES[name](r.level_info(last), r.level_info(last - 1))
+        g = r.level_info(last - 2) if levels >= 4 else None
+        nbytes = TRI_BYTES[name](r.level_info(last), r.level_info(last - 1), g)
         avg = tot / n
         gbs = nbytes / (avg / 1000.0) / 1e9
         roof[name] = {"avg_launch_ms": round(avg, 5), "algorithmic_bytes_per_launch": nbytes,

@@ -490,6 +490,9 @@ struct TriLag {
   int32_t Bk;            // sqrt(3): boundary edges of level k (its first ids)
   int32_t *cnt1;         // Loop, optional: [E_k] per level-k edge 2 + |N(e) below e| (scanned
                          // afterwards into level k's own edge bases)
+  float *Pk2;            // Loop, optional: level k+2 positions; the lane of e also writes the
+                         // level-(k+2) point of E_e (its level-(k+1) ring is the lane's run)
+  const int32_t *vhek;   // with Pk2: level k's ring starts (E_e's picks the order of its ring)
 };
 enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);

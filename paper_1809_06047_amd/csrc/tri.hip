@@ -66,6 +66,14 @@ __device__ __forceinline__ f3 loop_v6_pt(f3 p, f3 ring) {
   const float beta = c_loop_beta[6];
   return lin2(1.0f - 6.0f * beta, p, beta, ring);
 }
+// interior vertex of valence n: (1 - n beta_n) p + beta_n (sum of the ring),
+// the ring summed in the order of the walk from the vertex's start
+__device__ __forceinline__ f3 loop_old_pt(f3 p, f3 ring, int n) {
+#pragma clang fp contract(off)
+  const float beta = c_loop_beta[n];
+  return lin2(1.0f - (float)n * beta, p, beta, ring);
+}
+__device__ __forceinline__ f3 sel3(bool c, f3 a, f3 b) { return c ? a : b; }
 
 // sqrt(3) interior vertex: (1 - alpha_n) p + alpha_n / n (sum of the n
 // neighbours), uncontracted like the Loop stencils (the face point of a
@@ -677,14 +685,7 @@ __global__ void __launch_bounds__(BLK) k_loop_vertex(TriStep c) {
   const Ring R = c.Vg == 0                     ? ring3(c.t, c.a, c.P, v)
                  : (c.app.twin && v < c.Vq) ? ring_prev2_loop(c, v)
                                             : ring_prev_loop(c, v);
-  f3 S;
-  if (R.ub >= 0) {
-    S = fma3(0.75f, p, mul3(0.125f, add3(ld3(c.P, R.w0), ld3(c.P, R.ub))));
-  } else {
-    const int n = R.faces;
-    const float beta = c_loop_beta[n];
-    S = fma3(1.0f - (float)n * beta, p, mul3(beta, R.sum));
-  }
+  const f3 S = R.ub >= 0 ? loop_bnd_pt(p, add3(ld3(c.P, R.w0), ld3(c.P, R.ub))) : loop_old_pt(p, R.sum, R.faces);
   st3(c.P1, v, S);
   // an old vertex's half-edges at level k+1 are the first halves 3 (4r + j)
   // of its level-k half-edges 3r + j, in the same order
@@ -1461,16 +1462,19 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
   };
   const int lo_slot = a < b ? 0 : 1;  // (a, E_e) is base + 0 when a is the lower old end
   int sa_ = INT_MAX, sb_ = INT_MAX;  // s's edges at a and b (none on the boundary)
-  f3 S;
+  f3 S, S2{0.f, 0.f, 0.f};
   int n;
   if (t < 0) {
     S = loop_bnd_pt(pE, add3(pa, pb));
-    put(lo_slot, mul3(0.5f, add3(pa, pE)));
-    put(1 - lo_slot, mul3(0.5f, add3(pb, pE)));
+    const f3 ha = mul3(0.5f, add3(pa, pE)), hb = mul3(0.5f, add3(pb, pE));
+    put(lo_slot, ha);
+    put(1 - lo_slot, hb);
     n = 2;
     if (ra < e) put(2 + (rb < ra), loop_edge_pt(add3(pra, pE), add3(pa, prb)));
     if (rb < e) put(2 + (ra < rb), loop_edge_pt(add3(prb, pE), add3(pb, pra)));
     n += (ra < e) + (rb < e);
+    // two levels up, E_e stays on the boundary between the halves' edge points
+    if (c.Pk2) S2 = loop_bnd_pt(S, add3(ha, hb));
   } else {
     const int s = t / 3, i = t - 3 * s;  // t = s's half-edge b -> a
     const int sa = c.am.eid[3 * s + (i == 2 ? 0 : i + 1)], sb = c.am.eid[3 * s + (i == 0 ? 2 : i - 1)];
@@ -1478,15 +1482,38 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
     sb_ = sb;
     const f3 psa = ld3(c.Pk, Vm + sa), psb = ld3(c.Pk, Vm + sb);
     S = loop_v6_pt(pE, add3(add3(pa, pb), add3(add3(pra, prb), add3(psa, psb))));
-    put(lo_slot, loop_edge_pt(add3(pa, pE), add3(pra, psa)));
-    put(1 - lo_slot, loop_edge_pt(add3(pb, pE), add3(prb, psb)));
-    // the lower neighbours E_x, x < e, ranked among N(e) = {ra, rb, sa, sb}
+    const f3 ea = loop_edge_pt(add3(pa, pE), add3(pra, psa)), eb = loop_edge_pt(add3(pb, pE), add3(prb, psb));
+    put(lo_slot, ea);
+    put(1 - lo_slot, eb);
+    // the edges (E_x, E_e), x in N(e) = {ra, rb, sa, sb}: their ends and the
+    // two corners across them (the end x shares with e, and E of the face's
+    // third edge), grouped as the lane of max(x, e) groups them
+    const f3 mra = loop_edge_pt(add3(pra, pE), add3(pa, prb)), mrb = loop_edge_pt(add3(prb, pE), add3(pb, pra));
+    const f3 msa = loop_edge_pt(add3(psa, pE), add3(pa, psb)), msb = loop_edge_pt(add3(psb, pE), add3(pb, psa));
+    // the lower neighbours E_x, x < e, ranked among N(e)
     auto rank = [&](int x) { return (ra < x) + (rb < x) + (sa < x) + (sb < x); };
-    if (ra < e) put(2 + rank(ra), loop_edge_pt(add3(pra, pE), add3(pa, prb)));
-    if (rb < e) put(2 + rank(rb), loop_edge_pt(add3(prb, pE), add3(pb, pra)));
-    if (sa < e) put(2 + rank(sa), loop_edge_pt(add3(psa, pE), add3(pa, psb)));
-    if (sb < e) put(2 + rank(sb), loop_edge_pt(add3(psb, pE), add3(pb, psa)));
+    if (ra < e) put(2 + rank(ra), mra);
+    if (rb < e) put(2 + rank(rb), mrb);
+    if (sa < e) put(2 + rank(sa), msa);
+    if (sb < e) put(2 + rank(sb), msb);
     n = 2 + (ra < e) + (rb < e) + (sa < e) + (sb < e);
+    if (c.Pk2) {
+      // E_e's level-(k+1) ring, the six points above, in the order of the
+      // old-vertex walk from its level-k start h0. h0 is slot 1 of the corner
+      // child at e's first end in one of e's faces (taking e in that face's
+      // direction): the ring then runs E of the face's edge before e, the
+      // first end, E of the other face's edges at the first end and at the
+      // second, the second end, E of the face's edge after e. Or h0 is slot 2
+      // of the corner child at the second end: the same cycle from the fifth.
+      const int h0 = c.vhek[Vm + e];
+      const bool rs = h0 / 12 == r, first = h0 % 3 == 1;
+      const f3 w[6] = {sel3(rs, mra, msb), sel3(rs, ea, eb),  sel3(rs, msa, mrb),
+                       sel3(rs, msb, mra), sel3(rs, eb, ea), sel3(rs, mrb, msa)};
+      f3 sum{0.f, 0.f, 0.f};
+#pragma unroll
+      for (int x = 0; x < 6; ++x) sum = add3(sum, sel3(first, w[x], w[(x + 4) % 6]));
+      S2 = loop_old_pt(S, sum, 6);
+    }
   }
   if (c.edges && eid < E) {
     // level k's edges with higher end E_e, in id order: (lo, E_e), (hi, E_e),
@@ -1547,6 +1574,10 @@ __global__ void __launch_bounds__(BLK) k_loopl_edge(TriLag c) {
     const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
     const int count = 3 * (int)min(64ll, (long long)E - (eid - l));
     wave_store<3>(lds, row, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vm + eid - l)), l, count);
+    if (c.Pk2) {
+      const uint32_t row2[3] = {__float_as_uint(S2.x), __float_as_uint(S2.y), __float_as_uint(S2.z)};
+      wave_store<3>(lds, row2, reinterpret_cast<uint32_t *>(c.Pk2 + 3ll * (Vm + eid - l)), l, count);
+    }
   }
 }
 
