@@ -321,10 +321,12 @@ def main():
 #   vertex and twin rows (24 B), writes its 9 grandchildren (108 B) and the
 #   face points of its 3 children (36 B), and reads and writes the vertex
 #   point of its face point (24 B); the vertex kernel reads and writes the
-#   positions of level m's vertices.
+#   positions of level m's vertices, of level m-1's when the step before ran
+#   from two levels down (it wrote the final points of level m's face points
+#   away from the boundary; those few next to it are left out of the count).
 TRI_BYTES = {"loop_face": lambda k, m, g: 216 * m["F"], "loop_edge": lambda k, m, g: 12 * k["E"] + 28 * m["E"],
              "loop_vertex": lambda k, m, g: 24 * (g or m)["V"],
-             "sqrt3_face": lambda k, m, g: 192 * m["F"], "sqrt3_vertex": lambda k, m, g: 24 * m["V"]}
+             "sqrt3_face": lambda k, m, g: 192 * m["F"], "sqrt3_vertex": lambda k, m, g: 24 * (g or m)["V"]}
 
 
 def scheme_leg(mesh, scheme, levels, steps):

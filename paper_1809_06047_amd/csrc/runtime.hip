@@ -1005,7 +1005,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
   Adj aprev{};  // adjacency of level k-1 (the previous slot, or the cage's)
   Adj aprev2{};  // adjacency of level k-2
   Topo tprev{};  // mesh matrix of level k-1
-  bool ep_two_up = false;  // Loop: the step before the last wrote the final points of its level's edge points
+  bool ep_two_up = false;  // the step before the last wrote final points (Loop: edge points; sqrt(3): face points)
   // The last Loop or sqrt(3) step from level levels-2 (no adjacency of level
   // levels-1): when that level is a refined one and the caller wants no edge
   // list of level levels-1
@@ -1088,11 +1088,12 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       TriLag g{tprev, aprev, at<int32_t>(ws, y.tbase), P, (int32_t)L[k].V, (int32_t)L[k].E,
                outs[k + 1].face_verts, P1, outs[k + 1].edge_verts, (int32_t)L[k].B};
       // Loop: level k's edge counts come out of the edge kernel's runs (in
-      // closed form from level m) and are scanned after it; the same lanes
-      // write the final level's points of level k's edge points, unless the
-      // final buffer overlaps level k's or level k+1's
-      if (scheme == SUBDIV_LOOP) {
-        g.cnt1 = cnt.base;
+      // closed form from level m) and are scanned after it. The lanes also
+      // write the final points of level k's points born on level m (Loop: the
+      // edge points; sqrt(3): the face points), unless the final buffer
+      // overlaps level k's or level k+1's
+      if (scheme == SUBDIV_LOOP) g.cnt1 = cnt.base;
+      {
         float *PL = outs[levels].positions;
         auto apart = [&](const float *x, long long nx) { return PL + 3 * L[levels].V <= x || x + nx <= PL; };
         if (apart(P, 3 * L[k].V) && apart(P1, 3 * L[k + 1].V)) {
@@ -1135,9 +1136,10 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       // the older vertices walk there
       o.app = aprev2;
       o.Vr = k >= 3 ? (int32_t)L[k - 3].V : 0;
-      // level m's vertices born as edge points of level m-1 have their points
-      // from the step before: only the older ones walk
-      if (ep_two_up) o.t.V = o.Vq;
+      // level m's vertices born on level m-1 have their points from the step
+      // before (sqrt(3): those away from the boundary): only the others walk
+      if (ep_two_up && scheme == SUBDIV_LOOP) o.t.V = o.Vq;
+      if (ep_two_up && scheme == SUBDIV_SQRT3) o.fp_done = 1;
       if (scheme == SUBDIV_SQRT3) cage_rings(o, k - 1);
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_vertex", k, tri_launch(LOOP_VERTEX, o, s));

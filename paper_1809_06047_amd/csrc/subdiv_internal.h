@@ -441,6 +441,9 @@ struct TriStep {
   // boundary slot and rank of each level-(k-1) face (with ap = level k-1's
   // adjacency), from which the old vertices' rings follow; nullptr otherwise
   const int32_t *pbslot, *pbrank;
+  // sqrt(3), last step from two levels down: the points Vq .. Vg - 1 (face
+  // points of level k-2) whose three edges are interior already have theirs
+  int32_t fp_done;
 };
 enum { LOOP_EDGE = 0, LOOP_VERTEX = 1, LOOP_FACE = 2, SQRT3_FACE = 3, SQRT3_VERTEX = 4, SQRT3_COUNT = 5 };
 hipError_t tri_launch(int which, const TriStep &c, hipStream_t s);
@@ -490,9 +493,10 @@ struct TriLag {
   int32_t Bk;            // sqrt(3): boundary edges of level k (its first ids)
   int32_t *cnt1;         // Loop, optional: [E_k] per level-k edge 2 + |N(e) below e| (scanned
                          // afterwards into level k's own edge bases)
-  float *Pk2;            // Loop, optional: level k+2 positions; the lane of e also writes the
-                         // level-(k+2) point of E_e (its level-(k+1) ring is the lane's run)
-  const int32_t *vhek;   // with Pk2: level k's ring starts (E_e's picks the order of its ring)
+  float *Pk2;            // optional: level k+2 positions; the lane also writes the level-(k+2)
+                         // point of its level-k point (Loop: E_e; sqrt(3): F_r, when r's edges
+                         // are interior), whose level-(k+1) ring the lane holds
+  const int32_t *vhek;   // with Pk2: level k's ring starts (the start picks the ring's order)
 };
 enum { LAG_LOOP_FACE = 0, LAG_LOOP_EDGE = 1, LAG_SQRT3_FACE = 2 };
 hipError_t tri_lag_launch(int which, const TriLag &c, hipStream_t s);

@@ -917,6 +917,12 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
     if (c.a1.vhe) c.a1.vhe[v] = 3 * c.a.vhe[v];
     return;
   }
+  if (c.fp_done && v >= c.Vq && v < c.Vg) {
+    // written by the step before, with the closed-form ring of a face point
+    // whose three edges are interior (slot 1 of each child pairs with slot 1)
+    const int *tr = c.ap.twin + 9ll * (v - c.Vq);
+    if (tr[1] % 3 == 1 && tr[4] % 3 == 1 && tr[7] % 3 == 1) return;
+  }
   const f3 p = ld3(c.P, v);
   Ring R{{0.f, 0.f, 0.f}, 0, 0, -1};
   if (c.a0.twin && ring_cage_sqrt3(c, v, R)) {
@@ -928,14 +934,7 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_vertex(TriStep c) {
   } else {
     R = (c.app.twin && v < c.Vq) ? ring_prev2_sqrt3(c, v) : ring_prev_sqrt3(c, v);
   }
-  f3 S;
-  if (R.ub >= 0) {
-    S = p;
-  } else {
-    const int n = R.faces;
-    const float alpha = c_sqrt3_alpha[n];
-    S = fma3(1.0f - alpha, p, mul3(alpha / (float)n, R.sum));
-  }
+  const f3 S = R.ub >= 0 ? p : sqrt3_pt(p, R.sum, R.faces);
   st3(c.P1, v, S);
   // an old vertex's half-edges at level k+1 are the first slots 3 (3r + j) of
   // the children at its level-k half-edges 3r + j, in the same order
@@ -1663,6 +1662,41 @@ __global__ void __launch_bounds__(BLK) k_sqrt3l_face(TriLag c) {
     const f3 S = sqrt3_pt(pF, sum, n);
     const uint32_t row[3] = {__float_as_uint(S.x), __float_as_uint(S.y), __float_as_uint(S.z)};
     wave_store<3>(lds, row, reinterpret_cast<uint32_t *>(c.P2 + 3ll * (Vm + rw)), l, 3 * nw);
+    if (c.Pk2) {
+      // F_r two levels up, when r's three edges are interior (else the old-
+      // vertex kernel walks it): its level-(k+1) ring alternates the face
+      // points of the level-k faces across F_r -> v_j, the child of the face
+      // across edge j-1 at v_j, (v_j, F_r, F_s) in its slot order (formed
+      // as that face's lane forms it), and of r's child j; the walk starts at
+      // the first of these, or at r's child j when the start h0 is the twin of
+      // that child's slot 1, 3 t_j + 1. (Next to the boundary the row gets F_r's
+      // level-(k+1) point as a placeholder; the last step's walk replaces it.)
+      f3 S2 = S;
+      if (tw[0] >= 0 && tw[1] >= 0 && tw[2] >= 0) {
+        auto fq = [&](f3 x, f3 y, f3 z) { return mul3(1.0f / 3.0f, add3(add3(x, y), z)); };
+        const f3 n0 = fq(pv[0], pF, pX[2]), c0 = fq(pv[0], pX[0], pF);
+        const f3 n1 = fq(pv[1], pF, pX[0]), c1 = fq(pv[1], pX[1], pF);
+        const f3 n2 = fq(pv[2], pF, pX[1]), c2 = fq(pv[2], pX[2], pF);
+        const int h0 = c.vhek[Fr];
+        auto sum6 = [](f3 a, f3 b, f3 x, f3 y, f3 z, f3 w) {
+          f3 ring{0.f, 0.f, 0.f};
+          ring = add3(ring, a);
+          ring = add3(ring, b);
+          ring = add3(ring, x);
+          ring = add3(ring, y);
+          ring = add3(ring, z);
+          return add3(ring, w);
+        };
+        f3 ring;
+        if (h0 == 3 * tw[0] + 1) ring = sum6(c0, n1, c1, n2, c2, n0);
+        else if (h0 == 3 * tw[1] + 1) ring = sum6(c1, n2, c2, n0, c0, n1);
+        else if (h0 == 3 * tw[2] + 1) ring = sum6(c2, n0, c0, n1, c1, n2);
+        else ring = sum6(n0, c0, n1, c1, n2, c2);
+        S2 = sqrt3_pt(S, ring, 6);
+      }
+      const uint32_t row2[3] = {__float_as_uint(S2.x), __float_as_uint(S2.y), __float_as_uint(S2.z)};
+      wave_store<3>(lds, row2, reinterpret_cast<uint32_t *>(c.Pk2 + 3ll * (Vm + rw)), l, 3 * nw);
+    }
   }
   if (c.edges && rid < F) {
     // level k's edge list (the carried ids of the face kernel above): a kept
