@@ -84,6 +84,20 @@ __device__ __forceinline__ f3 sqrt3_pt(f3 p, f3 ring, int n) {
   return lin2(1.0f - alpha, p, alpha / (float)n, ring);
 }
 
+// a_j for a runtime j in 0..2, by selects (a dynamic index into an array
+// would put the array in scratch memory)
+__device__ __forceinline__ int pick3(int a0, int a1, int a2, int j) { return j == 0 ? a0 : j == 1 ? a1 : a2; }
+
+// s + a + b + c + d + e + f, added in that order (a ring sum from its start)
+__device__ __forceinline__ f3 sum6(f3 s, f3 a, f3 b, f3 c, f3 d, f3 e, f3 f) {
+  s = add3(s, a);
+  s = add3(s, b);
+  s = add3(s, c);
+  s = add3(s, d);
+  s = add3(s, e);
+  return add3(s, f);
+}
+
 // ring walk around v: sum of the neighbours, count of faces, boundary ends
 struct Ring {
   f3 sum;
@@ -163,8 +177,11 @@ __device__ __forceinline__ bool ring_rows_fp(const Topo &t, const Adj &a, const 
   f3 pt[6];
 #pragma unroll
   for (int y = 0; y < 6; ++y) pt[y] = ld3(P, x[3 * (y >> 1) + (y & 1)]);
-#pragma unroll
-  for (int u = 0; u < 6; ++u) R.sum = add3(R.sum, pt[p0 + u < 6 ? p0 + u : p0 + u - 6]);
+  // (the rotation by cases, so that pt stays in registers)
+  if (p0 == 1) R.sum = sum6(R.sum, pt[1], pt[2], pt[3], pt[4], pt[5], pt[0]);
+  else if (p0 == 3) R.sum = sum6(R.sum, pt[3], pt[4], pt[5], pt[0], pt[1], pt[2]);
+  else if (p0 == 5) R.sum = sum6(R.sum, pt[5], pt[0], pt[1], pt[2], pt[3], pt[4]);
+  else R.sum = sum6(R.sum, pt[0], pt[1], pt[2], pt[3], pt[4], pt[5]);
   R.faces = 6;
   return true;
 }
@@ -236,6 +253,7 @@ __device__ __forceinline__ bool ring_trisected_old(const TriStep &c, int v, Ring
       ++m;
     }
   R.faces = m;
+  R.ub = -1;
   return true;
 }
 
@@ -336,22 +354,26 @@ __device__ __forceinline__ void walk_below_sqrt3(const Adj &a, const float *P, i
     for (int i = 0; i < kFan; ++i)
       if (i < n && ts[i] >= 0) R.sum = add3(R.sum, pt[i]);
     R.faces = n;
-    if (hb >= 0) R.ub = 0;  // on the boundary: the vertex stays where it is
+    R.ub = hb >= 0 ? 0 : -1;  // on the boundary: the vertex stays where it is
     return;
   }
-  int h = h0;
+  // (every exit writes both counts: a store to one of them on some paths
+  // only makes the compiler keep the ring in scratch memory)
+  int h = h0, nf = R.faces, ub = -1;
   while (true) {
     const int ts = a.twin[h];
     if (ts >= 0) R.sum = add3(R.sum, ld3(P, Vg + ts / 3));
-    ++R.faces;
+    ++nf;
     const int tw = a.twin[h % 3 == 0 ? h + 2 : h - 1];
     if (tw < 0) {
-      R.ub = 0;  // on the boundary: the vertex stays where it is
+      ub = 0;  // on the boundary: the vertex stays where it is
       break;
     }
-    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    if (tw == h0 || nf >= SUBDIV_MAX_VALENCE) break;
     h = tw;
   }
+  R.faces = nf;
+  R.ub = ub;
 }
 
 __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
@@ -372,7 +394,7 @@ __device__ __forceinline__ Ring ring_prev_sqrt3(const TriStep &c, int v) {
       for (int t = 0; t < 6; ++t) {
         const int x = p0 + t < 6 ? p0 + t : p0 + t - 6, j = x >> 1;
         // across F_r -> v_j: the face holding v_j -> F_r; across F_r -> F_s: r's child j
-        const int face = (x & 1) ? 3 * r + j : t2[j] / 3;
+        const int face = (x & 1) ? 3 * r + j : pick3(t2[0], t2[1], t2[2], j) / 3;
         R.sum = add3(R.sum, ld3(c.P, c.Vg + face));
       }
       R.faces = 6;
@@ -490,21 +512,24 @@ __device__ __forceinline__ bool ring_cage_sqrt3(const TriStep &c, int v, Ring &R
 #pragma unroll
       for (int i = 0; i < kFan; ++i)
         if (i < n) R.sum = add3(R.sum, pt[i]);
+      R.ub = -1;
       return true;
     }
-    int h = h0;
+    int h = h0, nf = R.faces, ub = -1;
     while (true) {
       const int ts = tw0[h];
       if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + m0 * sqrt3_across_image(ts)));
-      ++R.faces;
+      ++nf;
       const int tw = tw0[h % 3 == 0 ? h + 2 : h - 1];
       if (tw < 0) {
-        R.ub = 0;
+        ub = 0;
         break;
       }
-      if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+      if (tw == h0 || nf >= SUBDIV_MAX_VALENCE) break;
       h = tw;
     }
+    R.faces = nf;
+    R.ub = ub;
     return true;
   }
   if (c.pow3 >= 3 && v < c.V0 + c.F0) {
@@ -523,11 +548,12 @@ __device__ __forceinline__ bool ring_cage_sqrt3(const TriStep &c, int v, Ring &R
     const int m1 = c.pow3 / 3;
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
-      const int y = p0 + u < 6 ? p0 + u : p0 + u - 6, j = y >> 1, tp = t[(j + 2) % 3];
+      const int y = p0 + u < 6 ? p0 + u : p0 + u - 6, j = y >> 1, tp = pick3(t[0], t[1], t[2], (j + 2) % 3);
       const int T = (y & 1) ? 9 * r + 3 * j + 1 : 9 * (tp / 3) + 3 * (tp % 3);
       R.sum = add3(R.sum, ld3(c.P, c.Vg + m1 * sqrt3_across_image(T)));
     }
     R.faces = 6;
+    R.ub = -1;
     return true;
   }
   return false;
@@ -552,10 +578,11 @@ __device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
         // the ring's half-edges alternate F_r -> v_j (slot 2 of r's child j,
         // twin t2[j]) and F_r -> F_s (t1[j], the twin of r's child j's slot
         // 1); all interior
-        const int tw = (y & 1) ? 9 * r + 3 * j + 1 : t2[j];
+        const int tw = (y & 1) ? 9 * r + 3 * j + 1 : pick3(t2[0], t2[1], t2[2], j);
         R.sum = add3(R.sum, ld3(c.P, c.Vg + sqrt3_across_image(tw)));
       }
       R.faces = 6;
+      R.ub = -1;
       return R;
     }
   }
@@ -577,21 +604,24 @@ __device__ __forceinline__ Ring ring_prev2_sqrt3(const TriStep &c, int v) {
     for (int i = 0; i < kFan; ++i)
       if (i < n) R.sum = add3(R.sum, pt[i]);
     R.faces = n;
+    R.ub = -1;
     return R;
   }
-  int h = h0;
+  int h = h0, nf = 0, ub = -1;
   while (true) {
     const int ts = x.twin[h];
     if (ts >= 0) R.sum = add3(R.sum, ld3(c.P, c.Vg + sqrt3_across_image(ts)));
-    ++R.faces;
+    ++nf;
     const int tw = x.twin[he_prev<3>(c.t, h)];
     if (tw < 0) {
-      R.ub = 0;  // on the boundary: the vertex stays where it is
+      ub = 0;  // on the boundary: the vertex stays where it is
       break;
     }
-    if (tw == h0 || R.faces >= SUBDIV_MAX_VALENCE) break;
+    if (tw == h0 || nf >= SUBDIV_MAX_VALENCE) break;
     h = tw;
   }
+  R.faces = nf;
+  R.ub = ub;
   return R;
 }
 
@@ -1678,20 +1708,12 @@ __global__ void __launch_bounds__(BLK) k_sqrt3l_face(TriLag c) {
         const f3 n1 = fq(pv[1], pF, pX[0]), c1 = fq(pv[1], pX[1], pF);
         const f3 n2 = fq(pv[2], pF, pX[1]), c2 = fq(pv[2], pX[2], pF);
         const int h0 = c.vhek[Fr];
-        auto sum6 = [](f3 a, f3 b, f3 x, f3 y, f3 z, f3 w) {
-          f3 ring{0.f, 0.f, 0.f};
-          ring = add3(ring, a);
-          ring = add3(ring, b);
-          ring = add3(ring, x);
-          ring = add3(ring, y);
-          ring = add3(ring, z);
-          return add3(ring, w);
-        };
+        const f3 z{0.f, 0.f, 0.f};
         f3 ring;
-        if (h0 == 3 * tw[0] + 1) ring = sum6(c0, n1, c1, n2, c2, n0);
-        else if (h0 == 3 * tw[1] + 1) ring = sum6(c1, n2, c2, n0, c0, n1);
-        else if (h0 == 3 * tw[2] + 1) ring = sum6(c2, n0, c0, n1, c1, n2);
-        else ring = sum6(n0, c0, n1, c1, n2, c2);
+        if (h0 == 3 * tw[0] + 1) ring = sum6(z, c0, n1, c1, n2, c2, n0);
+        else if (h0 == 3 * tw[1] + 1) ring = sum6(z, c1, n2, c2, n0, c0, n1);
+        else if (h0 == 3 * tw[2] + 1) ring = sum6(z, c2, n0, c0, n1, c1, n2);
+        else ring = sum6(z, n0, c0, n1, c1, n2, c2);
         S2 = sqrt3_pt(S, ring, 6);
       }
       const uint32_t row2[3] = {__float_as_uint(S2.x), __float_as_uint(S2.y), __float_as_uint(S2.z)};
