@@ -242,6 +242,26 @@ def test_status_codes_match_oracle(oracle_mod):
 
 
 @pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
+def test_final_buffer_shared_with_level_L_minus_2(scheme):
+    """The step before the last also writes the final points of its level's
+    newest vertices (they lie in the lanes that form their rings). A caller may
+    hand level L-2's positions the same buffer as the final level's (level L-2
+    is not read by the last step): the library then leaves those points to
+    the last step, and the final level is the same bit for bit."""
+    m = G.tri_cage(seed=19, level=2, hole_frac=0.08)
+    L = 4
+    print(f"[parity] {scheme} final buffer shared with level {L - 2}: {m.name} L={L}", flush=True)
+    want, _ = api.refine(m, scheme, L)
+    r = api.Refiner(m, scheme, L)
+    r.plan()
+    r._outs_struct[L - 2].positions = r.outs[L]["positions"].data_ptr()
+    r.run()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.outs[L]["face_verts"].cpu().numpy(), want[L]["face_verts"].cpu().numpy())
+    np.testing.assert_array_equal(r.outs[L]["positions"].cpu().numpy(), want[L]["positions"].cpu().numpy())
+
+
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
 @pytest.mark.parametrize("cage,levels", [(c, L) for c in ("icosphere", "holes", "fan", "bipyramid", "grid")
                                          for L in (3, 4)] + [("holes", 5), ("fan", 5)])
 def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
