@@ -170,6 +170,11 @@ int subdiv_plan(const subdiv_mesh *mesh, int scheme, int levels, uint32_t flags,
  * workspace plan used, the level-0 adjacency is reused. The mesh must be the
  * one planned (same face_verts pointer); positions may change, the crease
  * tags and sharpness are read by subdiv_plan.
+ * Output buffers of different levels must not overlap, with one exception:
+ * level levels-2's positions may share the final positions' buffer (it is
+ * not read after the final level's first write). For Loop and sqrt(3) the
+ * step before the last writes part of the final positions early, and skips
+ * that when the final positions overlap level levels-2's or levels-1's.
  * Enqueues work only: no host synchronisation. */
 int subdiv_refine(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_level_out *outs, void *ws,
                   size_t ws_bytes, void *stream);
