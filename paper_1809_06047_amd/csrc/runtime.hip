@@ -1206,11 +1206,18 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       double *sig1 = nullptr;
       if (lcr && L[k + 1].creases)
         sig1 = final ? outs[k + 1].crease_sharpness : adj_at(ws, tri_slot(k + 1), L[k + 1].E, true).sig;
+      // sqrt(3), the step before the two steps from the levels below: level
+      // k+1's edge ids (and level k's face bases, which number them) are read
+      // there only for edge lists; without those, carry the twins and ring
+      // starts alone
+      const bool twins_only = carry && scheme == SUBDIV_SQRT3 && lag2 && k == levels - 3 &&
+                              !outs[levels - 1].edge_verts && !outs[levels].edge_verts;
       if (carry) {
         c.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, L[k + 1].creases != 0);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
+        if (twins_only) c.a1.eid = c.a1.e2h = nullptr;
       }
-      if (carry || (before_lag && scheme == SUBDIV_LOOP) || sig1) c.base = at<int32_t>(ws, y.tbase);
+      if ((carry && !twins_only) || (before_lag && scheme == SUBDIV_LOOP) || sig1) c.base = at<int32_t>(ws, y.tbase);
       if (before_lag && !outs[k + 1].face_verts) c.fv1 = nullptr;
       if (scheme == SUBDIV_LOOP) {
         SUBDIV_TIMED("loop_edge", k, tri_launch(LOOP_EDGE, c, s));

@@ -865,7 +865,9 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_face(TriStep c) {
   }
   if (!c.a1.twin) return;
   // ---- carried adjacency of level k+1 (see above); h1(q, s) = 3 q + s
-  const int B = c.nbnd, br = B + c.base[r];
+  // (without c.a1.eid only the twins and ring starts: no edge ids, no face bases)
+  const bool ids = c.a1.eid != nullptr;
+  const int B = c.nbnd, br = ids ? B + c.base[r] : 0;
   int nb[3];  // neighbour across edge j, -1 on the boundary
 #pragma unroll
   for (int j = 0; j < 3; ++j) nb[j] = tw[j] < 0 ? -1 : tw[j] / 3;
@@ -882,43 +884,49 @@ __global__ void __launch_bounds__(BLK) k_sqrt3_face(TriStep c) {
     tw1[3 * j + 2] = t2;
     const int id2 = br + rk_j;
     ei1[3 * j + 2] = id2;
-    if (valid) c.a1.e2h[id2] = min(9 * r + 3 * j + 2, t2);
+    if (ids && valid) c.a1.e2h[id2] = min(9 * r + 3 * j + 2, t2);
     if (t < 0) {
       // boundary edge j kept: v_j -> v_{j+1}, then v_{j+1} -> F_r
-      const int e = c.a.eid[3 * r + j];
-      const int idb = c.a.bscan ? c.a.bscan[e] : e;  // its rank among the boundary edges
       tw1[3 * j + 0] = -1;
-      ei1[3 * j + 0] = idb;
-      if (valid) c.a1.e2h[idb] = 9 * r + 3 * j;
       tw1[3 * j + 1] = 9 * r + 3 * jn + 2;
       ei1[3 * j + 1] = br + rk_jn;
+      ei1[3 * j + 0] = 0;
+      if (ids) {
+        const int e = c.a.eid[3 * r + j];
+        const int idb = c.a.bscan ? c.a.bscan[e] : e;  // its rank among the boundary edges
+        ei1[3 * j + 0] = idb;
+        if (valid) c.a1.e2h[idb] = 9 * r + 3 * j;
+      }
     } else {
       const int s = t / 3, i = t % 3;  // t = s's half-edge v_{j+1} -> v_j
       // slot 0: v_j -> F_s; twin F_s -> v_j is slot 2 of s's child at v_j
       tw1[3 * j + 0] = 9 * s + 3 * ((i + 1) % 3) + 2;
-      const int w = c.t.fv[3 * s + (i + 2) % 3];  // the third corner of s
-      ei1[3 * j + 0] = B + c.base[s] + rank3(v[j], v[jn], w);
       // slot 1: F_s -> F_r, the flipped edge; twin F_r -> F_s is slot 1 of s's child i
       tw1[3 * j + 1] = 9 * s + 3 * i + 1;
-      int idf;
-      if (s < r) {
-        idf = br + 3 + (nb[0] >= 0 && nb[0] < s) + (nb[1] >= 0 && nb[1] < s) + (nb[2] >= 0 && nb[2] < s);
-        vhe_fp = min(vhe_fp, 9 * s + 3 * i + 1);
-      } else {
-        int k3 = 0;
+      if (s < r) vhe_fp = min(vhe_fp, 9 * s + 3 * i + 1);
+      ei1[3 * j + 0] = ei1[3 * j + 1] = 0;
+      if (ids) {
+        const int w = c.t.fv[3 * s + (i + 2) % 3];  // the third corner of s
+        ei1[3 * j + 0] = B + c.base[s] + rank3(v[j], v[jn], w);
+        int idf;
+        if (s < r) {
+          idf = br + 3 + (nb[0] >= 0 && nb[0] < s) + (nb[1] >= 0 && nb[1] < s) + (nb[2] >= 0 && nb[2] < s);
+        } else {
+          int k3 = 0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const int u = c.a.twin[3 * s + m];
-          k3 += (u >= 0 && u / 3 < r);
+          for (int m = 0; m < 3; ++m) {
+            const int u = c.a.twin[3 * s + m];
+            k3 += (u >= 0 && u / 3 < r);
+          }
+          idf = B + c.base[s] + 3 + k3;
+          if (valid) c.a1.e2h[idf] = 9 * r + 3 * j + 1;  // the lower of its two half-edges
         }
-        idf = B + c.base[s] + 3 + k3;
-        if (valid) c.a1.e2h[idf] = 9 * r + 3 * j + 1;  // the lower of its two half-edges
+        ei1[3 * j + 1] = idf;
       }
-      ei1[3 * j + 1] = idf;
     }
   }
   wave_store<9>(lds, tw1, reinterpret_cast<uint32_t *>(c.a1.twin) + 9 * rw, l, cnt);
-  wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
+  if (ids) wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
   if (valid) c.a1.vhe[V + r] = vhe_fp;
 }
 
