@@ -992,7 +992,13 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
     SUBDIV_TIMED("build", 0,
                  build_creases(t, b, full, mesh->num_creases, mesh->crease_verts, mesh->crease_sharpness, dinfo, s));
   }
-  if (L[0].B > 0 && scheme != SUBDIV_LOOP) {  // boundary prefix: CC edge-point ids, sqrt(3) kept boundary edges
+  bool any_edge_list = false;
+  for (int k = 1; k <= levels; ++k) any_edge_list = any_edge_list || outs[k].edge_verts != nullptr;
+  // (sqrt(3) numbers its kept boundary edges by this prefix only for edge ids,
+  // which it carries only for edge lists, or with the state kept)
+  const bool sqrt3_ids = scheme == SUBDIV_SQRT3 && (keep || any_edge_list);
+  if (L[0].B > 0 && scheme != SUBDIV_LOOP && (scheme != SUBDIV_SQRT3 || sqrt3_ids)) {
+    // boundary prefix: CC edge-point ids, sqrt(3) kept boundary edges
     BuildScratch b = scratch0(ws, y);
     SUBDIV_TIMED("bscan", 0, build_bscan(t, b, a, s));
   }
@@ -1206,12 +1212,11 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       double *sig1 = nullptr;
       if (lcr && L[k + 1].creases)
         sig1 = final ? outs[k + 1].crease_sharpness : adj_at(ws, tri_slot(k + 1), L[k + 1].E, true).sig;
-      // sqrt(3), the step before the two steps from the levels below: level
-      // k+1's edge ids (and level k's face bases, which number them) are read
-      // there only for edge lists; without those, carry the twins and ring
-      // starts alone
-      const bool twins_only = carry && scheme == SUBDIV_SQRT3 && lag2 && k == levels - 3 &&
-                              !outs[levels - 1].edge_verts && !outs[levels].edge_verts;
+      // sqrt(3): the edge ids of a level (and the face bases of the level
+      // before, which number them) are read only to number the next level's
+      // edges and for edge lists; with no edge list asked for, carry the
+      // twins and ring starts alone
+      const bool twins_only = carry && scheme == SUBDIV_SQRT3 && !sqrt3_ids;
       if (carry) {
         c.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, L[k + 1].creases != 0);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids
