@@ -994,10 +994,12 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
   }
   bool any_edge_list = false;
   for (int k = 1; k <= levels; ++k) any_edge_list = any_edge_list || outs[k].edge_verts != nullptr;
-  // (sqrt(3) numbers its kept boundary edges by this prefix only for edge ids,
-  // which it carries only for edge lists, or with the state kept)
-  const bool sqrt3_ids = scheme == SUBDIV_SQRT3 && (keep || any_edge_list);
-  if (L[0].B > 0 && scheme != SUBDIV_LOOP && (scheme != SUBDIV_SQRT3 || sqrt3_ids)) {
+  // (sqrt(3), with the boundary cycle too, numbers its kept boundary edges by
+  // this prefix only for edge ids, which it carries only for edge lists, or
+  // with the state kept: its new points are numbered by faces)
+  const bool sqrt3_family = scheme == SUBDIV_SQRT3 || scheme == SUBDIV_SQRT3_KOBBELT;
+  const bool sqrt3_ids = sqrt3_family && (keep || any_edge_list);
+  if (L[0].B > 0 && scheme != SUBDIV_LOOP && (!sqrt3_family || sqrt3_ids)) {
     // boundary prefix: CC edge-point ids, sqrt(3) kept boundary edges
     BuildScratch b = scratch0(ws, y);
     SUBDIV_TIMED("bscan", 0, build_bscan(t, b, a, s));
@@ -1162,9 +1164,13 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       const bool carry = !rebuild && !final;  // level k+1's adjacency in closed form
       if (carry) {
         ts.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, false);
-        ts.base = at<int32_t>(ws, y.tbase3);
-        ts.pmask = at<uint8_t>(ws, y.tmask);
-        ts.nbnd = (int32_t)L[k].B;
+        if (sqrt3_ids) {
+          ts.base = at<int32_t>(ws, y.tbase3);
+          ts.pmask = at<uint8_t>(ws, y.tmask);
+          ts.nbnd = (int32_t)L[k].B;
+        } else {  // twins and ring starts alone (see the sqrt(3) step)
+          ts.a1.eid = ts.a1.e2h = ts.a1.bscan = nullptr;
+        }
       }
       ts.fpV = (int32_t)L[k - 1].V;  // (k is odd: level k was refined from level k-1)
       ts.fpF = (int32_t)L[k - 1].F;
@@ -1173,7 +1179,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       if (!rebuild) ts.ap = aprev;
       SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_MARK, ts, s));
       SUBDIV_TIMED("sqrt3_trisect", k, launch_scan(ts.brank, ts.brank, t.F, at<int32_t>(ws, y.partials), nullptr, s));
-      if (carry) {
+      if (carry && sqrt3_ids) {
         SUBDIV_TIMED("sqrt3_trisect", k, trisect_launch(TRISECT_COUNT, ts, s));
         SUBDIV_TIMED("sqrt3_trisect", k,
                      launch_scan(ts.base, ts.base, 2ll * t.F, at<int32_t>(ws, y.partials), nullptr, s));
@@ -1216,7 +1222,7 @@ int refine_impl(const subdiv_mesh *mesh, const subdiv_plan_info *plan, subdiv_le
       // before, which number them) are read only to number the next level's
       // edges and for edge lists; with no edge list asked for, carry the
       // twins and ring starts alone
-      const bool twins_only = carry && scheme == SUBDIV_SQRT3 && !sqrt3_ids;
+      const bool twins_only = carry && sqrt3_family && !sqrt3_ids;
       if (carry) {
         c.a1 = adj_at(ws, tri_slot(k + 1), L[k + 1].E, L[k + 1].creases != 0);
         c.a1.bscan = nullptr;  // sqrt(3): the boundary edges of a refined level are its first ids

@@ -1197,6 +1197,8 @@ __global__ void __launch_bounds__(kBlock) k_trisect_count(TrisectStep c) {
 __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool valid, const int (&v)[3],
                                               const int (&X)[3], uint32_t *lds, long long rw, int l, int cnt) {
   const int V = c.t.V, F = c.t.F, j = c.bslot[r];
+  // (without c.a1.eid only the twins and ring starts: no edge ids, no bases)
+  const bool ids = c.a1.eid != nullptr;
   const int32_t *baseP = c.base, *baseQ = c.base + F;
   int s[3], ip[3], js[3];
   bool isp[3];
@@ -1208,7 +1210,7 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
     js[i] = t < 0 ? -1 : c.bslot[s[i]];
     isp[i] = X[i] >= 0 && X[i] < V + F;
   }
-  const int bP = baseP[r];
+  const int bP = ids ? baseP[r] : 0;
   // edge (v_i, X_i), edge i interior
   auto id_vX = [&](int i, int vi, int vn) {
     if (!isp[i]) return baseQ[s[i]] + (vi > vn);
@@ -1244,8 +1246,8 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
       tw1[3 * i + 0] = flip(i);
       tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
       tw1[3 * i + 2] = 9 * s[im] + 3 * ip[im];
-      ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
-      ei1[3 * i + 1] = id_XP(i, false);
+      ei1[3 * i + 0] = ids ? id_vX(i, v[i], v[in]) : 0;
+      ei1[3 * i + 1] = ids ? id_XP(i, false) : 0;
       ei1[3 * i + 2] = bP + rank3(v[i], v[in], v[im]);
     }
     if (valid) {
@@ -1255,7 +1257,7 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
       c.a1.vhe[V + r] = m0;
     }
   } else {
-    const int bQ = baseQ[r];
+    const int bQ = ids ? baseQ[r] : 0;
     int idPQ = 0, idwQ = 0, iduP = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -1274,30 +1276,32 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
         tw1[3 * i + 0] = flip(i);
         tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
         tw1[3 * i + 2] = -1;
-        ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
-        ei1[3 * i + 1] = isp[i] ? bQ + 2 + (s[i] > r) : (s[i] < r ? bQ + 3 : baseQ[s[i]] + 3);
+        ei1[3 * i + 0] = ids ? id_vX(i, v[i], v[in]) : 0;
+        ei1[3 * i + 1] = isp[i] ? bQ + 2 + (s[i] > r) : (s[i] < r || !ids ? bQ + 3 : baseQ[s[i]] + 3);
         ei1[3 * i + 2] = idwQ;
       } else {  // (z, X, p): z = v_i, u = v_in
         tw1[3 * i + 0] = flip(i);
         tw1[3 * i + 1] = 9 * s[i] + 3 * ip[i] + 1;
         tw1[3 * i + 2] = 9 * r + 3 * in + 2;
-        ei1[3 * i + 0] = id_vX(i, v[i], v[in]);
-        ei1[3 * i + 1] = id_XP(i, true);
+        ei1[3 * i + 0] = ids ? id_vX(i, v[i], v[in]) : 0;
+        ei1[3 * i + 1] = ids ? id_XP(i, true) : 0;
         ei1[3 * i + 2] = bP + (v[i] > v[in]);
       }
     }
     if (valid) {
       const int rk = c.brank[r], B = c.nbnd, jn = (j + 1) % 3;
-      c.a1.bscan[iduP] = rk;  // u - p
-      c.a1.bscan[idwQ] = B + 2 * rk;  // q - w
-      c.a1.bscan[idPQ] = B + 2 * rk + 1;
+      if (ids) {
+        c.a1.bscan[iduP] = rk;  // u - p
+        c.a1.bscan[idwQ] = B + 2 * rk;  // q - w
+        c.a1.bscan[idPQ] = B + 2 * rk + 1;
+      }
       c.a1.vhe[V + r] = 9 * r + 3 * j;
       c.a1.vhe[V + F + rk] = 9 * r + 3 * jn + 2;
       const int z = c.t.fv[3 * r + (j + 2) % 3];
       if (c.a.twin[c.a.vhe[z]] >= 0) atomicMin(&c.a1.vhe[z], 9 * r + 3 * j + 2);  // the apex z -> p
     }
   }
-  if (valid) {
+  if (valid && ids) {
     // every edge once, by its lower half-edge (the only one on the boundary)
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -1306,7 +1310,7 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
     }
   }
   wave_store<9>(lds, tw1, reinterpret_cast<uint32_t *>(c.a1.twin) + 9 * rw, l, cnt);
-  wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
+  if (ids) wave_store<9>(lds, ei1, reinterpret_cast<uint32_t *>(c.a1.eid) + 9 * rw, l, cnt);
 }
 
 __global__ void __launch_bounds__(kBlock) k_trisect_face(TrisectStep c) {

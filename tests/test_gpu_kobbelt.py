@@ -46,6 +46,26 @@ def test_kobbelt_matches_oracle(oracle_mod, cage, levels):
         assert err <= POS_TOL, f"level {k}: {err:.2e}"
 
 
+@pytest.mark.parametrize("scheme", ["sqrt3k", "sqrt3"])
+@pytest.mark.parametrize("cage,levels", [("holes", 5), ("grid", 4), ("fan12", 4), ("triangle", 3)])
+def test_without_edge_lists_no_edge_ids_are_carried(oracle_mod, scheme, cage, levels):
+    """With no edge list asked for, the sqrt(3) steps (and the trisection
+    steps) carry only twins and ring starts: every level's faces and positions
+    are the same bits as with edge lists (which carry the ids), and the oracle's
+    topology."""
+    m = CAGES[cage]()
+    print(f"[kobbelt] {scheme} without edge ids: {m.name} L={levels}", flush=True)
+    a, _ = api.refine(m, scheme, levels, keep="all")
+    b, _ = api.refine(m, scheme, levels, keep="all", edges=True)
+    ref = oracle_mod.refine(m, scheme, levels)
+    for k in range(1, levels + 1):
+        fa = a[k]["face_verts"].cpu().numpy()
+        np.testing.assert_array_equal(fa, b[k]["face_verts"].cpu().numpy(), err_msg=f"level {k}")
+        np.testing.assert_array_equal(fa, ref[k].verts, err_msg=f"level {k} topology")
+        np.testing.assert_array_equal(a[k]["positions"].cpu().numpy(), b[k]["positions"].cpu().numpy(),
+                                      err_msg=f"level {k}")
+
+
 def test_kobbelt_on_a_closed_cage_is_sqrt3():
     """Without a boundary the cycle is plain sqrt(3): same topology, and the
     same positions up to the summation order of the rings."""
