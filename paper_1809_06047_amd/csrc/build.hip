@@ -40,6 +40,24 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s
   return hipGetLastError();
 }
 
+// several regions cleared to zero by one launch (the build's counters and
+// crease tables: each launch of its own would add its own latency)
+__global__ void k_zero_regions(ZeroRegions z) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int r = 0; r < z.count; ++r)
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0;
+}
+
+hipError_t launch_zero_regions(const ZeroRegions &z, hipStream_t s) {
+  long long m = 0;
+  for (int r = 0; r < z.count; ++r) m = z.n[r] > m ? z.n[r] : m;
+  if (m <= 0) return hipSuccess;
+  unsigned g = grid_for(m);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_zero_regions, dim3(g), dim3(kBlock), 0, s, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s) {
   // callers only clear 4-byte aligned regions whose size is a multiple of 4
   return launch_fill_i32(reinterpret_cast<int32_t *>(p), 0, nbytes / 4, s);
@@ -239,22 +257,48 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t *in, 
 __global__ void __launch_bounds__(kScanOneThreads) k_scan_one(const int32_t *in, int32_t *out, long long n,
                                                               int32_t *total_dst) {
   constexpr int kI = kScanOneTile / kScanOneThreads;
+  static_assert(kI % 4 == 0, "a thread's items are whole int4s");
+  // a thread's items as int4 loads and stores when both arrays are 16-byte
+  // aligned and its items are all in range (one by one they leave every lane
+  // of an instruction on a different line)
+  const bool vec = reinterpret_cast<uintptr_t>(in) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
   int carry = 0;
   for (long long t0 = 0; t0 < n; t0 += kScanOneTile) {
     const long long base = t0 + (long long)threadIdx.x * kI;
+    const bool whole = vec && base + kI <= n;
     int v[kI];
     int s = 0;
+    if (whole) {
 #pragma unroll
-    for (int i = 0; i < kI; ++i) {
-      v[i] = (base + i < n) ? in[base + i] : 0;
-      s += v[i];
+      for (int q = 0; q < kI / 4; ++q) {
+        const int4 x = reinterpret_cast<const int4 *>(in + base)[q];
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kI; ++i) v[i] = (base + i < n) ? in[base + i] : 0;
     }
+#pragma unroll
+    for (int i = 0; i < kI; ++i) s += v[i];
     int tot;
     int off = block_excl_scan<kScanOneThreads>(s, &tot) + carry;
+    int o[kI];
 #pragma unroll
     for (int i = 0; i < kI; ++i) {
-      if (base + i < n) out[base + i] = off;
+      o[i] = off;
       off += v[i];
+    }
+    if (whole) {
+#pragma unroll
+      for (int q = 0; q < kI / 4; ++q)
+        reinterpret_cast<int4 *>(out + base)[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kI; ++i)
+        if (base + i < n) out[base + i] = o[i];
     }
     carry += tot;
   }
@@ -641,10 +685,18 @@ __global__ void k_build_eid(Topo t, const int32_t *rowptr, const int32_t *inc, c
   if (nb) atomicAdd(&info->num_boundary, nb);
 }
 
-hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s) {
+hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s,
+                       bool cleared) {
   hipError_t err;
-  if ((err = launch_fill_i32(b.nval, 0, t.V + 1ll, s)) != hipSuccess) return err;
-  if ((err = launch_fill_i32(b.cursor, 0, t.V, s)) != hipSuccess) return err;
+  if (!cleared) {
+    ZeroRegions z{};
+    z.p[0] = b.nval;
+    z.n[0] = t.V + 1ll;
+    z.p[1] = b.cursor;
+    z.n[1] = t.V;
+    z.count = 2;
+    if ((err = launch_zero_regions(z, s)) != hipSuccess) return err;
+  }
   const unsigned gf = grid_for(t.F);
   if (t.order == 4)
     hipLaunchKernelGGL(k_build_faces<4>, dim3(gf), dim3(kBlock), 0, s, t, scheme, b.nval, (int32_t *)nullptr, info);

@@ -519,16 +519,27 @@ hipError_t build_level0_faces(const subdiv_mesh *m, int scheme, const Topo &t, v
                               hipStream_t s) {
   DeviceInfo *info = at<DeviceInfo>(ws, y.info);
   hipError_t err;
-  if ((err = launch_fill_i32(reinterpret_cast<int32_t *>(info), 0, sizeof(DeviceInfo) / 4, s)) != hipSuccess)
-    return err;
   BuildScratch b = scratch0(ws, y);
   Adj a = adj_at(ws, y.adj0, t.H, m->num_creases > 0);
-  // clear edge-indexed crease state (E <= H)
+  // one launch clears the fault word and counters, the valence counts and
+  // incidence cursors, and the edge-indexed crease state (E <= H)
+  ZeroRegions z{};
+  z.p[0] = reinterpret_cast<int32_t *>(info);
+  z.n[0] = sizeof(DeviceInfo) / 4;
+  z.p[1] = b.nval;
+  z.n[1] = t.V + 1ll;
+  z.p[2] = b.cursor;
+  z.n[2] = t.V;
+  z.count = 3;
   if (a.sig) {
-    if ((err = launch_fill_i32(reinterpret_cast<int32_t *>(a.sig), 0, 2ll * t.H, s)) != hipSuccess) return err;
-    if ((err = launch_fill_i32(b.sigcnt, 0, t.H, s)) != hipSuccess) return err;
+    z.p[3] = reinterpret_cast<int32_t *>(a.sig);
+    z.n[3] = 2ll * t.H;
+    z.p[4] = b.sigcnt;
+    z.n[4] = t.H;
+    z.count = 5;
   }
-  return build_faces(t, scheme, b, info, s);
+  if ((err = launch_zero_regions(z, s)) != hipSuccess) return err;
+  return build_faces(t, scheme, b, info, s, true);
 }
 
 // Catmull-Clark with the adjacency carried over in closed form: step 0 on

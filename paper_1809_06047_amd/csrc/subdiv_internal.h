@@ -225,6 +225,13 @@ void subdiv_set_error(const char *msg);
 
 // ---- launchers (each returns hipGetLastError() of its launches) --------
 hipError_t launch_fill_i32(int32_t *p, int32_t value, long long n, hipStream_t s);
+// up to five int32 regions cleared to zero in one launch
+struct ZeroRegions {
+  int32_t *p[5];
+  long long n[5];
+  int count;
+};
+hipError_t launch_zero_regions(const ZeroRegions &z, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, long long nbytes, hipStream_t s);
 // channels c0..c0+2 of [V*dim] vertex data into a [V*3] array; up to six back
 hipError_t launch_pack3(const float *data, int dim, int c0, long long V, float *slice, hipStream_t s);
@@ -251,7 +258,9 @@ struct BuildScratch {
 };
 // phase A: validation of faces / indices, valence counts, column of every
 // non-zero (written to t.hface for a general cage)
-hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s);
+// (cleared: the caller has zeroed b.nval [V+1] and b.cursor [V] already)
+hipError_t build_faces(const Topo &t, int scheme, const BuildScratch &b, DeviceInfo *info, hipStream_t s,
+                       bool cleared = false);
 // phase B: row view of M, twins, edge ids, edge -> half-edge map, boundary flags
 hipError_t build_adjacency(const Topo &t, int scheme, const BuildScratch &b, Adj &a, DeviceInfo *info,
                            hipStream_t s);
