@@ -263,7 +263,7 @@ def test_final_buffer_shared_with_level_L_minus_2(scheme):
 
 @pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
 @pytest.mark.parametrize("cage,levels", [(c, L) for c in ("icosphere", "holes", "fan", "bipyramid", "grid")
-                                         for L in (3, 4)] + [("holes", 5), ("fan", 5)])
+                                         for L in (3, 4)] + [("holes", 5), ("fan", 5), ("tri", 4), ("tri", 5)])
 def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
     """The last Loop or sqrt(3) step runs from level L-2 (the level L-1 was
     refined from) and level L-1's adjacency is never built. The final level
@@ -275,7 +275,10 @@ def test_last_step_from_two_levels_down(oracle_mod, cage, levels, scheme):
          "holes": lambda: G.tri_cage(seed=19, level=2, hole_frac=0.08),
          "fan": lambda: _bipyramid(12, closed=False),
          "bipyramid": lambda: _bipyramid(9),
-         "grid": lambda: G.grid_patch(7, 5, tri=True, z_fn=lambda x, y: rng.normal(0, 0.2, x.shape))}[cage]()
+         "grid": lambda: G.grid_patch(7, 5, tri=True, z_fn=lambda x, y: rng.normal(0, 0.2, x.shape)),
+         # one triangle: every level-(L-3) wave of the steps from below is a partial one
+         "tri": lambda: G.Mesh(positions=np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0.5]], np.float32),
+                               verts=np.arange(3, dtype=np.int32), face_order=3, name="tri")}[cage]()
     L = levels
     print(f"[parity] {scheme} last step from level {L - 2}: {m.name} L={L}", flush=True)
     outs, _ = api.refine(m, scheme, L)
