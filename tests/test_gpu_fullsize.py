@@ -1,7 +1,7 @@
 """Parity at the full workload sizes (slow): the 10k-vertex mixed cage to
 Catmull-Clark level 6 (56.6M faces), the 40k-vertex holed triangle cage to
-Loop and sqrt(3) level 5, and the cage-fitting gradient at Catmull-Clark
-level 4. Every output of every level is compared with the FP64 oracle."""
+Loop, sqrt(3) and sqrt(3) with the boundary cycle level 5, and the
+cage-fitting gradient at Catmull-Clark level 4. Every output of every level is compared with the FP64 oracle."""
 import time
 
 import numpy as np
@@ -42,7 +42,7 @@ def test_cc_level6_mixed_cage(oracle_mod):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("scheme", ["loop", "sqrt3"])
+@pytest.mark.parametrize("scheme", ["loop", "sqrt3", "sqrt3k"])
 def test_triangle_cage_level5(oracle_mod, scheme):
     _full(oracle_mod, G.tri_cage(), scheme, 5, f"{scheme} L5")
 
