@@ -1199,7 +1199,7 @@ __device__ __forceinline__ void trisect_carry(const TrisectStep &c, int r, bool 
   const int V = c.t.V, F = c.t.F, j = c.bslot[r];
   // (without c.a1.eid only the twins and ring starts: no edge ids, no bases)
   const bool ids = c.a1.eid != nullptr;
-  const int32_t *baseP = c.base, *baseQ = c.base + F;
+  const int32_t *baseP = c.base, *baseQ = ids ? c.base + F : nullptr;
   int s[3], ip[3], js[3];
   bool isp[3];
 #pragma unroll
