@@ -387,9 +387,16 @@ __global__ void __launch_bounds__(BLK) k_lag2_group(Lag2Step c) {
   const int j = p & 3, pg = p >> 2;
   const int Vm = L.tm.V, VFm = L.tm.V + L.tm.F;
   const int Vk = L.Vk, VFk = L.Vk + L.Fk;
-  const int4 q = reinterpret_cast<const int4 *>(L.tm.fv)[p];
-  const int4 ed = reinterpret_cast<const int4 *>(L.am.eid)[p];
-  const int4 tq = reinterpret_cast<const int4 *>(L.am.twin)[p];
+  // the parent rows are read once here: non-temporal loads, so they do not
+  // displace the positions gathered from L2 (the edge kernel after this one
+  // reads some of them again, a smaller cost than this kernel's gain)
+  auto ntl = [](const int32_t *a, int i) {
+    const v4i32 x = __builtin_nontemporal_load(reinterpret_cast<const v4i32 *>(a) + i);
+    return make_int4(x[0], x[1], x[2], x[3]);
+  };
+  const int4 q = ntl(L.tm.fv, p);
+  const int4 ed = ntl(L.am.eid, p);
+  const int4 tq = ntl(L.am.twin, p);
   const int cv[4] = {q.x, q.y, q.z, q.w};
   const int e[4] = {ed.x, ed.y, ed.z, ed.w};
   const int tw[4] = {tq.x, tq.y, tq.z, tq.w};
